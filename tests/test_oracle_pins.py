@@ -1,0 +1,572 @@
+"""Pins of the CPU oracle against facts fixed independently of its code.
+
+Each test checks the oracle (oracle/vrt_oracle.c) against exact rational
+geometry, brute force over tiny inputs, or closed forms derived from the
+paper's definitions (arXiv 2510.09081, Sec. 3).  No GPU is needed.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2510_09081_amd import synth
+
+Q = 256
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")))
+
+
+def make_lineset(polys, G, radius_vox, vs=None):
+    """Polylines given in voxel units -> LineSet on a G^3 grid over the unit cube."""
+    vs = np.float32(1.0 / G) if vs is None else np.float32(vs)
+    xyz = np.concatenate([np.asarray(p, np.float64) for p in polys]) * float(vs)
+    off = np.concatenate([[0], np.cumsum([len(p) for p in polys])]).astype(np.int32)
+    return synth.LineSet(xyz=xyz.astype(np.float32), offsets=off, radius=float(np.float32(radius_vox * vs)),
+                         origin=np.zeros(3, np.float32), voxel_size=float(vs), dims=(G, G, G))
+
+
+# ---------------------------------------------------------------------------
+# exact rational geometry (independent of the oracle)
+
+
+def seg_box_dist2(A, B, lo, hi):
+    """Exact squared distance between segment AB and the closed box [lo, hi]."""
+    d = [B[c] - A[c] for c in range(3)]
+    bps = {Fraction(0), Fraction(1)}
+    for c in range(3):
+        if d[c] != 0:
+            for bnd in (lo[c], hi[c]):
+                h = Fraction(bnd - A[c], d[c])
+                if 0 < h < 1:
+                    bps.add(h)
+    bps = sorted(bps)
+    best = None
+    for h0, h1 in zip(bps[:-1], bps[1:]):
+        hm = (h0 + h1) / 2
+        a = b = cc = Fraction(0)
+        for c in range(3):
+            p = A[c] + hm * d[c]
+            if p < lo[c]:
+                bnd = lo[c]
+            elif p > hi[c]:
+                bnd = hi[c]
+            else:
+                continue
+            # (A_c - bnd + h d_c)^2
+            e0 = A[c] - bnd
+            a += d[c] * d[c]
+            b += 2 * e0 * d[c]
+            cc += e0 * e0
+        cands = [h0, h1]
+        if a > 0:
+            hs = -b / (2 * a)
+            if h0 < hs < h1:
+                cands.append(hs)
+        for h in cands:
+            v = a * h * h + b * h + cc
+            best = v if best is None or v < best else best
+    if best is None:  # zero-length segment: a single point
+        best = sum(max(lo[c] - A[c], 0, A[c] - hi[c]) ** 2 for c in range(3))
+    return best
+
+
+def exact_touched(A, B, rq, G):
+    """Voxels whose closed cube is within distance r of the segment (exact)."""
+    out = set()
+    rng = []
+    for c in range(3):
+        lo = min(A[c], B[c]) - rq
+        hi = max(A[c], B[c]) + rq
+        rng.append(range(max(0, (lo - 1) // Q), min(G - 1, hi // Q) + 1))
+    r2 = rq * rq
+    for x in rng[0]:
+        for y in rng[1]:
+            for z in rng[2]:
+                lo = (x * Q, y * Q, z * Q)
+                hi = ((x + 1) * Q, (y + 1) * Q, (z + 1) * Q)
+                if seg_box_dist2(A, B, lo, hi) <= r2:
+                    out.add((x, y, z))
+    return out
+
+
+def aabb_touched(A, B, rq, G):
+    out = set()
+    rng = []
+    for c in range(3):
+        lo = min(A[c], B[c]) - rq
+        hi = max(A[c], B[c]) + rq
+        rng.append(range(max(0, (lo - 1) // Q), min(G - 1, hi // Q) + 1))
+    for x in rng[0]:
+        for y in rng[1]:
+            for z in rng[2]:
+                out.add((x, y, z))
+    return out
+
+
+def adversarial_segments(rng, G, n_random):
+    c = G * Q // 2
+    segs = [
+        ((c, c, c), (c + 3 * Q, c, c)),                    # axis aligned
+        ((c + 17, c + 5, c + 130), (c + 17, c - 4 * Q, c + 130)),
+        ((c, c, c), (c + 2 * Q, c + 2 * Q, c + 2 * Q)),    # diagonal, ties everywhere
+        ((c + 77, c + 3, c + 200), (c + 77, c + 3, c + 200)),  # zero length
+        ((4 * Q, 4 * Q, 4 * Q), (6 * Q, 5 * Q, 4 * Q)),    # endpoints on voxel corners
+        ((c, c + Q, c - Q), (c - Q, c, c + Q)),            # |d| ties between axes
+        ((Q // 2, 3 * Q, 3 * Q), (-Q, 2 * Q, 4 * Q)),      # leaves the grid
+        ((c + 1, c + 2, c + 3), (c + 1 + 700, c + 2 - 699, c + 3 + 698)),
+    ]
+    for _ in range(n_random):
+        A = rng.integers(Q, (G - 1) * Q, size=3)
+        L = rng.uniform(0, 4) * Q
+        d = rng.normal(size=3)
+        d = d / np.linalg.norm(d) * L
+        B = np.clip(np.rint(A + d), 0, G * Q).astype(int)
+        segs.append((tuple(int(a) for a in A), tuple(int(b) for b in B)))
+    return segs
+
+
+# ---------------------------------------------------------------------------
+# C1 quantization
+
+
+def test_quantization_exact_on_fixed_point_grid(orc):
+    G = 64
+    rng = np.random.default_rng(5)
+    qs = rng.integers(0, G * Q, size=(500, 3))
+    vs = np.float32(1.0 / G)
+    xyz = (qs.astype(np.float64) * float(vs) / Q).astype(np.float32)  # exact in binary32
+    ls = synth.LineSet(xyz=xyz, offsets=np.array([0, 500], np.int32), radius=float(vs) * 0.5,
+                       origin=np.zeros(3, np.float32), voxel_size=float(vs), dims=(G, G, G))
+    ing = orc.ingest(ls)
+    assert ing.status == 0
+    assert np.array_equal(ing.q, qs)
+    assert ing.rq == 128
+
+
+def test_quantization_range_error(orc):
+    ls = make_lineset([[[0, 0, 0], [5000, 0, 0]]], 64, 0.5)
+    assert orc.ingest(ls).status == orc.ST_RANGE
+
+
+# ---------------------------------------------------------------------------
+# C3 membership (Alg. 1 with the conservative projected radius)
+
+
+@pytest.mark.parametrize("rq", [128, 90, 51, 0])
+def test_membership_conservative_and_tight(orc, rq):
+    G = 16
+    rng = np.random.default_rng(rq + 1)
+    for A, B in adversarial_segments(rng, G, 60):
+        got = {tuple(v) for v in orc.segment_voxels(A, B, rq, (G, G, G))}
+        assert len(got) == len(orc.segment_voxels(A, B, rq, (G, G, G)))  # no duplicates
+        exact = exact_touched(A, B, rq, G)
+        assert exact <= got, (A, B, rq, sorted(exact - got)[:5])       # conservative
+        assert got <= aabb_touched(A, B, rq, G), (A, B, rq)             # inside the capsule AABB
+
+
+def test_membership_axis_aligned_closed_form(orc):
+    G = 32
+    A, B, rq = (5 * Q + 40, 9 * Q + 100, 11 * Q + 7), (14 * Q + 3, 9 * Q + 100, 11 * Q + 7), 128
+    got = {tuple(v) for v in orc.segment_voxels(A, B, rq, (G, G, G))}
+    xr = range((A[0] - rq - 1) // Q, (B[0] + rq) // Q + 1)
+    yr = range((A[1] - rq - 1) // Q, (A[1] + rq) // Q + 1)
+    zr = range((A[2] - rq - 1) // Q, (A[2] + rq) // Q + 1)
+    assert got == {(x, y, z) for x in xr for y in yr for z in zr}
+
+
+def test_membership_zero_length_is_ball_aabb(orc):
+    G = 16
+    A = (7 * Q + 200, 3 * Q + 10, 9 * Q + 128)
+    got = {tuple(v) for v in orc.segment_voxels(A, A, 128, (G, G, G))}
+    assert got == aabb_touched(A, A, 128, G)
+
+
+def test_equation1_not_conservative_but_corrected_is(orc):
+    """The printed Eq. (1) radius misses voxels the capsule touches when both
+    minor components are non-zero; the corrected radius never does."""
+    G = 32
+    rng = np.random.default_rng(11)
+    missed = 0
+    for _ in range(150):
+        A = rng.integers(10 * Q, 20 * Q, size=3)
+        d = rng.normal(size=3)
+        d = d / np.linalg.norm(d) * rng.uniform(1.0, 4.0) * Q
+        B = np.rint(A + d).astype(int)
+        A, B = tuple(int(a) for a in A), tuple(int(b) for b in B)
+        exact = exact_touched(A, B, 128, G)
+        literal = {tuple(int(c) for c in v) for v in orc.segment_voxels(A, B, 128, (G, G, G), literal=True)}
+        fixed = {tuple(int(c) for c in v) for v in orc.segment_voxels(A, B, 128, (G, G, G))}
+        assert exact <= fixed
+        missed += bool(exact - literal)
+    assert missed > 0, "Eq. (1) should miss a touched voxel for some segment"
+
+
+def test_counts_sandwiched_by_exact_and_aabb(orc):
+    """count(v) lies between the number of capsules touching v exactly and the
+    number whose AABB touches v (brute force over all pairs)."""
+    G = 12
+    rng = np.random.default_rng(3)
+    polys = []
+    for _ in range(6):
+        p = rng.uniform(2, 10, size=3)
+        pts = [p]
+        for _k in range(6):
+            p = np.clip(p + rng.normal(size=3) * 0.8, 0.5, 11.5)
+            pts.append(p)
+        polys.append(np.array(pts))
+    ls = make_lineset(polys, G, 0.5)
+    ing = orc.ingest(ls)
+    words, st, nf = orc.voxelize(ing, ls.dims)
+    assert st == 0
+    cnt = (words & 0xFFFF).astype(int)
+    lo = np.zeros((G, G, G), int)
+    hi = np.zeros((G, G, G), int)
+    for i in range(ing.q.shape[0] - 1):
+        if not ing.seg_valid[i]:
+            continue
+        A, B = tuple(int(x) for x in ing.q[i]), tuple(int(x) for x in ing.q[i + 1])
+        for (x, y, z) in exact_touched(A, B, ing.rq, G):
+            lo[z, y, x] += 1
+        for (x, y, z) in aabb_touched(A, B, ing.rq, G):
+            hi[z, y, x] += 1
+    assert np.all(lo <= cnt) and np.all(cnt <= hi)
+    assert nf == cnt.sum()
+
+
+# ---------------------------------------------------------------------------
+# C5 occupancy quantum (Alg. 2, Alg. 3)
+
+
+@pytest.mark.parametrize("case", GOLD["occupancy"], ids=lambda c: c["case"][:40])
+def test_occupancy_closed_forms(orc, case):
+    n0 = case.get("n0", [0.0, 0.0, 0.0])
+    q = orc.occupancy_q(case["A"], case["B"], n0, [0, 0, 0], case.get("a_interior", 0), 0, case["rq"],
+                        case["voxel"])
+    assert q == case["q"]
+
+
+def test_clipping_removes_joint_overcount(orc):
+    """At an interior vertex the two capsules overlap; with the clip planes the
+    summed occupancy of a straight polyline equals that of one long segment."""
+    G = 32
+    one = make_lineset([[[4, 16.3, 16.6], [28, 16.3, 16.6]]], G, 0.5)
+    many = make_lineset([[[4 + 2 * k, 16.3, 16.6] for k in range(13)]], G, 0.5)
+    w1, _, _ = orc.voxelize(orc.ingest(one), one.dims)
+    w2, _, _ = orc.voxelize(orc.ingest(many), many.dims)
+    occ1, occ2 = (w1 >> 16).astype(int), (w2 >> 16).astype(int)
+    assert np.array_equal(occ1, occ2)
+    # without clip planes (every vertex an end vertex) the joints over-count
+    sep = make_lineset([[[4 + 2 * k, 16.3, 16.6], [6 + 2 * k, 16.3, 16.6]] for k in range(12)], G, 0.5)
+    w3, _, _ = orc.voxelize(orc.ingest(sep), sep.dims)
+    assert (w3 >> 16).astype(int).sum() > occ1.sum()
+
+
+def test_occupancy_independent_of_segment_order(orc):
+    w = synth.workload("random_walk_10k").lines
+    ls = synth.random_walk_set(seed=7, n_poly=40, n_seg=20, G=32)
+    perm = np.random.default_rng(0).permutation(ls.n_polylines)
+    polys = [ls.xyz[ls.offsets[p]:ls.offsets[p + 1]] for p in perm]
+    xyz = np.concatenate(polys)
+    off = np.concatenate([[0], np.cumsum([len(p) for p in polys])]).astype(np.int32)
+    ls2 = synth.LineSet(xyz=xyz, offsets=off, radius=ls.radius, origin=ls.origin, voxel_size=ls.voxel_size,
+                        dims=ls.dims)
+    a, _, _ = orc.voxelize(orc.ingest(ls), ls.dims)
+    b, _, _ = orc.voxelize(orc.ingest(ls2), ls2.dims)
+    assert np.array_equal(a, b)
+    assert w.n_segments == 10000
+
+
+# ---------------------------------------------------------------------------
+# C6 mips, C7 erosion
+
+
+def test_mip_chain_single_full_voxel(orc):
+    G = 16
+    words = np.zeros((G, G, G), np.uint32)
+    words[5, 6, 7] = 1 + (256 << 16)
+    lev = orc.occupancy_pyramid(words)
+    assert [int(l.max()) for l in lev] == GOLD["mips"]["single_full_voxel_chain"]
+    assert [l.shape for l in lev] == [(16,) * 3, (8,) * 3, (4,) * 3, (2,) * 3, (1,) * 3]
+
+
+def test_mip_constant_field_and_saturation(orc):
+    words = np.full((8, 8, 8), 300 + (5 << 16), np.uint32)  # count >= 256: full
+    lev = orc.occupancy_pyramid(words)
+    assert all(int(l.min()) == 256 and int(l.max()) == 256 for l in lev)
+    words = np.full((8, 8, 8), 3 + (500 << 16), np.uint32)  # sum > 256: saturates
+    assert int(orc.occupancy_pyramid(words)[0].max()) == 256
+
+
+def test_mip_odd_dims_missing_children_are_empty(orc):
+    words = np.zeros((1, 1, 3), np.uint32)
+    words[0, 0, :] = 1 + (200 << 16)
+    lev = orc.occupancy_pyramid(words)
+    # (3,1,1) -> (2,1,1): first parent sums 400, second sums 200 (one child)
+    assert lev[1].ravel().tolist() == [(400 + 4) // 8, (200 + 4) // 8]
+    assert lev[2].ravel().tolist() == [((404 // 8) + (204 // 8) + 4) // 8]
+
+
+def test_erosion_solid_block(orc):
+    o0 = np.zeros((16, 16, 16), np.uint16)
+    o0[4:12, 4:12, 4:12] = 256
+    b = orc.erode_blocking(o0)
+    expect = np.zeros_like(b)
+    expect[5:11, 5:11, 5:11] = 1
+    assert np.array_equal(b, expect)
+    o0[:, :, :] = 256  # the grid boundary counts as empty
+    b = orc.erode_blocking(o0)
+    assert b[0].sum() == 0 and b[1:15, 1:15, 1:15].all()
+
+
+# ---------------------------------------------------------------------------
+# C8 culling rays
+
+
+def meets_interior(c, E, u):
+    """Does the open segment (c, E) meet the open cube of voxel u?  (exact)"""
+    lo_t, hi_t = Fraction(0), Fraction(1)
+    for a in range(3):
+        L, H = u[a] * Q, (u[a] + 1) * Q
+        dlt = E[a] - c[a]
+        if dlt == 0:
+            if not (L < c[a] < H):
+                return False
+            continue
+        t1, t2 = Fraction(L - c[a], dlt), Fraction(H - c[a], dlt)
+        if t1 > t2:
+            t1, t2 = t2, t1
+        lo_t, hi_t = max(lo_t, t1), min(hi_t, t2)
+    return lo_t < hi_t
+
+
+@pytest.mark.parametrize("eye", [(100 * Q + 13, 40 * Q + 7, 70 * Q + 200),      # far, generic
+                                 (4 * Q + 128 + 9 * Q, 4 * Q + 128 + 9 * Q, 4 * Q + 128 + 9 * Q),  # corners
+                                 (4 * Q + 128 + 2 * Q, 4 * Q + 128 + Q, -3 * Q),  # edge ties
+                                 (6 * Q + 10, 2 * Q + 77, 5 * Q + 1)])            # eye inside the grid
+def test_culling_ray_visits_exactly_the_interiors_met(orc, eye):
+    G = 8
+    v = (4, 4, 4)
+    c = tuple(x * Q + Q // 2 for x in v)
+    for u in np.ndindex(G, G, G):
+        u = (u[2], u[1], u[0])
+        blk = np.zeros((G, G, G), np.uint8)
+        blk[u[2], u[1], u[0]] = 1
+        n, _ = orc.culling_ray(v, eye, blk, 100)
+        expect = (u != v) and meets_interior(c, eye, u)
+        assert n == int(expect), (u, eye)
+
+
+def test_culling_axis_aligned_column(orc):
+    G = 16
+    blk = np.ones((G, G, G), np.uint8)
+    eye = (3 * Q + 128, 5 * Q + 128, 40 * Q)
+    n, visited = orc.culling_ray((3, 5, 2), eye, blk, 1000)
+    assert n == visited == G - 1 - 2
+
+
+def test_visibility_no_culling_is_occupied(orc):
+    ls = synth.random_walk_set(seed=3, n_poly=20, n_seg=10, G=32)
+    fr = orc.build_frame(ls, np.array([2.0, 1.3, 1.5]), orc.CULL_NONE)
+    assert np.array_equal(fr.vis.astype(bool), (fr.words & 0xFFFF) > 0)
+
+
+def test_visibility_culls_behind_a_wall(orc):
+    """A dense wall of parallel lines hides the lines behind it (opaque), and
+    hides them only after enough layers (alpha)."""
+    G = 32
+    polys = [[[2, y + 0.5, z + 0.5], [30, y + 0.5, z + 0.5]] for y in range(4, 28) for z in range(4, 8)]
+    polys.append([[6, 16.5, 20.5], [26, 16.5, 20.5]])  # behind the wall seen from below
+    ls = make_lineset(polys, G, 0.75)
+    eye = np.array([16.5, 16.5, -40.0], np.float32) / G
+    fr = orc.build_frame(ls, eye, orc.CULL_OPAQUE)
+    assert fr.blocking.sum() > 0
+    back = fr.vis[19:23, 15:18, 8:24]
+    assert back.sum() == 0
+    fr_none = orc.build_frame(ls, eye, orc.CULL_NONE)
+    assert fr_none.vis[19:23, 15:18, 8:24].sum() > 0
+    assert fr.total < fr_none.total
+
+
+def test_cull_limit_layers(orc):
+    assert orc.cull_limit(orc.CULL_ALPHA, 0.3) == GOLD["compositing"]["layers_before_tau"]
+    assert orc.cull_limit(orc.CULL_ALPHA, 0.2) == 25
+    assert orc.cull_limit(orc.CULL_ALPHA, 0.5) == 9   # 0.5^8 == 1/256 exactly is not below tau
+    assert orc.cull_limit(orc.CULL_OPAQUE) == 1
+    assert orc.cull_limit(orc.CULL_NONE) == -1
+
+
+def test_culling_pyramid_or(orc):
+    vis = np.zeros((8, 8, 8), np.uint8)
+    vis[7, 0, 5] = 1
+    lev = orc.visibility_pyramid(vis)
+    assert lev[1][3, 0, 2] == 1 and lev[1].sum() == 1
+    assert lev[3].ravel().tolist() == [1]
+
+
+# ---------------------------------------------------------------------------
+# C10 CSR
+
+
+def test_csr_lists_match_independent_assembly(orc):
+    ls = synth.random_walk_set(seed=9, n_poly=30, n_seg=15, G=16)
+    eye = np.array([1.9, 1.2, 1.6], np.float32)
+    fr = orc.build_frame(ls, eye, orc.CULL_OPAQUE)
+    G = 16
+    lists = {}
+    for i in range(fr.ing.q.shape[0] - 1):
+        if not fr.ing.seg_valid[i]:
+            continue
+        for (x, y, z) in orc.segment_voxels(fr.ing.q[i], fr.ing.q[i + 1], fr.ing.rq, ls.dims):
+            if fr.vis[z, y, x]:
+                lists.setdefault((x, y, z), []).append(i)
+    # brick-major order of voxels
+    order = sorted(((z // 8, y // 8, x // 8, z % 8, y % 8, x % 8), (x, y, z))
+                   for z in range(G) for y in range(G) for x in range(G))
+    run = 0
+    for _, (x, y, z) in order:
+        assert fr.offsets[z, y, x] == run
+        if fr.vis[z, y, x]:
+            n = int(fr.words[z, y, x] & 0xFFFF)
+            got = fr.ids[run:run + n].tolist()
+            assert got == sorted(lists.get((x, y, z), []))
+            run += n
+    assert run == fr.total == sum(len(v) for v in lists.values())
+
+
+# ---------------------------------------------------------------------------
+# C11 rays
+
+
+def test_ray_centre_pixel_is_view_direction(orc):
+    cam = synth.Camera(eye=np.array([0.3, -1.2, 2.0]), target=np.array([0.5, 0.5, 0.5]),
+                       up=np.array([0.0, 0.0, 1.0]), fovy_deg=60.0, width=33, height=17)
+    d = orc.ray_dirs(cam, [8 * 33 + 16])[0].astype(np.float64)
+    f = np.asarray(cam.target, np.float32).astype(np.float64) - np.asarray(cam.eye, np.float32).astype(np.float64)
+    f /= np.linalg.norm(f)
+    assert np.linalg.norm(d - f) < 2e-7
+
+
+def test_ray_vertical_field_of_view(orc):
+    W, H, fovy = 31, 21, 50.0
+    cam = synth.Camera(eye=np.array([0.0, 0.0, 0.0]), target=np.array([1.0, 0.0, 0.0]),
+                       up=np.array([0.0, 0.0, 1.0]), fovy_deg=fovy, width=W, height=H)
+    d_top = orc.ray_dirs(cam, [0 * W + W // 2])[0].astype(np.float64)
+    ang = math.atan2(d_top[2], d_top[0])
+    assert abs(ang - math.atan((1 - 1 / H) * math.tan(math.radians(fovy / 2)))) < 1e-6
+    d_right = orc.ray_dirs(cam, [(H // 2) * W + W - 1])[0].astype(np.float64)
+    # the image's right edge points along f x up = -y
+    assert d_right[1] < 0 and abs(d_right[2]) < 1e-7
+    assert abs(math.atan2(-d_right[1], d_right[0])
+               - math.atan((1 - 1 / W) * math.tan(math.radians(fovy / 2)) * W / H)) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# C12 trace
+
+
+def centre_camera(eye_vox, target_vox, G, up=(0.0, 1.0, 0.0), W=5, H=5):
+    vs = 1.0 / G
+    return synth.Camera(eye=np.array(eye_vox) * vs, target=np.array(target_vox) * vs, up=np.array(up),
+                        fovy_deg=30.0, width=W, height=H)
+
+
+def trace_centre(orc, ls, cam, mode=0, alpha=1.0, cull=0):
+    fr = orc.build_frame(ls, cam.eye, cull)
+    pix = [(cam.height // 2) * cam.width + cam.width // 2]
+    return orc.trace(fr, ls, cam, pix, mode, alpha=alpha), fr
+
+
+def test_trace_perpendicular_hit_distance(orc):
+    G = 16
+    ls = make_lineset([[[2 + k, 8, 8] for k in range(13)]], G, 0.5)
+    cam = centre_camera((8.25, 8, 40), (8.25, 8, 8), G)
+    tr, fr = trace_centre(orc, ls, cam)
+    r = fr.ing.rq / Q
+    assert tr.id[0] == 6
+    assert abs(tr.t[0] - (32.0 - r)) < 1e-9
+    assert np.allclose(tr.rgba[0], [1, 0, 0, 1])
+
+
+def test_trace_axis_into_unclipped_end(orc):
+    G = 16
+    ls = make_lineset([[[4 + k, 8.5, 8.5] for k in range(7)]], G, 0.5)
+    cam = centre_camera((30, 8.5, 8.5), (0, 8.5, 8.5), G, up=(0, 0, 1))
+    tr, fr = trace_centre(orc, ls, cam)
+    assert tr.id[0] == 5
+    assert abs(tr.t[0] - (20.0 - fr.ing.rq / Q)) < 1e-9
+
+
+def test_trace_duplicate_segments_tie_to_lower_id(orc):
+    G = 16
+    p = [[2 + k, 8, 8] for k in range(13)]
+    ls = make_lineset([p, p], G, 0.5)
+    cam = centre_camera((8.25, 8, 40), (8.25, 8, 8), G)
+    tr, _ = trace_centre(orc, ls, cam)
+    assert tr.id[0] == 6
+
+
+@pytest.mark.parametrize("n", [1, 3, 10, 20])
+def test_trace_stacked_layers_composite(orc, n):
+    G = 64
+    polys = [[[20 + k, 32.3, 6.5 + 2 * j] for k in range(25)] for j in range(n)]
+    ls = make_lineset(polys, G, 0.5)
+    cam = centre_camera((32.4, 32.3, 60), (32.4, 32.3, 0), G)
+    a = GOLD["compositing"]["alpha"]
+    tr, _ = trace_centre(orc, ls, cam, mode=1, alpha=a)
+    m = min(n, GOLD["compositing"]["layers_before_tau"])
+    expect = 1 - (1 - a) ** m
+    assert tr.n_comp[0] == m
+    assert abs(tr.rgba[0, 0] - expect) < 1e-12 and abs(tr.rgba[0, 3] - expect) < 1e-12
+    assert abs(tr.rgba[0, 1]) < 1e-12
+
+
+def test_trace_lists_equal_bruteforce(orc):
+    """The list traversal reaches exactly the all-segments first hit (Sec. 3.5:
+    conservative lists plus the voxel order give correct hit order)."""
+    ls = synth.random_walk_set(seed=21, n_poly=40, n_seg=25, G=24, radius_vox=0.6)
+    cam = synth.grid_camera(ls, 48, 40, distance=1.2)
+    for mode, cull in [(0, 0), (1, 0), (0, 1)]:
+        fr = orc.build_frame(ls, cam.eye, cull)
+        pix = np.arange(cam.width * cam.height)
+        a = orc.trace(fr, ls, cam, pix, mode, alpha=0.3)
+        b = orc.trace(fr, ls, cam, pix, mode, alpha=0.3, brute=True)
+        assert (a.id >= 0).sum() > 100
+        assert np.array_equal(a.id, b.id)
+        assert np.array_equal(a.t, b.t)
+        assert np.array_equal(a.rgba, b.rgba)
+        c = orc.trace(fr, ls, cam, pix, mode, alpha=0.3, invoxel=True)
+        assert np.array_equal(c.id, b.id)
+        assert np.array_equal(c.t, b.t)
+        assert np.allclose(c.rgba, b.rgba, rtol=0, atol=1e-15)
+
+
+def test_nonconservative_lists_miss_hits(orc):
+    """With the printed Eq. (1) lists the per-voxel rule loses hits that the
+    brute-force definition has (the missing-segment artifacts of Sec. 4.1);
+    with the corrected lists it loses none."""
+    G = 32
+    rng = np.random.default_rng(0)
+    polys = []
+    for _ in range(60):
+        p = rng.uniform(8, 24, size=3)
+        d = rng.normal(size=3)
+        polys.append([p, p + rng.uniform(1, 4) * d / np.linalg.norm(d)])
+    ls = make_lineset(polys, G, 0.5)
+    u = rng.normal(size=3)
+    u /= np.linalg.norm(u)
+    cam = synth.Camera(eye=(np.array([16, 16, 16]) + 30 * u) / G, target=np.array([16, 16, 16]) / G,
+                       up=np.array([0.0, 0.0, 1.0]), fovy_deg=40.0, width=256, height=256)
+    fr = orc.build_frame(ls, cam.eye, orc.CULL_NONE)
+    pix = np.arange(256 * 256)
+    brute = orc.trace(fr, ls, cam, pix, 0, brute=True)
+    exact = orc.trace(fr, ls, cam, pix, 0, invoxel=True)
+    assert np.array_equal(brute.id, exact.id)
+    lit_words, _, _ = orc.voxelize(fr.ing, ls.dims, literal=True)
+    vis = (fr.vis & ((lit_words & 0xFFFF) > 0)).astype(np.uint8)
+    offsets, ids, total = orc.csr(fr.ing, lit_words, vis, literal=True)
+    lit = orc.Frame(fr.dims, fr.ing, lit_words, 0, 0, [], fr.blocking, fr.vis, [], offsets, ids, total, fr.eyeq,
+                    -1, {})
+    lit_tr = orc.trace(lit, ls, cam, pix, 0, invoxel=True)
+    assert (lit_tr.id != brute.id).sum() > 0
