@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Per-frame benchmark of the voxel ray tracing hot path on one MI355X.
+
+One step is one frame of the 5.5M-segment tractography-shaped line set at
+1920x1080: voxelization (pass 1 + occupancy pyramid), the opaque pass (cull
+with one blocking voxel, lists, opaque trace) and the transparent pass (cull
+with the alpha-layer limit, lists, sorted compositing at alpha = 0.2).  Inputs
+are resident in HBM before the timed region.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "per-frame AS build ms + Mrays/s at 1080p, 5M segs; batched/FP16 vs plain"
+HBM_PEAK_GBS = 8000.0
+VREC_BYTES = 32  # quantized position, flags, clip normal per vertex
+
+
+def kernel_bytes(name, n):
+    """Algorithmic HBM bytes of one launch (each distinct item moved once),
+    averaged over the frame's launches of that kernel (the list-building and
+    trace kernels run once per pass)."""
+    passes = ("opaque", "alpha")
+    if name == "k_vox_count":   # vertex records once; each occupied word read + written once
+        return VREC_BYTES * n["N_v"] + 8 * n["V_o"]
+    if name == "k_scatter":     # vertex records; visibility byte of touched voxels; cursor RMW; id writes
+        return float(np.mean([VREC_BYTES * n["N_v"] + n["V_o"] + 8 * n["V_v_" + p] + 4 * n["F_v_" + p]
+                              for p in passes]))
+    if name == "k_ingest":      # xyz + offsets in, records out
+        return 12 * n["N_v"] + 4 * n["N_p"] + VREC_BYTES * n["N_v"]
+    if name == "k_cull_vis":    # words in, visibility out, over occupied bricks
+        return 5 * 512 * n["bricks"]
+    if name == "k_trace":       # outputs (RGBA + depth + id) and the brick visibility table
+        return 24 * n["P"] + n["NB"]
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="bundles_5m")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-pixels", type=int, default=20000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path has no multi-GPU leg)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2510_09081_amd import synth, vrt
+
+    w = synth.workload(args.workload)
+    ls, cam = w.lines, w.camera
+    opq = next(p for p in w.passes if p.trace_mode == synth.MODE_OPAQUE)
+    alp = next(p for p in w.passes if p.trace_mode == synth.MODE_TRANSPARENT)
+    P = cam.width * cam.height
+    dev = torch.device("cuda", 0)
+    xyz = torch.from_numpy(ls.xyz).to(dev)
+    off = torch.from_numpy(ls.offsets).to(dev)
+    rgba = torch.empty(4 * P, device=dev)
+    depth = torch.empty(P, device=dev)
+    fid = torch.empty(P, dtype=torch.int32, device=dev)
+    cam_o = vrt.make_camera(cam.eye, cam.target, cam.up, cam.fovy_deg, cam.width, cam.height, vrt.TRACE_OPAQUE)
+    cam_a = vrt.make_camera(cam.eye, cam.target, cam.up, cam.fovy_deg, cam.width, cam.height,
+                            vrt.TRACE_TRANSPARENT, alp.alpha, alp.tau)
+    eye = np.asarray(cam.eye, np.float32)
+    cap = 8 * ls.n_segments
+    ctx = vrt.Context(max_vertices=ls.n_vertices, max_fragments=cap, max_dim=max(ls.dims), device=0)
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+
+    def frame(stage_events=False):
+        if stage_events:
+            ev[0].record()
+        ctx.voxelize(xyz, off, ls.radius, ls.origin, ls.voxel_size, ls.dims)
+        if stage_events:
+            ev[1].record()
+        ctx.cull(eye, opq.cull_mode, opq.alpha, opq.tau)
+        if stage_events:
+            ev[2].record()
+        ctx.trace(cam_o, rgba, depth, fid)
+        if stage_events:
+            ev[3].record()
+        ctx.cull(eye, alp.cull_mode, alp.alpha, alp.tau)
+        if stage_events:
+            ev[4].record()
+        ctx.trace(cam_a, rgba, depth, fid)
+        if stage_events:
+            ev[5].record()
+
+    # counts for the algorithmic-byte model (outside the timed region)
+    frame()
+    st = ctx.frame_status()
+    if st["device_status"] != 0:
+        raise SystemExit(f"device status {st['device_status']} during the first frame")
+    ctx.voxelize(xyz, off, ls.radius, ls.origin, ls.voxel_size, ls.dims)
+    ctx.cull(eye, opq.cull_mode, opq.alpha, opq.tau)
+    st_o = ctx.frame_status()
+    v = ctx.query_as()
+    nb = v.n_bricks
+    bricks = vrt.copy_to_host(v.brick_list, nb * 4, np.int32, nb).astype(np.int64)
+    top = int(bricks.max()) + 1
+    words = vrt.copy_to_host(v.words, top * 512 * 4, np.uint32, top * 512).reshape(top, 512)[bricks]
+    vis0 = vrt.copy_to_host(v.vis[0], top * 512, np.uint8, top * 512).reshape(top, 512)[bricks]
+    V_o = int(((words & 0xFFFF) > 0).sum())
+    V_v_o = int((vis0 > 0).sum())
+    ctx.cull(eye, alp.cull_mode, alp.alpha, alp.tau)
+    st_a = ctx.frame_status()
+    vis0a = vrt.copy_to_host(v.vis[0], top * 512, np.uint8, top * 512).reshape(top, 512)[bricks]
+    V_v_a = int((vis0a > 0).sum())
+    NB = (ls.dims[0] // 8) * (ls.dims[1] // 8) * (ls.dims[2] // 8)
+
+    for _ in range(args.warmup):
+        frame()
+    torch.cuda.synchronize()
+
+    # timed region: K frames, stage events on the stream
+    stage_ms = np.zeros(5)
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record()
+    for _ in range(args.steps):
+        frame(stage_events=True)
+        torch.cuda.synchronize()
+        stage_ms += np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(5)])
+    t_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    frame_ms_sync = t_start.elapsed_time(t_end) / args.steps
+    stage_ms /= args.steps
+
+    # back-to-back frames (no host synchronization between frames)
+    torch.cuda.synchronize()
+    t_start.record()
+    for _ in range(args.steps):
+        frame()
+    t_end.record()
+    torch.cuda.synchronize()
+    frame_ms = t_start.elapsed_time(t_end) / args.steps
+
+    # per-kernel durations: the library brackets every launch with HIP events on its stream
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t_start.record()
+    for _ in range(args.steps):
+        frame()
+    t_end.record()
+    torch.cuda.synchronize()
+    frame_ms_kev = t_start.elapsed_time(t_end) / args.steps
+    kern = ctx.profile_read()
+    ctx.profile_enable(False)
+    st_end = ctx.frame_status()
+    if st_end["device_status"] != 0:
+        raise SystemExit(f"device status {st_end['device_status']} in the timed frames")
+
+    counts = {"N_v": ls.n_vertices, "N_p": ls.n_polylines, "N_s": ls.n_segments, "F": st_o["n_fragments"],
+              "F_v_opaque": st_o["n_listed"], "F_v_alpha": st_a["n_listed"], "bricks": nb, "V_o": V_o,
+              "V_v_opaque": V_v_o, "V_v_alpha": V_v_a, "P": P, "NB": NB}
+    per_kernel = {k: {"launches_per_frame": n / args.steps, "avg_ms": ms / n, "ms_per_frame": ms / args.steps}
+                  for k, (n, ms) in sorted(kern.items(), key=lambda kv: -kv[1][1])}
+    dom = next(iter(per_kernel))
+    b = kernel_bytes(dom, counts)
+    roofline = None
+    if b is not None:
+        ach = b / (per_kernel[dom]["avg_ms"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "bytes_per_launch": int(b)}
+
+    as_build_ms = stage_ms[0] + stage_ms[1]
+    out = {
+        "metric": METRIC,
+        "value": round(2 * P / (frame_ms * 1e-3) / 1e6, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(frame_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "segments": ls.n_segments, "polylines": ls.n_polylines,
+                   "grid": list(ls.dims), "radius_vox": 0.35, "image": [cam.width, cam.height],
+                   "passes": ["opaque, cull opaque", f"transparent alpha={alp.alpha}, cull alpha"]},
+        "as_build_ms": round(as_build_ms, 4),
+        "trace_opaque_ms": round(stage_ms[2], 4),
+        "trace_opaque_mrays_s": round(P / (stage_ms[2] * 1e-3) / 1e6, 2),
+        "cull_alpha_ms": round(stage_ms[3], 4),
+        "trace_alpha_ms": round(stage_ms[4], 4),
+        "trace_alpha_mrays_s": round(P / (stage_ms[4] * 1e-3) / 1e6, 2),
+        "stage_ms": {"voxelize": round(stage_ms[0], 4), "cull_opaque": round(stage_ms[1], 4),
+                     "trace_opaque": round(stage_ms[2], 4), "cull_alpha": round(stage_ms[3], 4),
+                     "trace_alpha": round(stage_ms[4], 4)},
+        "frame_ms_host_sync_per_frame": round(frame_ms_sync, 4),
+        "frame_ms_with_kernel_events": round(frame_ms_kev, 4),
+        "kernels": {k: {kk: round(vv, 5) for kk, vv in d.items()} for k, d in per_kernel.items()},
+        "counts": counts,
+        "roofline": roofline,
+        "wall_s_timed": round(wall, 3),
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        t0 = time.perf_counter()
+        fo = O.build_frame(ls, eye, opq.cull_mode, opq.alpha, opq.tau)
+        t_build_o = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        fa = O.recull_frame(fo, ls, eye, alp.cull_mode, alp.alpha, alp.tau)
+        t_build_a = time.perf_counter() - t0
+        S = min(args.cpu_sample_pixels, P)
+        pix = np.random.default_rng(0).choice(P, S, replace=False)
+        t0 = time.perf_counter()
+        O.trace(fo, ls, cam, pix, 0)
+        t_tr_o = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.trace(fa, ls, cam, pix, 1, alpha=alp.alpha, tau=alp.tau)
+        t_tr_a = time.perf_counter() - t0
+        t_frame = t_build_o + t_build_a + (t_tr_o + t_tr_a) * P / S
+        out["cpu_baseline"] = {
+            "value": round(2 * P / t_frame / 1e6, 5), "unit": "Mrays/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": (f"full oracle build of the frame (voxelize, mips, erosion, both culls, both list sets: "
+                       f"{t_build_o + t_build_a:.1f} s) + both traces on {S} random pixels scaled to {P} "
+                       f"({t_tr_o + t_tr_a:.2f} s)"),
+            "frame_s": round(t_frame, 3), "stage_s": {k: round(v, 3) for k, v in {**fo.times, **{
+                "cull_alpha": fa.times["cull"], "lists_alpha": fa.times["lists"]}}.items()},
+        }
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

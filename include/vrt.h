@@ -1,0 +1,214 @@
+/*
+ * vrt.h -- C ABI of the MI355X voxel ray tracer for dynamic line sets.
+ *
+ * The library implements the per-frame path of arXiv 2510.09081 (Section 3):
+ *   vrt_voxelize  conservative capsule voxelization of every segment into a
+ *                 grid, per-voxel fragment count and occupancy in one packed
+ *                 32-bit word, and the averaging occupancy pyramid
+ *                 (Section 3.1, Alg. 1-3);
+ *   vrt_cull      erosion, camera-visibility culling and the culling pyramid
+ *                 (Section 3.2), then the exclusive scan of visible counts and
+ *                 the second voxelization pass that writes per-voxel segment
+ *                 lists (Section 3.3, voxelize-cull-scan-voxelize);
+ *   vrt_trace     one primary ray per pixel through the culling pyramid and the
+ *                 grid, exact ray-capsule hits with clip planes, the in-voxel
+ *                 acceptance rule, opaque first hit or sorted front-to-back
+ *                 compositing (Section 3.5).
+ *
+ * Conventions
+ *   - Pointers named "device" are HIP device memory owned by the caller; they
+ *     are only read or written by work enqueued on the given stream and must
+ *     stay valid until that work completes.  Struct arguments are read on the
+ *     host before the call returns.
+ *   - Positions are quantized to 1/256 voxel (int32, |q| < 2^20) relative to
+ *     the grid corner; the radius likewise.  Voxel membership, counts, culling
+ *     and list building are exact integer computations; the per-fragment
+ *     occupancy quantum is a fixed binary32 sequence.
+ *   - A segment is the pair of consecutive vertices (v_i, v_{i+1}) inside one
+ *     polyline; its id is i, the global index of its first vertex.
+ *   - The acceleration structure lives in arenas owned by the context and
+ *     sized at creation; no entry point allocates memory after vrt_create.
+ *     One context serves one stream at a time; contexts are independent.
+ *   - Status: 0 is success.  Argument errors are detected on the host before
+ *     anything is enqueued.  Errors that depend on device data (range,
+ *     capacity, count overflow) latch in a device status word, are reported
+ *     by vrt_frame_status, and leave that frame's outputs undefined.
+ */
+#ifndef VRT_H
+#define VRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vrt_status;
+
+#define VRT_OK 0
+#define VRT_ERR_INVALID_ARG 1    /* null pointer, bad size, bad enum, dims not a multiple of 8 ... */
+#define VRT_ERR_RANGE 2          /* coordinates beyond the fixed-point range, segment longer than 256 voxels */
+#define VRT_ERR_NOT_BUILT 3      /* vrt_cull before vrt_voxelize, vrt_trace before vrt_cull */
+#define VRT_ERR_CAPACITY 4       /* listed fragments exceed max_fragments */
+#define VRT_ERR_COUNT_OVERFLOW 5 /* more than 65535 fragments in one voxel (16-bit count field) */
+#define VRT_ERR_HIP 6            /* a HIP runtime call failed; see vrt_last_hip_error */
+
+#define VRT_CULL_NONE 0   /* every occupied voxel is visible (voxelize-scan-voxelize) */
+#define VRT_CULL_OPAQUE 1 /* hidden behind one blocking voxel */
+#define VRT_CULL_ALPHA 2  /* hidden behind as many blocking voxels as alpha layers reach tau */
+
+#define VRT_TRACE_OPAQUE 0
+#define VRT_TRACE_TRANSPARENT 1
+
+typedef struct vrt_ctx vrt_ctx;
+
+/* Capacities fixed at creation (Section 3.3: the lists are sized by the scan,
+ * so a capacity bounds them without a host round trip). */
+typedef struct {
+    int64_t max_vertices;  /* largest n_vertices accepted by vrt_voxelize */
+    int64_t max_fragments; /* capacity of the segment-id array (listed fragments) */
+    int32_t max_dim;       /* largest grid dimension; multiple of 8, <= 1024 */
+    int32_t device;        /* HIP device ordinal the arenas live on */
+} vrt_desc;
+
+/* A set of polylines with one radius (Section 3.1: capsules of uniform radius
+ * per polyline; polylines neither branch nor loop, Section 3.3). */
+typedef struct {
+    const float *xyz;            /* device, [3 * n_vertices], world units, xyz interleaved */
+    const int32_t *poly_offsets; /* device, [n_polylines + 1], polyline p = [off[p], off[p+1]); off[0] = 0,
+                                    off[n_polylines] = n_vertices, non-decreasing */
+    int64_t n_vertices;
+    int64_t n_polylines;
+    float radius;                /* capsule radius, world units, >= 0 */
+} vrt_lines;
+
+/* Axis-aligned grid of isotropic voxels; voxel (x,y,z) covers
+ * origin + voxel_size * [x, x+1) x [y, y+1) x [z, z+1). */
+typedef struct {
+    float origin[3];
+    float voxel_size; /* > 0 */
+    int32_t dims[3];  /* each a multiple of 8, 8 <= dims <= max_dim */
+} vrt_grid;
+
+/* View for culling (Section 3.2). */
+typedef struct {
+    float eye[3];      /* world units */
+    int32_t cull_mode; /* VRT_CULL_* */
+    float alpha;       /* VRT_CULL_ALPHA: per-layer opacity in (0, 1] */
+    float tau;         /* VRT_CULL_ALPHA: transmittance threshold in (0, 1) */
+} vrt_view;
+
+/* Pinhole camera (Section 3.5: one ray per pixel). */
+typedef struct {
+    float eye[3], target[3], up[3]; /* world units; up not parallel to target - eye */
+    float fovy_deg;                 /* vertical field of view, (0, 180) */
+    int32_t width, height;          /* pixels, >= 1 */
+    int32_t mode;                   /* VRT_TRACE_* */
+    float alpha;                    /* transparent: per-hit opacity in (0, 1] */
+    float tau;                      /* transparent: stop once transmittance < tau */
+} vrt_camera;
+
+/* Output image, row 0 at the top, pixel (x, y) at index y * width + x. */
+typedef struct {
+    float *rgba;       /* device, [4 * W * H]; opaque: colour of the first hit, alpha 1;
+                          transparent: premultiplied composite, A = 1 - transmittance; 0 on a miss */
+    float *depth;      /* device, [W * H] or NULL; world distance to the first hit, +inf on a miss */
+    int32_t *first_id; /* device, [W * H] or NULL; segment id of the first hit, -1 on a miss */
+} vrt_image;
+
+/* Per-frame totals; filled by vrt_frame_status. */
+typedef struct {
+    vrt_status device_status; /* first latched device error of the frame, or VRT_OK */
+    int64_t n_fragments;      /* pass-1 fragments: sum over segments of |voxel set| */
+    int64_t n_listed;         /* fragments written to lists (visible voxels only) */
+    int64_t n_bricks;         /* occupied 8^3 bricks */
+    int64_t required_fragments; /* capacity the frame needed (== n_listed) */
+} vrt_frame_info;
+
+/* Read-only device views of the acceleration structure for inspection.
+ * Layout: brick b = (bz * NBy + by) * NBx + bx with NB = dims / 8; level-0
+ * per-voxel arrays hold 512 entries per brick (x fastest inside the brick),
+ * level-1 arrays 64 (4^3) and level-2 arrays 8 (2^3) per brick; level-3
+ * arrays one entry per brick (dense over all bricks).  Only bricks listed in
+ * brick_list are defined at levels 0-2.  Levels >= 4 are dense x-fastest grids
+ * of size ceil(dims / 2^L), stored back to back from level 4 upwards. */
+typedef struct {
+    int32_t dims[3];
+    int32_t n_levels;            /* levels 0 .. n_levels-1; the last is 1^3 */
+    int32_t n_bricks;            /* occupied bricks (copied from the device; synchronizes) */
+    const int32_t *brick_list;   /* [n_bricks] ascending brick indices */
+    const uint32_t *words;       /* level 0: count (low 16 bits) + occupancy sum (high 16 bits) */
+    const uint16_t *occ[4];      /* occupancy levels 0..3 (1/256 units) */
+    const uint16_t *occ_hi;      /* occupancy levels >= 4 */
+    const uint8_t *blocking;     /* level 0: eroded occupancy is full */
+    const uint8_t *vis[4];       /* culling levels 0..3 */
+    const uint8_t *vis_hi;       /* culling levels >= 4 */
+    const uint32_t *list_end;    /* level 0: end of the voxel's list in ids (start = end - count) */
+    const uint32_t *ids;         /* [n_listed] segment ids */
+} vrt_as_view;
+
+/* Creates a context on desc->device and allocates every arena.
+ * Errors: VRT_ERR_INVALID_ARG, VRT_ERR_HIP (allocation failure). */
+vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out);
+
+/* Frees every arena; waits for outstanding work of the context. */
+vrt_status vrt_destroy(vrt_ctx *ctx);
+
+/* Section 3.1: quantizes the vertices, derives the clip-plane normals (the
+ * central-difference tangent at interior vertices), clears what the previous
+ * frame wrote, and runs voxelization pass 1 (count + occupancy, one packed
+ * atomic per fragment) and the occupancy pyramid.  stream: hipStream_t. */
+vrt_status vrt_voxelize(vrt_ctx *ctx, const vrt_lines *lines, const vrt_grid *grid, void *stream);
+
+/* Sections 3.2 and 3.3: erosion and blocking flags, one culling ray per
+ * occupied voxel toward view->eye, the culling pyramid, the exclusive scan of
+ * visible counts (8^3 bricks in order, x fastest inside a brick) and pass 2,
+ * which writes each segment's id into the lists of its visible voxels.
+ * Requires a preceding vrt_voxelize on the same context. */
+vrt_status vrt_cull(vrt_ctx *ctx, const vrt_view *view, void *stream);
+
+/* Section 3.5: traces one ray per pixel and writes the image.  Requires a
+ * preceding vrt_cull.  The ray origin is cam->eye quantized like the
+ * vertices; directions are a fixed binary32 function of the camera. */
+vrt_status vrt_trace(vrt_ctx *ctx, const vrt_camera *cam, const vrt_image *out, void *stream);
+
+/* Synchronizes the context's last stream, reads the device status word and
+ * the frame totals, and clears the latched error. */
+vrt_status vrt_frame_status(vrt_ctx *ctx, vrt_frame_info *out);
+
+/* Fills device pointers to the acceleration structure (synchronizes to read
+ * the brick count). */
+vrt_status vrt_query_as(vrt_ctx *ctx, vrt_as_view *out);
+
+/* Writes the binary32 primary-ray directions of n pixels (indices y*W + x)
+ * into dirs[3*n] (device) -- the exact rays vrt_trace uses. */
+vrt_status vrt_debug_rays(vrt_ctx *ctx, const vrt_camera *cam, const int64_t *pixels, int64_t n, float *dirs,
+                          void *stream);
+
+/* Per-kernel timing: when enabled, every kernel the context launches is
+ * bracketed by a pair of HIP events recorded on its launch stream (up to
+ * 65536 launches between reads).  vrt_profile_read synchronizes, writes one
+ * record per kernel name (launch count and summed event time), and resets. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} vrt_kernel_time;
+
+vrt_status vrt_profile_enable(vrt_ctx *ctx, int32_t enable);
+vrt_status vrt_profile_read(vrt_ctx *ctx, vrt_kernel_time *out, int32_t max_records, int32_t *n_records);
+
+/* Synchronous copy of `bytes` from device memory to host memory. */
+vrt_status vrt_copy_to_host(void *host_dst, const void *device_src, int64_t bytes);
+
+/* The HIP error code of the last VRT_ERR_HIP on this thread. */
+int32_t vrt_last_hip_error(void);
+
+/* Static description of a status code. */
+const char *vrt_status_string(vrt_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VRT_H */

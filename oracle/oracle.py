@@ -296,6 +296,24 @@ def build_frame(ls, eye, cull_mode, alpha=1.0, tau=1.0 / 256.0, literal=False) -
     return Frame(tuple(ls.dims), ing, words, st, nf, occ, blk, vis, vlev, offsets, ids, total, eq, lim, t)
 
 
+def recull_frame(fr: Frame, ls, eye, cull_mode, alpha=1.0, tau=1.0 / 256.0) -> Frame:
+    """Culling, culling pyramid and lists of an already voxelized frame for another view."""
+    t = {}
+    eq = eye_q(eye, ls)
+    lim = cull_limit(cull_mode, alpha, tau)
+    t0 = time.perf_counter()
+    vis = visibility(fr.words, fr.blocking, eq, lim)
+    t["cull"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    vlev = visibility_pyramid(vis)
+    t["cull_mips"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    offsets, ids, total = csr(fr.ing, fr.words, vis)
+    t["lists"] = time.perf_counter() - t0
+    return Frame(fr.dims, fr.ing, fr.words, fr.status, fr.n_fragments, fr.occ, fr.blocking, vis, vlev, offsets, ids,
+                 total, eq, lim, t)
+
+
 @dataclass
 class TraceResult:
     pix: np.ndarray

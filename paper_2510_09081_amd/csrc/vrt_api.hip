@@ -1,0 +1,428 @@
+// vrt_api.hip -- context, argument validation and the C ABI entry points.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "vrt_internal.h"
+
+using namespace vrt;
+
+namespace {
+
+thread_local int32_t g_last_hip = 0;
+
+vrt_status hip_fail(hipError_t e) {
+    g_last_hip = (int32_t)e;
+    return VRT_ERR_HIP;
+}
+
+#define VRT_HIP(call)                              \
+    do {                                           \
+        hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess) return hip_fail(e_); \
+    } while (0)
+
+template <class T>
+hipError_t alloc(T *&p, int64_t n) {
+    return hipMalloc((void **)&p, (size_t)(n > 0 ? n : 1) * sizeof(T));
+}
+
+void free_all(Arenas &a) {
+    void *ptrs[] = {a.vrec, a.words, a.occ0, a.occ1, a.occ2, a.occ3, a.occ_hi, a.blk, a.brick_blk, a.vis0,
+                    a.vis1, a.vis2,  a.vis3, a.vis_hi, a.cursor, a.ids, a.brick_flag, a.brick_list, a.brick_slot,
+                    a.brick_total, a.brick_base, a.status};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    a = Arenas();
+}
+
+// Pyramid level dims: level L = ceil(dims / 2^L) down to 1^3.
+int level_dims(const int dims[3], Level *lv) {
+    int n = 0;
+    int d[3] = {dims[0], dims[1], dims[2]};
+    int64_t off = 0;
+    for (;;) {
+        for (int k = 0; k < 3; ++k) lv[n].dims[k] = d[k];
+        lv[n].offset = 0;
+        if (n >= 4) {
+            lv[n].offset = off;
+            off += (int64_t)d[0] * d[1] * d[2];
+        }
+        ++n;
+        if (d[0] == 1 && d[1] == 1 && d[2] == 1) break;
+        for (int k = 0; k < 3; ++k) d[k] = (d[k] + 1) / 2;
+    }
+    return n;
+}
+
+int64_t hi_elems_for(int max_dim) {
+    Level lv[kMaxLevels + 1];
+    int dims[3] = {max_dim, max_dim, max_dim};
+    int n = level_dims(dims, lv);
+    int64_t s = 0;
+    for (int L = 4; L < n; ++L) s += (int64_t)lv[L].dims[0] * lv[L].dims[1] * lv[L].dims[2];
+    return s;
+}
+
+bool finite3(const float *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+// Eye in 1/256 voxel, rounded in binary64; |E| < 2^22 keeps every later
+// difference exact in binary32 and every culling product inside int64.
+vrt_status quantize_eye(const vrt_ctx *c, const float *eye, int64_t E[3]) {
+    if (!finite3(eye)) return VRT_ERR_INVALID_ARG;
+    double s = 256.0 / (double)c->voxel_size;
+    for (int k = 0; k < 3; ++k) {
+        double q = std::rint(((double)eye[k] - (double)c->origin[k]) * s);
+        if (!(std::fabs(q) < 4194304.0)) return VRT_ERR_RANGE;
+        E[k] = (int64_t)q;
+    }
+    return VRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
+    if (!desc || !out) return VRT_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (desc->max_vertices < 2 || desc->max_fragments < 1 || desc->max_dim < 8 || desc->max_dim > 1024 ||
+        desc->max_dim % 8 != 0 || desc->max_vertices > ((int64_t)1 << 31) || desc->max_fragments > 0xFFFFFFFFll)
+        return VRT_ERR_INVALID_ARG;
+    int ndev = 0;
+    VRT_HIP(hipGetDeviceCount(&ndev));
+    if (desc->device < 0 || desc->device >= ndev) return VRT_ERR_INVALID_ARG;
+    VRT_HIP(hipSetDevice(desc->device));
+    vrt_ctx *c = new (std::nothrow) vrt_ctx();
+    if (!c) return VRT_ERR_INVALID_ARG;
+    c->desc = *desc;
+    const int64_t nbd = desc->max_dim / 8;
+    c->max_bricks = nbd * nbd * nbd;
+    c->hi_elems = hi_elems_for(desc->max_dim);
+    Arenas &a = c->a;
+    const int64_t mb = c->max_bricks;
+    hipError_t e = hipSuccess;
+#define ALLOC(p, n) \
+    if (e == hipSuccess) e = alloc(p, n)
+    ALLOC(a.vrec, desc->max_vertices);
+    ALLOC(a.words, mb * kBrickVox);
+    ALLOC(a.occ0, mb * kBrickVox);
+    ALLOC(a.occ1, mb * 64);
+    ALLOC(a.occ2, mb * 8);
+    ALLOC(a.occ3, mb);
+    ALLOC(a.occ_hi, c->hi_elems);
+    ALLOC(a.blk, mb * kBrickVox);
+    ALLOC(a.brick_blk, mb);
+    ALLOC(a.vis0, mb * kBrickVox);
+    ALLOC(a.vis1, mb * 64);
+    ALLOC(a.vis2, mb * 8);
+    ALLOC(a.vis3, mb);
+    ALLOC(a.vis_hi, c->hi_elems);
+    ALLOC(a.cursor, mb * kBrickVox);
+    ALLOC(a.ids, desc->max_fragments);
+    ALLOC(a.brick_flag, mb);
+    ALLOC(a.brick_list, mb);
+    ALLOC(a.brick_slot, mb);
+    ALLOC(a.brick_total, mb);
+    ALLOC(a.brick_base, mb);
+    ALLOC(a.status, 1);
+#undef ALLOC
+    if (e == hipSuccess) e = hipMemset(a.words, 0, (size_t)mb * kBrickVox * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(a.brick_flag, 0, (size_t)mb);
+    if (e == hipSuccess) e = hipMemset(a.brick_slot, 0xFF, (size_t)mb * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemset(a.status, 0, sizeof(DevStatus));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_all(a);
+        delete c;
+        return hip_fail(e);
+    }
+    *out = c;
+    return VRT_OK;
+}
+
+static void profiler_free(Profiler &p) {
+    if (p.ev) {
+        for (int i = 0; i < 2 * Profiler::kMaxPairs; ++i) (void)hipEventDestroy(p.ev[i]);
+        delete[] p.ev;
+        delete[] p.names;
+    }
+    p = Profiler();
+}
+
+vrt_status vrt_destroy(vrt_ctx *c) {
+    if (!c) return VRT_ERR_INVALID_ARG;
+    (void)hipSetDevice(c->desc.device);
+    (void)hipDeviceSynchronize();
+    profiler_free(c->prof);
+    free_all(c->a);
+    delete c;
+    return VRT_OK;
+}
+
+vrt_status vrt_voxelize(vrt_ctx *c, const vrt_lines *L, const vrt_grid *g, void *stream) {
+    if (!c || !L || !g) return VRT_ERR_INVALID_ARG;
+    if (!L->xyz || !L->poly_offsets || L->n_polylines < 1 || L->n_vertices < 1 ||
+        L->n_vertices > c->desc.max_vertices || L->n_polylines > L->n_vertices)
+        return VRT_ERR_INVALID_ARG;
+    if (!(L->radius >= 0.0f) || !std::isfinite(L->radius)) return VRT_ERR_INVALID_ARG;
+    if (!(g->voxel_size > 0.0f) || !std::isfinite(g->voxel_size) || !finite3(g->origin)) return VRT_ERR_INVALID_ARG;
+    for (int k = 0; k < 3; ++k)
+        if (g->dims[k] < 8 || g->dims[k] % 8 != 0 || g->dims[k] > c->desc.max_dim) return VRT_ERR_INVALID_ARG;
+    double rq = std::rint((double)L->radius * 256.0 / (double)g->voxel_size);
+    if (!(rq <= 16384.0)) return VRT_ERR_RANGE;
+    VRT_HIP(hipSetDevice(c->desc.device));
+    hipStream_t st = (hipStream_t)stream;
+    for (int k = 0; k < 3; ++k) {
+        c->dims[k] = g->dims[k];
+        c->origin[k] = g->origin[k];
+    }
+    c->voxel_size = g->voxel_size;
+    c->rq = (int64_t)rq;
+    c->n_vertices = L->n_vertices;
+    c->n_levels = level_dims(c->dims, c->levels);
+    c->voxelized = false;
+    c->culled = false;
+    c->last_stream = st;
+    const float s_q = (float)(256.0 / (double)g->voxel_size);
+    VRT_HIP(launch_voxelize(c, L, s_q, st));
+    c->voxelized = true;
+    return VRT_OK;
+}
+
+vrt_status vrt_cull(vrt_ctx *c, const vrt_view *v, void *stream) {
+    if (!c || !v) return VRT_ERR_INVALID_ARG;
+    if (!c->voxelized) return VRT_ERR_NOT_BUILT;
+    int64_t limit;
+    if (v->cull_mode == VRT_CULL_NONE) {
+        limit = -1;
+    } else if (v->cull_mode == VRT_CULL_OPAQUE) {
+        limit = 1;
+    } else if (v->cull_mode == VRT_CULL_ALPHA) {
+        if (!(v->alpha > 0.0f && v->alpha <= 1.0f) || !(v->tau > 0.0f && v->tau < 1.0f)) return VRT_ERR_INVALID_ARG;
+        // layers after which transmittance (1 - alpha)^k drops below tau
+        double T = 1.0;
+        limit = 0;
+        while (!(T < (double)v->tau)) {
+            T *= 1.0 - (double)v->alpha;
+            ++limit;
+        }
+        if (limit < 1) limit = 1;
+    } else {
+        return VRT_ERR_INVALID_ARG;
+    }
+    int64_t E[3];
+    vrt_status s = quantize_eye(c, v->eye, E);
+    if (s != VRT_OK) return s;
+    VRT_HIP(hipSetDevice(c->desc.device));
+    hipStream_t st = (hipStream_t)stream;
+    c->last_stream = st;
+    c->culled = false;
+    VRT_HIP(launch_cull(c, E, limit, st));
+    c->culled = true;
+    return VRT_OK;
+}
+
+static vrt_status camera_params(const vrt_ctx *c, const vrt_camera *cam, TraceParams &p) {
+    if (!finite3(cam->eye) || !finite3(cam->target) || !finite3(cam->up)) return VRT_ERR_INVALID_ARG;
+    if (cam->width < 1 || cam->height < 1 || cam->width > 65536 || cam->height > 65536) return VRT_ERR_INVALID_ARG;
+    if (!(cam->fovy_deg > 0.0f && cam->fovy_deg < 180.0f)) return VRT_ERR_INVALID_ARG;
+    if (cam->mode != VRT_TRACE_OPAQUE && cam->mode != VRT_TRACE_TRANSPARENT) return VRT_ERR_INVALID_ARG;
+    if (cam->mode == VRT_TRACE_TRANSPARENT &&
+        (!(cam->alpha > 0.0f && cam->alpha <= 1.0f) || !(cam->tau > 0.0f && cam->tau < 1.0f)))
+        return VRT_ERR_INVALID_ARG;
+    // camera basis in binary64, rounded once to binary32
+    double f[3], r[3], u[3];
+    for (int k = 0; k < 3; ++k) f[k] = (double)cam->target[k] - (double)cam->eye[k];
+    double nf = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (!(nf > 0.0)) return VRT_ERR_INVALID_ARG;
+    for (int k = 0; k < 3; ++k) f[k] = f[k] / nf;
+    const double up0 = cam->up[0], up1 = cam->up[1], up2 = cam->up[2];
+    r[0] = f[1] * up2 - f[2] * up1;
+    r[1] = f[2] * up0 - f[0] * up2;
+    r[2] = f[0] * up1 - f[1] * up0;
+    double nr = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(nr > 0.0)) return VRT_ERR_INVALID_ARG;
+    for (int k = 0; k < 3; ++k) r[k] = r[k] / nr;
+    u[0] = r[1] * f[2] - r[2] * f[1];
+    u[1] = r[2] * f[0] - r[0] * f[2];
+    u[2] = r[0] * f[1] - r[1] * f[0];
+    const double th = std::tan((double)cam->fovy_deg * M_PI / 360.0);
+    const double aspect = (double)cam->width / (double)cam->height;
+    for (int k = 0; k < 3; ++k) {
+        p.F[k] = (float)f[k];
+        p.R[k] = (float)(r[k] * (th * aspect));
+        p.U[k] = (float)(u[k] * th);
+    }
+    int64_t E[3];
+    vrt_status s = quantize_eye(c, cam->eye, E);
+    if (s != VRT_OK) return s;
+    for (int k = 0; k < 3; ++k) p.O[k] = (float)E[k] / 256.0f;
+    p.W = cam->width;
+    p.H = cam->height;
+    p.mode = cam->mode;
+    p.alpha = cam->mode == VRT_TRACE_TRANSPARENT ? cam->alpha : 1.0f;
+    p.tau = cam->mode == VRT_TRACE_TRANSPARENT ? cam->tau : 0.5f;
+    p.radius = (float)c->rq / 256.0f;
+    p.voxel_size = c->voxel_size;
+    return VRT_OK;
+}
+
+vrt_status vrt_trace(vrt_ctx *c, const vrt_camera *cam, const vrt_image *img, void *stream) {
+    if (!c || !cam || !img || !img->rgba) return VRT_ERR_INVALID_ARG;
+    if (!c->culled) return VRT_ERR_NOT_BUILT;
+    TraceParams p;
+    vrt_status s = camera_params(c, cam, p);
+    if (s != VRT_OK) return s;
+    VRT_HIP(hipSetDevice(c->desc.device));
+    hipStream_t st = (hipStream_t)stream;
+    c->last_stream = st;
+    VRT_HIP(launch_trace(c, p, img, st));
+    return VRT_OK;
+}
+
+vrt_status vrt_debug_rays(vrt_ctx *c, const vrt_camera *cam, const int64_t *pixels, int64_t n, float *dirs,
+                          void *stream) {
+    if (!c || !cam || (n > 0 && (!pixels || !dirs)) || n < 0) return VRT_ERR_INVALID_ARG;
+    if (!c->voxelized) return VRT_ERR_NOT_BUILT;
+    TraceParams p;
+    vrt_status s = camera_params(c, cam, p);
+    if (s != VRT_OK) return s;
+    VRT_HIP(hipSetDevice(c->desc.device));
+    VRT_HIP(launch_debug_rays(p, pixels, n, dirs, (hipStream_t)stream));
+    return VRT_OK;
+}
+
+vrt_status vrt_frame_status(vrt_ctx *c, vrt_frame_info *out) {
+    if (!c || !out) return VRT_ERR_INVALID_ARG;
+    VRT_HIP(hipSetDevice(c->desc.device));
+    VRT_HIP(hipStreamSynchronize(c->last_stream));
+    DevStatus h;
+    VRT_HIP(hipMemcpy(&h, c->a.status, sizeof(DevStatus), hipMemcpyDeviceToHost));
+    vrt_status ds = VRT_OK;
+    if (h.err & kErrInvalid) ds = VRT_ERR_INVALID_ARG;
+    else if (h.err & kErrRange) ds = VRT_ERR_RANGE;
+    else if (h.err & kErrCount) ds = VRT_ERR_COUNT_OVERFLOW;
+    else if (h.err & kErrCapacity) ds = VRT_ERR_CAPACITY;
+    unsigned zero = 0;
+    VRT_HIP(hipMemcpy(&c->a.status->err, &zero, sizeof(unsigned), hipMemcpyHostToDevice));
+    out->device_status = ds;
+    out->n_fragments = (int64_t)h.n_fragments;
+    out->n_listed = (int64_t)h.n_listed;
+    out->n_bricks = (int64_t)h.n_bricks;
+    out->required_fragments = (int64_t)h.n_listed;
+    return VRT_OK;
+}
+
+vrt_status vrt_query_as(vrt_ctx *c, vrt_as_view *o) {
+    if (!c || !o) return VRT_ERR_INVALID_ARG;
+    if (!c->voxelized) return VRT_ERR_NOT_BUILT;
+    VRT_HIP(hipSetDevice(c->desc.device));
+    VRT_HIP(hipStreamSynchronize(c->last_stream));
+    unsigned nb = 0;
+    VRT_HIP(hipMemcpy(&nb, &c->a.status->n_bricks, sizeof(unsigned), hipMemcpyDeviceToHost));
+    std::memset(o, 0, sizeof(*o));
+    for (int k = 0; k < 3; ++k) o->dims[k] = c->dims[k];
+    o->n_levels = c->n_levels;
+    o->n_bricks = (int32_t)nb;
+    const Arenas &a = c->a;
+    o->brick_list = a.brick_list;
+    o->words = a.words;
+    o->occ[0] = a.occ0;
+    o->occ[1] = a.occ1;
+    o->occ[2] = a.occ2;
+    o->occ[3] = a.occ3;
+    o->occ_hi = a.occ_hi;
+    o->blocking = a.blk;
+    o->vis[0] = a.vis0;
+    o->vis[1] = a.vis1;
+    o->vis[2] = a.vis2;
+    o->vis[3] = a.vis3;
+    o->vis_hi = a.vis_hi;
+    o->list_end = a.cursor;
+    o->ids = a.ids;
+    return VRT_OK;
+}
+
+vrt_status vrt_copy_to_host(void *dst, const void *src, int64_t bytes) {
+    if (bytes < 0 || (bytes > 0 && (!dst || !src))) return VRT_ERR_INVALID_ARG;
+    if (bytes == 0) return VRT_OK;
+    VRT_HIP(hipMemcpy(dst, src, (size_t)bytes, hipMemcpyDeviceToHost));
+    return VRT_OK;
+}
+
+vrt_status vrt_profile_enable(vrt_ctx *c, int32_t enable) {
+    if (!c) return VRT_ERR_INVALID_ARG;
+    VRT_HIP(hipSetDevice(c->desc.device));
+    Profiler &p = c->prof;
+    if (enable && !p.ev) {
+        p.ev = new (std::nothrow) hipEvent_t[2 * Profiler::kMaxPairs];
+        p.names = new (std::nothrow) const char *[Profiler::kMaxPairs];
+        if (!p.ev || !p.names) {
+            delete[] p.ev;
+            delete[] p.names;
+            p = Profiler();
+            return VRT_ERR_INVALID_ARG;
+        }
+        for (int i = 0; i < 2 * Profiler::kMaxPairs; ++i) {
+            hipError_t e = hipEventCreate(&p.ev[i]);
+            if (e != hipSuccess) {
+                for (int k = 0; k < i; ++k) (void)hipEventDestroy(p.ev[k]);
+                delete[] p.ev;
+                delete[] p.names;
+                p = Profiler();
+                return hip_fail(e);
+            }
+        }
+    }
+    p.enabled = enable != 0 && p.ev != nullptr;
+    p.used = 0;
+    p.overflow = false;
+    return VRT_OK;
+}
+
+vrt_status vrt_profile_read(vrt_ctx *c, vrt_kernel_time *out, int32_t max_records, int32_t *n_records) {
+    if (!c || !n_records || max_records < 0 || (max_records > 0 && !out)) return VRT_ERR_INVALID_ARG;
+    VRT_HIP(hipSetDevice(c->desc.device));
+    Profiler &p = c->prof;
+    *n_records = 0;
+    if (p.used > 0) VRT_HIP(hipEventSynchronize(p.ev[2 * p.used - 1]));
+    for (int i = 0; i < p.used; ++i) {
+        float ms = 0.0f;
+        VRT_HIP(hipEventElapsedTime(&ms, p.ev[2 * i], p.ev[2 * i + 1]));
+        int k = 0;
+        for (; k < *n_records; ++k)
+            if (std::strncmp(out[k].name, p.names[i], sizeof(out[k].name)) == 0) break;
+        if (k == *n_records) {
+            if (k >= max_records) continue;
+            std::memset(out[k].name, 0, sizeof(out[k].name));
+            std::strncpy(out[k].name, p.names[i], sizeof(out[k].name) - 1);
+            out[k].launches = 0;
+            out[k].total_ms = 0.0;
+            ++*n_records;
+        }
+        out[k].launches += 1;
+        out[k].total_ms += ms;
+    }
+    const bool over = p.overflow;
+    p.used = 0;
+    p.overflow = false;
+    return over ? VRT_ERR_CAPACITY : VRT_OK;
+}
+
+int32_t vrt_last_hip_error(void) { return g_last_hip; }
+
+const char *vrt_status_string(vrt_status s) {
+    switch (s) {
+    case VRT_OK: return "ok";
+    case VRT_ERR_INVALID_ARG: return "invalid argument";
+    case VRT_ERR_RANGE: return "coordinate or length outside the fixed-point range";
+    case VRT_ERR_NOT_BUILT: return "acceleration structure not built for this call";
+    case VRT_ERR_CAPACITY: return "listed fragments exceed the context capacity";
+    case VRT_ERR_COUNT_OVERFLOW: return "more than 65535 fragments in one voxel";
+    case VRT_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

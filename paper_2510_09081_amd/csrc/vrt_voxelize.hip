@@ -1,0 +1,332 @@
+// vrt_voxelize.hip -- Section 3.1: ingest, voxelization pass 1 and the occupancy pyramid.
+#include "vrt_internal.h"
+
+namespace vrt {
+namespace {
+
+// Zeroes the level-0 words of every brick the previous frame occupied.
+__global__ void k_clear_prev(uint32_t *__restrict__ words, const int32_t *__restrict__ brick_list,
+                             const DevStatus *__restrict__ st) {
+    const unsigned nb = st->n_bricks;
+    uint4 *w4 = reinterpret_cast<uint4 *>(words);
+    for (unsigned slot = blockIdx.x; slot < nb; slot += gridDim.x) {
+        int64_t b = brick_list[slot];
+        w4[b * (kBrickVox / 4) + threadIdx.x] = make_uint4(0, 0, 0, 0);  // 128 threads x 4 words
+    }
+}
+
+__global__ void k_reset(uint16_t *__restrict__ occ3, int64_t nbricks, DevStatus *__restrict__ st) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nbricks) occ3[i] = 0;
+    if (i == 0) st->n_fragments = 0;
+}
+
+// fixed-point coordinate: rint((x - origin) * s) as two binary32 operations
+__device__ __forceinline__ bool quantize1(float x, float o, float s, int &q) {
+    float u = (x - o) * s;
+    if (!(fabsf(u) < 1048576.0f)) {
+        q = 0;
+        return false;
+    }
+    q = (int)rintf(u);
+    return q < (1 << 20) && q > -(1 << 20);
+}
+
+__device__ __forceinline__ bool quantize3(const float *__restrict__ xyz, int64_t i, const float *o, float s, int *q) {
+    bool ok = quantize1(xyz[3 * i + 0], o[0], s, q[0]);
+    ok &= quantize1(xyz[3 * i + 1], o[1], s, q[1]);
+    ok &= quantize1(xyz[3 * i + 2], o[2], s, q[2]);
+    return ok;
+}
+
+struct IngestArgs {
+    const float *xyz;
+    const int32_t *off;
+    int64_t np, nv;
+    float o[3];
+    float s;
+};
+
+// One thread per vertex: polyline lookup by binary search over the offsets,
+// quantization, segment/interior flags and the central-difference clip normal.
+__global__ void k_ingest(IngestArgs a, VRec *__restrict__ out, DevStatus *__restrict__ st) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.nv) return;
+    if (i == 0 && (a.off[0] != 0 || a.off[a.np] != a.nv)) set_err(st, kErrInvalid);
+    int64_t lo = 0, hi = a.np - 1;  // largest p with off[p] <= i
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if ((int64_t)a.off[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    int64_t pa = a.off[lo], pb = a.off[lo + 1];
+    VRec r;
+    int q[3];
+    bool ok = quantize3(a.xyz, i, a.o, a.s, q);
+    r.x = q[0];
+    r.y = q[1];
+    r.z = q[2];
+    r.flags = 0;
+    r.nx = r.ny = r.nz = r.pad = 0.0f;
+    if (!(pa <= i && i < pb) || pa < 0 || pb > a.nv) {  // offsets not a partition of [0, nv)
+        set_err(st, kErrInvalid);
+    } else {
+        if (i + 1 < pb) r.flags |= kSegValid;
+        if (i > pa && i + 1 < pb) {
+            int qp[3], qn[3];
+            ok &= quantize3(a.xyz, i - 1, a.o, a.s, qp);
+            ok &= quantize3(a.xyz, i + 1, a.o, a.s, qn);
+            long long T0 = (long long)qn[0] - qp[0], T1 = (long long)qn[1] - qp[1], T2 = (long long)qn[2] - qp[2];
+            long long TT = T0 * T0 + T1 * T1 + T2 * T2;
+            if (TT > 0) {
+                float len = sqrtf((float)TT);
+                r.nx = (float)T0 / len;
+                r.ny = (float)T1 / len;
+                r.nz = (float)T2 / len;
+                r.flags |= kInterior;
+            }
+        }
+    }
+    if (!ok) set_err(st, kErrRange);
+    out[i] = r;
+}
+
+// Occupancy quantum of one (segment, voxel) pair: the clipped-capsule SDF at
+// the voxel centre with the PWAA radius clamp (Alg. 2, Alg. 3), evaluated as a
+// fixed binary32 sequence (no contraction, sums left to right).  Lengths in
+// 1/256 voxel.  Returns rint(256 * occupancy) in [0, 256].
+__device__ __forceinline__ int occupancy_quantum(const VRec &A, const VRec &B, float rc, float corr, int vx, int vy,
+                                                 int vz) {
+    int px = vx * kQ + kQ / 2, py = vy * kQ + kQ / 2, pz = vz * kQ + kQ / 2;
+    float pax = (float)(px - A.x), pay = (float)(py - A.y), paz = (float)(pz - A.z);
+    float pbx = (float)(px - B.x), pby = (float)(py - B.y), pbz = (float)(pz - B.z);
+    float dx = (float)(B.x - A.x), dy = (float)(B.y - A.y), dz = (float)(B.z - A.z);
+    float num = pax * dx;
+    num = num + pay * dy;
+    num = num + paz * dz;
+    float den = dx * dx;
+    den = den + dy * dy;
+    den = den + dz * dz;
+    float h = 0.0f;
+    if (den > 0.0f) h = fminf(fmaxf(num / den, 0.0f), 1.0f);
+    float ex = pax - dx * h, ey = pay - dy * h, ez = paz - dz * h;
+    float ss = ex * ex;
+    ss = ss + ey * ey;
+    ss = ss + ez * ez;
+    float sdf = sqrtf(ss) - rc;
+    if (A.flags & kInterior) {
+        float s0 = pax * A.nx;
+        s0 = s0 + pay * A.ny;
+        s0 = s0 + paz * A.nz;
+        sdf = fmaxf(sdf, -s0);
+    }
+    if (B.flags & kInterior) {
+        float s1 = pbx * B.nx;
+        s1 = s1 + pby * B.ny;
+        s1 = s1 + pbz * B.nz;
+        sdf = fmaxf(sdf, s1);
+    }
+    float occ = fminf(fmaxf(0.5f - sdf / 256.0f, 0.0f), 1.0f) * corr;
+    return (int)rintf(occ * 256.0f);
+}
+
+struct CountArgs {
+    const VRec *vrec;
+    int64_t nv;
+    long long rq;
+    float rc, corr;
+    int G[3];
+    int nbx, nby;
+    uint32_t *words;
+    uint8_t *brick_flag;
+};
+
+// Pass 1: one thread per segment walks its voxel set and adds
+// 1 + (q << 16) to each voxel's packed word (count low, occupancy high).
+__global__ void __launch_bounds__(256) k_vox_count(CountArgs a, DevStatus *__restrict__ st) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long nfrag = 0;
+    if (i + 1 < a.nv) {
+        VRec A = a.vrec[i];
+        if (A.flags & kSegValid) {
+            VRec B = a.vrec[i + 1];
+            long long dx = (long long)B.x - A.x, dy = (long long)B.y - A.y, dz = (long long)B.z - A.z;
+            if (dx >= 65536 || dx <= -65536 || dy >= 65536 || dy <= -65536 || dz >= 65536 || dz <= -65536) {
+                set_err(st, kErrRange);
+            } else {
+                SlabSpan s = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), a.rq, a.G);
+                int64_t last_b = -1;
+                bool over = false;
+                nfrag = for_each_voxel(s, [&](int x, int y, int z) {
+                    int q = occupancy_quantum(A, B, a.rc, a.corr, x, y, z);
+                    int64_t b = brick_index_of(x, y, z, a.nbx, a.nby);
+                    uint32_t old = atomicAdd(&a.words[b * kBrickVox + local_of(x, y, z)], 1u + ((uint32_t)q << 16));
+                    over |= (old & 0xFFFFu) == 0xFFFFu;
+                    if (b != last_b) {
+                        a.brick_flag[b] = 1;
+                        last_b = b;
+                    }
+                });
+                if (over) set_err(st, kErrCount);
+            }
+        }
+    }
+    nfrag = wave_sum_u64(nfrag);
+    if ((threadIdx.x & 63) == 0 && nfrag) atomicAdd(&st->n_fragments, nfrag);
+}
+
+// Single workgroup: compacts the touched-brick flags into the ascending list
+// of occupied bricks, writes each brick's slot (or -1), clears the flags.
+__global__ void __launch_bounds__(1024) k_brick_compact(uint8_t *__restrict__ flag, int64_t nb,
+                                                        int32_t *__restrict__ list, int32_t *__restrict__ slot,
+                                                        DevStatus *__restrict__ st) {
+    __shared__ unsigned warp_tot[16];
+    __shared__ unsigned warp_base[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = (int64_t)t * per, b1 = b0 + per < nb ? b0 + per : nb;
+    unsigned cnt = 0;
+    for (int64_t b = b0; b < b1; ++b) cnt += flag[b] ? 1u : 0u;
+    // exclusive scan over the block
+    unsigned incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        unsigned v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) warp_tot[w] = incl;
+    __syncthreads();
+    if (t == 0) {
+        unsigned run = 0;
+        for (int k = 0; k < 16; ++k) {
+            warp_base[k] = run;
+            run += warp_tot[k];
+        }
+        st->n_bricks = run;
+    }
+    __syncthreads();
+    unsigned pos = warp_base[w] + incl - cnt;
+    for (int64_t b = b0; b < b1; ++b) {
+        if (flag[b]) {
+            list[pos] = (int32_t)b;
+            slot[b] = (int32_t)pos;
+            ++pos;
+            flag[b] = 0;
+        } else {
+            slot[b] = -1;
+        }
+    }
+}
+
+// One workgroup (512 threads) per occupied brick: level-0 occupancy (saturated
+// at 1.0; a voxel with 256 or more fragments is full) and the in-brick mips
+// 1..3, each parent floor((sum of 8 children + 4) / 8).
+__global__ void __launch_bounds__(512) k_occ_brick(const uint32_t *__restrict__ words,
+                                                   const int32_t *__restrict__ list, const DevStatus *__restrict__ st,
+                                                   uint16_t *__restrict__ occ0, uint16_t *__restrict__ occ1,
+                                                   uint16_t *__restrict__ occ2, uint16_t *__restrict__ occ3) {
+    __shared__ uint16_t s0[512];
+    __shared__ uint16_t s1[64];
+    __shared__ uint16_t s2[8];
+    const unsigned nbk = st->n_bricks;
+    const int t = threadIdx.x;
+    for (unsigned sl = blockIdx.x; sl < nbk; sl += gridDim.x) {
+        int64_t b = list[sl];
+        uint32_t w = words[b * kBrickVox + t];
+        uint32_t cnt = w & 0xFFFFu, sum = w >> 16;
+        uint16_t o = (uint16_t)(cnt >= 256u ? 256u : (sum > 256u ? 256u : sum));
+        occ0[b * kBrickVox + t] = o;
+        s0[t] = o;
+        __syncthreads();
+        if (t < 64) {
+            int X = t & 3, Y = (t >> 2) & 3, Z = t >> 4;
+            unsigned s = 0;
+            for (int k = 0; k < 8; ++k)
+                s += s0[((2 * Z + (k >> 2)) << 6) | ((2 * Y + ((k >> 1) & 1)) << 3) | (2 * X + (k & 1))];
+            uint16_t p = (uint16_t)((s + 4u) >> 3);
+            s1[t] = p;
+            occ1[b * 64 + t] = p;
+        }
+        __syncthreads();
+        if (t < 8) {
+            int X = t & 1, Y = (t >> 1) & 1, Z = t >> 2;
+            unsigned s = 0;
+            for (int k = 0; k < 8; ++k)
+                s += s1[((2 * Z + (k >> 2)) << 4) | ((2 * Y + ((k >> 1) & 1)) << 2) | (2 * X + (k & 1))];
+            uint16_t p = (uint16_t)((s + 4u) >> 3);
+            s2[t] = p;
+            occ2[b * 8 + t] = p;
+        }
+        __syncthreads();
+        if (t == 0) {
+            unsigned s = 0;
+            for (int k = 0; k < 8; ++k) s += s2[k];
+            occ3[b] = (uint16_t)((s + 4u) >> 3);
+        }
+        __syncthreads();
+    }
+}
+
+// Averaging step on dense grids (levels >= 3): parent = floor((sum of the
+// children inside the grid + 4) / 8), parent dims = ceil(child dims / 2).
+__global__ void k_mip_avg(const uint16_t *__restrict__ src, int sx, int sy, int sz, uint16_t *__restrict__ dst, int dx,
+                          int dy, int dz) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)dx * dy * dz) return;
+    int x = (int)(i % dx), y = (int)((i / dx) % dy), z = (int)(i / ((int64_t)dx * dy));
+    unsigned s = 0;
+    for (int k = 0; k < 8; ++k) {
+        int cx = 2 * x + (k & 1), cy = 2 * y + ((k >> 1) & 1), cz = 2 * z + (k >> 2);
+        if (cx < sx && cy < sy && cz < sz) s += src[((int64_t)cz * sy + cy) * sx + cx];
+    }
+    dst[i] = (uint16_t)((s + 4u) >> 3);
+}
+
+}  // namespace
+
+hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *L, float s_q, hipStream_t st) {
+    Arenas &A = c->a;
+    const int64_t nb = (int64_t)(c->dims[0] / 8) * (c->dims[1] / 8) * (c->dims[2] / 8);
+    VRT_LAUNCH(c, "k_clear_prev", st, k_clear_prev<<<2048, 128, 0, st>>>(A.words, A.brick_list, A.status));
+    VRT_LAUNCH(c, "k_reset", st, k_reset<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(A.occ3, nb, A.status));
+    IngestArgs ia;
+    ia.xyz = L->xyz;
+    ia.off = L->poly_offsets;
+    ia.np = L->n_polylines;
+    ia.nv = L->n_vertices;
+    for (int k = 0; k < 3; ++k) ia.o[k] = c->origin[k];
+    ia.s = s_q;
+    VRT_LAUNCH(c, "k_ingest", st, k_ingest<<<(unsigned)((L->n_vertices + 255) / 256), 256, 0, st>>>(ia, A.vrec, A.status));
+    CountArgs ca;
+    ca.vrec = A.vrec;
+    ca.nv = L->n_vertices;
+    ca.rq = c->rq;
+    int64_t rcl = c->rq > kRMinQ ? c->rq : kRMinQ;
+    double ratio = (double)c->rq / (double)rcl;
+    ca.rc = (float)rcl;
+    ca.corr = (float)(ratio * ratio);
+    for (int k = 0; k < 3; ++k) ca.G[k] = c->dims[k];
+    ca.nbx = c->dims[0] / 8;
+    ca.nby = c->dims[1] / 8;
+    ca.words = A.words;
+    ca.brick_flag = A.brick_flag;
+    VRT_LAUNCH(c, "k_vox_count", st, k_vox_count<<<(unsigned)((L->n_vertices + 255) / 256), 256, 0, st>>>(ca, A.status));
+    VRT_LAUNCH(c, "k_brick_compact", st, k_brick_compact<<<1, 1024, 0, st>>>(A.brick_flag, nb, A.brick_list, A.brick_slot, A.status));
+    VRT_LAUNCH(c, "k_occ_brick", st, k_occ_brick<<<4096, 512, 0, st>>>(A.words, A.brick_list, A.status, A.occ0, A.occ1, A.occ2, A.occ3));
+    // levels >= 4 from the dense level 3
+    const uint16_t *src = A.occ3;
+    int sx = c->dims[0] / 8, sy = c->dims[1] / 8, sz = c->dims[2] / 8;
+    for (int L4 = 4; L4 < c->n_levels; ++L4) {
+        const Level &lv = c->levels[L4];
+        uint16_t *dst = A.occ_hi + lv.offset;
+        int64_t n = (int64_t)lv.dims[0] * lv.dims[1] * lv.dims[2];
+        VRT_LAUNCH(c, "k_mip_avg", st, k_mip_avg<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, sx, sy, sz, dst, lv.dims[0], lv.dims[1],
+                                                               lv.dims[2]));
+        src = dst;
+        sx = lv.dims[0];
+        sy = lv.dims[1];
+        sz = lv.dims[2];
+    }
+    return hipGetLastError();
+}
+
+}  // namespace vrt

@@ -1,0 +1,216 @@
+"""ctypes binding of libvrt.so (argument marshalling only).
+
+Every step of the path runs in the HIP library; this module converts Python
+values into the C ABI structs of ``include/vrt.h`` and raises on any non-zero
+status.  PyTorch supplies device memory and the stream.  There is no CPU
+fallback: importing works without a GPU, but creating a context needs the
+built library and a HIP device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libvrt.so")
+
+VRT_OK, VRT_ERR_INVALID_ARG, VRT_ERR_RANGE, VRT_ERR_NOT_BUILT = 0, 1, 2, 3
+VRT_ERR_CAPACITY, VRT_ERR_COUNT_OVERFLOW, VRT_ERR_HIP = 4, 5, 6
+CULL_NONE, CULL_OPAQUE, CULL_ALPHA = 0, 1, 2
+TRACE_OPAQUE, TRACE_TRANSPARENT = 0, 1
+
+EXPORTED = ["vrt_create", "vrt_destroy", "vrt_voxelize", "vrt_cull", "vrt_trace", "vrt_frame_status",
+            "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_last_hip_error", "vrt_status_string",
+            "vrt_profile_enable", "vrt_profile_read"]
+
+
+class VrtError(RuntimeError):
+    def __init__(self, status, what, hip=0):
+        self.status = status
+        super().__init__(f"{what}: status {status} ({_status_string(status)})" + (f", hip error {hip}" if hip else ""))
+
+
+class vrt_desc(C.Structure):
+    _fields_ = [("max_vertices", C.c_int64), ("max_fragments", C.c_int64), ("max_dim", C.c_int32),
+                ("device", C.c_int32)]
+
+
+class vrt_lines(C.Structure):
+    _fields_ = [("xyz", C.c_void_p), ("poly_offsets", C.c_void_p), ("n_vertices", C.c_int64),
+                ("n_polylines", C.c_int64), ("radius", C.c_float)]
+
+
+class vrt_grid(C.Structure):
+    _fields_ = [("origin", C.c_float * 3), ("voxel_size", C.c_float), ("dims", C.c_int32 * 3)]
+
+
+class vrt_view(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("cull_mode", C.c_int32), ("alpha", C.c_float), ("tau", C.c_float)]
+
+
+class vrt_camera(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("target", C.c_float * 3), ("up", C.c_float * 3), ("fovy_deg", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32), ("mode", C.c_int32), ("alpha", C.c_float),
+                ("tau", C.c_float)]
+
+
+class vrt_image(C.Structure):
+    _fields_ = [("rgba", C.c_void_p), ("depth", C.c_void_p), ("first_id", C.c_void_p)]
+
+
+class vrt_frame_info(C.Structure):
+    _fields_ = [("device_status", C.c_int32), ("n_fragments", C.c_int64), ("n_listed", C.c_int64),
+                ("n_bricks", C.c_int64), ("required_fragments", C.c_int64)]
+
+
+class vrt_as_view(C.Structure):
+    _fields_ = [("dims", C.c_int32 * 3), ("n_levels", C.c_int32), ("n_bricks", C.c_int32),
+                ("brick_list", C.c_void_p), ("words", C.c_void_p), ("occ", C.c_void_p * 4), ("occ_hi", C.c_void_p),
+                ("blocking", C.c_void_p), ("vis", C.c_void_p * 4), ("vis_hi", C.c_void_p), ("list_end", C.c_void_p),
+                ("ids", C.c_void_p)]
+
+
+class vrt_kernel_time(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Loads libvrt.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2510_09081_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.vrt_create.argtypes = [C.POINTER(vrt_desc), C.POINTER(P)]
+        L.vrt_destroy.argtypes = [P]
+        L.vrt_voxelize.argtypes = [P, C.POINTER(vrt_lines), C.POINTER(vrt_grid), P]
+        L.vrt_cull.argtypes = [P, C.POINTER(vrt_view), P]
+        L.vrt_trace.argtypes = [P, C.POINTER(vrt_camera), C.POINTER(vrt_image), P]
+        L.vrt_frame_status.argtypes = [P, C.POINTER(vrt_frame_info)]
+        L.vrt_query_as.argtypes = [P, C.POINTER(vrt_as_view)]
+        L.vrt_debug_rays.argtypes = [P, C.POINTER(vrt_camera), P, C.c_int64, P, P]
+        L.vrt_copy_to_host.argtypes = [P, P, C.c_int64]
+        L.vrt_profile_enable.argtypes = [P, C.c_int32]
+        L.vrt_profile_read.argtypes = [P, C.POINTER(vrt_kernel_time), C.c_int32, C.POINTER(C.c_int32)]
+        L.vrt_last_hip_error.restype = C.c_int32
+        L.vrt_status_string.argtypes = [C.c_int32]
+        L.vrt_status_string.restype = C.c_char_p
+        for name in ["vrt_create", "vrt_destroy", "vrt_voxelize", "vrt_cull", "vrt_trace", "vrt_frame_status",
+                     "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_profile_enable",
+                     "vrt_profile_read"]:
+            getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _status_string(s):
+    try:
+        return load().vrt_status_string(int(s)).decode()
+    except Exception:  # noqa: BLE001 - only used to decorate an error message
+        return "?"
+
+
+def _check(status, what):
+    if status != VRT_OK:
+        hip = load().vrt_last_hip_error() if status == VRT_ERR_HIP else 0
+        raise VrtError(status, what, hip)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def copy_to_host(dev_ptr, nbytes, dtype, count):
+    out = np.empty(count, dtype=dtype)
+    if count:
+        _check(load().vrt_copy_to_host(out.ctypes.data_as(C.c_void_p), C.c_void_p(dev_ptr), int(nbytes)),
+               "vrt_copy_to_host")
+    return out
+
+
+def _f3(v):
+    v = np.asarray(v, dtype=np.float32).reshape(3)
+    return (C.c_float * 3)(*[float(x) for x in v])
+
+
+def make_camera(eye, target, up, fovy_deg, width, height, mode=TRACE_OPAQUE, alpha=1.0, tau=1.0 / 256.0):
+    return vrt_camera(_f3(eye), _f3(target), _f3(up), float(np.float32(fovy_deg)), int(width), int(height), int(mode),
+                      float(alpha), float(tau))
+
+
+class Context:
+    """One voxel ray tracing context: arenas sized at creation, reused per frame."""
+
+    def __init__(self, max_vertices, max_fragments, max_dim, device=0):
+        L = load()
+        d = vrt_desc(int(max_vertices), int(max_fragments), int(max_dim), int(device))
+        h = C.c_void_p()
+        _check(L.vrt_create(C.byref(d), C.byref(h)), "vrt_create")
+        self._h = h
+        self.device = device
+        self.max_fragments = int(max_fragments)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(load().vrt_destroy(self._h), "vrt_destroy")
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def voxelize(self, xyz, offsets, radius, origin, voxel_size, dims, stream=None):
+        """xyz: device float32 [n, 3]; offsets: device int32 [n_polylines + 1]."""
+        lines = vrt_lines(_ptr(xyz), _ptr(offsets), int(xyz.shape[0]), int(offsets.shape[0] - 1), float(radius))
+        grid = vrt_grid(_f3(origin), float(voxel_size), (C.c_int32 * 3)(*[int(x) for x in dims]))
+        _check(load().vrt_voxelize(self._h, C.byref(lines), C.byref(grid), _stream_ptr(stream)), "vrt_voxelize")
+
+    def cull(self, eye, mode, alpha=1.0, tau=1.0 / 256.0, stream=None):
+        view = vrt_view(_f3(eye), int(mode), float(alpha), float(tau))
+        _check(load().vrt_cull(self._h, C.byref(view), _stream_ptr(stream)), "vrt_cull")
+
+    def trace(self, camera: vrt_camera, rgba, depth=None, first_id=None, stream=None):
+        img = vrt_image(_ptr(rgba), _ptr(depth), _ptr(first_id))
+        _check(load().vrt_trace(self._h, C.byref(camera), C.byref(img), _stream_ptr(stream)), "vrt_trace")
+
+    def debug_rays(self, camera: vrt_camera, pixels, dirs, stream=None):
+        _check(load().vrt_debug_rays(self._h, C.byref(camera), _ptr(pixels), int(pixels.shape[0]), _ptr(dirs),
+                                     _stream_ptr(stream)), "vrt_debug_rays")
+
+    def frame_status(self):
+        info = vrt_frame_info()
+        _check(load().vrt_frame_status(self._h, C.byref(info)), "vrt_frame_status")
+        return {"device_status": info.device_status, "n_fragments": info.n_fragments, "n_listed": info.n_listed,
+                "n_bricks": info.n_bricks}
+
+    def profile_enable(self, enable=True):
+        _check(load().vrt_profile_enable(self._h, int(bool(enable))), "vrt_profile_enable")
+
+    def profile_read(self):
+        """{kernel name: (launches, total ms)} since the last read (synchronizes)."""
+        buf = (vrt_kernel_time * 64)()
+        n = C.c_int32()
+        _check(load().vrt_profile_read(self._h, buf, 64, C.byref(n)), "vrt_profile_read")
+        return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(n.value)}
+
+    def query_as(self):
+        v = vrt_as_view()
+        _check(load().vrt_query_as(self._h, C.byref(v)), "vrt_query_as")
+        return v

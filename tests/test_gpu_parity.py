@@ -1,0 +1,288 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bit-exact: quantized membership via counts, packed words, occupancy and
+culling pyramids, blocking flags, list offsets, canonical (sorted) lists and
+primary-ray directions.  Trace: first-hit ids, depth and colour are compared
+on pixels the oracle certifies (every decision has a margin above the
+binary32 error bound); the uncertified fraction is bounded.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2510_09081_amd import synth, vrt
+
+from . import _gpu as G
+
+pytestmark = pytest.mark.gpu
+
+EPS_GEOM = 2e-5       # voxel units: hit/miss, clip plane and hit-order margins
+EPS_FACE0 = 1e-5      # voxel units, plus EPS_FACE_T * t: voxel-face margins
+EPS_FACE_T = 2.4e-7   # 4x the binary32 rounding of a boundary parameter t
+MAX_UNCERTIFIED = 2e-3
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU: the gpu tests need an MI355X")
+    c = vrt.Context(max_vertices=300_000, max_fragments=6_000_000, max_dim=128, device=0)
+    yield c
+    c.close()
+
+
+WORKLOADS = ["random_walk_10k", "bundles_small"]
+
+
+@pytest.fixture(scope="module")
+def wl_cache():
+    return {}
+
+
+def get_wl(name, cache):
+    if name not in cache:
+        cache[name] = synth.workload(name)
+    return cache[name]
+
+
+def compare_structure(orc, fr, got, check_lists=True, ids=None):
+    assert got["dims"] == fr.dims
+    assert np.array_equal(got["words"], fr.words), "packed words differ"
+    assert len(got["occ"]) == len(fr.occ)
+    for L, (a, b) in enumerate(zip(got["occ"], fr.occ)):
+        assert np.array_equal(a, b), f"occupancy level {L} differs"
+    assert np.array_equal(got["blocking"], fr.blocking), "blocking flags differ"
+    for L, (a, b) in enumerate(zip(got["vis"], fr.vis_levels)):
+        assert np.array_equal(a, b), f"culling level {L} differs"
+    cnt = (fr.words & 0xFFFF).astype(np.int64)
+    start = got["list_end"].astype(np.int64) - cnt * (fr.vis > 0)
+    occupied = np.zeros(fr.words.shape, bool)
+    nbx, nby = fr.dims[0] // 8, fr.dims[1] // 8
+    for b in got["bricks"]:
+        bz, r = divmod(int(b), nbx * nby)
+        by, bx = divmod(r, nbx)
+        occupied[bz * 8:bz * 8 + 8, by * 8:by * 8 + 8, bx * 8:bx * 8 + 8] = True
+    assert np.array_equal(start[occupied], fr.offsets.astype(np.int64)[occupied]), "list offsets differ"
+    if check_lists:
+        assert ids is not None
+        gl = G.canonical_lists(fr.words, fr.vis, start, ids)
+        ol = G.canonical_lists(fr.words, fr.vis, fr.offsets.astype(np.int64), fr.ids)
+        assert gl == ol, "canonical lists differ"
+
+
+def certified(tr, mode):
+    t = np.where(np.isfinite(tr.t), tr.t, 0.0)
+    return (tr.m_geom > EPS_GEOM) & (tr.m_face > EPS_FACE0 + EPS_FACE_T * t)
+
+
+def compare_trace(tr, gid, gdepth, grgba, ls, mode, label):
+    cert = certified(tr, mode)
+    frac_unc = 1.0 - cert.mean()
+    assert frac_unc <= MAX_UNCERTIFIED, f"{label}: {frac_unc:.2e} of pixels uncertified"
+    bad = cert & (gid != tr.id)
+    assert not bad.any(), f"{label}: first-hit id differs on {bad.sum()} certified pixels, e.g. {np.flatnonzero(bad)[:5]}"
+    hit = cert & (tr.id >= 0)
+    vs = float(ls.voxel_size)
+    tol = (1e-5 * tr.t[hit] + 1e-4) * vs
+    dd = np.abs(gdepth[hit].astype(np.float64) - tr.depth[hit])
+    assert (dd <= tol).all(), f"{label}: depth error {dd.max():.3e}"
+    assert np.isinf(gdepth[cert & (tr.id < 0)]).all()
+    err = np.abs(grgba[cert].astype(np.float64) - tr.rgba[cert])
+    ctol = 1e-6 if mode == 0 else 1e-4
+    assert err.max(initial=0) <= ctol, f"{label}: colour error {err.max():.3e}"
+    if mode == 1 and cert.any():
+        assert err.mean() <= 1e-6
+    return frac_unc
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_rays_bit_exact(orc, ctx, wl_cache, name):
+    w = get_wl(name, wl_cache)
+    G.run_build(ctx, w.lines, w.camera.eye, vrt.CULL_NONE)
+    pix = np.arange(w.camera.width * w.camera.height)
+    got = G.debug_rays(ctx, w.camera, pix)
+    exp = orc.ray_dirs(w.camera, pix)
+    assert np.array_equal(got.view(np.uint32), exp.view(np.uint32))
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+@pytest.mark.parametrize("cull", [vrt.CULL_NONE, vrt.CULL_OPAQUE, vrt.CULL_ALPHA])
+def test_structure_parity(orc, ctx, wl_cache, name, cull):
+    w = get_wl(name, wl_cache)
+    alpha = 0.2
+    fr = orc.build_frame(w.lines, w.camera.eye, cull, alpha=alpha)
+    assert fr.status == 0
+    G.run_build(ctx, w.lines, w.camera.eye, cull, alpha=alpha)
+    st = ctx.frame_status()
+    assert st["device_status"] == 0
+    assert st["n_fragments"] == fr.n_fragments
+    assert st["n_listed"] == fr.total
+    got = G.fetch_as(ctx)
+    ids = G.fetch_ids(ctx, fr.total)
+    compare_structure(orc, fr, got, ids=ids)
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+@pytest.mark.parametrize("mode,cull,alpha", [(0, vrt.CULL_NONE, 1.0), (0, vrt.CULL_OPAQUE, 1.0),
+                                             (1, vrt.CULL_NONE, 0.3), (1, vrt.CULL_ALPHA, 0.2)])
+def test_trace_parity(orc, ctx, wl_cache, name, mode, cull, alpha):
+    w = get_wl(name, wl_cache)
+    ls, cam = w.lines, w.camera
+    fr = orc.build_frame(ls, cam.eye, cull, alpha=alpha)
+    G.run_build(ctx, ls, cam.eye, cull, alpha=alpha)
+    gid, gdepth, grgba = G.run_trace(ctx, cam, mode, alpha=alpha)
+    pix = np.arange(cam.width * cam.height)
+    tr = orc.trace(fr, ls, cam, pix, mode, alpha=alpha)
+    assert (tr.id >= 0).sum() > 1000
+    compare_trace(tr, gid, gdepth, grgba, ls, mode, f"{name} mode={mode} cull={cull}")
+
+
+def test_repeat_runs_bit_identical(orc, ctx, wl_cache):
+    w = get_wl("bundles_small", wl_cache)
+    out = []
+    for _ in range(3):
+        G.run_build(ctx, w.lines, w.camera.eye, vrt.CULL_OPAQUE)
+        got = G.fetch_as(ctx)
+        st = ctx.frame_status()
+        ids = G.fetch_ids(ctx, st["n_listed"])
+        lists = G.canonical_lists(got["words"], got["vis"][0],
+                                  got["list_end"].astype(np.int64) - (got["words"] & 0xFFFF) * (got["vis"][0] > 0), ids)
+        img = G.run_trace(ctx, w.camera, 1, alpha=0.2)
+        out.append((got["words"], lists, img))
+    for o in out[1:]:
+        assert np.array_equal(o[0], out[0][0])
+        assert o[1] == out[0][1]
+        for a, b in zip(o[2], out[0][2]):
+            assert np.array_equal(a, b)
+
+
+def _make(polys, G_, radius_vox, vs=None):
+    vs = np.float32(1.0 / G_) if vs is None else np.float32(vs)
+    xyz = np.concatenate([np.asarray(p, np.float64).reshape(-1, 3) for p in polys]) * float(vs)
+    off = np.concatenate([[0], np.cumsum([len(p) for p in polys])]).astype(np.int32)
+    return synth.LineSet(xyz=xyz.astype(np.float32), offsets=off, radius=float(np.float32(radius_vox * vs)),
+                         origin=np.zeros(3, np.float32), voxel_size=float(vs), dims=(G_, G_, G_))
+
+
+EDGE_SETS = {
+    # a single segment
+    "one_segment": lambda: _make([[[3.2, 4.1, 5.5], [9.7, 6.2, 4.4]]], 16, 0.5),
+    # polylines of one vertex (no segments) between real ones, ragged lengths
+    "ragged": lambda: _make([[[2, 2, 2]], [[3, 3, 3], [5, 7, 4], [9, 9, 9], [12, 3, 11]], [[8, 8, 8]],
+                             [[1, 14, 3], [4, 13, 5]]], 16, 0.4),
+    # segments leaving the grid on every side, and zero-length segments
+    "outside_and_zero": lambda: _make([[[-3, 8, 8], [20, 8.5, 7.5]], [[8, -4, 8], [8.3, 19, 9]],
+                                       [[5.5, 5.5, 5.5], [5.5, 5.5, 5.5], [6.5, 5.5, 5.5]],
+                                       [[15.9, 15.9, 15.9], [17, 17, 17]]], 16, 0.5),
+    # axis-aligned segments on voxel faces, and exact ties between axes
+    "faces_and_ties": lambda: _make([[[4, 4, 4], [12, 4, 4]], [[2, 10, 10], [6, 14, 14]],
+                                     [[8, 2, 13], [11, 5, 10]]], 16, 0.25),
+    # thin lines: radius below the PWAA minimum, radius zero
+    "thin": lambda: _make([[[1.3, 2.7, 3.1], [14.2, 12.9, 6.6], [3.3, 9.9, 14.4]]], 16, 0.05),
+    "zero_radius": lambda: _make([[[1.3, 2.7, 3.1], [14.2, 12.9, 6.6]]], 16, 0.0),
+    # non-cubic grid
+    "non_cubic": lambda: synth.LineSet(**{**synth.random_walk_set(seed=5, n_poly=30, n_seg=20, G=24).__dict__,
+                                          "dims": (24, 16, 40)}),
+}
+
+
+@pytest.mark.parametrize("name", sorted(EDGE_SETS))
+def test_edge_cases(orc, ctx, name):
+    ls = EDGE_SETS[name]()
+    ext = np.array(ls.dims, float) * ls.voxel_size
+    centre = ls.origin + 0.5 * ext
+    cam = synth.Camera(eye=centre + np.array([1.3, -0.9, 1.1]) * float(ext.max()), target=centre,
+                       up=np.array([0.0, 0.0, 1.0]), fovy_deg=50.0, width=97, height=61)
+    for cull in (vrt.CULL_NONE, vrt.CULL_OPAQUE):
+        fr = orc.build_frame(ls, cam.eye, cull)
+        G.run_build(ctx, ls, cam.eye, cull)
+        st = ctx.frame_status()
+        assert st["device_status"] == fr.status == 0
+        assert st["n_fragments"] == fr.n_fragments
+        got = G.fetch_as(ctx)
+        compare_structure(orc, fr, got, ids=G.fetch_ids(ctx, fr.total))
+        for mode in (0, 1):
+            gid, gdepth, grgba = G.run_trace(ctx, cam, mode, alpha=0.3)
+            tr = orc.trace(fr, ls, cam, np.arange(cam.width * cam.height), mode, alpha=0.3)
+            cert = certified(tr, mode)
+            assert not (cert & (gid != tr.id)).any()
+            err = np.abs(grgba[cert].astype(np.float64) - tr.rgba[cert])
+            assert err.max(initial=0) <= (1e-6 if mode == 0 else 1e-4)
+
+
+def test_capacity_error_and_recovery(orc, ctx):
+    import torch
+    ls = synth.random_walk_set(seed=3, n_poly=50, n_seg=30, G=32)
+    fr = orc.build_frame(ls, np.array([2.0, 1.3, 1.5]), vrt.CULL_NONE)
+    small = vrt.Context(max_vertices=ls.n_vertices, max_fragments=fr.total - 1, max_dim=32)
+    try:
+        G.run_build(small, ls, [2.0, 1.3, 1.5], vrt.CULL_NONE)
+        st = small.frame_status()
+        assert st["device_status"] == vrt.VRT_ERR_CAPACITY
+        assert st["n_listed"] == fr.total
+    finally:
+        small.close()
+    big = vrt.Context(max_vertices=ls.n_vertices, max_fragments=fr.total, max_dim=32)
+    try:
+        G.run_build(big, ls, [2.0, 1.3, 1.5], vrt.CULL_NONE)
+        assert big.frame_status()["device_status"] == 0
+        got = G.fetch_as(big)
+        compare_structure(orc, fr, got, ids=G.fetch_ids(big, fr.total))
+    finally:
+        big.close()
+    torch.cuda.synchronize()
+
+
+def test_count_overflow_error(ctx):
+    # 65536 identical segments inside one voxel: the 16-bit count field overflows
+    n = 65536
+    p = np.array([[4.3, 4.4, 4.5], [4.6, 4.5, 4.4]], np.float64) / 16
+    xyz = np.tile(p, (n, 1)).astype(np.float32)
+    off = np.arange(0, 2 * n + 1, 2, dtype=np.int32)
+    ls = synth.LineSet(xyz=xyz, offsets=off, radius=float(np.float32(0.05 / 16)), origin=np.zeros(3, np.float32),
+                       voxel_size=float(np.float32(1 / 16)), dims=(16, 16, 16))
+    G.run_build(ctx, ls, [2.0, 1.3, 1.5], vrt.CULL_NONE)
+    assert ctx.frame_status()["device_status"] == vrt.VRT_ERR_COUNT_OVERFLOW
+    assert ctx.frame_status()["device_status"] == 0  # the latch clears once read
+
+
+def test_range_and_argument_errors(ctx):
+    import torch
+    ls = _make([[[1, 1, 1], [3, 3, 3]]], 16, 0.5)
+    xyz, off = G.to_device(ls)
+    far = xyz.clone()
+    far[0, 0] = 1.0e4
+    ctx.voxelize(far, off, ls.radius, ls.origin, ls.voxel_size, ls.dims)
+    torch.cuda.synchronize()
+    assert ctx.frame_status()["device_status"] == vrt.VRT_ERR_RANGE
+    with pytest.raises(vrt.VrtError) as e:
+        ctx.voxelize(xyz, off, ls.radius, ls.origin, ls.voxel_size, (12, 16, 16))
+    assert e.value.status == vrt.VRT_ERR_INVALID_ARG
+    with pytest.raises(vrt.VrtError):
+        ctx.voxelize(xyz, off, -1.0, ls.origin, ls.voxel_size, ls.dims)
+    with pytest.raises(vrt.VrtError):
+        ctx.voxelize(xyz, off, ls.radius, ls.origin, ls.voxel_size, (256, 256, 256))  # beyond max_dim
+    ctx.voxelize(xyz, off, ls.radius, ls.origin, ls.voxel_size, ls.dims)
+    with pytest.raises(vrt.VrtError):
+        ctx.cull([0.5, 0.5, 2.0], 7)
+    with pytest.raises(vrt.VrtError) as e:
+        ctx.cull([1.0e6, 0.5, 2.0], vrt.CULL_OPAQUE)
+    assert e.value.status == vrt.VRT_ERR_RANGE
+    ctx.cull([0.5, 0.5, 2.0], vrt.CULL_NONE)
+    rgba = torch.empty(4 * 16, device="cuda")
+    with pytest.raises(vrt.VrtError):  # up parallel to the view direction
+        ctx.trace(vrt.make_camera([0.5, 0.5, 2.0], [0.5, 0.5, 0.5], [0, 0, 1], 40, 4, 4), rgba)
+    torch.cuda.synchronize()
+    assert ctx.frame_status()["device_status"] == 0
+
+
+def test_not_built_order():
+    c = vrt.Context(max_vertices=16, max_fragments=16, max_dim=16)
+    try:
+        with pytest.raises(vrt.VrtError) as e:
+            c.cull([0.5, 0.5, 2.0], vrt.CULL_NONE)
+        assert e.value.status == vrt.VRT_ERR_NOT_BUILT
+    finally:
+        c.close()
