@@ -38,8 +38,13 @@ def kernel_bytes(name, n):
         return 12 * n["N_v"] + 4 * n["N_p"] + VREC_BYTES * n["N_v"]
     if name == "k_cull_vis":    # words in, visibility out, over occupied bricks
         return 5 * 512 * n["bricks"]
-    if name == "k_trace":       # outputs (RGBA + depth + id) and the brick visibility table
+    if name == "k_trace_march":  # every pixel: brick table once, miss outputs (RGBA + depth + id)
         return 24 * n["P"] + n["NB"]
+    if name == "k_trace_shade":  # per pass: distinct voxel descriptors (8 B), list entries (4 B) and segments
+        # (two 32-B vertex records) any ray touched, and the outputs of the rays that reached a list
+        return float(np.mean([8 * n[p]["distinct_list_voxels"] + 4 * n[p]["distinct_list_entries"]
+                              + 2 * VREC_BYTES * n[p]["distinct_segments"] + 24 * n[p]["rays_hit"]
+                              for p in ("trace_opaque", "trace_alpha")]))
     return None
 
 
@@ -167,13 +172,20 @@ def main():
     if st_end["device_status"] != 0:
         raise SystemExit(f"device status {st_end['device_status']} in the timed frames")
 
+    # work counters of both traces (outside the timed region)
+    ctx.voxelize(xyz, off, ls.radius, ls.origin, ls.voxel_size, ls.dims)
+    ctx.cull(eye, opq.cull_mode, opq.alpha, opq.tau)
+    ts_o = ctx.trace_stats(cam_o, rgba, depth, fid)
+    ctx.cull(eye, alp.cull_mode, alp.alpha, alp.tau)
+    ts_a = ctx.trace_stats(cam_a, rgba, depth, fid)
+
     counts = {"N_v": ls.n_vertices, "N_p": ls.n_polylines, "N_s": ls.n_segments, "F": st_o["n_fragments"],
               "F_v_opaque": st_o["n_listed"], "F_v_alpha": st_a["n_listed"], "bricks": nb, "V_o": V_o,
               "V_v_opaque": V_v_o, "V_v_alpha": V_v_a, "P": P, "NB": NB}
     per_kernel = {k: {"launches_per_frame": n / args.steps, "avg_ms": ms / n, "ms_per_frame": ms / args.steps}
                   for k, (n, ms) in sorted(kern.items(), key=lambda kv: -kv[1][1])}
     dom = next(iter(per_kernel))
-    b = kernel_bytes(dom, counts)
+    b = kernel_bytes(dom, dict(counts, trace_opaque=ts_o, trace_alpha=ts_a))
     roofline = None
     if b is not None:
         ach = b / (per_kernel[dom]["avg_ms"] * 1e-3) / 1e9
@@ -205,6 +217,7 @@ def main():
         "frame_ms_with_kernel_events": round(frame_ms_kev, 4),
         "kernels": {k: {kk: round(vv, 5) for kk, vv in d.items()} for k, d in per_kernel.items()},
         "counts": counts,
+        "trace_work": {"opaque": ts_o, "alpha": ts_a},
         "roofline": roofline,
         "wall_s_timed": round(wall, 3),
     }

@@ -69,6 +69,7 @@ typedef struct {
     int64_t max_fragments; /* capacity of the segment-id array (listed fragments) */
     int32_t max_dim;       /* largest grid dimension; multiple of 8, <= 1024 */
     int32_t device;        /* HIP device ordinal the arenas live on */
+    int64_t max_pixels;    /* largest width * height accepted by vrt_trace */
 } vrt_desc;
 
 /* A set of polylines with one radius (Section 3.1: capsules of uniform radius
@@ -197,6 +198,27 @@ typedef struct {
 
 vrt_status vrt_profile_enable(vrt_ctx *ctx, int32_t enable);
 vrt_status vrt_profile_read(vrt_ctx *ctx, vrt_kernel_time *out, int32_t max_records, int32_t *n_records);
+
+/* Work counters of one trace (inspection): the same trace as vrt_trace, run
+ * with per-ray counters and marks of the voxels and segments it touches;
+ * writes the image too.  Synchronizes. */
+typedef struct {
+    int64_t rays;               /* W * H */
+    int64_t rays_hit;           /* rays with a first hit */
+    int64_t cell_skips_64;      /* empty 64^3 cells crossed in one step */
+    int64_t cell_skips_8;       /* empty bricks crossed in one step */
+    int64_t voxel_steps;        /* voxels visited in non-empty bricks */
+    int64_t list_visits;        /* visits of voxels with a non-empty list */
+    int64_t capsule_tests;      /* ray-capsule tests, repeats included */
+    int64_t kbuffer_passes;     /* transparent: passes over a voxel list */
+    int64_t distinct_list_voxels;  /* voxels whose list was read by any ray */
+    int64_t distinct_list_entries; /* sum of the list lengths of those voxels */
+    int64_t distinct_segments;     /* segments tested by any ray */
+    int64_t max_tests_per_ray;
+} vrt_trace_stats;
+
+vrt_status vrt_trace_stats_run(vrt_ctx *ctx, const vrt_camera *cam, const vrt_image *out, vrt_trace_stats *stats,
+                               void *stream);
 
 /* Synchronous copy of `bytes` from device memory to host memory. */
 vrt_status vrt_copy_to_host(void *host_dst, const void *device_src, int64_t bytes);

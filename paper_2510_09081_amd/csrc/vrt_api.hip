@@ -28,9 +28,10 @@ hipError_t alloc(T *&p, int64_t n) {
 }
 
 void free_all(Arenas &a) {
-    void *ptrs[] = {a.vrec, a.words, a.occ0, a.occ1, a.occ2, a.occ3, a.occ_hi, a.blk, a.brick_blk, a.vis0,
-                    a.vis1, a.vis2,  a.vis3, a.vis_hi, a.cursor, a.ids, a.brick_flag, a.brick_list, a.brick_slot,
-                    a.brick_total, a.brick_base, a.status};
+    void *ptrs[] = {a.vrec, a.words, a.occ0, a.occ1, a.occ2, a.occ3, a.occ_hi, a.blk, a.brick_blk, a.super_blk,
+                    a.occ_list, a.vis0,
+                    a.vis1, a.vis2,  a.vis3, a.vis_hi, a.cursor, a.cell, a.queue, a.ids, a.brick_flag, a.brick_list, a.brick_slot,
+                    a.brick_total, a.brick_base, a.status, a.stat_vox, a.stat_seg, a.stat_acc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     a = Arenas();
@@ -87,7 +88,8 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     if (!desc || !out) return VRT_ERR_INVALID_ARG;
     *out = nullptr;
     if (desc->max_vertices < 2 || desc->max_fragments < 1 || desc->max_dim < 8 || desc->max_dim > 1024 ||
-        desc->max_dim % 8 != 0 || desc->max_vertices > ((int64_t)1 << 31) || desc->max_fragments > 0xFFFFFFFFll)
+        desc->max_dim % 8 != 0 || desc->max_vertices > ((int64_t)1 << 31) || desc->max_fragments > 0xFFFFFFFFll ||
+        desc->max_pixels < 1 || desc->max_pixels > ((int64_t)1 << 31))
         return VRT_ERR_INVALID_ARG;
     int ndev = 0;
     VRT_HIP(hipGetDeviceCount(&ndev));
@@ -98,6 +100,8 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     c->desc = *desc;
     const int64_t nbd = desc->max_dim / 8;
     c->max_bricks = nbd * nbd * nbd;
+    const int64_t nsd = (desc->max_dim + 63) / 64;
+    c->max_supers = nsd * nsd * nsd;
     c->hi_elems = hi_elems_for(desc->max_dim);
     Arenas &a = c->a;
     const int64_t mb = c->max_bricks;
@@ -113,12 +117,16 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     ALLOC(a.occ_hi, c->hi_elems);
     ALLOC(a.blk, mb * kBrickVox);
     ALLOC(a.brick_blk, mb);
+    ALLOC(a.super_blk, c->max_supers);
+    ALLOC(a.occ_list, mb * kBrickVox);
     ALLOC(a.vis0, mb * kBrickVox);
     ALLOC(a.vis1, mb * 64);
     ALLOC(a.vis2, mb * 8);
     ALLOC(a.vis3, mb);
     ALLOC(a.vis_hi, c->hi_elems);
     ALLOC(a.cursor, mb * kBrickVox);
+    ALLOC(a.cell, mb * kBrickVox);
+    ALLOC(a.queue, desc->max_pixels);
     ALLOC(a.ids, desc->max_fragments);
     ALLOC(a.brick_flag, mb);
     ALLOC(a.brick_list, mb);
@@ -126,6 +134,9 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     ALLOC(a.brick_total, mb);
     ALLOC(a.brick_base, mb);
     ALLOC(a.status, 1);
+    ALLOC(a.stat_vox, mb * kBrickVox);
+    ALLOC(a.stat_seg, desc->max_vertices);
+    ALLOC(a.stat_acc, 16);
 #undef ALLOC
     if (e == hipSuccess) e = hipMemset(a.words, 0, (size_t)mb * kBrickVox * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(a.brick_flag, 0, (size_t)mb);
@@ -225,7 +236,9 @@ vrt_status vrt_cull(vrt_ctx *c, const vrt_view *v, void *stream) {
 
 static vrt_status camera_params(const vrt_ctx *c, const vrt_camera *cam, TraceParams &p) {
     if (!finite3(cam->eye) || !finite3(cam->target) || !finite3(cam->up)) return VRT_ERR_INVALID_ARG;
-    if (cam->width < 1 || cam->height < 1 || cam->width > 65536 || cam->height > 65536) return VRT_ERR_INVALID_ARG;
+    if (cam->width < 1 || cam->height < 1 || cam->width > 65536 || cam->height > 65536 ||
+        (int64_t)cam->width * cam->height > c->desc.max_pixels)
+        return VRT_ERR_INVALID_ARG;
     if (!(cam->fovy_deg > 0.0f && cam->fovy_deg < 180.0f)) return VRT_ERR_INVALID_ARG;
     if (cam->mode != VRT_TRACE_OPAQUE && cam->mode != VRT_TRACE_TRANSPARENT) return VRT_ERR_INVALID_ARG;
     if (cam->mode == VRT_TRACE_TRANSPARENT &&
@@ -278,6 +291,35 @@ vrt_status vrt_trace(vrt_ctx *c, const vrt_camera *cam, const vrt_image *img, vo
     hipStream_t st = (hipStream_t)stream;
     c->last_stream = st;
     VRT_HIP(launch_trace(c, p, img, st));
+    return VRT_OK;
+}
+
+vrt_status vrt_trace_stats_run(vrt_ctx *c, const vrt_camera *cam, const vrt_image *img, vrt_trace_stats *out,
+                               void *stream) {
+    if (!c || !cam || !img || !img->rgba || !out) return VRT_ERR_INVALID_ARG;
+    if (!c->culled) return VRT_ERR_NOT_BUILT;
+    TraceParams p;
+    vrt_status s = camera_params(c, cam, p);
+    if (s != VRT_OK) return s;
+    VRT_HIP(hipSetDevice(c->desc.device));
+    hipStream_t st = (hipStream_t)stream;
+    c->last_stream = st;
+    VRT_HIP(launch_trace_stats(c, p, img, st));
+    VRT_HIP(hipStreamSynchronize(st));
+    unsigned long long acc[16];
+    VRT_HIP(hipMemcpy(acc, c->a.stat_acc, sizeof(acc), hipMemcpyDeviceToHost));
+    out->rays = (int64_t)cam->width * cam->height;
+    out->rays_hit = (int64_t)acc[0];
+    out->cell_skips_64 = (int64_t)acc[1];
+    out->cell_skips_8 = (int64_t)acc[2];
+    out->voxel_steps = (int64_t)acc[3];
+    out->list_visits = (int64_t)acc[4];
+    out->capsule_tests = (int64_t)acc[5];
+    out->kbuffer_passes = (int64_t)acc[6];
+    out->max_tests_per_ray = (int64_t)acc[7];
+    out->distinct_list_voxels = (int64_t)acc[8];
+    out->distinct_list_entries = (int64_t)acc[9];
+    out->distinct_segments = (int64_t)acc[10];
     return VRT_OK;
 }
 

@@ -2,133 +2,44 @@
 // Section 3.3 (scan of visible counts, voxelization pass 2 into the lists).
 #include <climits>
 
+#include "vrt_cullwalk.h"
 #include "vrt_internal.h"
 
 namespace vrt {
 namespace {
 
-__global__ void k_cull_reset(uint8_t *__restrict__ vis3, uint8_t *__restrict__ brick_blk, int64_t nb,
-                             DevStatus *__restrict__ st) {
+__global__ void k_cull_reset(uint8_t *__restrict__ vis3, int64_t nb, DevStatus *__restrict__ st) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nb) {
-        vis3[i] = 0;
-        brick_blk[i] = 0;
-    }
+    if (i < nb) vis3[i] = 0;
     if (i == 0) {
         st->n_listed = 0;
-        st->bbox[0] = st->bbox[1] = st->bbox[2] = INT_MAX;
-        st->bbox[3] = st->bbox[4] = st->bbox[5] = INT_MIN;
+        st->vbox[0] = st->vbox[1] = st->vbox[2] = INT_MAX;
+        st->vbox[3] = st->vbox[4] = st->vbox[5] = INT_MIN;
     }
 }
 
 struct GridArgs {
     int G[3];
     int nb[3];  // bricks per axis
+    int ns[3];  // 64^3 cells per axis
 };
 
-// Level-0 occupancy of any voxel (0 outside the grid and in empty bricks).
-__device__ __forceinline__ unsigned occ_at(const GridArgs &g, const uint16_t *__restrict__ occ0,
-                                           const int32_t *__restrict__ slot, int x, int y, int z) {
-    if (x < 0 || y < 0 || z < 0 || x >= g.G[0] || y >= g.G[1] || z >= g.G[2]) return 0;
-    int64_t b = brick_index_of(x, y, z, g.nb[0], g.nb[1]);
-    if (slot[b] < 0) return 0;
-    return occ0[b * kBrickVox + local_of(x, y, z)];
-}
-
-// Erosion (Section 3.2): minimum occupancy over the voxel and its 6 face
-// neighbours; the voxel blocks culling rays when that minimum is full.
-__global__ void __launch_bounds__(512) k_erode(GridArgs g, const uint16_t *__restrict__ occ0,
-                                               const int32_t *__restrict__ list, const int32_t *__restrict__ slot,
-                                               DevStatus *__restrict__ st, uint8_t *__restrict__ blk,
-                                               uint8_t *__restrict__ brick_blk) {
-    __shared__ int bb[6];
-    const unsigned nbk = st->n_bricks;
-    const int t = threadIdx.x;
-    for (unsigned sl = blockIdx.x; sl < nbk; sl += gridDim.x) {
-        int64_t b = list[sl];
-        if (t < 3) bb[t] = INT_MAX;
-        else if (t < 6) bb[t] = INT_MIN;
-        __syncthreads();
-        int bx = (int)(b % g.nb[0]), by = (int)((b / g.nb[0]) % g.nb[1]), bz = (int)(b / ((int64_t)g.nb[0] * g.nb[1]));
-        int x = bx * 8 + (t & 7), y = by * 8 + ((t >> 3) & 7), z = bz * 8 + (t >> 6);
-        unsigned e = occ0[b * kBrickVox + t];
-        if (e >= 256u) {
-            unsigned n;
-            n = occ_at(g, occ0, slot, x - 1, y, z); e = n < e ? n : e;
-            n = occ_at(g, occ0, slot, x + 1, y, z); e = n < e ? n : e;
-            n = occ_at(g, occ0, slot, x, y - 1, z); e = n < e ? n : e;
-            n = occ_at(g, occ0, slot, x, y + 1, z); e = n < e ? n : e;
-            n = occ_at(g, occ0, slot, x, y, z - 1); e = n < e ? n : e;
-            n = occ_at(g, occ0, slot, x, y, z + 1); e = n < e ? n : e;
-        }
-        bool blocking = e >= 256u;
-        blk[b * kBrickVox + t] = blocking ? 1 : 0;
-        if (blocking) {
-            atomicMin(&bb[0], x); atomicMin(&bb[1], y); atomicMin(&bb[2], z);
-            atomicMax(&bb[3], x); atomicMax(&bb[4], y); atomicMax(&bb[5], z);
-        }
-        int any = __syncthreads_or(blocking ? 1 : 0);
-        if (t == 0) {
-            brick_blk[b] = any ? 1 : 0;
-            if (any) {
-                atomicMin(&st->bbox[0], bb[0]); atomicMin(&st->bbox[1], bb[1]); atomicMin(&st->bbox[2], bb[2]);
-                atomicMax(&st->bbox[3], bb[3]); atomicMax(&st->bbox[4], bb[4]); atomicMax(&st->bbox[5], bb[5]);
-            }
-        }
-        __syncthreads();
+// Blocking lookups for the culling walk: 64^3 cells and bricks holding a
+// blocking voxel, and the level-0 blocking flags (defined in occupied bricks).
+struct CullCells {
+    const uint8_t *super_blk, *brick_blk, *blk;
+    int nb0, nb1, ns0, ns1;
+    __host__ __device__ bool super_empty(int x, int y, int z) const {
+        return !super_blk[((int64_t)(z >> 6) * ns1 + (y >> 6)) * ns0 + (x >> 6)];
     }
-}
-
-// Blocking voxels met by the open segment from the centre of voxel (x,y,z) to
-// the eye, up to `limit`: exact integer grid walk; the next crossing on each
-// axis is found by comparing g_a*|D_b| with g_b*|D_a| (g: distance from the
-// start to the next boundary, D: start-to-eye vector); tied axes step
-// together.  Stops at the grid boundary, at the eye, or once the walk has left
-// the bounding box of all blocking voxels.
-__device__ int culling_ray(const GridArgs &g, int x, int y, int z, const long long *E, int limit, const int *bbox,
-                           const uint8_t *__restrict__ blk, const uint8_t *__restrict__ brick_blk) {
-    long long adel[3], gd[3];
-    int step[3], cur[3] = {x, y, z};
-    for (int a = 0; a < 3; ++a) {
-        long long c = (long long)cur[a] * kQ + kQ / 2;
-        long long dl = E[a] - c;
-        step[a] = dl > 0 ? 1 : (dl < 0 ? -1 : 0);
-        adel[a] = dl < 0 ? -dl : dl;
-        gd[a] = kQ / 2;
+    __host__ __device__ bool brick_empty(int x, int y, int z) const {
+        return !brick_blk[((int64_t)(z >> 3) * nb1 + (y >> 3)) * nb0 + (x >> 3)];
     }
-    int n = 0;
-    for (;;) {
-        // leaving the blocking box for good
-        bool gone = false;
-        for (int a = 0; a < 3; ++a) {
-            if (step[a] > 0 && cur[a] > bbox[3 + a]) gone = true;
-            if (step[a] < 0 && cur[a] < bbox[a]) gone = true;
-            if (step[a] == 0 && (cur[a] < bbox[a] || cur[a] > bbox[3 + a])) gone = true;
-        }
-        if (gone) break;
-        int m = -1;
-        for (int a = 0; a < 3; ++a) {
-            if (step[a] == 0) continue;
-            if (m < 0 || gd[a] * adel[m] < gd[m] * adel[a]) m = a;
-        }
-        if (m < 0 || !(gd[m] < adel[m])) break;
-        bool out = false;
-        long long gm = gd[m], am = adel[m];
-        for (int a = 0; a < 3; ++a) {
-            if (step[a] != 0 && gd[a] * am == gm * adel[a]) {
-                cur[a] += step[a];
-                gd[a] += kQ;
-                if (cur[a] < 0 || cur[a] >= g.G[a]) out = true;
-            }
-        }
-        if (out) break;
-        int64_t b = brick_index_of(cur[0], cur[1], cur[2], g.nb[0], g.nb[1]);
-        if (brick_blk[b] && blk[b * kBrickVox + local_of(cur[0], cur[1], cur[2])]) {
-            if (++n >= limit) break;
-        }
+    __host__ __device__ bool blocking(int x, int y, int z) const {
+        const int64_t b = ((int64_t)(z >> 3) * nb1 + (y >> 3)) * nb0 + (x >> 3);
+        return blk[b * kBrickVox + (((z & 7) << 6) | ((y & 7) << 3) | (x & 7))] != 0;
     }
-    return n;
-}
+};
 
 struct CullArgs {
     GridArgs g;
@@ -136,35 +47,47 @@ struct CullArgs {
     int limit;  // < 0: no culling
 };
 
-// One workgroup per occupied brick: level-0 visibility (occupied and fewer
-// than `limit` blockers toward the eye), the in-brick culling mips 1..3
-// (parent = OR of children), and the brick's visible-fragment total.
-__global__ void __launch_bounds__(512) k_cull_vis(CullArgs a, const uint32_t *__restrict__ words,
-                                                  const int32_t *__restrict__ list, const DevStatus *__restrict__ st,
-                                                  const uint8_t *__restrict__ blk,
-                                                  const uint8_t *__restrict__ brick_blk, uint8_t *__restrict__ vis0,
-                                                  uint8_t *__restrict__ vis1, uint8_t *__restrict__ vis2,
-                                                  uint8_t *__restrict__ vis3, uint32_t *__restrict__ brick_total) {
+// One thread per occupied voxel (Section 3.2): visible iff its culling ray
+// meets fewer than `limit` blocking voxels.  Writes level-0 visibility of
+// occupied voxels only; k_cull_brick completes the rest of the brick.
+__global__ void __launch_bounds__(256) k_cull_walk(CullArgs a, CullCells cells, const uint32_t *__restrict__ occ_list,
+                                                   const DevStatus *__restrict__ st, uint8_t *__restrict__ vis0) {
+    __shared__ int bbox[6];
+    if (threadIdx.x < 6) bbox[threadIdx.x] = st->bbox[threadIdx.x];
+    __syncthreads();
+    const unsigned n = st->n_occ;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t v = occ_list[i];
+        const int64_t b = v >> 9;
+        const int l = (int)(v & 511u);
+        const int bx = (int)(b % a.g.nb[0]), by = (int)((b / a.g.nb[0]) % a.g.nb[1]);
+        const int bz = (int)(b / ((int64_t)a.g.nb[0] * a.g.nb[1]));
+        const int x = bx * 8 + (l & 7), y = by * 8 + ((l >> 3) & 7), z = bz * 8 + (l >> 6);
+        const int nblk = culling_walk(a.g.G, x, y, z, a.E, a.limit, bbox, cells);
+        vis0[v] = nblk < a.limit ? 1 : 0;
+    }
+}
+
+// One workgroup per occupied brick: final level-0 visibility (unoccupied
+// voxels are invisible; without culling every occupied voxel is visible), the
+// in-brick culling mips 1..3 (parent = OR of children), and the brick's
+// visible-fragment total.
+__global__ void __launch_bounds__(512) k_cull_brick(int limit, GridArgs g, const uint32_t *__restrict__ words,
+                                                    const int32_t *__restrict__ list, DevStatus *__restrict__ st,
+                                                    uint8_t *__restrict__ vis0, uint8_t *__restrict__ vis1,
+                                                    uint8_t *__restrict__ vis2, uint8_t *__restrict__ vis3,
+                                                    uint32_t *__restrict__ brick_total) {
     __shared__ uint8_t s0[512];
     __shared__ uint8_t s1[64];
     __shared__ uint8_t s2[8];
     __shared__ unsigned wsum[8];
-    __shared__ int bbox[6];
     const unsigned nbk = st->n_bricks;
     const int t = threadIdx.x;
-    if (t < 6) bbox[t] = st->bbox[t];
-    __syncthreads();
     for (unsigned sl = blockIdx.x; sl < nbk; sl += gridDim.x) {
         int64_t b = list[sl];
-        int bx = (int)(b % a.g.nb[0]), by = (int)((b / a.g.nb[0]) % a.g.nb[1]);
-        int bz = (int)(b / ((int64_t)a.g.nb[0] * a.g.nb[1]));
-        int x = bx * 8 + (t & 7), y = by * 8 + ((t >> 3) & 7), z = bz * 8 + (t >> 6);
         unsigned cnt = words[b * kBrickVox + t] & 0xFFFFu;
         uint8_t v = 0;
-        if (cnt) {
-            if (a.limit < 0) v = 1;
-            else v = culling_ray(a.g, x, y, z, a.E, a.limit, bbox, blk, brick_blk) < a.limit ? 1 : 0;
-        }
+        if (cnt) v = limit < 0 ? 1 : vis0[b * kBrickVox + t];
         vis0[b * kBrickVox + t] = v;
         s0[t] = v;
         unsigned c = v ? cnt : 0u;
@@ -196,6 +119,12 @@ __global__ void __launch_bounds__(512) k_cull_vis(CullArgs a, const uint32_t *__
             unsigned tot = 0;
             for (int k = 0; k < 8; ++k) tot += wsum[k];
             brick_total[sl] = tot;
+            if (o) {
+                const int bx = (int)(b % g.nb[0]), by = (int)((b / g.nb[0]) % g.nb[1]);
+                const int bz = (int)(b / ((int64_t)g.nb[0] * g.nb[1]));
+                atomicMin(&st->vbox[0], bx); atomicMin(&st->vbox[1], by); atomicMin(&st->vbox[2], bz);
+                atomicMax(&st->vbox[3], bx); atomicMax(&st->vbox[4], by); atomicMax(&st->vbox[5], bz);
+            }
         }
         __syncthreads();
     }
@@ -255,7 +184,7 @@ __global__ void __launch_bounds__(512) k_list_offsets(const uint32_t *__restrict
                                                       const int32_t *__restrict__ list,
                                                       const uint32_t *__restrict__ base,
                                                       const DevStatus *__restrict__ st,
-                                                      uint32_t *__restrict__ cursor) {
+                                                      uint32_t *__restrict__ cursor, uint64_t *__restrict__ cell) {
     __shared__ unsigned wt[8];
     const unsigned nbk = st->n_bricks;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -271,7 +200,9 @@ __global__ void __launch_bounds__(512) k_list_offsets(const uint32_t *__restrict
         __syncthreads();
         unsigned wb = 0;
         for (int k = 0; k < w; ++k) wb += wt[k];
-        cursor[b * kBrickVox + t] = base[sl] + wb + incl - c;
+        const uint32_t start = base[sl] + wb + incl - c;
+        cursor[b * kBrickVox + t] = start;
+        cell[b * kBrickVox + t] = (uint64_t)start | ((uint64_t)c << 32);
         __syncthreads();
     }
 }
@@ -302,10 +233,14 @@ __global__ void __launch_bounds__(256) k_scatter(ScatterArgs a) {
     if (dx >= 65536 || dx <= -65536 || dy >= 65536 || dy <= -65536 || dz >= 65536 || dz <= -65536) return;
     SlabSpan s = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), a.rq, a.G);
     if (s.empty) return;
+    // voxel ranges back on (x, y, z)
+    const int lx = s.a0 == 0 ? s.vlo0 : (s.a1 == 0 ? s.vlo1 : s.vlo2), hx = s.a0 == 0 ? s.vhi0 : (s.a1 == 0 ? s.vhi1 : s.vhi2);
+    const int ly = s.a0 == 1 ? s.vlo0 : (s.a1 == 1 ? s.vlo1 : s.vlo2), hy = s.a0 == 1 ? s.vhi0 : (s.a1 == 1 ? s.vhi1 : s.vhi2);
+    const int lz = s.a0 == 2 ? s.vlo0 : (s.a1 == 2 ? s.vlo1 : s.vlo2), hz = s.a0 == 2 ? s.vhi0 : (s.a1 == 2 ? s.vhi1 : s.vhi2);
     bool any = false;
-    for (int bz = s.vlo[2] >> 3; bz <= s.vhi[2] >> 3 && !any; ++bz)
-        for (int by = s.vlo[1] >> 3; by <= s.vhi[1] >> 3 && !any; ++by)
-            for (int bx = s.vlo[0] >> 3; bx <= s.vhi[0] >> 3; ++bx)
+    for (int bz = lz >> 3; bz <= hz >> 3 && !any; ++bz)
+        for (int by = ly >> 3; by <= hy >> 3 && !any; ++by)
+            for (int bx = lx >> 3; bx <= hx >> 3; ++bx)
                 if (a.vis3[((int64_t)bz * a.nb[1] + by) * a.nb[0] + bx]) {
                     any = true;
                     break;
@@ -329,16 +264,30 @@ hipError_t launch_cull(vrt_ctx *c, const int64_t E[3], int64_t limit, hipStream_
     for (int k = 0; k < 3; ++k) {
         g.G[k] = c->dims[k];
         g.nb[k] = c->dims[k] / 8;
+        g.ns[k] = (c->dims[k] + 63) / 64;
     }
     const int64_t nb = (int64_t)g.nb[0] * g.nb[1] * g.nb[2];
-    VRT_LAUNCH(c, "k_cull_reset", st, k_cull_reset<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(A.vis3, A.brick_blk, nb, A.status));
-    VRT_LAUNCH(c, "k_erode", st, k_erode<<<4096, 512, 0, st>>>(g, A.occ0, A.brick_list, A.brick_slot, A.status, A.blk, A.brick_blk));
-    CullArgs ca;
-    ca.g = g;
-    for (int k = 0; k < 3; ++k) ca.E[k] = E[k];
-    ca.limit = limit < 0 ? -1 : (int)(limit > INT_MAX ? INT_MAX : limit);
-    VRT_LAUNCH(c, "k_cull_vis", st, k_cull_vis<<<4096, 512, 0, st>>>(ca, A.words, A.brick_list, A.status, A.blk, A.brick_blk, A.vis0, A.vis1, A.vis2,
-                                     A.vis3, A.brick_total));
+    const int lim = limit < 0 ? -1 : (int)(limit > INT_MAX ? INT_MAX : limit);
+    VRT_LAUNCH(c, "k_cull_reset", st, k_cull_reset<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(A.vis3, nb, A.status));
+    if (lim >= 0) {
+        CullArgs ca;
+        ca.g = g;
+        for (int k = 0; k < 3; ++k) ca.E[k] = E[k];
+        ca.limit = lim;
+        CullCells cells;
+        cells.super_blk = A.super_blk;
+        cells.brick_blk = A.brick_blk;
+        cells.blk = A.blk;
+        cells.nb0 = g.nb[0];
+        cells.nb1 = g.nb[1];
+        cells.ns0 = g.ns[0];
+        cells.ns1 = g.ns[1];
+        VRT_LAUNCH(c, "k_cull_walk", st,
+                   k_cull_walk<<<8192, 256, 0, st>>>(ca, cells, A.occ_list, A.status, A.vis0));
+    }
+    VRT_LAUNCH(c, "k_cull_brick", st,
+               k_cull_brick<<<4096, 512, 0, st>>>(lim, g, A.words, A.brick_list, A.status, A.vis0, A.vis1, A.vis2, A.vis3,
+                                                  A.brick_total));
     const uint8_t *src = A.vis3;
     int sx = g.nb[0], sy = g.nb[1], sz = g.nb[2];
     for (int L = 4; L < c->n_levels; ++L) {
@@ -352,7 +301,7 @@ hipError_t launch_cull(vrt_ctx *c, const int64_t E[3], int64_t limit, hipStream_
         sz = lv.dims[2];
     }
     VRT_LAUNCH(c, "k_scan_bricks", st, k_scan_bricks<<<1, 1024, 0, st>>>(A.brick_total, A.brick_base, A.status, c->desc.max_fragments));
-    VRT_LAUNCH(c, "k_list_offsets", st, k_list_offsets<<<4096, 512, 0, st>>>(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor));
+    VRT_LAUNCH(c, "k_list_offsets", st, k_list_offsets<<<4096, 512, 0, st>>>(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor, A.cell));
     ScatterArgs sa;
     sa.vrec = A.vrec;
     sa.nv = c->n_vertices;

@@ -31,7 +31,9 @@ struct DevStatus {
     unsigned long long n_fragments;
     unsigned long long n_listed;
     int bbox[6];  // blocking-voxel bounds: min x,y,z then max x,y,z (voxels)
-    unsigned int pad[4];
+    unsigned int n_occ;  // occupied voxels (entries of occ_list)
+    int vbox[6];         // visible-brick bounds: min bx,by,bz then max (bricks)
+    unsigned int n_queue;  // rays queued by the trace's march phase
 };
 
 struct Arenas {
@@ -44,12 +46,16 @@ struct Arenas {
     uint16_t *occ_hi = nullptr;     // levels >= 4
     uint8_t *blk = nullptr;         // [max_bricks * 512]
     uint8_t *brick_blk = nullptr;   // [max_bricks]
+    uint8_t *super_blk = nullptr;   // [max_supers] 64^3 cells holding a blocking voxel
+    uint32_t *occ_list = nullptr;   // [max_bricks * 512] brick-major index of every occupied voxel
     uint8_t *vis0 = nullptr;        // [max_bricks * 512]
     uint8_t *vis1 = nullptr;        // [max_bricks * 64]
     uint8_t *vis2 = nullptr;        // [max_bricks * 8]
     uint8_t *vis3 = nullptr;        // [max_bricks]
     uint8_t *vis_hi = nullptr;      // levels >= 4
     uint32_t *cursor = nullptr;     // [max_bricks * 512] list start, then end after pass 2
+    uint64_t *cell = nullptr;       // [max_bricks * 512] list start (low 32) | visible count (high 32)
+    uint4 *queue = nullptr;         // [max_pixels] rays that reached a list
     uint32_t *ids = nullptr;        // [max_fragments]
     uint8_t *brick_flag = nullptr;  // [max_bricks]
     int32_t *brick_list = nullptr;  // [max_bricks]
@@ -57,6 +63,10 @@ struct Arenas {
     uint32_t *brick_total = nullptr;// [max_bricks] visible fragments per occupied brick (by slot)
     uint32_t *brick_base = nullptr; // [max_bricks] exclusive scan of brick_total
     DevStatus *status = nullptr;
+    // trace statistics (inspection only)
+    uint8_t *stat_vox = nullptr;            // [max_bricks * 512] voxel list read
+    uint8_t *stat_seg = nullptr;            // [max_vertices] segment tested
+    unsigned long long *stat_acc = nullptr; // [16]
 };
 
 // Event-pair profiler (host side); disabled unless vrt_profile_enable.
@@ -79,6 +89,7 @@ struct Level {
 struct vrt_ctx {
     vrt_desc desc;
     int64_t max_bricks;
+    int64_t max_supers;
     int64_t hi_elems;  // capacity of occ_hi / vis_hi
     vrt::Arenas a;
     // frame state
@@ -138,6 +149,7 @@ struct TraceParams {
     float voxel_size;
 };
 hipError_t launch_trace(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st);
+hipError_t launch_trace_stats(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st);
 hipError_t launch_debug_rays(const TraceParams &p, const int64_t *pix, int64_t n, float *dirs, hipStream_t st);
 
 // ------------------------------------------------------------------------
@@ -174,86 +186,111 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 
 // Capsule voxel set of one segment (Section 3.1, Alg. 1 with the projected
 // radius that is conservative in 3D): per major-axis slab, a 2D box on the
-// minor axes.  Calls f(x, y, z) for every voxel, each exactly once.
+// minor axes.  Calls f(x, y, z) for every voxel, each exactly once.  The span
+// is kept in axis-permuted scalars (index 0 = major axis a0, 1 and 2 = the
+// minor axes a1 < a2): runtime-indexed arrays would live in per-lane scratch.
 struct SlabSpan {
     int a0, a1, a2;
-    long long A[3], d[3], D;
-    long long lo[3], hi[3];
-    int vlo[3], vhi[3];
-    long long W1, W2;
+    long long A0, A1, A2;  // start point on (a0, a1, a2) after the swap
+    long long D, d1, d2;   // direction on (a0, a1, a2), D >= 0
+    long long lo0, hi0;    // closed capsule extent along a0
+    int vlo0, vhi0, vlo1, vhi1, vlo2, vhi2;  // voxel ranges
+    long long W1, W2;      // half-widths scaled by D
     bool empty;
 };
 
+__device__ __forceinline__ long long sel3(long long x, long long y, long long z, int k) {
+    return k == 0 ? x : (k == 1 ? y : z);
+}
+
 __device__ __forceinline__ SlabSpan make_span(int3 a, int3 b, long long rq, const int *G) {
     SlabSpan s;
-    long long A[3] = {a.x, a.y, a.z}, B[3] = {b.x, b.y, b.z};
-    long long d[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
-    long long ad[3] = {d[0] < 0 ? -d[0] : d[0], d[1] < 0 ? -d[1] : d[1], d[2] < 0 ? -d[2] : d[2]};
+    const long long dx = (long long)b.x - a.x, dy = (long long)b.y - a.y, dz = (long long)b.z - a.z;
+    const long long ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy, az = dz < 0 ? -dz : dz;
     int a0 = 0;
-    if (ad[1] > ad[a0]) a0 = 1;
-    if (ad[2] > ad[a0]) a0 = 2;
-    bool swap = d[a0] < 0;
-    for (int c = 0; c < 3; ++c) {
-        s.A[c] = swap ? B[c] : A[c];
-        s.d[c] = swap ? -d[c] : d[c];
+    long long am = ax;
+    if (ay > am) {
+        a0 = 1;
+        am = ay;
     }
+    if (az > am) a0 = 2;
     s.a0 = a0;
     s.a1 = a0 == 0 ? 1 : 0;
     s.a2 = a0 == 2 ? 1 : 2;
-    s.D = s.d[a0];
-    s.empty = false;
-    for (int c = 0; c < 3; ++c) {
-        long long mn = A[c] < B[c] ? A[c] : B[c], mx = A[c] < B[c] ? B[c] : A[c];
-        s.lo[c] = mn - rq;
-        s.hi[c] = mx + rq;
-        long long vl = floor_div(s.lo[c] - 1, kQ), vh = floor_div(s.hi[c], kQ);
-        if (vl < 0) vl = 0;
-        if (vh > G[c] - 1) vh = G[c] - 1;
-        s.vlo[c] = (int)vl;
-        s.vhi[c] = (int)vh;
-        if (vl > vh) s.empty = true;
-    }
+    const bool swap = sel3(dx, dy, dz, a0) < 0;
+    const long long sx = swap ? b.x : a.x, sy = swap ? b.y : a.y, sz = swap ? b.z : a.z;
+    const long long ex = swap ? -dx : dx, ey = swap ? -dy : dy, ez = swap ? -dz : dz;
+    s.A0 = sel3(sx, sy, sz, s.a0);
+    s.A1 = sel3(sx, sy, sz, s.a1);
+    s.A2 = sel3(sx, sy, sz, s.a2);
+    s.D = sel3(ex, ey, ez, s.a0);
+    s.d1 = sel3(ex, ey, ez, s.a1);
+    s.d2 = sel3(ex, ey, ez, s.a2);
+    // closed capsule AABB and the voxel range touching it, per original axis
+    const long long lox = (a.x < b.x ? a.x : b.x) - rq, hix = (a.x < b.x ? b.x : a.x) + rq;
+    const long long loy = (a.y < b.y ? a.y : b.y) - rq, hiy = (a.y < b.y ? b.y : a.y) + rq;
+    const long long loz = (a.z < b.z ? a.z : b.z) - rq, hiz = (a.z < b.z ? b.z : a.z) + rq;
+    long long vlx = floor_div(lox - 1, kQ), vhx = floor_div(hix, kQ);
+    long long vly = floor_div(loy - 1, kQ), vhy = floor_div(hiy, kQ);
+    long long vlz = floor_div(loz - 1, kQ), vhz = floor_div(hiz, kQ);
+    vlx = vlx < 0 ? 0 : vlx;
+    vly = vly < 0 ? 0 : vly;
+    vlz = vlz < 0 ? 0 : vlz;
+    vhx = vhx > G[0] - 1 ? G[0] - 1 : vhx;
+    vhy = vhy > G[1] - 1 ? G[1] - 1 : vhy;
+    vhz = vhz > G[2] - 1 ? G[2] - 1 : vhz;
+    s.empty = vlx > vhx || vly > vhy || vlz > vhz;
+    s.lo0 = sel3(lox, loy, loz, s.a0);
+    s.hi0 = sel3(hix, hiy, hiz, s.a0);
+    s.vlo0 = (int)sel3(vlx, vly, vlz, s.a0);
+    s.vhi0 = (int)sel3(vhx, vhy, vhz, s.a0);
+    s.vlo1 = (int)sel3(vlx, vly, vlz, s.a1);
+    s.vhi1 = (int)sel3(vhx, vhy, vhz, s.a1);
+    s.vlo2 = (int)sel3(vlx, vly, vlz, s.a2);
+    s.vhi2 = (int)sel3(vhx, vhy, vhz, s.a2);
     s.W1 = s.W2 = 0;
     if (s.D > 0) {
-        s.W1 = ceil_isqrt(rq * rq * (s.D * s.D + s.d[s.a1] * s.d[s.a1]));
-        s.W2 = ceil_isqrt(rq * rq * (s.D * s.D + s.d[s.a2] * s.d[s.a2]));
+        s.W1 = ceil_isqrt(rq * rq * (s.D * s.D + s.d1 * s.d1));
+        s.W2 = ceil_isqrt(rq * rq * (s.D * s.D + s.d2 * s.d2));
     }
     return s;
 }
 
-// minor-axis voxel range of slab x on axis i with half-width W
-__device__ __forceinline__ void slab_range(const SlabSpan &s, int x, int i, long long W, int &rl, int &rh) {
+// Minor-axis voxel range of slab x: the segment's line at the slab's ends
+// (ta, tb), widened by W (numerators scaled by D), clipped to [vlo, vhi].
+__device__ __forceinline__ void slab_range(const SlabSpan &s, int x, long long A, long long d, long long W, int vlo,
+                                           int vhi, int &rl, int &rh) {
     if (s.D == 0) {
-        rl = s.vlo[i];
-        rh = s.vhi[i];
+        rl = vlo;
+        rh = vhi;
         return;
     }
-    long long ta = s.lo[s.a0] > (long long)x * kQ ? s.lo[s.a0] : (long long)x * kQ;
-    long long tb = s.hi[s.a0] < (long long)(x + 1) * kQ ? s.hi[s.a0] : (long long)(x + 1) * kQ;
-    long long ca = s.A[i] * s.D + s.d[i] * (ta - s.A[s.a0]);
-    long long cb = s.A[i] * s.D + s.d[i] * (tb - s.A[s.a0]);
-    long long nlo = (ca < cb ? ca : cb) - W, nhi = (ca < cb ? cb : ca) + W;
-    long long m = s.D * kQ;
-    long long l = floor_div(nlo - 1, m), h = floor_div(nhi, m);
-    rl = (int)(l > s.vlo[i] ? l : s.vlo[i]);
-    rh = (int)(h < s.vhi[i] ? h : s.vhi[i]);
+    const long long ta = s.lo0 > (long long)x * kQ ? s.lo0 : (long long)x * kQ;
+    const long long tb = s.hi0 < (long long)(x + 1) * kQ ? s.hi0 : (long long)(x + 1) * kQ;
+    const long long ca = A * s.D + d * (ta - s.A0);
+    const long long cb = A * s.D + d * (tb - s.A0);
+    const long long nlo = (ca < cb ? ca : cb) - W, nhi = (ca < cb ? cb : ca) + W;
+    const long long m = s.D * kQ;
+    const long long l = floor_div(nlo - 1, m), h = floor_div(nhi, m);
+    rl = (int)(l > vlo ? l : vlo);
+    rh = (int)(h < vhi ? h : vhi);
 }
 
 template <class F>
 __device__ __forceinline__ int for_each_voxel(const SlabSpan &s, F &&f) {
     if (s.empty) return 0;
     int n = 0;
-    for (int x = s.vlo[s.a0]; x <= s.vhi[s.a0]; ++x) {
+    for (int x = s.vlo0; x <= s.vhi0; ++x) {
         int l1, h1, l2, h2;
-        slab_range(s, x, s.a1, s.W1, l1, h1);
-        slab_range(s, x, s.a2, s.W2, l2, h2);
+        slab_range(s, x, s.A1, s.d1, s.W1, s.vlo1, s.vhi1, l1, h1);
+        slab_range(s, x, s.A2, s.d2, s.W2, s.vlo2, s.vhi2, l2, h2);
         for (int j = l1; j <= h1; ++j)
             for (int k = l2; k <= h2; ++k) {
-                int C[3];
-                C[s.a0] = x;
-                C[s.a1] = j;
-                C[s.a2] = k;
-                f(C[0], C[1], C[2]);
+                // (x, j, k) on axes (a0, a1, a2) back to (x, y, z)
+                const int vx = s.a0 == 0 ? x : (s.a1 == 0 ? j : k);
+                const int vy = s.a0 == 1 ? x : (s.a1 == 1 ? j : k);
+                const int vz = s.a0 == 2 ? x : (s.a1 == 2 ? j : k);
+                f(vx, vy, vz);
                 ++n;
             }
     }

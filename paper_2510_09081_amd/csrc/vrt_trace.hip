@@ -4,7 +4,9 @@
 namespace vrt {
 namespace {
 
-constexpr int kKeys = 8;  // k-buffer entries per pass (transparent)
+constexpr int kBatch = 4;  // list entries per lane whose vertex records are fetched together
+constexpr int kGroup = 16;    // lanes that share one ray in the shade phase
+constexpr int kLaneKeys = 4;  // accepted (t, id) keys a lane keeps per pass (transparent)
 
 // Primary ray through the centre of pixel (px, py), row 0 at the top, as a
 // fixed binary32 sequence (no contraction): u = 2(x + .5)/W - 1,
@@ -82,17 +84,26 @@ struct TraceArgs {
     TraceParams p;
     int G[3];
     int nb[3];
-    const uint8_t *vis0;
-    const uint8_t *vis3;
-    const uint32_t *words;
-    const uint32_t *cursor;
+    int n6[3];                // 64^3 cells per axis (culling level 6)
+    const uint8_t *vis6;      // culling level 6, or null when the grid has no such level
+    const uint8_t *vis3;      // culling level 3 (bricks)
+    const uint64_t *cell;     // per voxel: list start | visible count << 32
+    DevStatus *st;            // visible-brick box, ray-queue length
     const uint32_t *ids;
     const VRec *vrec;
-    int64_t nv;        // vertices of the frame (ids must be < nv - 1)
-    int64_t capacity;  // entries of ids
+    int64_t nv;               // vertices of the frame (ids must be < nv - 1)
+    int64_t capacity;         // entries of ids
+    uint4 *queue;             // rays that reached a list: pixel, packed voxel, t
     float *rgba;
     float *depth;
     int *first_id;
+    uint8_t *stat_vox;        // statistics variant only
+    uint8_t *stat_seg;
+    unsigned long long *stat_acc;
+};
+
+struct Counters {
+    unsigned long long skip64 = 0, skip8 = 0, vox = 0, list = 0, test = 0, pass = 0;
 };
 
 __device__ __forceinline__ float3 rel(const VRec &v, int cx, int cy, int cz) {
@@ -100,17 +111,15 @@ __device__ __forceinline__ float3 rel(const VRec &v, int cx, int cy, int cz) {
                        (float)(v.z - cz * kQ) * (1.0f / kQ));
 }
 
-// Accepted hit of segment id inside the current voxel: entry parameter s in
+// Accepted hit of segment (A, B) inside the current voxel: entry parameter s in
 // [0, tl) from the voxel-local origin ro, and on the kept side of both clip
 // planes ((P - A).n0 >= 0 at an interior A, (P - B).n1 < 0 at an interior B).
-__device__ __forceinline__ bool voxel_hit(const TraceArgs &a, uint32_t id, float3 ro, float3 D, int cx, int cy, int cz,
-                                          float tl, float &s) {
-    if ((int64_t)id + 1 >= a.nv) return false;
-    VRec A = a.vrec[id], B = a.vrec[id + 1];
-    float3 pa = rel(A, cx, cy, cz), pb = rel(B, cx, cy, cz);
-    s = capsule_entry(ro, D, pa, pb, a.p.radius);
+__device__ __forceinline__ bool voxel_hit(const VRec &A, const VRec &B, float radius, float3 ro, float3 D, int cx,
+                                          int cy, int cz, float tl, float &s) {
+    const float3 pa = rel(A, cx, cy, cz), pb = rel(B, cx, cy, cz);
+    s = capsule_entry(ro, D, pa, pb, radius);
     if (!(s >= 0.0f && s < tl)) return false;
-    float3 P = make_float3(fmaf(s, D.x, ro.x), fmaf(s, D.y, ro.y), fmaf(s, D.z, ro.z));
+    const float3 P = make_float3(fmaf(s, D.x, ro.x), fmaf(s, D.y, ro.y), fmaf(s, D.z, ro.z));
     if (A.flags & kInterior) {
         if (!(dot3(sub3(P, pa), make_float3(A.nx, A.ny, A.nz)) >= 0.0f)) return false;
     }
@@ -120,10 +129,9 @@ __device__ __forceinline__ bool voxel_hit(const TraceArgs &a, uint32_t id, float
     return true;
 }
 
-__device__ __forceinline__ float3 seg_colour(const TraceArgs &a, uint32_t id) {
-    VRec A = a.vrec[id], B = a.vrec[id + 1];
-    float dx = (float)(B.x - A.x), dy = (float)(B.y - A.y), dz = (float)(B.z - A.z);
-    float len = sqrtf(dx * dx + dy * dy + dz * dz);
+__device__ __forceinline__ float3 seg_colour(const VRec &A, const VRec &B) {
+    const float dx = (float)(B.x - A.x), dy = (float)(B.y - A.y), dz = (float)(B.z - A.z);
+    const float len = sqrtf(dx * dx + dy * dy + dz * dz);
     if (len == 0.0f) return make_float3(0.0f, 0.0f, 0.0f);
     return make_float3(fabsf(dx) / len, fabsf(dy) / len, fabsf(dz) / len);
 }
@@ -132,177 +140,451 @@ __device__ __forceinline__ bool key_less(float s0, uint32_t i0, float s1, uint32
     return s0 < s1 || (s0 == s1 && i0 < i1);
 }
 
-__device__ __forceinline__ float tcross(int bnd, float o, float d) { return ((float)bnd - o) / d; }
+// Parameter of the crossing with plane `bnd` on one axis: (bnd - O) * (1/D).
+// bnd - O is exact in binary32 (both are multiples of 1/256 below 2^16), and
+// every boundary is computed by this one expression, so neighbouring cells
+// share their boundary parameters exactly.
+__device__ __forceinline__ float tcross(int bnd, float o, float inv) { return ((float)bnd - o) * inv; }
 
-// One thread per pixel; a 64-lane wavefront covers an 8x8 pixel tile.
-__global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int px = blockIdx.x * 16 + (w & 1) * 8 + (lane & 7);
-    const int py = blockIdx.y * 16 + (w >> 1) * 8 + (lane >> 3);
-    if (px >= a.p.W || py >= a.p.H) return;
-    const float3 D = primary_dir(a.p, px, py);
-    const float O[3] = {a.p.O[0], a.p.O[1], a.p.O[2]};
-    const float Dv[3] = {D.x, D.y, D.z};
-    float tin = 0.0f, tout = INFINITY;
-    bool inside = true;
+struct Ray {
+    float O[3], D[3], inv[3];
+    int step[3];
+};
+
+// Element m of a 3-array without a runtime-indexed access (which would place
+// the array in per-lane scratch memory).
+template <class T>
+__device__ __forceinline__ T pick3(const T *a, int m) {
+    return m == 0 ? a[0] : (m == 1 ? a[1] : a[2]);
+}
+template <class T>
+__device__ __forceinline__ void put3(T *a, int m, T v) {
+    if (m == 0) a[0] = v;
+    else if (m == 1) a[1] = v;
+    else a[2] = v;
+}
+
+__device__ __forceinline__ Ray make_ray(const TraceParams &p, float3 D) {
+    Ray r;
+    r.O[0] = p.O[0];
+    r.O[1] = p.O[1];
+    r.O[2] = p.O[2];
+    r.D[0] = D.x;
+    r.D[1] = D.y;
+    r.D[2] = D.z;
     for (int k = 0; k < 3; ++k) {
-        if (Dv[k] == 0.0f) {
-            if (O[k] < 0.0f || O[k] > (float)a.G[k]) inside = false;
+        r.step[k] = r.D[k] > 0.0f ? 1 : (r.D[k] < 0.0f ? -1 : 0);
+        r.inv[k] = r.step[k] == 0 ? 0.0f : 1.0f / r.D[k];
+    }
+    return r;
+}
+
+// Parameter interval of the ray inside the box of visible bricks.
+__device__ __forceinline__ bool clip_visible(const TraceArgs &a, const Ray &r, float &tin, float &tout, int *vb) {
+    for (int k = 0; k < 6; ++k) vb[k] = a.st->vbox[k];
+    tin = 0.0f;
+    tout = INFINITY;
+    if (!(vb[0] <= vb[3] && vb[1] <= vb[4] && vb[2] <= vb[5])) return false;
+    for (int k = 0; k < 3; ++k) {
+        const int lo = 8 * vb[k], hi = 8 * (vb[3 + k] + 1);
+        if (r.step[k] == 0) {
+            if (r.O[k] < (float)lo || r.O[k] > (float)hi) return false;
             continue;
         }
-        float t1 = tcross(0, O[k], Dv[k]), t2 = tcross(a.G[k], O[k], Dv[k]);
+        float t1 = tcross(lo, r.O[k], r.inv[k]), t2 = tcross(hi, r.O[k], r.inv[k]);
         if (t1 > t2) {
-            float tt = t1;
+            const float tt = t1;
             t1 = t2;
             t2 = tt;
         }
         tin = fmaxf(tin, t1);
         tout = fminf(tout, t2);
     }
-    const int64_t pixel = (int64_t)py * a.p.W + px;
-    float3 col = make_float3(0.0f, 0.0f, 0.0f);
-    float T = 1.0f, first_t = INFINITY;
-    int first = -1;
-    const bool opaque = a.p.mode == VRT_TRACE_OPAQUE;
-    if (inside && tin < tout) {
-        int v[3], step[3];
-        float tnext[3];
-        for (int k = 0; k < 3; ++k) {
-            float pk = fmaf(tin, Dv[k], O[k]);
-            int vk = (int)floorf(pk);
-            vk = vk < 0 ? 0 : (vk >= a.G[k] ? a.G[k] - 1 : vk);
-            v[k] = vk;
-            step[k] = Dv[k] > 0.0f ? 1 : (Dv[k] < 0.0f ? -1 : 0);
-            tnext[k] = step[k] == 0 ? INFINITY : tcross(v[k] + (step[k] > 0), O[k], Dv[k]);
+    return tin < tout;
+}
+
+// Crosses the empty S^3 cell holding voxel v: returns false when the ray
+// leaves the grid; else v becomes the voxel entered after the cell's exit
+// face (monotone in the direction of travel, clamped to the cell on the other
+// axes) and tcur the exit parameter.
+__device__ __forceinline__ bool skip_cell(const Ray &r, const int *G, int S, int *v, float &tcur) {
+    int cellk[3];
+    float tb[3];
+    for (int k = 0; k < 3; ++k) {
+        cellk[k] = v[k] / S;
+        tb[k] = r.step[k] == 0 ? INFINITY : tcross(S * (cellk[k] + (r.step[k] > 0)), r.O[k], r.inv[k]);
+    }
+    int m = 0;
+    float tm = tb[0];
+    if (tb[1] < tm) {
+        m = 1;
+        tm = tb[1];
+    }
+    if (tb[2] < tm) {
+        m = 2;
+        tm = tb[2];
+    }
+    const float te = fmaxf(tm, tcur);
+    for (int k = 0; k < 3; ++k) {
+        int nv;
+        if (k == m) {
+            nv = r.step[k] > 0 ? S * (cellk[k] + 1) : S * cellk[k] - 1;
+            if (nv < 0 || nv >= G[k]) return false;
+        } else {
+            nv = (int)floorf(fmaf(te, r.D[k], r.O[k]));
+            if (r.step[k] > 0) nv = nv < v[k] ? v[k] : nv;
+            if (r.step[k] < 0) nv = nv > v[k] ? v[k] : nv;
+            const int lo = S * cellk[k];
+            const int hi = min(S * cellk[k] + S - 1, G[k] - 1);
+            nv = nv < lo ? lo : (nv > hi ? hi : nv);
         }
-        float tcur = tin;
-        const int max_iter = 3 * (a.G[0] + a.G[1] + a.G[2]) + 16;
-        for (int it = 0; it < max_iter; ++it) {
-            const int bx = v[0] >> 3, by = v[1] >> 3, bz = v[2] >> 3;
-            const int64_t b = ((int64_t)bz * a.nb[1] + by) * a.nb[0] + bx;
-            if (!a.vis3[b]) {
-                // skip the whole brick: exit through its nearest face
-                const int bb[3] = {bx, by, bz};
-                float tb[3];
-                int m = 0;
-                for (int k = 0; k < 3; ++k) {
-                    tb[k] = step[k] == 0 ? INFINITY : tcross(8 * (bb[k] + (step[k] > 0)), O[k], Dv[k]);
-                    if (tb[k] < tb[m]) m = k;
-                }
-                float te = fmaxf(tb[m], tcur);
-                bool out = false;
-                for (int k = 0; k < 3; ++k) {
-                    int nv;
-                    if (k == m) {
-                        nv = step[k] > 0 ? 8 * (bb[k] + 1) : 8 * bb[k] - 1;
-                        if (nv < 0 || nv >= a.G[k]) out = true;
-                    } else {
-                        nv = (int)floorf(fmaf(te, Dv[k], O[k]));
-                        if (step[k] > 0) nv = nv < v[k] ? v[k] : nv;
-                        if (step[k] < 0) nv = nv > v[k] ? v[k] : nv;
-                        int lo = 8 * bb[k], hi = 8 * bb[k] + 7;
-                        nv = nv < lo ? lo : (nv > hi ? hi : nv);
-                    }
-                    v[k] = nv;
-                }
-                if (out) break;
-                tcur = te;
-                for (int k = 0; k < 3; ++k)
-                    tnext[k] = step[k] == 0 ? INFINITY : tcross(v[k] + (step[k] > 0), O[k], Dv[k]);
-                if (!(tcur < tout)) break;
-                continue;
+        v[k] = nv;
+    }
+    tcur = te;
+    return true;
+}
+
+// DDA state of one ray: current voxel, its entry parameter, the next boundary
+// parameter on each axis (valid unless `fresh`), and the end of the walk.
+struct Walk {
+    int v[3];
+    float tcur, tout;
+    float tnext[3];
+    bool fresh;
+    int m;          // axis of the current voxel's exit
+    float texit;    // exit parameter of the current voxel
+    int64_t vi;     // brick-major index of the current voxel
+    uint64_t cd;    // its list descriptor
+};
+
+// Steps past the current voxel along its exit axis; false when the ray leaves the grid.
+__device__ __forceinline__ bool step_voxel(const TraceArgs &a, const Ray &r, Walk &w) {
+    const int m = w.m;
+    const int st = pick3(r.step, m);
+    const int nv = pick3(w.v, m) + st;
+    if (nv < 0 || nv >= pick3(a.G, m)) return false;
+    put3(w.v, m, nv);
+    w.tcur = w.texit;
+    put3(w.tnext, m, tcross(nv + (st > 0), pick3(r.O, m), pick3(r.inv, m)));
+    return true;
+}
+
+// Advances from the current voxel (included) to the first visible voxel with
+// a non-empty list, skipping empty 64^3 cells and bricks; false if none.
+template <bool kStats>
+__device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w, Counters &cn) {
+    const int max_iter = 3 * (a.G[0] + a.G[1] + a.G[2]) + 16;
+    for (int it = 0; it < max_iter; ++it) {
+        if (!(w.tcur < w.tout)) return false;
+        if (a.vis6 && !a.vis6[((int64_t)(w.v[2] >> 6) * a.n6[1] + (w.v[1] >> 6)) * a.n6[0] + (w.v[0] >> 6)]) {
+            if (kStats) ++cn.skip64;
+            if (!skip_cell(r, a.G, 64, w.v, w.tcur)) return false;
+            w.fresh = true;
+            continue;
+        }
+        const int64_t b = ((int64_t)(w.v[2] >> 3) * a.nb[1] + (w.v[1] >> 3)) * a.nb[0] + (w.v[0] >> 3);
+        if (!a.vis3[b]) {
+            if (kStats) ++cn.skip8;
+            if (!skip_cell(r, a.G, 8, w.v, w.tcur)) return false;
+            w.fresh = true;
+            continue;
+        }
+        if (w.fresh) {
+            for (int k = 0; k < 3; ++k)
+                w.tnext[k] = r.step[k] == 0 ? INFINITY : tcross(w.v[k] + (r.step[k] > 0), r.O[k], r.inv[k]);
+            w.fresh = false;
+        }
+        float tm = w.tnext[0];
+        w.m = 0;
+        if (w.tnext[1] < tm) {
+            w.m = 1;
+            tm = w.tnext[1];
+        }
+        if (w.tnext[2] < tm) {
+            w.m = 2;
+            tm = w.tnext[2];
+        }
+        w.texit = fmaxf(tm, w.tcur);
+        w.vi = b * kBrickVox + local_of(w.v[0], w.v[1], w.v[2]);
+        w.cd = a.cell[w.vi];
+        if (kStats) ++cn.vox;
+        if (w.cd >> 32) return true;
+        if (!step_voxel(a, r, w)) return false;
+    }
+    return false;
+}
+
+// Calls f(id, A, B) for the entries of the current voxel's list that belong
+// to lane `gl` of a kGroup-lane group (entries gl, gl + kGroup, ...).  The
+// vertex records of kBatch entries are fetched before any of them is tested,
+// so each lane keeps several independent loads in flight.
+template <bool kStats, class F>
+__device__ __forceinline__ void for_each_entry(const TraceArgs &a, const Walk &w, int gl, Counters &cn, F &&f) {
+    // after a capacity overflow the lists are undefined but reads stay inside ids
+    const uint32_t start = (uint32_t)w.cd, cnt = (uint32_t)(w.cd >> 32);
+    const uint32_t end = (int64_t)start + cnt <= a.capacity ? start + cnt : start;
+    for (uint32_t k = start + gl; k < end; k += kGroup * kBatch) {
+        uint32_t id[kBatch];
+        VRec A[kBatch], B[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) id[j] = k + j * kGroup < end ? a.ids[k + j * kGroup] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const uint32_t safe = (int64_t)id[j] + 1 < a.nv ? id[j] : 0u;
+            A[j] = a.vrec[safe];
+            B[j] = a.vrec[safe + 1];
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            if (!((int64_t)id[j] + 1 < a.nv)) continue;
+            if (kStats) {
+                ++cn.test;
+                a.stat_seg[id[j]] = 1;
             }
-            int m = 0;
-            if (tnext[1] < tnext[m]) m = 1;
-            if (tnext[2] < tnext[m]) m = 2;
-            const float texit = fmaxf(tnext[m], tcur);
-            const int64_t vi = b * kBrickVox + local_of(v[0], v[1], v[2]);
-            const uint32_t cnt = a.vis0[vi] ? (a.words[vi] & 0xFFFFu) : 0u;
-            if (cnt) {
-                // after a capacity overflow the lists are undefined but reads stay inside ids
-                const uint32_t cend = a.cursor[vi];
-                const uint32_t end = (int64_t)cend < a.capacity ? cend : (uint32_t)a.capacity;
-                const uint32_t start = end >= cnt ? end - cnt : 0u;
-                const float3 ro = make_float3(fmaf(tcur, D.x, O[0] - (float)v[0]), fmaf(tcur, D.y, O[1] - (float)v[1]),
-                                              fmaf(tcur, D.z, O[2] - (float)v[2]));
-                const float tl = texit - tcur;
-                if (opaque) {
-                    float best = INFINITY;
-                    uint32_t bid = 0xFFFFFFFFu;
-                    for (uint32_t k = start; k < end; ++k) {
-                        uint32_t id = a.ids[k];
-                        float s;
-                        if (voxel_hit(a, id, ro, D, v[0], v[1], v[2], tl, s) && key_less(s, id, best, bid)) {
-                            best = s;
-                            bid = id;
-                        }
-                    }
-                    if (bid != 0xFFFFFFFFu) {
-                        first = (int)bid;
-                        first_t = tcur + best;
-                        col = seg_colour(a, bid);
-                        T = 0.0f;
-                        break;
-                    }
-                } else {
-                    // k-buffer passes: the kKeys smallest (s, id) keys above the last composited key
-                    float ls = -INFINITY;
-                    uint32_t lid = 0;
-                    bool first_pass = true;
-                    for (;;) {
-                        float ks[kKeys];
-                        uint32_t ki[kKeys];
-                        int nk = 0, above = 0;
-                        for (uint32_t k = start; k < end; ++k) {
-                            uint32_t id = a.ids[k];
-                            float s;
-                            if (!voxel_hit(a, id, ro, D, v[0], v[1], v[2], tl, s)) continue;
-                            if (!first_pass && !key_less(ls, lid, s, id)) continue;
-                            ++above;
-                            if (nk == kKeys && !key_less(s, id, ks[kKeys - 1], ki[kKeys - 1])) continue;
-                            int j = nk < kKeys ? nk++ : kKeys - 1;
-                            while (j > 0 && key_less(s, id, ks[j - 1], ki[j - 1])) {
-                                ks[j] = ks[j - 1];
-                                ki[j] = ki[j - 1];
-                                --j;
-                            }
-                            ks[j] = s;
-                            ki[j] = id;
-                        }
-                        for (int j = 0; j < nk && !(T < a.p.tau); ++j) {
-                            if (first < 0) {
-                                first = (int)ki[j];
-                                first_t = tcur + ks[j];
-                            }
-                            float3 c = seg_colour(a, ki[j]);
-                            float wgt = T * a.p.alpha;
-                            col.x += wgt * c.x;
-                            col.y += wgt * c.y;
-                            col.z += wgt * c.z;
-                            T *= (1.0f - a.p.alpha);
-                        }
-                        if (above <= kKeys || T < a.p.tau || nk == 0) break;
-                        ls = ks[kKeys - 1];
-                        lid = ki[kKeys - 1];
-                        first_pass = false;
-                    }
-                    if (T < a.p.tau) break;
-                }
-            }
-            // step to the next voxel
-            v[m] += step[m];
-            if (v[m] < 0 || v[m] >= a.G[m]) break;
-            tcur = texit;
-            tnext[m] = tcross(v[m] + (step[m] > 0), O[m], Dv[m]);
-            if (!(tcur < tout)) break;
+            f(id[j], A[j], B[j]);
         }
     }
+}
+
+// (t, id) order as one integer: t >= 0, so its binary32 bits order like t.
+__device__ __forceinline__ unsigned long long hit_key(float s, uint32_t id) {
+    return ((unsigned long long)__float_as_uint(s) << 32) | id;
+}
+constexpr unsigned long long kNoKey = ~0ull;
+
+// Minimum over the kGroup lanes of this lane's group (xor offsets stay inside
+// an aligned group).
+__device__ __forceinline__ unsigned long long group_min(unsigned long long k) {
+    for (int o = kGroup / 2; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(k, o, 64);
+        k = y < k ? y : k;
+    }
+    return k;
+}
+__device__ __forceinline__ bool group_any(bool p, int lane) {
+    const unsigned long long m = __ballot(p);
+    return ((m >> (lane & ~(kGroup - 1))) & ((1ull << kGroup) - 1ull)) != 0ull;
+}
+
+// Result of one ray.
+struct Shade {
+    float3 col = make_float3(0.0f, 0.0f, 0.0f);
+    float T = 1.0f;
+    float first_t = INFINITY;
+    int first = -1;
+};
+
+// Processes the current voxel's list with the kGroup lanes of the ray's group;
+// true when the ray is finished (opaque: a hit in this voxel; transparent:
+// transmittance below tau).  Every lane of the group returns the same result.
+template <bool kStats>
+__device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, const Walk &w, Shade &sh, Counters &cn,
+                                            int lane) {
+    const int gl = lane & (kGroup - 1);
+    const float3 D = make_float3(r.D[0], r.D[1], r.D[2]);
+    const float3 ro = make_float3(fmaf(w.tcur, D.x, r.O[0] - (float)w.v[0]), fmaf(w.tcur, D.y, r.O[1] - (float)w.v[1]),
+                                  fmaf(w.tcur, D.z, r.O[2] - (float)w.v[2]));
+    const float tl = w.texit - w.tcur;
+    const int cx = w.v[0], cy = w.v[1], cz = w.v[2];
+    const float radius = a.p.radius;
+    if (kStats && gl == 0) {
+        ++cn.list;
+        a.stat_vox[w.vi] = 1;
+    }
+    if (a.p.mode == VRT_TRACE_OPAQUE) {
+        unsigned long long best = kNoKey;
+        for_each_entry<kStats>(a, w, gl, cn, [&](uint32_t id, const VRec &A, const VRec &B) {
+            float s;
+            if (voxel_hit(A, B, radius, ro, D, cx, cy, cz, tl, s)) {
+                const unsigned long long key = hit_key(s, id);
+                best = key < best ? key : best;
+            }
+        });
+        best = group_min(best);
+        if (best == kNoKey) return false;
+        const uint32_t id = (uint32_t)best;
+        sh.first = (int)id;
+        sh.first_t = w.tcur + __uint_as_float((uint32_t)(best >> 32));
+        sh.col = seg_colour(a.vrec[id], a.vrec[id + 1]);
+        sh.T = 0.0f;
+        return true;
+    }
+    // Transparent: each lane keeps its kLaneKeys smallest accepted keys above
+    // the threshold; the group composites the smallest head key of all lanes
+    // while it is safe, i.e. while no lane that dropped keys has run dry;
+    // otherwise it rescans above the last composited key.
+    unsigned long long thr = 0ull;
+    bool have_thr = false;
+    for (;;) {
+        unsigned long long kk[kLaneKeys];
+#pragma unroll
+        for (int j = 0; j < kLaneKeys; ++j) kk[j] = kNoKey;
+        int nacc = 0;
+        if (kStats && gl == 0) ++cn.pass;
+        for_each_entry<kStats>(a, w, gl, cn, [&](uint32_t id, const VRec &A, const VRec &B) {
+            float s;
+            if (!voxel_hit(A, B, radius, ro, D, cx, cy, cz, tl, s)) return;
+            unsigned long long key = hit_key(s, id);
+            if (have_thr && !(key > thr)) return;
+            ++nacc;
+#pragma unroll
+            for (int j = 0; j < kLaneKeys; ++j) {  // sorted insert, the largest falls off the end
+                const unsigned long long lo = key < kk[j] ? key : kk[j];
+                key = key < kk[j] ? kk[j] : key;
+                kk[j] = lo;
+            }
+        });
+        const bool dropped = nacc > kLaneKeys;
+        bool rescan = false;
+        for (;;) {
+            if (group_any(dropped && kk[0] == kNoKey, lane)) {
+                rescan = true;
+                break;
+            }
+            const unsigned long long m = group_min(kk[0]);
+            if (m == kNoKey) break;
+            if (kk[0] == m) {  // keys are unique (one per segment), so exactly one lane pops
+#pragma unroll
+                for (int j = 0; j + 1 < kLaneKeys; ++j) kk[j] = kk[j + 1];
+                kk[kLaneKeys - 1] = kNoKey;
+            }
+            const uint32_t id = (uint32_t)m;
+            if (sh.first < 0) {
+                sh.first = (int)id;
+                sh.first_t = w.tcur + __uint_as_float((uint32_t)(m >> 32));
+            }
+            const float3 c = seg_colour(a.vrec[id], a.vrec[id + 1]);
+            const float wgt = sh.T * a.p.alpha;
+            sh.col.x += wgt * c.x;
+            sh.col.y += wgt * c.y;
+            sh.col.z += wgt * c.z;
+            sh.T *= (1.0f - a.p.alpha);
+            thr = m;
+            have_thr = true;
+            if (sh.T < a.p.tau) return true;
+        }
+        if (!rescan) return false;
+    }
+}
+
+__device__ __forceinline__ void write_pixel(const TraceArgs &a, int64_t pixel, const Shade &sh) {
     float4 out;
-    if (opaque) out = first >= 0 ? make_float4(col.x, col.y, col.z, 1.0f) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    else out = make_float4(col.x, col.y, col.z, 1.0f - T);
+    if (a.p.mode == VRT_TRACE_OPAQUE)
+        out = sh.first >= 0 ? make_float4(sh.col.x, sh.col.y, sh.col.z, 1.0f) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    else
+        out = make_float4(sh.col.x, sh.col.y, sh.col.z, 1.0f - sh.T);
     reinterpret_cast<float4 *>(a.rgba)[pixel] = out;
-    if (a.depth) a.depth[pixel] = first >= 0 ? first_t * a.p.voxel_size : INFINITY;
-    if (a.first_id) a.first_id[pixel] = first;
+    if (a.depth) a.depth[pixel] = sh.first >= 0 ? sh.first_t * a.p.voxel_size : INFINITY;
+    if (a.first_id) a.first_id[pixel] = sh.first;
+}
+
+// Adds the wave's counters to the statistics (per-ray test counts are summed
+// over the ray's group before the maximum is taken).
+template <bool kStats>
+__device__ __forceinline__ void flush_counters(const TraceArgs &a, const Counters &cn, bool hit, int lane, int group) {
+    if (!kStats) return;
+    unsigned long long v[7] = {hit ? 1ull : 0ull, cn.skip64, cn.skip8, cn.vox, cn.list, cn.test, cn.pass};
+    for (int k = 0; k < 7; ++k) {
+        unsigned long long x = v[k];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (lane == 0 && x) atomicAdd(&a.stat_acc[k], x);
+    }
+    unsigned long long mx = cn.test;
+    for (int o = group / 2; o > 0; o >>= 1) mx += __shfl_xor(mx, o, 64);
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(mx, o, 64);
+        mx = y > mx ? y : mx;
+    }
+    if (lane == 0 && mx) atomicMax(&a.stat_acc[7], mx);
+}
+
+__global__ void k_trace_begin(DevStatus *st) { st->n_queue = 0; }
+
+// Phase 1, one thread per pixel (a 64-lane wavefront covers an 8x8 tile):
+// primary ray, clip to the box of visible bricks, march through empty cells to
+// the first visible voxel with a list.  Rays that reach one are appended to the
+// queue (wave-aggregated); the others are written as misses.
+template <bool kStats>
+__global__ void __launch_bounds__(256) k_trace_march(TraceArgs a) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int px = blockIdx.x * 16 + (wv & 1) * 8 + (lane & 7);
+    const int py = blockIdx.y * 16 + (wv >> 1) * 8 + (lane >> 3);
+    const bool live = px < a.p.W && py < a.p.H;
+    const float3 D = primary_dir(a.p, live ? px : 0, live ? py : 0);
+    const Ray r = make_ray(a.p, D);
+    Counters cn;
+    Walk w;
+    int vb[6];
+    bool found = false;
+    if (live && clip_visible(a, r, w.tcur, w.tout, vb)) {
+        for (int k = 0; k < 3; ++k) {
+            const int vk = (int)floorf(fmaf(w.tcur, r.D[k], r.O[k]));
+            const int lo = 8 * vb[k], hi = 8 * vb[3 + k] + 7;
+            w.v[k] = vk < lo ? lo : (vk > hi ? hi : vk);
+        }
+        w.fresh = true;
+        found = march<kStats>(a, r, w, cn);
+    }
+    const unsigned long long mask = __ballot(found);
+    if (mask) {
+        const int leader = __ffsll((long long)mask) - 1;
+        unsigned base = 0;
+        if (lane == leader) base = atomicAdd(&a.st->n_queue, (unsigned)__popcll(mask));
+        base = __shfl(base, leader, 64);
+        if (found) {
+            const unsigned pos = base + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+            const uint32_t pix = (uint32_t)(py * a.p.W + px);
+            const uint32_t vp = (uint32_t)w.v[0] | ((uint32_t)w.v[1] << 10) | ((uint32_t)w.v[2] << 20);
+            a.queue[pos] = make_uint4(pix, vp, __float_as_uint(w.tcur), __float_as_uint(w.tout));
+        }
+    }
+    flush_counters<kStats>(a, cn, false, lane, 1);
+    if (live && !found) write_pixel(a, (int64_t)py * a.p.W + px, Shade());
+}
+
+// Phase 2, one kGroup-lane group per queued ray: lists, capsule tests and
+// compositing, continuing the walk until the ray is finished.  All lanes of a
+// group follow the same walk; list entries are split across them.
+template <bool kStats>
+__global__ void __launch_bounds__(256) k_trace_shade(TraceArgs a) {
+    const int lane = threadIdx.x & 63;
+    const unsigned n = a.st->n_queue;
+    const unsigned ngroups = gridDim.x * (blockDim.x / kGroup);
+    const unsigned grp = blockIdx.x * (blockDim.x / kGroup) + threadIdx.x / kGroup;
+    // every group runs the same number of rounds so counters can be reduced per wave
+    const unsigned rounds = (n + ngroups - 1) / ngroups;
+    for (unsigned rd = 0; rd < rounds; ++rd) {
+        const unsigned i = rd * ngroups + grp;
+        Counters cn;
+        Shade sh;
+        if (i < n) {
+            const uint4 q = a.queue[i];
+            const int px = (int)(q.x % (uint32_t)a.p.W), py = (int)(q.x / (uint32_t)a.p.W);
+            const float3 D = primary_dir(a.p, px, py);
+            const Ray r = make_ray(a.p, D);
+            Walk w;
+            w.v[0] = (int)(q.y & 1023u);
+            w.v[1] = (int)((q.y >> 10) & 1023u);
+            w.v[2] = (int)((q.y >> 20) & 1023u);
+            w.tcur = __uint_as_float(q.z);
+            w.tout = __uint_as_float(q.w);
+            w.fresh = true;
+            Counters walk_cn;  // walk counters once per ray
+            bool have = march<kStats>(a, r, w, walk_cn);  // recomputes the exit data of the queued voxel
+            while (have) {
+                if (shade_voxel<kStats>(a, r, w, sh, cn, lane)) break;
+                if (!step_voxel(a, r, w)) break;
+                have = march<kStats>(a, r, w, walk_cn);
+            }
+            if ((lane & (kGroup - 1)) == 0) {
+                write_pixel(a, (int64_t)q.x, sh);
+                cn.skip64 += walk_cn.skip64;
+                cn.skip8 += walk_cn.skip8;
+                cn.vox += walk_cn.vox;
+            }
+        }
+        flush_counters<kStats>(a, cn, sh.first >= 0 && (lane & (kGroup - 1)) == 0, lane, kGroup);
+    }
 }
 
 __global__ void k_debug_rays(TraceParams p, const int64_t *__restrict__ pix, int64_t n, float *__restrict__ dirs) {
@@ -316,28 +598,96 @@ __global__ void k_debug_rays(TraceParams p, const int64_t *__restrict__ pix, int
     dirs[3 * i + 2] = d.z;
 }
 
+// Clears the statistics marks of the occupied bricks, the segments and the counters.
+__global__ void k_stat_clear(const int32_t *__restrict__ list, const DevStatus *__restrict__ st, int64_t nv,
+                             uint8_t *__restrict__ vox, uint8_t *__restrict__ seg, unsigned long long *__restrict__ acc) {
+    const unsigned nb = st->n_bricks;
+    for (unsigned sl = blockIdx.x; sl < nb; sl += gridDim.x) {
+        const int64_t b = list[sl];
+        for (int t = threadIdx.x; t < kBrickVox; t += blockDim.x) vox[b * kBrickVox + t] = 0;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x)
+        seg[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 16) acc[threadIdx.x] = 0;
+}
+
+// Distinct voxels read, their list lengths, and distinct segments tested.
+__global__ void k_stat_reduce(const int32_t *__restrict__ list, const DevStatus *__restrict__ st, int64_t nv,
+                              const uint8_t *__restrict__ vox, const uint64_t *__restrict__ cell,
+                              const uint8_t *__restrict__ seg, unsigned long long *__restrict__ acc) {
+    unsigned long long nvx = 0, nent = 0, nseg = 0;
+    const unsigned nb = st->n_bricks;
+    for (unsigned sl = blockIdx.x; sl < nb; sl += gridDim.x) {
+        const int64_t b = list[sl];
+        for (int t = threadIdx.x; t < kBrickVox; t += blockDim.x)
+            if (vox[b * kBrickVox + t]) {
+                ++nvx;
+                nent += cell[b * kBrickVox + t] >> 32;
+            }
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x)
+        nseg += seg[i];
+    unsigned long long v[3] = {nvx, nent, nseg};
+    for (int k = 0; k < 3; ++k) {
+        unsigned long long x = v[k];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if ((threadIdx.x & 63) == 0 && x) atomicAdd(&acc[8 + k], x);
+    }
+}
+
 }  // namespace
 
-hipError_t launch_trace(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st) {
+static TraceArgs trace_args(vrt_ctx *c, const TraceParams &p, const vrt_image *img) {
     TraceArgs a;
     a.p = p;
     for (int k = 0; k < 3; ++k) {
         a.G[k] = c->dims[k];
         a.nb[k] = c->dims[k] / 8;
     }
-    a.vis0 = c->a.vis0;
     a.vis3 = c->a.vis3;
-    a.words = c->a.words;
-    a.cursor = c->a.cursor;
+    a.vis6 = nullptr;
+    a.n6[0] = a.n6[1] = a.n6[2] = 0;
+    if (c->n_levels > 6) {
+        const Level &l6 = c->levels[6];
+        a.vis6 = c->a.vis_hi + l6.offset;
+        for (int k = 0; k < 3; ++k) a.n6[k] = l6.dims[k];
+    }
+    a.cell = c->a.cell;
+    a.st = c->a.status;
     a.ids = c->a.ids;
     a.vrec = c->a.vrec;
     a.nv = c->n_vertices;
     a.capacity = c->desc.max_fragments;
+    a.queue = c->a.queue;
     a.rgba = img->rgba;
     a.depth = img->depth;
     a.first_id = img->first_id;
+    a.stat_vox = c->a.stat_vox;
+    a.stat_seg = c->a.stat_seg;
+    a.stat_acc = c->a.stat_acc;
+    return a;
+}
+
+static constexpr unsigned kShadeBlocks = 4096;
+
+hipError_t launch_trace(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st) {
+    TraceArgs a = trace_args(c, p, img);
     dim3 grid((p.W + 15) / 16, (p.H + 15) / 16);
-    VRT_LAUNCH(c, "k_trace", st, k_trace<<<grid, 256, 0, st>>>(a));
+    VRT_LAUNCH(c, "k_trace_begin", st, k_trace_begin<<<1, 1, 0, st>>>(a.st));
+    VRT_LAUNCH(c, "k_trace_march", st, k_trace_march<false><<<grid, 256, 0, st>>>(a));
+    VRT_LAUNCH(c, "k_trace_shade", st, k_trace_shade<false><<<kShadeBlocks, 256, 0, st>>>(a));
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_stats(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st) {
+    TraceArgs a = trace_args(c, p, img);
+    k_stat_clear<<<1024, 256, 0, st>>>(c->a.brick_list, c->a.status, c->n_vertices, a.stat_vox, a.stat_seg, a.stat_acc);
+    dim3 grid((p.W + 15) / 16, (p.H + 15) / 16);
+    k_trace_begin<<<1, 1, 0, st>>>(a.st);
+    k_trace_march<true><<<grid, 256, 0, st>>>(a);
+    k_trace_shade<true><<<kShadeBlocks, 256, 0, st>>>(a);
+    k_stat_reduce<<<1024, 256, 0, st>>>(c->a.brick_list, c->a.status, c->n_vertices, a.stat_vox, a.cell, a.stat_seg,
+                                        a.stat_acc);
     return hipGetLastError();
 }
 

@@ -1,4 +1,6 @@
 // vrt_voxelize.hip -- Section 3.1: ingest, voxelization pass 1 and the occupancy pyramid.
+#include <climits>
+
 #include "vrt_internal.h"
 
 namespace vrt {
@@ -15,10 +17,22 @@ __global__ void k_clear_prev(uint32_t *__restrict__ words, const int32_t *__rest
     }
 }
 
-__global__ void k_reset(uint16_t *__restrict__ occ3, int64_t nbricks, DevStatus *__restrict__ st) {
+// Clears the per-frame brick-level state: level-3 occupancy, blocking flags
+// of bricks and 64^3 cells, the blocking box and the frame counters.
+__global__ void k_reset(uint16_t *__restrict__ occ3, uint8_t *__restrict__ brick_blk, int64_t nbricks,
+                        uint8_t *__restrict__ super_blk, int64_t nsupers, DevStatus *__restrict__ st) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nbricks) occ3[i] = 0;
-    if (i == 0) st->n_fragments = 0;
+    if (i < nbricks) {
+        occ3[i] = 0;
+        brick_blk[i] = 0;
+    }
+    if (i < nsupers) super_blk[i] = 0;
+    if (i == 0) {
+        st->n_fragments = 0;
+        st->n_occ = 0;
+        st->bbox[0] = st->bbox[1] = st->bbox[2] = INT_MAX;
+        st->bbox[3] = st->bbox[4] = st->bbox[5] = INT_MIN;
+    }
 }
 
 // fixed-point coordinate: rint((x - origin) * s) as two binary32 operations
@@ -221,22 +235,39 @@ __global__ void __launch_bounds__(1024) k_brick_compact(uint8_t *__restrict__ fl
 // at 1.0; a voxel with 256 or more fragments is full) and the in-brick mips
 // 1..3, each parent floor((sum of 8 children + 4) / 8).
 __global__ void __launch_bounds__(512) k_occ_brick(const uint32_t *__restrict__ words,
-                                                   const int32_t *__restrict__ list, const DevStatus *__restrict__ st,
+                                                   const int32_t *__restrict__ list, DevStatus *__restrict__ st,
                                                    uint16_t *__restrict__ occ0, uint16_t *__restrict__ occ1,
-                                                   uint16_t *__restrict__ occ2, uint16_t *__restrict__ occ3) {
+                                                   uint16_t *__restrict__ occ2, uint16_t *__restrict__ occ3,
+                                                   uint32_t *__restrict__ occ_list) {
     __shared__ uint16_t s0[512];
     __shared__ uint16_t s1[64];
     __shared__ uint16_t s2[8];
+    __shared__ unsigned wcnt[8];
+    __shared__ unsigned base;
     const unsigned nbk = st->n_bricks;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     for (unsigned sl = blockIdx.x; sl < nbk; sl += gridDim.x) {
         int64_t b = list[sl];
-        uint32_t w = words[b * kBrickVox + t];
-        uint32_t cnt = w & 0xFFFFu, sum = w >> 16;
+        uint32_t wd = words[b * kBrickVox + t];
+        uint32_t cnt = wd & 0xFFFFu, sum = wd >> 16;
         uint16_t o = (uint16_t)(cnt >= 256u ? 256u : (sum > 256u ? 256u : sum));
         occ0[b * kBrickVox + t] = o;
         s0[t] = o;
+        // append the brick's occupied voxels (x-fastest inside the brick) to the occupied list
+        const unsigned long long m = __ballot(cnt != 0u);
+        if (lane == 0) wcnt[w] = (unsigned)__popcll(m);
         __syncthreads();
+        if (t == 0) {
+            unsigned tot = 0;
+            for (int k = 0; k < 8; ++k) tot += wcnt[k];
+            base = tot ? atomicAdd(&st->n_occ, tot) : 0u;
+        }
+        __syncthreads();
+        if (cnt) {
+            unsigned pos = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+            for (int k = 0; k < w; ++k) pos += wcnt[k];
+            occ_list[pos] = (uint32_t)(b * kBrickVox + t);
+        }
         if (t < 64) {
             int X = t & 3, Y = (t >> 2) & 3, Z = t >> 4;
             unsigned s = 0;
@@ -266,6 +297,65 @@ __global__ void __launch_bounds__(512) k_occ_brick(const uint32_t *__restrict__ 
     }
 }
 
+struct GridArgs {
+    int G[3];
+    int nb[3];  // bricks per axis
+    int ns[3];  // 64^3 cells per axis
+};
+
+// Level-0 occupancy of any voxel (0 outside the grid and in empty bricks).
+__device__ __forceinline__ unsigned occ_at(const GridArgs &g, const uint16_t *__restrict__ occ0,
+                                           const int32_t *__restrict__ slot, int x, int y, int z) {
+    if (x < 0 || y < 0 || z < 0 || x >= g.G[0] || y >= g.G[1] || z >= g.G[2]) return 0;
+    int64_t b = brick_index_of(x, y, z, g.nb[0], g.nb[1]);
+    if (slot[b] < 0) return 0;
+    return occ0[b * kBrickVox + local_of(x, y, z)];
+}
+
+// Erosion (Section 3.2): the minimum occupancy over the voxel and its 6 face
+// neighbours; the voxel blocks culling rays when that minimum is full.  Also
+// marks bricks and 64^3 cells holding a blocking voxel and the blocking box.
+__global__ void __launch_bounds__(512) k_erode(GridArgs g, const uint16_t *__restrict__ occ0,
+                                               const int32_t *__restrict__ list, const int32_t *__restrict__ slot,
+                                               DevStatus *__restrict__ st, uint8_t *__restrict__ blk,
+                                               uint8_t *__restrict__ brick_blk, uint8_t *__restrict__ super_blk) {
+    __shared__ int bb[6];
+    const unsigned nbk = st->n_bricks;
+    const int t = threadIdx.x;
+    for (unsigned sl = blockIdx.x; sl < nbk; sl += gridDim.x) {
+        int64_t b = list[sl];
+        if (t < 3) bb[t] = INT_MAX;
+        else if (t < 6) bb[t] = INT_MIN;
+        __syncthreads();
+        int bx = (int)(b % g.nb[0]), by = (int)((b / g.nb[0]) % g.nb[1]), bz = (int)(b / ((int64_t)g.nb[0] * g.nb[1]));
+        int x = bx * 8 + (t & 7), y = by * 8 + ((t >> 3) & 7), z = bz * 8 + (t >> 6);
+        unsigned e = occ0[b * kBrickVox + t];
+        if (e >= 256u) {
+            unsigned n;
+            n = occ_at(g, occ0, slot, x - 1, y, z); e = n < e ? n : e;
+            n = occ_at(g, occ0, slot, x + 1, y, z); e = n < e ? n : e;
+            n = occ_at(g, occ0, slot, x, y - 1, z); e = n < e ? n : e;
+            n = occ_at(g, occ0, slot, x, y + 1, z); e = n < e ? n : e;
+            n = occ_at(g, occ0, slot, x, y, z - 1); e = n < e ? n : e;
+            n = occ_at(g, occ0, slot, x, y, z + 1); e = n < e ? n : e;
+        }
+        bool blocking = e >= 256u;
+        blk[b * kBrickVox + t] = blocking ? 1 : 0;
+        if (blocking) {
+            atomicMin(&bb[0], x); atomicMin(&bb[1], y); atomicMin(&bb[2], z);
+            atomicMax(&bb[3], x); atomicMax(&bb[4], y); atomicMax(&bb[5], z);
+        }
+        int any = __syncthreads_or(blocking ? 1 : 0);
+        if (t == 0 && any) {
+            brick_blk[b] = 1;
+            super_blk[((int64_t)(bz >> 3) * g.ns[1] + (by >> 3)) * g.ns[0] + (bx >> 3)] = 1;
+            atomicMin(&st->bbox[0], bb[0]); atomicMin(&st->bbox[1], bb[1]); atomicMin(&st->bbox[2], bb[2]);
+            atomicMax(&st->bbox[3], bb[3]); atomicMax(&st->bbox[4], bb[4]); atomicMax(&st->bbox[5], bb[5]);
+        }
+        __syncthreads();
+    }
+}
+
 // Averaging step on dense grids (levels >= 3): parent = floor((sum of the
 // children inside the grid + 4) / 8), parent dims = ceil(child dims / 2).
 __global__ void k_mip_avg(const uint16_t *__restrict__ src, int sx, int sy, int sz, uint16_t *__restrict__ dst, int dx,
@@ -287,7 +377,16 @@ hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *L, float s_q, hipStream_
     Arenas &A = c->a;
     const int64_t nb = (int64_t)(c->dims[0] / 8) * (c->dims[1] / 8) * (c->dims[2] / 8);
     VRT_LAUNCH(c, "k_clear_prev", st, k_clear_prev<<<2048, 128, 0, st>>>(A.words, A.brick_list, A.status));
-    VRT_LAUNCH(c, "k_reset", st, k_reset<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(A.occ3, nb, A.status));
+    GridArgs g;
+    for (int k = 0; k < 3; ++k) {
+        g.G[k] = c->dims[k];
+        g.nb[k] = c->dims[k] / 8;
+        g.ns[k] = (c->dims[k] + 63) / 64;
+    }
+    const int64_t ns = (int64_t)g.ns[0] * g.ns[1] * g.ns[2];
+    VRT_LAUNCH(c, "k_reset", st,
+               k_reset<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(A.occ3, A.brick_blk, nb, A.super_blk, ns,
+                                                                     A.status));
     IngestArgs ia;
     ia.xyz = L->xyz;
     ia.off = L->poly_offsets;
@@ -311,7 +410,12 @@ hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *L, float s_q, hipStream_
     ca.brick_flag = A.brick_flag;
     VRT_LAUNCH(c, "k_vox_count", st, k_vox_count<<<(unsigned)((L->n_vertices + 255) / 256), 256, 0, st>>>(ca, A.status));
     VRT_LAUNCH(c, "k_brick_compact", st, k_brick_compact<<<1, 1024, 0, st>>>(A.brick_flag, nb, A.brick_list, A.brick_slot, A.status));
-    VRT_LAUNCH(c, "k_occ_brick", st, k_occ_brick<<<4096, 512, 0, st>>>(A.words, A.brick_list, A.status, A.occ0, A.occ1, A.occ2, A.occ3));
+    VRT_LAUNCH(c, "k_occ_brick", st,
+               k_occ_brick<<<4096, 512, 0, st>>>(A.words, A.brick_list, A.status, A.occ0, A.occ1, A.occ2, A.occ3,
+                                                 A.occ_list));
+    VRT_LAUNCH(c, "k_erode", st,
+               k_erode<<<4096, 512, 0, st>>>(g, A.occ0, A.brick_list, A.brick_slot, A.status, A.blk, A.brick_blk,
+                                             A.super_blk));
     // levels >= 4 from the dense level 3
     const uint16_t *src = A.occ3;
     int sx = c->dims[0] / 8, sy = c->dims[1] / 8, sz = c->dims[2] / 8;

@@ -23,7 +23,7 @@ TRACE_OPAQUE, TRACE_TRANSPARENT = 0, 1
 
 EXPORTED = ["vrt_create", "vrt_destroy", "vrt_voxelize", "vrt_cull", "vrt_trace", "vrt_frame_status",
             "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_last_hip_error", "vrt_status_string",
-            "vrt_profile_enable", "vrt_profile_read"]
+            "vrt_profile_enable", "vrt_profile_read", "vrt_trace_stats_run"]
 
 
 class VrtError(RuntimeError):
@@ -34,7 +34,7 @@ class VrtError(RuntimeError):
 
 class vrt_desc(C.Structure):
     _fields_ = [("max_vertices", C.c_int64), ("max_fragments", C.c_int64), ("max_dim", C.c_int32),
-                ("device", C.c_int32)]
+                ("device", C.c_int32), ("max_pixels", C.c_int64)]
 
 
 class vrt_lines(C.Structure):
@@ -76,6 +76,12 @@ class vrt_kernel_time(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
 
+class vrt_trace_stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ["rays", "rays_hit", "cell_skips_64", "cell_skips_8", "voxel_steps",
+                                         "list_visits", "capsule_tests", "kbuffer_passes", "distinct_list_voxels",
+                                         "distinct_list_entries", "distinct_segments", "max_tests_per_ray"]]
+
+
 _lib = None
 
 
@@ -97,13 +103,14 @@ def load():
         L.vrt_debug_rays.argtypes = [P, C.POINTER(vrt_camera), P, C.c_int64, P, P]
         L.vrt_copy_to_host.argtypes = [P, P, C.c_int64]
         L.vrt_profile_enable.argtypes = [P, C.c_int32]
+        L.vrt_trace_stats_run.argtypes = [P, C.POINTER(vrt_camera), C.POINTER(vrt_image), C.POINTER(vrt_trace_stats), P]
         L.vrt_profile_read.argtypes = [P, C.POINTER(vrt_kernel_time), C.c_int32, C.POINTER(C.c_int32)]
         L.vrt_last_hip_error.restype = C.c_int32
         L.vrt_status_string.argtypes = [C.c_int32]
         L.vrt_status_string.restype = C.c_char_p
         for name in ["vrt_create", "vrt_destroy", "vrt_voxelize", "vrt_cull", "vrt_trace", "vrt_frame_status",
                      "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_profile_enable",
-                     "vrt_profile_read"]:
+                     "vrt_profile_read", "vrt_trace_stats_run"]:
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -156,9 +163,9 @@ def make_camera(eye, target, up, fovy_deg, width, height, mode=TRACE_OPAQUE, alp
 class Context:
     """One voxel ray tracing context: arenas sized at creation, reused per frame."""
 
-    def __init__(self, max_vertices, max_fragments, max_dim, device=0):
+    def __init__(self, max_vertices, max_fragments, max_dim, device=0, max_pixels=1920 * 1080):
         L = load()
-        d = vrt_desc(int(max_vertices), int(max_fragments), int(max_dim), int(device))
+        d = vrt_desc(int(max_vertices), int(max_fragments), int(max_dim), int(device), int(max_pixels))
         h = C.c_void_p()
         _check(L.vrt_create(C.byref(d), C.byref(h)), "vrt_create")
         self._h = h
@@ -189,6 +196,14 @@ class Context:
     def trace(self, camera: vrt_camera, rgba, depth=None, first_id=None, stream=None):
         img = vrt_image(_ptr(rgba), _ptr(depth), _ptr(first_id))
         _check(load().vrt_trace(self._h, C.byref(camera), C.byref(img), _stream_ptr(stream)), "vrt_trace")
+
+    def trace_stats(self, camera: vrt_camera, rgba, depth=None, first_id=None, stream=None):
+        """Work counters of one trace (synchronizes); also writes the image."""
+        img = vrt_image(_ptr(rgba), _ptr(depth), _ptr(first_id))
+        st = vrt_trace_stats()
+        _check(load().vrt_trace_stats_run(self._h, C.byref(camera), C.byref(img), C.byref(st), _stream_ptr(stream)),
+               "vrt_trace_stats_run")
+        return {n: int(getattr(st, n)) for n, _ in vrt_trace_stats._fields_}
 
     def debug_rays(self, camera: vrt_camera, pixels, dirs, stream=None):
         _check(load().vrt_debug_rays(self._h, C.byref(camera), _ptr(pixels), int(pixels.shape[0]), _ptr(dirs),
