@@ -56,6 +56,7 @@ def main():
     ap.add_argument("--workload", default="bundles_5m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-pixels", type=int, default=20000)
+    ap.add_argument("--no-fp16", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path has no multi-GPU leg)",
@@ -248,6 +249,74 @@ def main():
                 "cull_alpha": fa.times["cull"], "lists_alpha": fa.times["lists"]}}.items()},
         }
     ctx.close()
+
+    # FP16 precision form: same frame, the tracer reads brick-relative binary16 records
+    if not args.no_fp16:
+        ctx16 = vrt.Context(max_vertices=ls.n_vertices, max_fragments=cap, max_dim=max(ls.dims), device=0,
+                            form=vrt.FORM_FP16)
+        rgba16 = torch.empty_like(rgba)
+        depth16 = torch.empty_like(depth)
+        fid16 = torch.empty_like(fid)
+        plain_img = {}
+
+        def frame16(stage_events=False):
+            if stage_events:
+                ev[0].record()
+            ctx16.voxelize(xyz, off, ls.radius, ls.origin, ls.voxel_size, ls.dims)
+            if stage_events:
+                ev[1].record()
+            ctx16.cull(eye, opq.cull_mode, opq.alpha, opq.tau)
+            if stage_events:
+                ev[2].record()
+            ctx16.trace(cam_o, rgba16, depth16, fid16)
+            if stage_events:
+                ev[3].record()
+            ctx16.cull(eye, alp.cull_mode, alp.alpha, alp.tau)
+            if stage_events:
+                ev[4].record()
+            ctx16.trace(cam_a, rgba16, depth16, fid16)
+            if stage_events:
+                ev[5].record()
+
+        for _ in range(args.warmup):
+            frame16()
+        torch.cuda.synchronize()
+        s16 = np.zeros(5)
+        for _ in range(args.steps):
+            frame16(stage_events=True)
+            torch.cuda.synchronize()
+            s16 += np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(5)])
+        s16 /= args.steps
+        t_start.record()
+        for _ in range(args.steps):
+            frame16()
+        t_end.record()
+        torch.cuda.synchronize()
+        f16 = t_start.elapsed_time(t_end) / args.steps
+        if ctx16.frame_status()["device_status"] != 0:
+            raise SystemExit("device status error in the FP16 frames")
+        # accuracy against the plain form on the full image (same rays)
+        agree = {}
+        for label, c_, cm in (("opaque", opq, cam_o), ("alpha", alp, cam_a)):
+            ctx16.cull(eye, c_.cull_mode, c_.alpha, c_.tau)
+            ctx16.trace(cm, rgba16, depth16, fid16)
+            ref = vrt.Context(max_vertices=ls.n_vertices, max_fragments=cap, max_dim=max(ls.dims), device=0)
+            ref.voxelize(xyz, off, ls.radius, ls.origin, ls.voxel_size, ls.dims)
+            ref.cull(eye, c_.cull_mode, c_.alpha, c_.tau)
+            ref.trace(cm, rgba, depth, fid)
+            torch.cuda.synchronize()
+            ref.close()
+            d = (rgba16 - rgba).abs().view(-1, 4).amax(dim=1)
+            agree[label] = {"first_id_equal": float((fid16 == fid).float().mean()),
+                            "colour_diff_max": float(d.max()), "colour_diff_mean": float(d.mean()),
+                            "pixels_diff_gt_1e-4": float((d > 1e-4).float().mean())}
+        ctx16.close()
+        out["fp16"] = {"ms_per_step": round(f16, 4), "speedup_vs_plain": round(frame_ms / f16, 4),
+                       "value": round(2 * P / (f16 * 1e-3) / 1e6, 3),
+                       "stage_ms": {k: round(v, 4) for k, v in zip(
+                           ["voxelize", "cull_opaque", "trace_opaque", "cull_alpha", "trace_alpha"], s16)},
+                       "trace_speedup_vs_plain": round((stage_ms[2] + stage_ms[4]) / (s16[2] + s16[4]), 4),
+                       "agreement_with_plain": agree}
     print(json.dumps(out))
 
 

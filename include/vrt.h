@@ -60,6 +60,9 @@ typedef int32_t vrt_status;
 #define VRT_TRACE_OPAQUE 0
 #define VRT_TRACE_TRANSPARENT 1
 
+#define VRT_FORM_PLAIN 0 /* the tracer reads the int32 vertex records */
+#define VRT_FORM_FP16 1  /* the tracer reads per-segment FP16 records (brick-relative endpoints) */
+
 typedef struct vrt_ctx vrt_ctx;
 
 /* Capacities fixed at creation (Section 3.3: the lists are sized by the scan,
@@ -70,6 +73,13 @@ typedef struct {
     int32_t max_dim;       /* largest grid dimension; multiple of 8, <= 1024 */
     int32_t device;        /* HIP device ordinal the arenas live on */
     int64_t max_pixels;    /* largest width * height accepted by vrt_trace */
+    int32_t form;          /* VRT_FORM_PLAIN or VRT_FORM_FP16: the segment records the tracer reads.  FP16:
+                              each segment stores its endpoints as binary16 offsets (voxel units) from the centre
+                              of the 8^3 brick holding its midpoint, binary16 clip normals and int16 brick
+                              coordinates (32 B per segment instead of two 32-B vertex records); intersection
+                              and compositing stay binary32 and voxel membership stays exact int32.  Offsets
+                              are exact while |offset| < 8 voxels. */
+    int32_t reserved;
 } vrt_desc;
 
 /* A set of polylines with one radius (Section 3.1: capsules of uniform radius
@@ -172,6 +182,22 @@ vrt_status vrt_cull(vrt_ctx *ctx, const vrt_view *view, void *stream);
  * preceding vrt_cull.  The ray origin is cam->eye quantized like the
  * vertices; directions are a fixed binary32 function of the camera. */
 vrt_status vrt_trace(vrt_ctx *ctx, const vrt_camera *cam, const vrt_image *out, void *stream);
+
+/* Per-frame graph (spec batching pattern for dynamic line sets): captures
+ * one frame -- vrt_voxelize, then for each pass i vrt_cull(views[i]) and
+ * vrt_trace(cams[i], imgs[i]) -- into a HIP graph on a private capture stream.
+ * Each vrt_graph_launch replays the whole frame on `stream` with no host work;
+ * it reads the vertex and offset buffers and writes the images at the
+ * addresses given here, so a dynamic line set updates those buffers in place
+ * between launches (same vertex and polyline counts).  The context must
+ * outlive the graph and must not be used by other calls while a replay runs.
+ * Errors: VRT_ERR_INVALID_ARG / VRT_ERR_RANGE as for the captured calls,
+ * VRT_ERR_HIP if capture or instantiation fails. */
+typedef struct vrt_graph vrt_graph;
+vrt_status vrt_graph_create(vrt_ctx *ctx, const vrt_lines *lines, const vrt_grid *grid, const vrt_view *views,
+                            const vrt_camera *cams, const vrt_image *imgs, int32_t n_passes, vrt_graph **out);
+vrt_status vrt_graph_launch(vrt_graph *g, void *stream);
+vrt_status vrt_graph_destroy(vrt_graph *g);
 
 /* Synchronizes the context's last stream, reads the device status word and
  * the frame totals, and clears the latched error. */

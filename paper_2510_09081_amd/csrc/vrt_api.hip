@@ -30,7 +30,7 @@ hipError_t alloc(T *&p, int64_t n) {
 void free_all(Arenas &a) {
     void *ptrs[] = {a.vrec, a.words, a.occ0, a.occ1, a.occ2, a.occ3, a.occ_hi, a.blk, a.brick_blk, a.super_blk,
                     a.occ_list, a.vis0,
-                    a.vis1, a.vis2,  a.vis3, a.vis_hi, a.cursor, a.cell, a.queue, a.ids, a.brick_flag, a.brick_list, a.brick_slot,
+                    a.vis1, a.vis2,  a.vis3, a.vis_hi, a.cursor, a.cell, a.queue, a.srec16, a.ids, a.brick_flag, a.brick_list, a.brick_slot,
                     a.brick_total, a.brick_base, a.status, a.stat_vox, a.stat_seg, a.stat_acc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -89,7 +89,8 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     *out = nullptr;
     if (desc->max_vertices < 2 || desc->max_fragments < 1 || desc->max_dim < 8 || desc->max_dim > 1024 ||
         desc->max_dim % 8 != 0 || desc->max_vertices > ((int64_t)1 << 31) || desc->max_fragments > 0xFFFFFFFFll ||
-        desc->max_pixels < 1 || desc->max_pixels > ((int64_t)1 << 31))
+        desc->max_pixels < 1 || desc->max_pixels > ((int64_t)1 << 31) ||
+        (desc->form != VRT_FORM_PLAIN && desc->form != VRT_FORM_FP16))
         return VRT_ERR_INVALID_ARG;
     int ndev = 0;
     VRT_HIP(hipGetDeviceCount(&ndev));
@@ -127,6 +128,7 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     ALLOC(a.cursor, mb * kBrickVox);
     ALLOC(a.cell, mb * kBrickVox);
     ALLOC(a.queue, desc->max_pixels);
+    if (desc->form == VRT_FORM_FP16) ALLOC(a.srec16, desc->max_vertices);
     ALLOC(a.ids, desc->max_fragments);
     ALLOC(a.brick_flag, mb);
     ALLOC(a.brick_list, mb);
@@ -450,6 +452,80 @@ vrt_status vrt_profile_read(vrt_ctx *c, vrt_kernel_time *out, int32_t max_record
     p.used = 0;
     p.overflow = false;
     return over ? VRT_ERR_CAPACITY : VRT_OK;
+}
+
+struct vrt_graph {
+    vrt_ctx *ctx;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+vrt_status vrt_graph_create(vrt_ctx *c, const vrt_lines *lines, const vrt_grid *grid, const vrt_view *views,
+                            const vrt_camera *cams, const vrt_image *imgs, int32_t n_passes, vrt_graph **out) {
+    if (!c || !lines || !grid || !out || n_passes < 0 || (n_passes > 0 && (!views || !cams || !imgs)))
+        return VRT_ERR_INVALID_ARG;
+    *out = nullptr;
+    VRT_HIP(hipSetDevice(c->desc.device));
+    const bool prof = c->prof.enabled;
+    c->prof.enabled = false;  // no event records inside the graph
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        c->prof.enabled = prof;
+        return hip_fail(e);
+    }
+    hipGraph_t graph = nullptr;
+    vrt_status st = VRT_OK;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = vrt_voxelize(c, lines, grid, cap);
+        for (int32_t i = 0; st == VRT_OK && i < n_passes; ++i) {
+            st = vrt_cull(c, &views[i], cap);
+            if (st == VRT_OK) st = vrt_trace(c, &cams[i], &imgs[i], cap);
+        }
+        hipError_t e2 = hipStreamEndCapture(cap, &graph);
+        if (e2 != hipSuccess && st == VRT_OK) st = hip_fail(e2);
+    } else {
+        st = hip_fail(e);
+    }
+    hipGraphExec_t exec = nullptr;
+    if (st == VRT_OK) {
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) st = hip_fail(e);
+    }
+    (void)hipStreamDestroy(cap);
+    c->prof.enabled = prof;
+    c->last_stream = nullptr;
+    if (st != VRT_OK) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    vrt_graph *g = new (std::nothrow) vrt_graph{c, graph, exec};
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return VRT_ERR_INVALID_ARG;
+    }
+    *out = g;
+    return VRT_OK;
+}
+
+vrt_status vrt_graph_launch(vrt_graph *g, void *stream) {
+    if (!g) return VRT_ERR_INVALID_ARG;
+    VRT_HIP(hipSetDevice(g->ctx->desc.device));
+    VRT_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    g->ctx->last_stream = (hipStream_t)stream;
+    return VRT_OK;
+}
+
+vrt_status vrt_graph_destroy(vrt_graph *g) {
+    if (!g) return VRT_ERR_INVALID_ARG;
+    (void)hipSetDevice(g->ctx->desc.device);
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return VRT_OK;
 }
 
 int32_t vrt_last_hip_error(void) { return g_last_hip; }

@@ -1,6 +1,7 @@
 // vrt_internal.h -- shared declarations of the HIP implementation (not part of the ABI).
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,6 +25,17 @@ struct __align__(16) VRec {
     float nx, ny, nz, pad;
 };
 constexpr int kSegValid = 1, kInterior = 2;
+
+// FP16-form segment record (32 B): endpoints as binary16 offsets (voxel units)
+// from the centre of brick (bx, by, bz), binary16 clip normals, flags bit 0:
+// interior A (clip with n0), bit 1: interior B (clip with n1).
+struct __align__(16) SRec16 {
+    __half a[3], b[3];
+    __half n0[3], n1[3];
+    short bx, by, bz;
+    unsigned short flags;
+};
+static_assert(sizeof(SRec16) == 32, "SRec16 is 32 bytes");
 
 struct DevStatus {
     unsigned int err;
@@ -56,6 +68,7 @@ struct Arenas {
     uint32_t *cursor = nullptr;     // [max_bricks * 512] list start, then end after pass 2
     uint64_t *cell = nullptr;       // [max_bricks * 512] list start (low 32) | visible count (high 32)
     uint4 *queue = nullptr;         // [max_pixels] rays that reached a list
+    SRec16 *srec16 = nullptr;       // [max_vertices] FP16-form segment records (FP16 form only)
     uint32_t *ids = nullptr;        // [max_fragments]
     uint8_t *brick_flag = nullptr;  // [max_bricks]
     int32_t *brick_list = nullptr;  // [max_bricks]

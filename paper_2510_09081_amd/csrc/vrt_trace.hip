@@ -91,6 +91,7 @@ struct TraceArgs {
     DevStatus *st;            // visible-brick box, ray-queue length
     const uint32_t *ids;
     const VRec *vrec;
+    const SRec16 *srec16;     // FP16 form only
     int64_t nv;               // vertices of the frame (ids must be < nv - 1)
     int64_t capacity;         // entries of ids
     uint4 *queue;             // rays that reached a list: pixel, packed voxel, t
@@ -106,31 +107,61 @@ struct Counters {
     unsigned long long skip64 = 0, skip8 = 0, vox = 0, list = 0, test = 0, pass = 0;
 };
 
+// A segment in the frame of voxel (cx, cy, cz): endpoints relative to the
+// voxel corner (voxel units), clip normals, and which ends are clipped.
+struct LocalSeg {
+    float3 pa, pb, n0, n1;
+    bool ia, ib;
+};
+
 __device__ __forceinline__ float3 rel(const VRec &v, int cx, int cy, int cz) {
     return make_float3((float)(v.x - cx * kQ) * (1.0f / kQ), (float)(v.y - cy * kQ) * (1.0f / kQ),
                        (float)(v.z - cz * kQ) * (1.0f / kQ));
 }
 
-// Accepted hit of segment (A, B) inside the current voxel: entry parameter s in
+// Plain form: from the two int32 vertex records (exact).
+__device__ __forceinline__ LocalSeg local_seg(const VRec &A, const VRec &B, int cx, int cy, int cz) {
+    LocalSeg s;
+    s.pa = rel(A, cx, cy, cz);
+    s.pb = rel(B, cx, cy, cz);
+    s.n0 = make_float3(A.nx, A.ny, A.nz);
+    s.n1 = make_float3(B.nx, B.ny, B.nz);
+    s.ia = (A.flags & kInterior) != 0;
+    s.ib = (B.flags & kInterior) != 0;
+    return s;
+}
+
+// FP16 form: brick centre minus voxel corner (an exact small integer plus one
+// half) plus the binary16 offset; the sum is exact in binary32.
+__device__ __forceinline__ LocalSeg local_seg(const SRec16 &r, int cx, int cy, int cz) {
+    LocalSeg s;
+    const float ox = (float)(8 * (int)r.bx + 4 - cx), oy = (float)(8 * (int)r.by + 4 - cy),
+                oz = (float)(8 * (int)r.bz + 4 - cz);
+    s.pa = make_float3(ox + __half2float(r.a[0]), oy + __half2float(r.a[1]), oz + __half2float(r.a[2]));
+    s.pb = make_float3(ox + __half2float(r.b[0]), oy + __half2float(r.b[1]), oz + __half2float(r.b[2]));
+    s.n0 = make_float3(__half2float(r.n0[0]), __half2float(r.n0[1]), __half2float(r.n0[2]));
+    s.n1 = make_float3(__half2float(r.n1[0]), __half2float(r.n1[1]), __half2float(r.n1[2]));
+    s.ia = (r.flags & 1u) != 0;
+    s.ib = (r.flags & 2u) != 0;
+    return s;
+}
+
+// Accepted hit of a segment inside the current voxel: entry parameter s in
 // [0, tl) from the voxel-local origin ro, and on the kept side of both clip
 // planes ((P - A).n0 >= 0 at an interior A, (P - B).n1 < 0 at an interior B).
-__device__ __forceinline__ bool voxel_hit(const VRec &A, const VRec &B, float radius, float3 ro, float3 D, int cx,
-                                          int cy, int cz, float tl, float &s) {
-    const float3 pa = rel(A, cx, cy, cz), pb = rel(B, cx, cy, cz);
-    s = capsule_entry(ro, D, pa, pb, radius);
+__device__ __forceinline__ bool voxel_hit(const LocalSeg &g, float radius, float3 ro, float3 D, float tl, float &s) {
+    s = capsule_entry(ro, D, g.pa, g.pb, radius);
     if (!(s >= 0.0f && s < tl)) return false;
     const float3 P = make_float3(fmaf(s, D.x, ro.x), fmaf(s, D.y, ro.y), fmaf(s, D.z, ro.z));
-    if (A.flags & kInterior) {
-        if (!(dot3(sub3(P, pa), make_float3(A.nx, A.ny, A.nz)) >= 0.0f)) return false;
-    }
-    if (B.flags & kInterior) {
-        if (!(dot3(sub3(P, pb), make_float3(B.nx, B.ny, B.nz)) < 0.0f)) return false;
-    }
+    if (g.ia && !(dot3(sub3(P, g.pa), g.n0) >= 0.0f)) return false;
+    if (g.ib && !(dot3(sub3(P, g.pb), g.n1) < 0.0f)) return false;
     return true;
 }
 
-__device__ __forceinline__ float3 seg_colour(const VRec &A, const VRec &B) {
-    const float dx = (float)(B.x - A.x), dy = (float)(B.y - A.y), dz = (float)(B.z - A.z);
+// Colour = |unit tangent|, from the endpoints (identical in both forms while
+// the FP16 offsets are exact).
+__device__ __forceinline__ float3 seg_colour(float3 pa, float3 pb) {
+    const float dx = pb.x - pa.x, dy = pb.y - pa.y, dz = pb.z - pa.z;
     const float len = sqrtf(dx * dx + dy * dy + dz * dz);
     if (len == 0.0f) return make_float3(0.0f, 0.0f, 0.0f);
     return make_float3(fabsf(dx) / len, fabsf(dy) / len, fabsf(dz) / len);
@@ -314,26 +345,30 @@ __device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w,
     return false;
 }
 
-// Calls f(id, A, B) for the entries of the current voxel's list that belong
-// to lane `gl` of a kGroup-lane group (entries gl, gl + kGroup, ...).  The
-// vertex records of kBatch entries are fetched before any of them is tested,
-// so each lane keeps several independent loads in flight.
-template <bool kStats, class F>
+// Segment id in the frame of voxel (cx, cy, cz), read in the context's form.
+template <int kForm>
+__device__ __forceinline__ LocalSeg load_seg(const TraceArgs &a, uint32_t id, int cx, int cy, int cz) {
+    if (kForm == VRT_FORM_FP16) return local_seg(a.srec16[id], cx, cy, cz);
+    return local_seg(a.vrec[id], a.vrec[id + 1], cx, cy, cz);
+}
+
+// Calls f(id, seg) for the entries of the current voxel's list that belong to
+// lane `gl` of a kGroup-lane group (entries gl, gl + kGroup, ...).  The
+// records of kBatch entries are fetched before any of them is tested, so each
+// lane keeps several independent loads in flight.
+template <bool kStats, int kForm, class F>
 __device__ __forceinline__ void for_each_entry(const TraceArgs &a, const Walk &w, int gl, Counters &cn, F &&f) {
     // after a capacity overflow the lists are undefined but reads stay inside ids
     const uint32_t start = (uint32_t)w.cd, cnt = (uint32_t)(w.cd >> 32);
     const uint32_t end = (int64_t)start + cnt <= a.capacity ? start + cnt : start;
+    const int cx = w.v[0], cy = w.v[1], cz = w.v[2];
     for (uint32_t k = start + gl; k < end; k += kGroup * kBatch) {
         uint32_t id[kBatch];
-        VRec A[kBatch], B[kBatch];
+        LocalSeg g[kBatch];
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) id[j] = k + j * kGroup < end ? a.ids[k + j * kGroup] : 0xFFFFFFFFu;
 #pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-            const uint32_t safe = (int64_t)id[j] + 1 < a.nv ? id[j] : 0u;
-            A[j] = a.vrec[safe];
-            B[j] = a.vrec[safe + 1];
-        }
+        for (int j = 0; j < kBatch; ++j) g[j] = load_seg<kForm>(a, (int64_t)id[j] + 1 < a.nv ? id[j] : 0u, cx, cy, cz);
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) {
             if (!((int64_t)id[j] + 1 < a.nv)) continue;
@@ -341,7 +376,7 @@ __device__ __forceinline__ void for_each_entry(const TraceArgs &a, const Walk &w
                 ++cn.test;
                 a.stat_seg[id[j]] = 1;
             }
-            f(id[j], A[j], B[j]);
+            f(id[j], g[j]);
         }
     }
 }
@@ -377,7 +412,7 @@ struct Shade {
 // Processes the current voxel's list with the kGroup lanes of the ray's group;
 // true when the ray is finished (opaque: a hit in this voxel; transparent:
 // transmittance below tau).  Every lane of the group returns the same result.
-template <bool kStats>
+template <bool kStats, int kForm>
 __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, const Walk &w, Shade &sh, Counters &cn,
                                             int lane) {
     const int gl = lane & (kGroup - 1);
@@ -393,9 +428,9 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
     }
     if (a.p.mode == VRT_TRACE_OPAQUE) {
         unsigned long long best = kNoKey;
-        for_each_entry<kStats>(a, w, gl, cn, [&](uint32_t id, const VRec &A, const VRec &B) {
+        for_each_entry<kStats, kForm>(a, w, gl, cn, [&](uint32_t id, const LocalSeg &g) {
             float s;
-            if (voxel_hit(A, B, radius, ro, D, cx, cy, cz, tl, s)) {
+            if (voxel_hit(g, radius, ro, D, tl, s)) {
                 const unsigned long long key = hit_key(s, id);
                 best = key < best ? key : best;
             }
@@ -405,7 +440,8 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
         const uint32_t id = (uint32_t)best;
         sh.first = (int)id;
         sh.first_t = w.tcur + __uint_as_float((uint32_t)(best >> 32));
-        sh.col = seg_colour(a.vrec[id], a.vrec[id + 1]);
+        const LocalSeg g = load_seg<kForm>(a, id, cx, cy, cz);
+        sh.col = seg_colour(g.pa, g.pb);
         sh.T = 0.0f;
         return true;
     }
@@ -421,9 +457,9 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
         for (int j = 0; j < kLaneKeys; ++j) kk[j] = kNoKey;
         int nacc = 0;
         if (kStats && gl == 0) ++cn.pass;
-        for_each_entry<kStats>(a, w, gl, cn, [&](uint32_t id, const VRec &A, const VRec &B) {
+        for_each_entry<kStats, kForm>(a, w, gl, cn, [&](uint32_t id, const LocalSeg &g) {
             float s;
-            if (!voxel_hit(A, B, radius, ro, D, cx, cy, cz, tl, s)) return;
+            if (!voxel_hit(g, radius, ro, D, tl, s)) return;
             unsigned long long key = hit_key(s, id);
             if (have_thr && !(key > thr)) return;
             ++nacc;
@@ -453,7 +489,8 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
                 sh.first = (int)id;
                 sh.first_t = w.tcur + __uint_as_float((uint32_t)(m >> 32));
             }
-            const float3 c = seg_colour(a.vrec[id], a.vrec[id + 1]);
+            const LocalSeg g = load_seg<kForm>(a, id, cx, cy, cz);
+            const float3 c = seg_colour(g.pa, g.pb);
             const float wgt = sh.T * a.p.alpha;
             sh.col.x += wgt * c.x;
             sh.col.y += wgt * c.y;
@@ -545,7 +582,7 @@ __global__ void __launch_bounds__(256) k_trace_march(TraceArgs a) {
 // Phase 2, one kGroup-lane group per queued ray: lists, capsule tests and
 // compositing, continuing the walk until the ray is finished.  All lanes of a
 // group follow the same walk; list entries are split across them.
-template <bool kStats>
+template <bool kStats, int kForm>
 __global__ void __launch_bounds__(256) k_trace_shade(TraceArgs a) {
     const int lane = threadIdx.x & 63;
     const unsigned n = a.st->n_queue;
@@ -572,7 +609,7 @@ __global__ void __launch_bounds__(256) k_trace_shade(TraceArgs a) {
             Counters walk_cn;  // walk counters once per ray
             bool have = march<kStats>(a, r, w, walk_cn);  // recomputes the exit data of the queued voxel
             while (have) {
-                if (shade_voxel<kStats>(a, r, w, sh, cn, lane)) break;
+                if (shade_voxel<kStats, kForm>(a, r, w, sh, cn, lane)) break;
                 if (!step_voxel(a, r, w)) break;
                 have = march<kStats>(a, r, w, walk_cn);
             }
@@ -656,6 +693,7 @@ static TraceArgs trace_args(vrt_ctx *c, const TraceParams &p, const vrt_image *i
     a.st = c->a.status;
     a.ids = c->a.ids;
     a.vrec = c->a.vrec;
+    a.srec16 = c->a.srec16;
     a.nv = c->n_vertices;
     a.capacity = c->desc.max_fragments;
     a.queue = c->a.queue;
@@ -675,7 +713,10 @@ hipError_t launch_trace(vrt_ctx *c, const TraceParams &p, const vrt_image *img, 
     dim3 grid((p.W + 15) / 16, (p.H + 15) / 16);
     VRT_LAUNCH(c, "k_trace_begin", st, k_trace_begin<<<1, 1, 0, st>>>(a.st));
     VRT_LAUNCH(c, "k_trace_march", st, k_trace_march<false><<<grid, 256, 0, st>>>(a));
-    VRT_LAUNCH(c, "k_trace_shade", st, k_trace_shade<false><<<kShadeBlocks, 256, 0, st>>>(a));
+    if (c->desc.form == VRT_FORM_FP16)
+        VRT_LAUNCH(c, "k_trace_shade", st, k_trace_shade<false, VRT_FORM_FP16><<<kShadeBlocks, 256, 0, st>>>(a));
+    else
+        VRT_LAUNCH(c, "k_trace_shade", st, k_trace_shade<false, VRT_FORM_PLAIN><<<kShadeBlocks, 256, 0, st>>>(a));
     return hipGetLastError();
 }
 
@@ -685,7 +726,8 @@ hipError_t launch_trace_stats(vrt_ctx *c, const TraceParams &p, const vrt_image 
     dim3 grid((p.W + 15) / 16, (p.H + 15) / 16);
     k_trace_begin<<<1, 1, 0, st>>>(a.st);
     k_trace_march<true><<<grid, 256, 0, st>>>(a);
-    k_trace_shade<true><<<kShadeBlocks, 256, 0, st>>>(a);
+    if (c->desc.form == VRT_FORM_FP16) k_trace_shade<true, VRT_FORM_FP16><<<kShadeBlocks, 256, 0, st>>>(a);
+    else k_trace_shade<true, VRT_FORM_PLAIN><<<kShadeBlocks, 256, 0, st>>>(a);
     k_stat_reduce<<<1024, 256, 0, st>>>(c->a.brick_list, c->a.status, c->n_vertices, a.stat_vox, a.cell, a.stat_seg,
                                         a.stat_acc);
     return hipGetLastError();

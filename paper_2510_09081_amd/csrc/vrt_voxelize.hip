@@ -144,6 +144,39 @@ __device__ __forceinline__ int occupancy_quantum(const VRec &A, const VRec &B, f
     return (int)rintf(occ * 256.0f);
 }
 
+// FP16 form: one record per segment with its endpoints relative to the centre
+// of the brick holding its midpoint (binary16, voxel units) and its clip
+// normals in binary16.  Quantized positions are multiples of 1/256 voxel, so
+// offsets below 8 voxels are exact.
+__global__ void k_pack16(const VRec *__restrict__ vrec, int64_t nv, SRec16 *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i + 1 >= nv) return;
+    const VRec A = vrec[i];
+    if (!(A.flags & kSegValid)) return;
+    const VRec B = vrec[i + 1];
+    const long long mx = ((long long)A.x + B.x) >> 1, my = ((long long)A.y + B.y) >> 1, mz = ((long long)A.z + B.z) >> 1;
+    const long long bx = mx >> 11, by = my >> 11, bz = mz >> 11;  // 8 voxels = 2^11 steps
+    const long long cx = bx * 2048 + 1024, cy = by * 2048 + 1024, cz = bz * 2048 + 1024;
+    SRec16 r;
+    r.a[0] = __float2half((float)(A.x - cx) * (1.0f / kQ));
+    r.a[1] = __float2half((float)(A.y - cy) * (1.0f / kQ));
+    r.a[2] = __float2half((float)(A.z - cz) * (1.0f / kQ));
+    r.b[0] = __float2half((float)(B.x - cx) * (1.0f / kQ));
+    r.b[1] = __float2half((float)(B.y - cy) * (1.0f / kQ));
+    r.b[2] = __float2half((float)(B.z - cz) * (1.0f / kQ));
+    r.n0[0] = __float2half(A.nx);
+    r.n0[1] = __float2half(A.ny);
+    r.n0[2] = __float2half(A.nz);
+    r.n1[0] = __float2half(B.nx);
+    r.n1[1] = __float2half(B.ny);
+    r.n1[2] = __float2half(B.nz);
+    r.bx = (short)bx;
+    r.by = (short)by;
+    r.bz = (short)bz;
+    r.flags = (unsigned short)(((A.flags & kInterior) ? 1 : 0) | ((B.flags & kInterior) ? 2 : 0));
+    out[i] = r;
+}
+
 struct CountArgs {
     const VRec *vrec;
     int64_t nv;
@@ -408,6 +441,9 @@ hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *L, float s_q, hipStream_
     ca.nby = c->dims[1] / 8;
     ca.words = A.words;
     ca.brick_flag = A.brick_flag;
+    if (c->desc.form == VRT_FORM_FP16)
+        VRT_LAUNCH(c, "k_pack16", st,
+                   k_pack16<<<(unsigned)((L->n_vertices + 255) / 256), 256, 0, st>>>(A.vrec, L->n_vertices, A.srec16));
     VRT_LAUNCH(c, "k_vox_count", st, k_vox_count<<<(unsigned)((L->n_vertices + 255) / 256), 256, 0, st>>>(ca, A.status));
     VRT_LAUNCH(c, "k_brick_compact", st, k_brick_compact<<<1, 1024, 0, st>>>(A.brick_flag, nb, A.brick_list, A.brick_slot, A.status));
     VRT_LAUNCH(c, "k_occ_brick", st,

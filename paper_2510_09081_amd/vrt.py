@@ -20,10 +20,12 @@ VRT_OK, VRT_ERR_INVALID_ARG, VRT_ERR_RANGE, VRT_ERR_NOT_BUILT = 0, 1, 2, 3
 VRT_ERR_CAPACITY, VRT_ERR_COUNT_OVERFLOW, VRT_ERR_HIP = 4, 5, 6
 CULL_NONE, CULL_OPAQUE, CULL_ALPHA = 0, 1, 2
 TRACE_OPAQUE, TRACE_TRANSPARENT = 0, 1
+FORM_PLAIN, FORM_FP16 = 0, 1
 
 EXPORTED = ["vrt_create", "vrt_destroy", "vrt_voxelize", "vrt_cull", "vrt_trace", "vrt_frame_status",
             "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_last_hip_error", "vrt_status_string",
-            "vrt_profile_enable", "vrt_profile_read", "vrt_trace_stats_run"]
+            "vrt_profile_enable", "vrt_profile_read", "vrt_trace_stats_run", "vrt_graph_create",
+            "vrt_graph_launch", "vrt_graph_destroy"]
 
 
 class VrtError(RuntimeError):
@@ -34,7 +36,7 @@ class VrtError(RuntimeError):
 
 class vrt_desc(C.Structure):
     _fields_ = [("max_vertices", C.c_int64), ("max_fragments", C.c_int64), ("max_dim", C.c_int32),
-                ("device", C.c_int32), ("max_pixels", C.c_int64)]
+                ("device", C.c_int32), ("max_pixels", C.c_int64), ("form", C.c_int32), ("reserved", C.c_int32)]
 
 
 class vrt_lines(C.Structure):
@@ -103,6 +105,10 @@ def load():
         L.vrt_debug_rays.argtypes = [P, C.POINTER(vrt_camera), P, C.c_int64, P, P]
         L.vrt_copy_to_host.argtypes = [P, P, C.c_int64]
         L.vrt_profile_enable.argtypes = [P, C.c_int32]
+        L.vrt_graph_create.argtypes = [P, C.POINTER(vrt_lines), C.POINTER(vrt_grid), C.POINTER(vrt_view),
+                                       C.POINTER(vrt_camera), C.POINTER(vrt_image), C.c_int32, C.POINTER(P)]
+        L.vrt_graph_launch.argtypes = [P, P]
+        L.vrt_graph_destroy.argtypes = [P]
         L.vrt_trace_stats_run.argtypes = [P, C.POINTER(vrt_camera), C.POINTER(vrt_image), C.POINTER(vrt_trace_stats), P]
         L.vrt_profile_read.argtypes = [P, C.POINTER(vrt_kernel_time), C.c_int32, C.POINTER(C.c_int32)]
         L.vrt_last_hip_error.restype = C.c_int32
@@ -110,7 +116,8 @@ def load():
         L.vrt_status_string.restype = C.c_char_p
         for name in ["vrt_create", "vrt_destroy", "vrt_voxelize", "vrt_cull", "vrt_trace", "vrt_frame_status",
                      "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_profile_enable",
-                     "vrt_profile_read", "vrt_trace_stats_run"]:
+                     "vrt_profile_read", "vrt_trace_stats_run", "vrt_graph_create", "vrt_graph_launch",
+                     "vrt_graph_destroy"]:
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -163,9 +170,9 @@ def make_camera(eye, target, up, fovy_deg, width, height, mode=TRACE_OPAQUE, alp
 class Context:
     """One voxel ray tracing context: arenas sized at creation, reused per frame."""
 
-    def __init__(self, max_vertices, max_fragments, max_dim, device=0, max_pixels=1920 * 1080):
+    def __init__(self, max_vertices, max_fragments, max_dim, device=0, max_pixels=1920 * 1080, form=FORM_PLAIN):
         L = load()
-        d = vrt_desc(int(max_vertices), int(max_fragments), int(max_dim), int(device), int(max_pixels))
+        d = vrt_desc(int(max_vertices), int(max_fragments), int(max_dim), int(device), int(max_pixels), int(form), 0)
         h = C.c_void_p()
         _check(L.vrt_create(C.byref(d), C.byref(h)), "vrt_create")
         self._h = h
@@ -225,7 +232,49 @@ class Context:
         _check(load().vrt_profile_read(self._h, buf, 64, C.byref(n)), "vrt_profile_read")
         return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(n.value)}
 
+    def frame_graph(self, xyz, offsets, radius, origin, voxel_size, dims, passes):
+        """Captures one frame as a HIP graph.  passes: list of (view, camera, rgba, depth, first_id) with
+        view = (eye, cull_mode, alpha, tau).  Returns a FrameGraph; keep the tensors alive while it exists."""
+        lines = vrt_lines(_ptr(xyz), _ptr(offsets), int(xyz.shape[0]), int(offsets.shape[0] - 1), float(radius))
+        grid = vrt_grid(_f3(origin), float(voxel_size), (C.c_int32 * 3)(*[int(x) for x in dims]))
+        n = len(passes)
+        views = (vrt_view * max(n, 1))()
+        cams = (vrt_camera * max(n, 1))()
+        imgs = (vrt_image * max(n, 1))()
+        for i, (view, cam, rgba, depth, fid) in enumerate(passes):
+            eye, mode, alpha, tau = view
+            views[i] = vrt_view(_f3(eye), int(mode), float(alpha), float(tau))
+            cams[i] = cam
+            imgs[i] = vrt_image(_ptr(rgba), _ptr(depth), _ptr(fid))
+        h = C.c_void_p()
+        _check(load().vrt_graph_create(self._h, C.byref(lines), C.byref(grid), views, cams, imgs, n, C.byref(h)),
+               "vrt_graph_create")
+        return FrameGraph(h, self, (xyz, offsets, passes))
+
     def query_as(self):
         v = vrt_as_view()
         _check(load().vrt_query_as(self._h, C.byref(v)), "vrt_query_as")
         return v
+
+
+class FrameGraph:
+    """A captured frame; launch() replays it on the current (or given) stream."""
+
+    def __init__(self, handle, ctx, keepalive):
+        self._h = handle
+        self._ctx = ctx
+        self._keep = keepalive
+
+    def launch(self, stream=None):
+        _check(load().vrt_graph_launch(self._h, _stream_ptr(stream)), "vrt_graph_launch")
+
+    def close(self):
+        if self._h and self._h.value:
+            _check(load().vrt_graph_destroy(self._h), "vrt_graph_destroy")
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass

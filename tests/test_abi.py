@@ -41,7 +41,7 @@ def test_status_strings_and_host_validation():
     # host-side argument validation fails before touching a device
     assert L.vrt_create(None, None) == vrt.VRT_ERR_INVALID_ARG
     h = ctypes.c_void_p()
-    bad = vrt.vrt_desc(16, 16, 12, 0, 64)  # max_dim not a multiple of 8
+    bad = vrt.vrt_desc(16, 16, 12, 0, 64, 0, 0)  # max_dim not a multiple of 8
     assert L.vrt_create(ctypes.byref(bad), ctypes.byref(h)) == vrt.VRT_ERR_INVALID_ARG
     assert L.vrt_voxelize(None, None, None, None) == vrt.VRT_ERR_INVALID_ARG
     assert L.vrt_copy_to_host(None, None, -1) == vrt.VRT_ERR_INVALID_ARG

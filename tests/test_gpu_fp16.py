@@ -1,0 +1,73 @@
+"""FP16 precision form: brick-relative binary16 segment records in the tracer.
+
+Voxel membership, lists and culling are unchanged (int32); the tracer reads
+binary16 endpoints (exact here: offsets below 8 voxels on the 1/256 grid) and
+binary16 clip normals (relative error 2^-11), so results differ from the plain
+form only where a hit point lies within ~1e-3 voxel of a clip plane.  The
+error against the binary64 oracle is reported and bounded.
+"""
+import numpy as np
+import pytest
+
+from paper_2510_09081_amd import synth, vrt
+
+from . import _gpu as G
+from .test_gpu_parity import certified
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctxs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU: the gpu tests need an MI355X")
+    plain = vrt.Context(max_vertices=300_000, max_fragments=4_000_000, max_dim=128, form=vrt.FORM_PLAIN)
+    half = vrt.Context(max_vertices=300_000, max_fragments=4_000_000, max_dim=128, form=vrt.FORM_FP16)
+    yield plain, half
+    plain.close()
+    half.close()
+
+
+def error_report(tr, gid, gdepth, grgba, ls):
+    cert = certified(tr, 0)
+    hit = tr.id >= 0
+    match = (gid == tr.id)
+    vs = float(ls.voxel_size)
+    both = hit & (gid >= 0) & match
+    derr = np.abs(gdepth[both].astype(np.float64) - tr.depth[both]) / vs
+    cerr = np.abs(grgba.astype(np.float64) - tr.rgba)
+    return {
+        "id_match_all": float(match.mean()),
+        "id_match_certified": float(match[cert].mean()),
+        "depth_err_max_vox": float(derr.max(initial=0)), "depth_err_mean_vox": float(derr.mean() if derr.size else 0),
+        "colour_err_max": float(cerr.max()), "colour_err_mean": float(cerr.mean()),
+    }
+
+
+@pytest.mark.parametrize("name", ["random_walk_10k", "bundles_small"])
+@pytest.mark.parametrize("mode,cull,alpha", [(0, vrt.CULL_NONE, 1.0), (1, vrt.CULL_NONE, 0.3)])
+def test_fp16_form_error_against_oracle(orc, ctxs, name, mode, cull, alpha):
+    plain, half = ctxs
+    w = synth.workload(name)
+    ls, cam = w.lines, w.camera
+    fr = orc.build_frame(ls, cam.eye, cull, alpha=alpha)
+    tr = orc.trace(fr, ls, cam, np.arange(cam.width * cam.height), mode, alpha=alpha)
+    out = {}
+    for label, ctx in (("plain", plain), ("fp16", half)):
+        G.run_build(ctx, ls, cam.eye, cull, alpha=alpha)
+        assert ctx.frame_status()["device_status"] == 0
+        out[label] = G.run_trace(ctx, cam, mode, alpha=alpha)
+        out[label + "_err"] = error_report(tr, *out[label], ls)
+    print(f"\n{name} mode={mode}: plain {out['plain_err']}\n{name} mode={mode}: fp16  {out['fp16_err']}")
+    e = out["fp16_err"]
+    # the FP16 form agrees with the oracle on (almost) every certified pixel ...
+    assert e["id_match_certified"] >= 0.999
+    assert e["colour_err_mean"] <= 1e-4
+    # ... and with the plain form except where a hit lies within ~1e-3 voxel of
+    # a clip plane (a flipped clip decision changes that pixel by one layer)
+    same = out["plain"][0] == out["fp16"][0]
+    assert same.mean() >= 0.999
+    d = np.abs(out["plain"][2] - out["fp16"][2]).max(axis=1)
+    assert (d > 1e-4).mean() <= 2e-3
+    assert d.mean() <= 1e-4
