@@ -199,6 +199,34 @@ vrt_status vrt_graph_create(vrt_ctx *ctx, const vrt_lines *lines, const vrt_grid
 vrt_status vrt_graph_launch(vrt_graph *g, void *stream);
 vrt_status vrt_graph_destroy(vrt_graph *g);
 
+/* Batched form: many independent line sets, each with its own grid, view,
+ * camera and image, built and traced together.  VRT_BATCH_PERSISTENT runs
+ * every stage of every set in ONE cooperative launch: the frame's stages are
+ * phases separated by grid barriers, and inside a phase the resident blocks
+ * take (set, stage, block) work items from a counter, largest sets first.
+ * VRT_BATCH_SEQUENTIAL issues the plain vrt_voxelize / vrt_cull / vrt_trace
+ * calls set after set (the reference the persistent form is compared with).
+ * Both give identical results.  Set i uses the arenas of a context created
+ * from descs[i] (reachable with vrt_batch_context for vrt_frame_status and
+ * vrt_query_as); all sets share one device.  vrt_batch_run validates every set
+ * on the host before anything is enqueued and never allocates. */
+#define VRT_BATCH_PERSISTENT 0
+#define VRT_BATCH_SEQUENTIAL 1
+
+typedef struct {
+    vrt_lines lines;
+    vrt_grid grid;
+    vrt_view view;
+    vrt_camera cam;
+    vrt_image image;
+} vrt_batch_item;
+
+typedef struct vrt_batch vrt_batch;
+vrt_status vrt_batch_create(const vrt_desc *descs, int32_t n, vrt_batch **out);
+vrt_status vrt_batch_run(vrt_batch *b, const vrt_batch_item *items, int32_t n, int32_t mode, void *stream);
+vrt_status vrt_batch_context(vrt_batch *b, int32_t i, vrt_ctx **ctx);
+vrt_status vrt_batch_destroy(vrt_batch *b);
+
 /* Synchronizes the context's last stream, reads the device status word and
  * the frame totals, and clears the latched error. */
 vrt_status vrt_frame_status(vrt_ctx *ctx, vrt_frame_info *out);

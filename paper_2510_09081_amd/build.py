@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libvrt.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["vrt_api.hip", "vrt_voxelize.hip", "vrt_cull.hip", "vrt_trace.hip"]
+# one translation unit (vrt_unity.hip includes every stage, the API and the batch kernel)
+SOURCES = ["vrt_unity.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -173,7 +173,9 @@ vrt_status vrt_destroy(vrt_ctx *c) {
     return VRT_OK;
 }
 
-vrt_status vrt_voxelize(vrt_ctx *c, const vrt_lines *L, const vrt_grid *g, void *stream) {
+// Validation and context state of one voxelization (shared by the plain and
+// the batched paths); on success *s_q is the binary32 fixed-point scale.
+static vrt_status prepare_voxelize(vrt_ctx *c, const vrt_lines *L, const vrt_grid *g, float *s_q) {
     if (!c || !L || !g) return VRT_ERR_INVALID_ARG;
     if (!L->xyz || !L->poly_offsets || L->n_polylines < 1 || L->n_vertices < 1 ||
         L->n_vertices > c->desc.max_vertices || L->n_polylines > L->n_vertices)
@@ -182,10 +184,8 @@ vrt_status vrt_voxelize(vrt_ctx *c, const vrt_lines *L, const vrt_grid *g, void 
     if (!(g->voxel_size > 0.0f) || !std::isfinite(g->voxel_size) || !finite3(g->origin)) return VRT_ERR_INVALID_ARG;
     for (int k = 0; k < 3; ++k)
         if (g->dims[k] < 8 || g->dims[k] % 8 != 0 || g->dims[k] > c->desc.max_dim) return VRT_ERR_INVALID_ARG;
-    double rq = std::rint((double)L->radius * 256.0 / (double)g->voxel_size);
+    const double rq = std::rint((double)L->radius * 256.0 / (double)g->voxel_size);
     if (!(rq <= 16384.0)) return VRT_ERR_RANGE;
-    VRT_HIP(hipSetDevice(c->desc.device));
-    hipStream_t st = (hipStream_t)stream;
     for (int k = 0; k < 3; ++k) {
         c->dims[k] = g->dims[k];
         c->origin[k] = g->origin[k];
@@ -196,36 +196,49 @@ vrt_status vrt_voxelize(vrt_ctx *c, const vrt_lines *L, const vrt_grid *g, void 
     c->n_levels = level_dims(c->dims, c->levels);
     c->voxelized = false;
     c->culled = false;
+    *s_q = (float)(256.0 / (double)g->voxel_size);
+    return VRT_OK;
+}
+
+vrt_status vrt_voxelize(vrt_ctx *c, const vrt_lines *L, const vrt_grid *g, void *stream) {
+    float s_q;
+    const vrt_status s = prepare_voxelize(c, L, g, &s_q);
+    if (s != VRT_OK) return s;
+    VRT_HIP(hipSetDevice(c->desc.device));
+    hipStream_t st = (hipStream_t)stream;
     c->last_stream = st;
-    const float s_q = (float)(256.0 / (double)g->voxel_size);
     VRT_HIP(launch_voxelize(c, L, s_q, st));
     c->voxelized = true;
     return VRT_OK;
 }
 
-vrt_status vrt_cull(vrt_ctx *c, const vrt_view *v, void *stream) {
+// Validation of one view: the eye in 1/256 voxel and the blocking limit
+// (-1: no culling; 1: opaque; else the alpha layers until transmittance < tau).
+static vrt_status prepare_cull(const vrt_ctx *c, const vrt_view *v, int64_t E[3], int64_t *limit) {
     if (!c || !v) return VRT_ERR_INVALID_ARG;
     if (!c->voxelized) return VRT_ERR_NOT_BUILT;
-    int64_t limit;
     if (v->cull_mode == VRT_CULL_NONE) {
-        limit = -1;
+        *limit = -1;
     } else if (v->cull_mode == VRT_CULL_OPAQUE) {
-        limit = 1;
+        *limit = 1;
     } else if (v->cull_mode == VRT_CULL_ALPHA) {
         if (!(v->alpha > 0.0f && v->alpha <= 1.0f) || !(v->tau > 0.0f && v->tau < 1.0f)) return VRT_ERR_INVALID_ARG;
-        // layers after which transmittance (1 - alpha)^k drops below tau
         double T = 1.0;
-        limit = 0;
+        int64_t k = 0;
         while (!(T < (double)v->tau)) {
             T *= 1.0 - (double)v->alpha;
-            ++limit;
+            ++k;
         }
-        if (limit < 1) limit = 1;
+        *limit = k < 1 ? 1 : k;
     } else {
         return VRT_ERR_INVALID_ARG;
     }
-    int64_t E[3];
-    vrt_status s = quantize_eye(c, v->eye, E);
+    return quantize_eye(c, v->eye, E);
+}
+
+vrt_status vrt_cull(vrt_ctx *c, const vrt_view *v, void *stream) {
+    int64_t E[3], limit;
+    const vrt_status s = prepare_cull(c, v, E, &limit);
     if (s != VRT_OK) return s;
     VRT_HIP(hipSetDevice(c->desc.device));
     hipStream_t st = (hipStream_t)stream;

@@ -1,0 +1,328 @@
+// vrt_batch.hip -- batched form: many line sets, each with its own grid, view
+// and camera, voxelized, culled, listed and traced in one persistent launch.
+//
+// The launch is cooperative (every block resident) and walks the frame's
+// stages as phases separated by grid barriers.  Inside a phase every (set,
+// stage) pair contributes a number of virtual blocks -- the grid the plain
+// launch of that stage would use, counted from the device-side sizes the
+// previous phases produced -- and the resident blocks take them from a ticket
+// counter, the sets in decreasing size order so the largest start first.
+// Each virtual block runs the same kernel body as the plain launch.
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "vrt_internal.h"
+
+namespace vrt {
+namespace {
+
+constexpr int kBatchThreads = 512;
+constexpr int kMaxBatch = 1024;
+constexpr int kParts = 3;  // stages sharing one phase
+enum : int {
+    P_CLEAR, P_INGEST, P_COUNT, P_COMPACT, P_OCC, P_ERODE, P_WALK, P_CBRICK, P_SCAN, P_OFFSETS, P_SCATTER, P_MARCH,
+    P_SHADE, kPhases
+};
+
+struct SetDesc {
+    Arenas a;
+    VoxPlan vp;
+    CullPlan cp;
+    TraceArgs ta;
+    int64_t capacity;
+    int n_levels;
+    Level levels[kMaxLevels];
+    unsigned march_blocks;
+    int fp16;
+};
+
+__device__ __forceinline__ unsigned cdiv(uint64_t n, unsigned d) { return (unsigned)((n + d - 1) / d); }
+
+// Virtual blocks of stage `part` of phase `ph` for one set.
+__device__ unsigned part_blocks(int ph, int part, const SetDesc &d) {
+    const DevStatus *st = d.a.status;
+    const unsigned T = kBatchThreads;
+    switch (ph) {
+    case P_CLEAR: return part == 0 ? st->n_bricks : (part == 1 ? cdiv(d.vp.nb, T) : 0u);
+    case P_INGEST: return part == 0 ? cdiv(d.vp.nv, T) : 0u;
+    case P_COUNT: return part == 0 ? (d.fp16 ? cdiv(d.vp.nv, T) : 0u) : (part == 1 ? cdiv(d.vp.nv, T) : 0u);
+    case P_COMPACT: return part == 0 ? 1u : 0u;
+    case P_OCC: return part == 0 ? st->n_bricks : 0u;
+    case P_ERODE:
+        if (part == 0) return st->n_bricks;
+        if (part == 1) return d.n_levels > 4 ? 1u : 0u;
+        return cdiv(d.cp.nb, T);
+    case P_WALK: return part == 0 && d.cp.limit >= 0 ? cdiv(st->n_occ, T) : 0u;
+    case P_CBRICK: return part == 0 ? st->n_bricks : 0u;
+    case P_SCAN: return part == 0 ? (d.n_levels > 4 ? 1u : 0u) : (part == 1 ? 1u : 0u);
+    case P_OFFSETS: return part == 0 ? st->n_bricks : 0u;
+    case P_SCATTER: return part == 0 ? cdiv(d.cp.nv, T) : (part == 1 ? 1u : 0u);
+    case P_MARCH: return part == 0 ? d.march_blocks : 0u;
+    case P_SHADE: return part == 0 ? cdiv(st->n_queue, T / kGroup) : 0u;
+    default: return 0u;
+    }
+}
+
+// Occupancy levels >= 4 by one block, level after level.
+__device__ void mip_avg_chain(const SetDesc &d) {
+    const uint16_t *src = d.a.occ3;
+    int sx = d.vp.g.nb[0], sy = d.vp.g.nb[1], sz = d.vp.g.nb[2];
+    for (int L = 4; L < d.n_levels; ++L) {
+        const Level &lv = d.levels[L];
+        uint16_t *dst = d.a.occ_hi + lv.offset;
+        const int64_t n = (int64_t)lv.dims[0] * lv.dims[1] * lv.dims[2];
+        for (unsigned vb = 0; (int64_t)vb * blockDim.x < n; ++vb)
+            b_mip_avg(src, sx, sy, sz, dst, lv.dims[0], lv.dims[1], lv.dims[2], vb, 0u);
+        __syncthreads();
+        src = dst;
+        sx = lv.dims[0];
+        sy = lv.dims[1];
+        sz = lv.dims[2];
+    }
+}
+
+// Culling levels >= 4 by one block, level after level.
+__device__ void mip_or_chain(const SetDesc &d) {
+    const uint8_t *src = d.a.vis3;
+    int sx = d.cp.g.nb[0], sy = d.cp.g.nb[1], sz = d.cp.g.nb[2];
+    for (int L = 4; L < d.n_levels; ++L) {
+        const Level &lv = d.levels[L];
+        uint8_t *dst = d.a.vis_hi + lv.offset;
+        const int64_t n = (int64_t)lv.dims[0] * lv.dims[1] * lv.dims[2];
+        for (unsigned vb = 0; (int64_t)vb * blockDim.x < n; ++vb)
+            b_mip_or(src, sx, sy, sz, dst, lv.dims[0], lv.dims[1], lv.dims[2], vb, 0u);
+        __syncthreads();
+        src = dst;
+        sx = lv.dims[0];
+        sy = lv.dims[1];
+        sz = lv.dims[2];
+    }
+}
+
+// Virtual block vb of nvb of stage `part` of phase `ph` for set d.
+__device__ void run_part(int ph, int part, const SetDesc &d, unsigned vb, unsigned nvb) {
+    const Arenas &A = d.a;
+    switch (ph) {
+    case P_CLEAR:
+        if (part == 0) b_clear_prev(A.words, A.brick_list, A.status, vb, nvb);
+        else b_reset(A.occ3, A.brick_blk, d.vp.nb, A.super_blk, d.vp.ns, A.status, vb, nvb);
+        break;
+    case P_INGEST: b_ingest(d.vp.ia, A.vrec, A.status, vb, nvb); break;
+    case P_COUNT:
+        if (part == 0) b_pack16(A.vrec, d.vp.nv, A.srec16, vb, nvb);
+        else b_vox_count(d.vp.ca, A.status, vb, nvb);
+        break;
+    case P_COMPACT: b_brick_compact(A.brick_flag, d.vp.nb, A.brick_list, A.brick_slot, A.status, 0u, 1u); break;
+    case P_OCC: b_occ_brick(A.words, A.brick_list, A.status, A.occ0, A.occ1, A.occ2, A.occ3, A.occ_list, vb, nvb); break;
+    case P_ERODE:
+        if (part == 0)
+            b_erode(d.vp.g, A.occ0, A.brick_list, A.brick_slot, A.status, A.blk, A.brick_blk, A.super_blk, vb, nvb);
+        else if (part == 1) mip_avg_chain(d);
+        else b_cull_reset(A.vis3, d.cp.nb, A.status, vb, nvb);
+        break;
+    case P_WALK: b_cull_walk(d.cp.ca, d.cp.cells, A.occ_list, A.status, A.vis0, vb, nvb); break;
+    case P_CBRICK:
+        b_cull_brick(d.cp.limit, d.cp.g, A.words, A.brick_list, A.status, A.vis0, A.vis1, A.vis2, A.vis3,
+                     A.brick_total, vb, nvb);
+        break;
+    case P_SCAN:
+        if (part == 0) mip_or_chain(d);
+        else b_scan_bricks(A.brick_total, A.brick_base, A.status, d.capacity, 0u, 1u);
+        break;
+    case P_OFFSETS: b_list_offsets(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor, A.cell, vb, nvb); break;
+    case P_SCATTER:
+        if (part == 0) b_scatter(d.cp.sa, vb, nvb);
+        else b_trace_begin(A.status, 0u, 1u);
+        break;
+    case P_MARCH: b_trace_march<false>(d.ta, vb, nvb); break;
+    case P_SHADE:
+        if (d.fp16) b_trace_shade<false, VRT_FORM_FP16>(d.ta, vb, nvb);
+        else b_trace_shade<false, VRT_FORM_PLAIN>(d.ta, vb, nvb);
+        break;
+    default: break;
+    }
+}
+
+// The persistent batch kernel.  tickets[ph] counts the virtual blocks of phase
+// ph handed out; block 0 clears the next phase's counter during each phase (it
+// is not read before the barrier), so the counters are zero at every launch.
+__global__ void __launch_bounds__(kBatchThreads) k_batch(const SetDesc *__restrict__ sets, int nsets,
+                                                         unsigned *__restrict__ tickets) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    __shared__ unsigned pre[kMaxBatch * kParts + 1];
+    __shared__ unsigned ticket;
+    const int nk = nsets * kParts;
+    for (int ph = 0; ph < kPhases; ++ph) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) tickets[(ph + 1) % kPhases] = 0u;
+        for (int k = threadIdx.x; k < nk; k += blockDim.x) pre[k + 1] = part_blocks(ph, k % kParts, sets[k / kParts]);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            pre[0] = 0u;
+            for (int k = 1; k <= nk; ++k) pre[k] += pre[k - 1];
+        }
+        __syncthreads();
+        const unsigned total = pre[nk];
+        for (;;) {
+            if (threadIdx.x == 0) ticket = atomicAdd(&tickets[ph], 1u);
+            __syncthreads();
+            const unsigned t = ticket;
+            __syncthreads();
+            if (t >= total) break;
+            int lo = 0, hi = nk - 1;  // the (set, stage) whose range holds ticket t
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            run_part(ph, lo % kParts, sets[lo / kParts], t - pre[lo], pre[lo + 1] - pre[lo]);
+            __syncthreads();
+        }
+        grid.sync();
+    }
+}
+
+}  // namespace
+}  // namespace vrt
+
+struct vrt_batch {
+    int n = 0;
+    int device = 0;
+    std::vector<vrt_ctx *> ctx;
+    vrt::SetDesc *d_sets = nullptr;
+    vrt::SetDesc *h_sets = nullptr;  // pinned staging
+    unsigned *d_tickets = nullptr;
+    hipEvent_t copied = nullptr;
+    bool copy_pending = false;
+    unsigned grid = 0;
+};
+
+extern "C" {
+
+vrt_status vrt_batch_create(const vrt_desc *descs, int32_t n, vrt_batch **out) {
+    using namespace vrt;
+    if (!descs || !out || n < 1 || n > kMaxBatch) return VRT_ERR_INVALID_ARG;
+    *out = nullptr;
+    for (int i = 1; i < n; ++i)
+        if (descs[i].device != descs[0].device) return VRT_ERR_INVALID_ARG;
+    VRT_HIP(hipSetDevice(descs[0].device));
+    int coop = 0;
+    VRT_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, descs[0].device));
+    if (!coop) return VRT_ERR_INVALID_ARG;
+    vrt_batch *b = new (std::nothrow) vrt_batch();
+    if (!b) return VRT_ERR_INVALID_ARG;
+    b->n = n;
+    b->device = descs[0].device;
+    vrt_status st = VRT_OK;
+    for (int i = 0; i < n && st == VRT_OK; ++i) {
+        vrt_ctx *c = nullptr;
+        st = vrt_create(&descs[i], &c);
+        if (st == VRT_OK) b->ctx.push_back(c);
+    }
+    hipError_t e = hipSuccess;
+    if (st == VRT_OK) e = hipMalloc((void **)&b->d_sets, sizeof(SetDesc) * n);
+    if (st == VRT_OK && e == hipSuccess) e = hipHostMalloc((void **)&b->h_sets, sizeof(SetDesc) * n);
+    if (st == VRT_OK && e == hipSuccess) e = hipMalloc((void **)&b->d_tickets, sizeof(unsigned) * kPhases);
+    if (st == VRT_OK && e == hipSuccess) e = hipMemset(b->d_tickets, 0, sizeof(unsigned) * kPhases);
+    if (st == VRT_OK && e == hipSuccess) e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming);
+    int per_cu = 0, ncu = 0;
+    if (st == VRT_OK && e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kBatchThreads, 0);
+    if (st == VRT_OK && e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device);
+    if (st == VRT_OK && e == hipSuccess) e = hipDeviceSynchronize();
+    if (st == VRT_OK && e != hipSuccess) st = hip_fail(e);
+    if (st == VRT_OK && per_cu < 1) st = VRT_ERR_INVALID_ARG;
+    b->grid = (unsigned)(per_cu * ncu);
+    if (st != VRT_OK) {
+        vrt_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return VRT_OK;
+}
+
+vrt_status vrt_batch_run(vrt_batch *b, const vrt_batch_item *items, int32_t n, int32_t mode, void *stream) {
+    using namespace vrt;
+    if (!b || !items || n != b->n) return VRT_ERR_INVALID_ARG;
+    if (mode != VRT_BATCH_PERSISTENT && mode != VRT_BATCH_SEQUENTIAL) return VRT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    VRT_HIP(hipSetDevice(b->device));
+    if (mode == VRT_BATCH_SEQUENTIAL) {
+        for (int i = 0; i < n; ++i) {
+            vrt_status s = vrt_voxelize(b->ctx[i], &items[i].lines, &items[i].grid, stream);
+            if (s == VRT_OK) s = vrt_cull(b->ctx[i], &items[i].view, stream);
+            if (s == VRT_OK) s = vrt_trace(b->ctx[i], &items[i].cam, &items[i].image, stream);
+            if (s != VRT_OK) return s;
+        }
+        return VRT_OK;
+    }
+    // validate every set and compute its arguments exactly as the plain calls do
+    std::vector<float> sq(n);
+    std::vector<int64_t> E(3 * n), lim(n);
+    std::vector<TraceParams> tp(n);
+    for (int i = 0; i < n; ++i) {
+        vrt_ctx *c = b->ctx[i];
+        vrt_status s = prepare_voxelize(c, &items[i].lines, &items[i].grid, &sq[i]);
+        if (s != VRT_OK) return s;
+        c->voxelized = true;
+        s = prepare_cull(c, &items[i].view, &E[3 * i], &lim[i]);
+        if (s != VRT_OK) return s;
+        c->culled = true;
+        if (!items[i].image.rgba) return VRT_ERR_INVALID_ARG;
+        s = camera_params(c, &items[i].cam, tp[i]);
+        if (s != VRT_OK) return s;
+    }
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return items[x].lines.n_vertices > items[y].lines.n_vertices; });
+    if (b->copy_pending) VRT_HIP(hipEventSynchronize(b->copied));  // the staging buffer is free again
+    for (int k = 0; k < n; ++k) {
+        const int i = order[k];
+        vrt_ctx *c = b->ctx[i];
+        SetDesc &d = b->h_sets[k];
+        d.a = c->a;
+        d.vp = make_vox_plan(c, &items[i].lines, sq[i]);
+        d.cp = make_cull_plan(c, &E[3 * i], lim[i]);
+        d.ta = trace_args(c, tp[i], &items[i].image);
+        d.capacity = c->desc.max_fragments;
+        d.n_levels = c->n_levels;
+        for (int L = 0; L < kMaxLevels; ++L) d.levels[L] = c->levels[L];
+        d.march_blocks = (unsigned)(((tp[i].W + 15) / 16) *
+                                    ((tp[i].H + march_tile_rows(kBatchThreads) - 1) / march_tile_rows(kBatchThreads)));
+        d.fp16 = c->desc.form == VRT_FORM_FP16;
+        c->last_stream = st;
+    }
+    VRT_HIP(hipMemcpyAsync(b->d_sets, b->h_sets, sizeof(SetDesc) * n, hipMemcpyHostToDevice, st));
+    VRT_HIP(hipEventRecord(b->copied, st));
+    b->copy_pending = true;
+    const SetDesc *sets = b->d_sets;
+    int nsets = n;
+    unsigned *tickets = b->d_tickets;
+    void *args[] = {(void *)&sets, (void *)&nsets, (void *)&tickets};
+    VRT_HIP(hipLaunchCooperativeKernel((const void *)k_batch, dim3(b->grid), dim3(kBatchThreads), args, 0, st));
+    return VRT_OK;
+}
+
+vrt_status vrt_batch_context(vrt_batch *b, int32_t i, vrt_ctx **out) {
+    if (!b || !out || i < 0 || i >= b->n) return VRT_ERR_INVALID_ARG;
+    *out = b->ctx[i];
+    return VRT_OK;
+}
+
+vrt_status vrt_batch_destroy(vrt_batch *b) {
+    if (!b) return VRT_ERR_INVALID_ARG;
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    for (vrt_ctx *c : b->ctx) vrt_destroy(c);
+    if (b->d_sets) (void)hipFree(b->d_sets);
+    if (b->h_sets) (void)hipHostFree(b->h_sets);
+    if (b->d_tickets) (void)hipFree(b->d_tickets);
+    if (b->copied) (void)hipEventDestroy(b->copied);
+    delete b;
+    return VRT_OK;
+}
+
+}  // extern "C"

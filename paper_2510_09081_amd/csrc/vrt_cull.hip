@@ -8,8 +8,8 @@
 namespace vrt {
 namespace {
 
-__global__ void k_cull_reset(uint8_t *__restrict__ vis3, int64_t nb, DevStatus *__restrict__ st) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void b_cull_reset(uint8_t *__restrict__ vis3, int64_t nb, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
+    int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     if (i < nb) vis3[i] = 0;
     if (i == 0) {
         st->n_listed = 0;
@@ -18,11 +18,7 @@ __global__ void k_cull_reset(uint8_t *__restrict__ vis3, int64_t nb, DevStatus *
     }
 }
 
-struct GridArgs {
-    int G[3];
-    int nb[3];  // bricks per axis
-    int ns[3];  // 64^3 cells per axis
-};
+__global__ void k_cull_reset(uint8_t *__restrict__ vis3, int64_t nb, DevStatus *__restrict__ st) { b_cull_reset(vis3, nb, st, blockIdx.x, gridDim.x); }
 
 // Blocking lookups for the culling walk: 64^3 cells and bricks holding a
 // blocking voxel, and the level-0 blocking flags (defined in occupied bricks).
@@ -50,13 +46,13 @@ struct CullArgs {
 // One thread per occupied voxel (Section 3.2): visible iff its culling ray
 // meets fewer than `limit` blocking voxels.  Writes level-0 visibility of
 // occupied voxels only; k_cull_brick completes the rest of the brick.
-__global__ void __launch_bounds__(256) k_cull_walk(CullArgs a, CullCells cells, const uint32_t *__restrict__ occ_list,
-                                                   const DevStatus *__restrict__ st, uint8_t *__restrict__ vis0) {
+__device__ __forceinline__ void b_cull_walk(CullArgs a, CullCells cells, const uint32_t *__restrict__ occ_list,
+                                                   const DevStatus *__restrict__ st, uint8_t *__restrict__ vis0, unsigned bid_, unsigned nblk_) {
     __shared__ int bbox[6];
     if (threadIdx.x < 6) bbox[threadIdx.x] = st->bbox[threadIdx.x];
     __syncthreads();
     const unsigned n = st->n_occ;
-    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (unsigned i = bid_ * blockDim.x + threadIdx.x; i < n; i += nblk_ * blockDim.x) {
         const uint32_t v = occ_list[i];
         const int64_t b = v >> 9;
         const int l = (int)(v & 511u);
@@ -68,22 +64,25 @@ __global__ void __launch_bounds__(256) k_cull_walk(CullArgs a, CullCells cells, 
     }
 }
 
+__global__ void __launch_bounds__(256) k_cull_walk(CullArgs a, CullCells cells, const uint32_t *__restrict__ occ_list,
+                                                   const DevStatus *__restrict__ st, uint8_t *__restrict__ vis0) { b_cull_walk(a, cells, occ_list, st, vis0, blockIdx.x, gridDim.x); }
+
 // One workgroup per occupied brick: final level-0 visibility (unoccupied
 // voxels are invisible; without culling every occupied voxel is visible), the
 // in-brick culling mips 1..3 (parent = OR of children), and the brick's
 // visible-fragment total.
-__global__ void __launch_bounds__(512) k_cull_brick(int limit, GridArgs g, const uint32_t *__restrict__ words,
+__device__ __forceinline__ void b_cull_brick(int limit, GridArgs g, const uint32_t *__restrict__ words,
                                                     const int32_t *__restrict__ list, DevStatus *__restrict__ st,
                                                     uint8_t *__restrict__ vis0, uint8_t *__restrict__ vis1,
                                                     uint8_t *__restrict__ vis2, uint8_t *__restrict__ vis3,
-                                                    uint32_t *__restrict__ brick_total) {
+                                                    uint32_t *__restrict__ brick_total, unsigned bid_, unsigned nblk_) {
     __shared__ uint8_t s0[512];
     __shared__ uint8_t s1[64];
     __shared__ uint8_t s2[8];
     __shared__ unsigned wsum[8];
     const unsigned nbk = st->n_bricks;
     const int t = threadIdx.x;
-    for (unsigned sl = blockIdx.x; sl < nbk; sl += gridDim.x) {
+    for (unsigned sl = bid_; sl < nbk; sl += nblk_) {
         int64_t b = list[sl];
         unsigned cnt = words[b * kBrickVox + t] & 0xFFFFu;
         uint8_t v = 0;
@@ -130,9 +129,15 @@ __global__ void __launch_bounds__(512) k_cull_brick(int limit, GridArgs g, const
     }
 }
 
-__global__ void k_mip_or(const uint8_t *__restrict__ src, int sx, int sy, int sz, uint8_t *__restrict__ dst, int dx,
-                         int dy, int dz) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(512) k_cull_brick(int limit, GridArgs g, const uint32_t *__restrict__ words,
+                                                    const int32_t *__restrict__ list, DevStatus *__restrict__ st,
+                                                    uint8_t *__restrict__ vis0, uint8_t *__restrict__ vis1,
+                                                    uint8_t *__restrict__ vis2, uint8_t *__restrict__ vis3,
+                                                    uint32_t *__restrict__ brick_total) { b_cull_brick(limit, g, words, list, st, vis0, vis1, vis2, vis3, brick_total, blockIdx.x, gridDim.x); }
+
+__device__ __forceinline__ void b_mip_or(const uint8_t *__restrict__ src, int sx, int sy, int sz, uint8_t *__restrict__ dst, int dx,
+                         int dy, int dz, unsigned bid_, unsigned nblk_) {
+    int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     if (i >= (int64_t)dx * dy * dz) return;
     int x = (int)(i % dx), y = (int)((i / dx) % dy), z = (int)(i / ((int64_t)dx * dy));
     uint8_t o = 0;
@@ -143,17 +148,20 @@ __global__ void k_mip_or(const uint8_t *__restrict__ src, int sx, int sy, int sz
     dst[i] = o;
 }
 
+__global__ void k_mip_or(const uint8_t *__restrict__ src, int sx, int sy, int sz, uint8_t *__restrict__ dst, int dx,
+                         int dy, int dz) { b_mip_or(src, sx, sy, sz, dst, dx, dy, dz, blockIdx.x, gridDim.x); }
+
 // Single workgroup: exclusive scan of the per-brick visible totals in
 // ascending brick order; the grand total is the number of listed fragments.
-__global__ void __launch_bounds__(1024) k_scan_bricks(const uint32_t *__restrict__ tot, uint32_t *__restrict__ base,
-                                                      DevStatus *__restrict__ st, int64_t capacity) {
+__device__ __forceinline__ void b_scan_bricks(const uint32_t *__restrict__ tot, uint32_t *__restrict__ base,
+                                                      DevStatus *__restrict__ st, int64_t capacity, unsigned bid_, unsigned nblk_) {
     __shared__ unsigned long long wt[16];
     __shared__ unsigned long long carry;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const unsigned n = st->n_bricks;
     if (t == 0) carry = 0;
     __syncthreads();
-    for (unsigned start = 0; start < n; start += 1024) {
+    for (unsigned start = 0; start < n; start += blockDim.x) {
         unsigned i = start + t;
         unsigned long long v = i < n ? tot[i] : 0ull;
         unsigned long long incl = v;
@@ -168,7 +176,7 @@ __global__ void __launch_bounds__(1024) k_scan_bricks(const uint32_t *__restrict
         unsigned long long ex = carry + wb + incl - v;
         if (i < n) base[i] = (uint32_t)ex;
         __syncthreads();
-        if (t == 1023) carry = ex + v;
+        if (t == (int)blockDim.x - 1) carry = ex + v;
         __syncthreads();
     }
     if (t == 0) {
@@ -177,18 +185,21 @@ __global__ void __launch_bounds__(1024) k_scan_bricks(const uint32_t *__restrict
     }
 }
 
+__global__ void __launch_bounds__(1024) k_scan_bricks(const uint32_t *__restrict__ tot, uint32_t *__restrict__ base,
+                                                      DevStatus *__restrict__ st, int64_t capacity) { b_scan_bricks(tot, base, st, capacity, blockIdx.x, gridDim.x); }
+
 // One workgroup per occupied brick: list start of every voxel = brick base +
 // exclusive prefix of visible counts inside the brick (x fastest).
-__global__ void __launch_bounds__(512) k_list_offsets(const uint32_t *__restrict__ words,
+__device__ __forceinline__ void b_list_offsets(const uint32_t *__restrict__ words,
                                                       const uint8_t *__restrict__ vis0,
                                                       const int32_t *__restrict__ list,
                                                       const uint32_t *__restrict__ base,
                                                       const DevStatus *__restrict__ st,
-                                                      uint32_t *__restrict__ cursor, uint64_t *__restrict__ cell) {
+                                                      uint32_t *__restrict__ cursor, uint64_t *__restrict__ cell, unsigned bid_, unsigned nblk_) {
     __shared__ unsigned wt[8];
     const unsigned nbk = st->n_bricks;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    for (unsigned sl = blockIdx.x; sl < nbk; sl += gridDim.x) {
+    for (unsigned sl = bid_; sl < nbk; sl += nblk_) {
         int64_t b = list[sl];
         unsigned c = vis0[b * kBrickVox + t] ? (words[b * kBrickVox + t] & 0xFFFFu) : 0u;
         unsigned incl = c;
@@ -207,6 +218,13 @@ __global__ void __launch_bounds__(512) k_list_offsets(const uint32_t *__restrict
     }
 }
 
+__global__ void __launch_bounds__(512) k_list_offsets(const uint32_t *__restrict__ words,
+                                                      const uint8_t *__restrict__ vis0,
+                                                      const int32_t *__restrict__ list,
+                                                      const uint32_t *__restrict__ base,
+                                                      const DevStatus *__restrict__ st,
+                                                      uint32_t *__restrict__ cursor, uint64_t *__restrict__ cell) { b_list_offsets(words, vis0, list, base, st, cursor, cell, blockIdx.x, gridDim.x); }
+
 struct ScatterArgs {
     const VRec *vrec;
     int64_t nv;
@@ -223,8 +241,8 @@ struct ScatterArgs {
 // Pass 2 (Section 3.3): a segment whose capsule AABB touches no visible brick
 // is skipped; otherwise its voxel set is walked again and every visible voxel
 // gets the segment id at an atomically claimed slot of its list.
-__global__ void __launch_bounds__(256) k_scatter(ScatterArgs a) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void b_scatter(ScatterArgs a, unsigned bid_, unsigned nblk_) {
+    int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     if (i + 1 >= a.nv) return;
     VRec A = a.vrec[i];
     if (!(A.flags & kSegValid)) return;
@@ -256,66 +274,86 @@ __global__ void __launch_bounds__(256) k_scatter(ScatterArgs a) {
     });
 }
 
+__global__ void __launch_bounds__(256) k_scatter(ScatterArgs a) { b_scatter(a, blockIdx.x, gridDim.x); }
+
 }  // namespace
+
+// Arguments of every culling and list kernel for one view of context c.
+struct CullPlan {
+    int64_t nb, nv;
+    int limit;  // < 0: no culling
+    GridArgs g;
+    CullArgs ca;
+    CullCells cells;
+    ScatterArgs sa;
+};
+
+static CullPlan make_cull_plan(const vrt_ctx *c, const int64_t E[3], int64_t limit) {
+    const Arenas &A = c->a;
+    CullPlan p;
+    for (int k = 0; k < 3; ++k) {
+        p.g.G[k] = c->dims[k];
+        p.g.nb[k] = c->dims[k] / 8;
+        p.g.ns[k] = (c->dims[k] + 63) / 64;
+    }
+    p.nb = (int64_t)p.g.nb[0] * p.g.nb[1] * p.g.nb[2];
+    p.nv = c->n_vertices;
+    p.limit = limit < 0 ? -1 : (int)(limit > INT_MAX ? INT_MAX : limit);
+    p.ca.g = p.g;
+    for (int k = 0; k < 3; ++k) p.ca.E[k] = E[k];
+    p.ca.limit = p.limit;
+    p.cells.super_blk = A.super_blk;
+    p.cells.brick_blk = A.brick_blk;
+    p.cells.blk = A.blk;
+    p.cells.nb0 = p.g.nb[0];
+    p.cells.nb1 = p.g.nb[1];
+    p.cells.ns0 = p.g.ns[0];
+    p.cells.ns1 = p.g.ns[1];
+    p.sa.vrec = A.vrec;
+    p.sa.nv = c->n_vertices;
+    p.sa.rq = c->rq;
+    for (int k = 0; k < 3; ++k) {
+        p.sa.G[k] = p.g.G[k];
+        p.sa.nb[k] = p.g.nb[k];
+    }
+    p.sa.vis0 = A.vis0;
+    p.sa.vis3 = A.vis3;
+    p.sa.cursor = A.cursor;
+    p.sa.ids = A.ids;
+    p.sa.capacity = c->desc.max_fragments;
+    return p;
+}
 
 hipError_t launch_cull(vrt_ctx *c, const int64_t E[3], int64_t limit, hipStream_t st) {
     Arenas &A = c->a;
-    GridArgs g;
-    for (int k = 0; k < 3; ++k) {
-        g.G[k] = c->dims[k];
-        g.nb[k] = c->dims[k] / 8;
-        g.ns[k] = (c->dims[k] + 63) / 64;
-    }
-    const int64_t nb = (int64_t)g.nb[0] * g.nb[1] * g.nb[2];
-    const int lim = limit < 0 ? -1 : (int)(limit > INT_MAX ? INT_MAX : limit);
-    VRT_LAUNCH(c, "k_cull_reset", st, k_cull_reset<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(A.vis3, nb, A.status));
-    if (lim >= 0) {
-        CullArgs ca;
-        ca.g = g;
-        for (int k = 0; k < 3; ++k) ca.E[k] = E[k];
-        ca.limit = lim;
-        CullCells cells;
-        cells.super_blk = A.super_blk;
-        cells.brick_blk = A.brick_blk;
-        cells.blk = A.blk;
-        cells.nb0 = g.nb[0];
-        cells.nb1 = g.nb[1];
-        cells.ns0 = g.ns[0];
-        cells.ns1 = g.ns[1];
-        VRT_LAUNCH(c, "k_cull_walk", st,
-                   k_cull_walk<<<8192, 256, 0, st>>>(ca, cells, A.occ_list, A.status, A.vis0));
-    }
+    const CullPlan p = make_cull_plan(c, E, limit);
+    VRT_LAUNCH(c, "k_cull_reset", st,
+               k_cull_reset<<<(unsigned)((p.nb + 255) / 256), 256, 0, st>>>(A.vis3, p.nb, A.status));
+    if (p.limit >= 0)
+        VRT_LAUNCH(c, "k_cull_walk", st, k_cull_walk<<<8192, 256, 0, st>>>(p.ca, p.cells, A.occ_list, A.status, A.vis0));
     VRT_LAUNCH(c, "k_cull_brick", st,
-               k_cull_brick<<<4096, 512, 0, st>>>(lim, g, A.words, A.brick_list, A.status, A.vis0, A.vis1, A.vis2, A.vis3,
-                                                  A.brick_total));
+               k_cull_brick<<<4096, 512, 0, st>>>(p.limit, p.g, A.words, A.brick_list, A.status, A.vis0, A.vis1, A.vis2,
+                                                  A.vis3, A.brick_total));
     const uint8_t *src = A.vis3;
-    int sx = g.nb[0], sy = g.nb[1], sz = g.nb[2];
+    int sx = p.g.nb[0], sy = p.g.nb[1], sz = p.g.nb[2];
     for (int L = 4; L < c->n_levels; ++L) {
         const Level &lv = c->levels[L];
         uint8_t *dst = A.vis_hi + lv.offset;
-        int64_t n = (int64_t)lv.dims[0] * lv.dims[1] * lv.dims[2];
-        VRT_LAUNCH(c, "k_mip_or", st, k_mip_or<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, sx, sy, sz, dst, lv.dims[0], lv.dims[1], lv.dims[2]));
+        const int64_t n = (int64_t)lv.dims[0] * lv.dims[1] * lv.dims[2];
+        VRT_LAUNCH(c, "k_mip_or", st,
+                   k_mip_or<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, sx, sy, sz, dst, lv.dims[0], lv.dims[1],
+                                                                         lv.dims[2]));
         src = dst;
         sx = lv.dims[0];
         sy = lv.dims[1];
         sz = lv.dims[2];
     }
-    VRT_LAUNCH(c, "k_scan_bricks", st, k_scan_bricks<<<1, 1024, 0, st>>>(A.brick_total, A.brick_base, A.status, c->desc.max_fragments));
-    VRT_LAUNCH(c, "k_list_offsets", st, k_list_offsets<<<4096, 512, 0, st>>>(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor, A.cell));
-    ScatterArgs sa;
-    sa.vrec = A.vrec;
-    sa.nv = c->n_vertices;
-    sa.rq = c->rq;
-    for (int k = 0; k < 3; ++k) {
-        sa.G[k] = g.G[k];
-        sa.nb[k] = g.nb[k];
-    }
-    sa.vis0 = A.vis0;
-    sa.vis3 = A.vis3;
-    sa.cursor = A.cursor;
-    sa.ids = A.ids;
-    sa.capacity = c->desc.max_fragments;
-    VRT_LAUNCH(c, "k_scatter", st, k_scatter<<<(unsigned)((c->n_vertices + 255) / 256), 256, 0, st>>>(sa));
+    VRT_LAUNCH(c, "k_scan_bricks", st,
+               k_scan_bricks<<<1, 1024, 0, st>>>(A.brick_total, A.brick_base, A.status, c->desc.max_fragments));
+    VRT_LAUNCH(c, "k_list_offsets", st,
+               k_list_offsets<<<4096, 512, 0, st>>>(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor,
+                                                    A.cell));
+    VRT_LAUNCH(c, "k_scatter", st, k_scatter<<<(unsigned)((p.nv + 255) / 256), 256, 0, st>>>(p.sa));
     return hipGetLastError();
 }
 

@@ -82,6 +82,13 @@ struct Arenas {
     unsigned long long *stat_acc = nullptr; // [16]
 };
 
+// Grid extents shared by the per-brick kernels.
+struct GridArgs {
+    int G[3];
+    int nb[3];  // bricks per axis
+    int ns[3];  // 64^3 cells per axis
+};
+
 // Event-pair profiler (host side); disabled unless vrt_profile_enable.
 struct Profiler {
     static constexpr int kMaxPairs = 65536;

@@ -535,17 +535,24 @@ __device__ __forceinline__ void flush_counters(const TraceArgs &a, const Counter
     if (lane == 0 && mx) atomicMax(&a.stat_acc[7], mx);
 }
 
-__global__ void k_trace_begin(DevStatus *st) { st->n_queue = 0; }
+__device__ __forceinline__ void b_trace_begin(DevStatus *st, unsigned bid_, unsigned nblk_) { st->n_queue = 0; }
+
+__global__ void k_trace_begin(DevStatus *st) { b_trace_begin(st, blockIdx.x, gridDim.x); }
 
 // Phase 1, one thread per pixel (a 64-lane wavefront covers an 8x8 tile):
 // primary ray, clip to the box of visible bricks, march through empty cells to
 // the first visible voxel with a list.  Rays that reach one are appended to the
 // queue (wave-aggregated); the others are written as misses.
+// Block tile of the march phase: 16 pixels wide, 8 rows per pair of wavefronts.
+__device__ __host__ inline int march_tile_rows(int threads) { return (threads / 128) * 8; }
+
 template <bool kStats>
-__global__ void __launch_bounds__(256) k_trace_march(TraceArgs a) {
+__device__ __forceinline__ void b_trace_march(TraceArgs a, unsigned bid_, unsigned nblk_) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int px = blockIdx.x * 16 + (wv & 1) * 8 + (lane & 7);
-    const int py = blockIdx.y * 16 + (wv >> 1) * 8 + (lane >> 3);
+    const int tiles_x = (a.p.W + 15) / 16;
+    const int bx = (int)(bid_ % (unsigned)tiles_x), by = (int)(bid_ / (unsigned)tiles_x);
+    const int px = bx * 16 + (wv & 1) * 8 + (lane & 7);
+    const int py = by * march_tile_rows(blockDim.x) + (wv >> 1) * 8 + (lane >> 3);
     const bool live = px < a.p.W && py < a.p.H;
     const float3 D = primary_dir(a.p, live ? px : 0, live ? py : 0);
     const Ray r = make_ray(a.p, D);
@@ -579,15 +586,18 @@ __global__ void __launch_bounds__(256) k_trace_march(TraceArgs a) {
     if (live && !found) write_pixel(a, (int64_t)py * a.p.W + px, Shade());
 }
 
+template <bool kStats>
+__global__ void __launch_bounds__(256) k_trace_march(TraceArgs a) { b_trace_march<kStats>(a, blockIdx.x, gridDim.x); }
+
 // Phase 2, one kGroup-lane group per queued ray: lists, capsule tests and
 // compositing, continuing the walk until the ray is finished.  All lanes of a
 // group follow the same walk; list entries are split across them.
 template <bool kStats, int kForm>
-__global__ void __launch_bounds__(256) k_trace_shade(TraceArgs a) {
+__device__ __forceinline__ void b_trace_shade(TraceArgs a, unsigned bid_, unsigned nblk_) {
     const int lane = threadIdx.x & 63;
     const unsigned n = a.st->n_queue;
-    const unsigned ngroups = gridDim.x * (blockDim.x / kGroup);
-    const unsigned grp = blockIdx.x * (blockDim.x / kGroup) + threadIdx.x / kGroup;
+    const unsigned ngroups = nblk_ * (blockDim.x / kGroup);
+    const unsigned grp = bid_ * (blockDim.x / kGroup) + threadIdx.x / kGroup;
     // every group runs the same number of rounds so counters can be reduced per wave
     const unsigned rounds = (n + ngroups - 1) / ngroups;
     for (unsigned rd = 0; rd < rounds; ++rd) {
@@ -624,8 +634,8 @@ __global__ void __launch_bounds__(256) k_trace_shade(TraceArgs a) {
     }
 }
 
-__global__ void k_debug_rays(TraceParams p, const int64_t *__restrict__ pix, int64_t n, float *__restrict__ dirs) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void b_debug_rays(TraceParams p, const int64_t *__restrict__ pix, int64_t n, float *__restrict__ dirs, unsigned bid_, unsigned nblk_) {
+    int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t q = pix[i];
     int px = (int)(q % p.W), py = (int)(q / p.W);
@@ -635,26 +645,34 @@ __global__ void k_debug_rays(TraceParams p, const int64_t *__restrict__ pix, int
     dirs[3 * i + 2] = d.z;
 }
 
+template <bool kStats, int kForm>
+__global__ void __launch_bounds__(256) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm>(a, blockIdx.x, gridDim.x); }
+
+__global__ void k_debug_rays(TraceParams p, const int64_t *__restrict__ pix, int64_t n, float *__restrict__ dirs) { b_debug_rays(p, pix, n, dirs, blockIdx.x, gridDim.x); }
+
 // Clears the statistics marks of the occupied bricks, the segments and the counters.
-__global__ void k_stat_clear(const int32_t *__restrict__ list, const DevStatus *__restrict__ st, int64_t nv,
-                             uint8_t *__restrict__ vox, uint8_t *__restrict__ seg, unsigned long long *__restrict__ acc) {
+__device__ __forceinline__ void b_stat_clear(const int32_t *__restrict__ list, const DevStatus *__restrict__ st, int64_t nv,
+                             uint8_t *__restrict__ vox, uint8_t *__restrict__ seg, unsigned long long *__restrict__ acc, unsigned bid_, unsigned nblk_) {
     const unsigned nb = st->n_bricks;
-    for (unsigned sl = blockIdx.x; sl < nb; sl += gridDim.x) {
+    for (unsigned sl = bid_; sl < nb; sl += nblk_) {
         const int64_t b = list[sl];
         for (int t = threadIdx.x; t < kBrickVox; t += blockDim.x) vox[b * kBrickVox + t] = 0;
     }
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x; i < nv; i += (int64_t)nblk_ * blockDim.x)
         seg[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x < 16) acc[threadIdx.x] = 0;
+    if (bid_ == 0 && threadIdx.x < 16) acc[threadIdx.x] = 0;
 }
 
+__global__ void k_stat_clear(const int32_t *__restrict__ list, const DevStatus *__restrict__ st, int64_t nv,
+                             uint8_t *__restrict__ vox, uint8_t *__restrict__ seg, unsigned long long *__restrict__ acc) { b_stat_clear(list, st, nv, vox, seg, acc, blockIdx.x, gridDim.x); }
+
 // Distinct voxels read, their list lengths, and distinct segments tested.
-__global__ void k_stat_reduce(const int32_t *__restrict__ list, const DevStatus *__restrict__ st, int64_t nv,
+__device__ __forceinline__ void b_stat_reduce(const int32_t *__restrict__ list, const DevStatus *__restrict__ st, int64_t nv,
                               const uint8_t *__restrict__ vox, const uint64_t *__restrict__ cell,
-                              const uint8_t *__restrict__ seg, unsigned long long *__restrict__ acc) {
+                              const uint8_t *__restrict__ seg, unsigned long long *__restrict__ acc, unsigned bid_, unsigned nblk_) {
     unsigned long long nvx = 0, nent = 0, nseg = 0;
     const unsigned nb = st->n_bricks;
-    for (unsigned sl = blockIdx.x; sl < nb; sl += gridDim.x) {
+    for (unsigned sl = bid_; sl < nb; sl += nblk_) {
         const int64_t b = list[sl];
         for (int t = threadIdx.x; t < kBrickVox; t += blockDim.x)
             if (vox[b * kBrickVox + t]) {
@@ -662,7 +680,7 @@ __global__ void k_stat_reduce(const int32_t *__restrict__ list, const DevStatus 
                 nent += cell[b * kBrickVox + t] >> 32;
             }
     }
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x; i < nv; i += (int64_t)nblk_ * blockDim.x)
         nseg += seg[i];
     unsigned long long v[3] = {nvx, nent, nseg};
     for (int k = 0; k < 3; ++k) {
@@ -671,6 +689,10 @@ __global__ void k_stat_reduce(const int32_t *__restrict__ list, const DevStatus 
         if ((threadIdx.x & 63) == 0 && x) atomicAdd(&acc[8 + k], x);
     }
 }
+
+__global__ void k_stat_reduce(const int32_t *__restrict__ list, const DevStatus *__restrict__ st, int64_t nv,
+                              const uint8_t *__restrict__ vox, const uint64_t *__restrict__ cell,
+                              const uint8_t *__restrict__ seg, unsigned long long *__restrict__ acc) { b_stat_reduce(list, st, nv, vox, cell, seg, acc, blockIdx.x, gridDim.x); }
 
 }  // namespace
 
@@ -710,7 +732,7 @@ static constexpr unsigned kShadeBlocks = 4096;
 
 hipError_t launch_trace(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st) {
     TraceArgs a = trace_args(c, p, img);
-    dim3 grid((p.W + 15) / 16, (p.H + 15) / 16);
+    const unsigned grid = (unsigned)(((p.W + 15) / 16) * ((p.H + march_tile_rows(256) - 1) / march_tile_rows(256)));
     VRT_LAUNCH(c, "k_trace_begin", st, k_trace_begin<<<1, 1, 0, st>>>(a.st));
     VRT_LAUNCH(c, "k_trace_march", st, k_trace_march<false><<<grid, 256, 0, st>>>(a));
     if (c->desc.form == VRT_FORM_FP16)
@@ -723,7 +745,7 @@ hipError_t launch_trace(vrt_ctx *c, const TraceParams &p, const vrt_image *img, 
 hipError_t launch_trace_stats(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st) {
     TraceArgs a = trace_args(c, p, img);
     k_stat_clear<<<1024, 256, 0, st>>>(c->a.brick_list, c->a.status, c->n_vertices, a.stat_vox, a.stat_seg, a.stat_acc);
-    dim3 grid((p.W + 15) / 16, (p.H + 15) / 16);
+    const unsigned grid = (unsigned)(((p.W + 15) / 16) * ((p.H + march_tile_rows(256) - 1) / march_tile_rows(256)));
     k_trace_begin<<<1, 1, 0, st>>>(a.st);
     k_trace_march<true><<<grid, 256, 0, st>>>(a);
     if (c->desc.form == VRT_FORM_FP16) k_trace_shade<true, VRT_FORM_FP16><<<kShadeBlocks, 256, 0, st>>>(a);

@@ -7,21 +7,24 @@ namespace vrt {
 namespace {
 
 // Zeroes the level-0 words of every brick the previous frame occupied.
-__global__ void k_clear_prev(uint32_t *__restrict__ words, const int32_t *__restrict__ brick_list,
-                             const DevStatus *__restrict__ st) {
+__device__ __forceinline__ void b_clear_prev(uint32_t *__restrict__ words, const int32_t *__restrict__ brick_list,
+                             const DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
     const unsigned nb = st->n_bricks;
     uint4 *w4 = reinterpret_cast<uint4 *>(words);
-    for (unsigned slot = blockIdx.x; slot < nb; slot += gridDim.x) {
+    for (unsigned slot = bid_; slot < nb; slot += nblk_) {
         int64_t b = brick_list[slot];
-        w4[b * (kBrickVox / 4) + threadIdx.x] = make_uint4(0, 0, 0, 0);  // 128 threads x 4 words
+        for (int t = threadIdx.x; t < kBrickVox / 4; t += blockDim.x) w4[b * (kBrickVox / 4) + t] = make_uint4(0, 0, 0, 0);
     }
 }
 
+__global__ void k_clear_prev(uint32_t *__restrict__ words, const int32_t *__restrict__ brick_list,
+                             const DevStatus *__restrict__ st) { b_clear_prev(words, brick_list, st, blockIdx.x, gridDim.x); }
+
 // Clears the per-frame brick-level state: level-3 occupancy, blocking flags
 // of bricks and 64^3 cells, the blocking box and the frame counters.
-__global__ void k_reset(uint16_t *__restrict__ occ3, uint8_t *__restrict__ brick_blk, int64_t nbricks,
-                        uint8_t *__restrict__ super_blk, int64_t nsupers, DevStatus *__restrict__ st) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void b_reset(uint16_t *__restrict__ occ3, uint8_t *__restrict__ brick_blk, int64_t nbricks,
+                        uint8_t *__restrict__ super_blk, int64_t nsupers, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
+    int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     if (i < nbricks) {
         occ3[i] = 0;
         brick_blk[i] = 0;
@@ -34,6 +37,9 @@ __global__ void k_reset(uint16_t *__restrict__ occ3, uint8_t *__restrict__ brick
         st->bbox[3] = st->bbox[4] = st->bbox[5] = INT_MIN;
     }
 }
+
+__global__ void k_reset(uint16_t *__restrict__ occ3, uint8_t *__restrict__ brick_blk, int64_t nbricks,
+                        uint8_t *__restrict__ super_blk, int64_t nsupers, DevStatus *__restrict__ st) { b_reset(occ3, brick_blk, nbricks, super_blk, nsupers, st, blockIdx.x, gridDim.x); }
 
 // fixed-point coordinate: rint((x - origin) * s) as two binary32 operations
 __device__ __forceinline__ bool quantize1(float x, float o, float s, int &q) {
@@ -63,8 +69,8 @@ struct IngestArgs {
 
 // One thread per vertex: polyline lookup by binary search over the offsets,
 // quantization, segment/interior flags and the central-difference clip normal.
-__global__ void k_ingest(IngestArgs a, VRec *__restrict__ out, DevStatus *__restrict__ st) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void b_ingest(IngestArgs a, VRec *__restrict__ out, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
+    int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     if (i >= a.nv) return;
     if (i == 0 && (a.off[0] != 0 || a.off[a.np] != a.nv)) set_err(st, kErrInvalid);
     int64_t lo = 0, hi = a.np - 1;  // largest p with off[p] <= i
@@ -104,6 +110,8 @@ __global__ void k_ingest(IngestArgs a, VRec *__restrict__ out, DevStatus *__rest
     if (!ok) set_err(st, kErrRange);
     out[i] = r;
 }
+
+__global__ void k_ingest(IngestArgs a, VRec *__restrict__ out, DevStatus *__restrict__ st) { b_ingest(a, out, st, blockIdx.x, gridDim.x); }
 
 // Occupancy quantum of one (segment, voxel) pair: the clipped-capsule SDF at
 // the voxel centre with the PWAA radius clamp (Alg. 2, Alg. 3), evaluated as a
@@ -148,8 +156,8 @@ __device__ __forceinline__ int occupancy_quantum(const VRec &A, const VRec &B, f
 // of the brick holding its midpoint (binary16, voxel units) and its clip
 // normals in binary16.  Quantized positions are multiples of 1/256 voxel, so
 // offsets below 8 voxels are exact.
-__global__ void k_pack16(const VRec *__restrict__ vrec, int64_t nv, SRec16 *__restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void b_pack16(const VRec *__restrict__ vrec, int64_t nv, SRec16 *__restrict__ out, unsigned bid_, unsigned nblk_) {
+    const int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     if (i + 1 >= nv) return;
     const VRec A = vrec[i];
     if (!(A.flags & kSegValid)) return;
@@ -177,6 +185,8 @@ __global__ void k_pack16(const VRec *__restrict__ vrec, int64_t nv, SRec16 *__re
     out[i] = r;
 }
 
+__global__ void k_pack16(const VRec *__restrict__ vrec, int64_t nv, SRec16 *__restrict__ out) { b_pack16(vrec, nv, out, blockIdx.x, gridDim.x); }
+
 struct CountArgs {
     const VRec *vrec;
     int64_t nv;
@@ -190,8 +200,8 @@ struct CountArgs {
 
 // Pass 1: one thread per segment walks its voxel set and adds
 // 1 + (q << 16) to each voxel's packed word (count low, occupancy high).
-__global__ void __launch_bounds__(256) k_vox_count(CountArgs a, DevStatus *__restrict__ st) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void b_vox_count(CountArgs a, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
+    int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     unsigned long long nfrag = 0;
     if (i + 1 < a.nv) {
         VRec A = a.vrec[i];
@@ -222,56 +232,79 @@ __global__ void __launch_bounds__(256) k_vox_count(CountArgs a, DevStatus *__res
     if ((threadIdx.x & 63) == 0 && nfrag) atomicAdd(&st->n_fragments, nfrag);
 }
 
+__global__ void __launch_bounds__(256) k_vox_count(CountArgs a, DevStatus *__restrict__ st) { b_vox_count(a, st, blockIdx.x, gridDim.x); }
+
 // Single workgroup: compacts the touched-brick flags into the ascending list
 // of occupied bricks, writes each brick's slot (or -1), clears the flags.
+// Rounds of 16 flags per thread (coalesced), a block-wide exclusive scan of
+// the per-thread counts and a running carry keep the list in brick order.
+__device__ __forceinline__ void b_brick_compact(uint8_t *__restrict__ flag, int64_t nb,
+                                                int32_t *__restrict__ list, int32_t *__restrict__ slot,
+                                                DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
+    __shared__ unsigned wtot[16];
+    __shared__ unsigned carry;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += (int64_t)blockDim.x * 16) {
+        const int64_t b0 = base + (int64_t)t * 16;
+        uint8_t f[16];
+        if (b0 + 16 <= nb) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(flag + b0);
+            const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int k = 0; k < 16; ++k) f[k] = (uint8_t)(qq[k >> 2] >> (8 * (k & 3)));
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) f[k] = b0 + k < nb ? flag[b0 + k] : 0;
+        }
+        unsigned cnt = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cnt += f[k] ? 1u : 0u;
+        unsigned incl = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        if (lane == 63) wtot[w] = incl;
+        __syncthreads();
+        unsigned pos = carry + incl - cnt, round = 0;
+        for (int k = 0; k < nw; ++k) {
+            if (k < w) pos += wtot[k];
+            round += wtot[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int64_t b = b0 + k;
+            if (b >= nb) break;
+            if (f[k]) {
+                list[pos] = (int32_t)b;
+                slot[b] = (int32_t)pos;
+                ++pos;
+                flag[b] = 0;
+            } else {
+                slot[b] = -1;
+            }
+        }
+        __syncthreads();
+        if (t == 0) carry += round;
+        __syncthreads();
+    }
+    if (t == 0) st->n_bricks = carry;
+}
+
 __global__ void __launch_bounds__(1024) k_brick_compact(uint8_t *__restrict__ flag, int64_t nb,
                                                         int32_t *__restrict__ list, int32_t *__restrict__ slot,
-                                                        DevStatus *__restrict__ st) {
-    __shared__ unsigned warp_tot[16];
-    __shared__ unsigned warp_base[16];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int64_t per = (nb + 1023) / 1024;
-    const int64_t b0 = (int64_t)t * per, b1 = b0 + per < nb ? b0 + per : nb;
-    unsigned cnt = 0;
-    for (int64_t b = b0; b < b1; ++b) cnt += flag[b] ? 1u : 0u;
-    // exclusive scan over the block
-    unsigned incl = cnt;
-    for (int o = 1; o < 64; o <<= 1) {
-        unsigned v = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += v;
-    }
-    if (lane == 63) warp_tot[w] = incl;
-    __syncthreads();
-    if (t == 0) {
-        unsigned run = 0;
-        for (int k = 0; k < 16; ++k) {
-            warp_base[k] = run;
-            run += warp_tot[k];
-        }
-        st->n_bricks = run;
-    }
-    __syncthreads();
-    unsigned pos = warp_base[w] + incl - cnt;
-    for (int64_t b = b0; b < b1; ++b) {
-        if (flag[b]) {
-            list[pos] = (int32_t)b;
-            slot[b] = (int32_t)pos;
-            ++pos;
-            flag[b] = 0;
-        } else {
-            slot[b] = -1;
-        }
-    }
-}
+                                                        DevStatus *__restrict__ st) { b_brick_compact(flag, nb, list, slot, st, blockIdx.x, gridDim.x); }
 
 // One workgroup (512 threads) per occupied brick: level-0 occupancy (saturated
 // at 1.0; a voxel with 256 or more fragments is full) and the in-brick mips
 // 1..3, each parent floor((sum of 8 children + 4) / 8).
-__global__ void __launch_bounds__(512) k_occ_brick(const uint32_t *__restrict__ words,
+__device__ __forceinline__ void b_occ_brick(const uint32_t *__restrict__ words,
                                                    const int32_t *__restrict__ list, DevStatus *__restrict__ st,
                                                    uint16_t *__restrict__ occ0, uint16_t *__restrict__ occ1,
                                                    uint16_t *__restrict__ occ2, uint16_t *__restrict__ occ3,
-                                                   uint32_t *__restrict__ occ_list) {
+                                                   uint32_t *__restrict__ occ_list, unsigned bid_, unsigned nblk_) {
     __shared__ uint16_t s0[512];
     __shared__ uint16_t s1[64];
     __shared__ uint16_t s2[8];
@@ -279,7 +312,7 @@ __global__ void __launch_bounds__(512) k_occ_brick(const uint32_t *__restrict__ 
     __shared__ unsigned base;
     const unsigned nbk = st->n_bricks;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    for (unsigned sl = blockIdx.x; sl < nbk; sl += gridDim.x) {
+    for (unsigned sl = bid_; sl < nbk; sl += nblk_) {
         int64_t b = list[sl];
         uint32_t wd = words[b * kBrickVox + t];
         uint32_t cnt = wd & 0xFFFFu, sum = wd >> 16;
@@ -330,11 +363,11 @@ __global__ void __launch_bounds__(512) k_occ_brick(const uint32_t *__restrict__ 
     }
 }
 
-struct GridArgs {
-    int G[3];
-    int nb[3];  // bricks per axis
-    int ns[3];  // 64^3 cells per axis
-};
+__global__ void __launch_bounds__(512) k_occ_brick(const uint32_t *__restrict__ words,
+                                                   const int32_t *__restrict__ list, DevStatus *__restrict__ st,
+                                                   uint16_t *__restrict__ occ0, uint16_t *__restrict__ occ1,
+                                                   uint16_t *__restrict__ occ2, uint16_t *__restrict__ occ3,
+                                                   uint32_t *__restrict__ occ_list) { b_occ_brick(words, list, st, occ0, occ1, occ2, occ3, occ_list, blockIdx.x, gridDim.x); }
 
 // Level-0 occupancy of any voxel (0 outside the grid and in empty bricks).
 __device__ __forceinline__ unsigned occ_at(const GridArgs &g, const uint16_t *__restrict__ occ0,
@@ -348,14 +381,14 @@ __device__ __forceinline__ unsigned occ_at(const GridArgs &g, const uint16_t *__
 // Erosion (Section 3.2): the minimum occupancy over the voxel and its 6 face
 // neighbours; the voxel blocks culling rays when that minimum is full.  Also
 // marks bricks and 64^3 cells holding a blocking voxel and the blocking box.
-__global__ void __launch_bounds__(512) k_erode(GridArgs g, const uint16_t *__restrict__ occ0,
+__device__ __forceinline__ void b_erode(GridArgs g, const uint16_t *__restrict__ occ0,
                                                const int32_t *__restrict__ list, const int32_t *__restrict__ slot,
                                                DevStatus *__restrict__ st, uint8_t *__restrict__ blk,
-                                               uint8_t *__restrict__ brick_blk, uint8_t *__restrict__ super_blk) {
+                                               uint8_t *__restrict__ brick_blk, uint8_t *__restrict__ super_blk, unsigned bid_, unsigned nblk_) {
     __shared__ int bb[6];
     const unsigned nbk = st->n_bricks;
     const int t = threadIdx.x;
-    for (unsigned sl = blockIdx.x; sl < nbk; sl += gridDim.x) {
+    for (unsigned sl = bid_; sl < nbk; sl += nblk_) {
         int64_t b = list[sl];
         if (t < 3) bb[t] = INT_MAX;
         else if (t < 6) bb[t] = INT_MIN;
@@ -389,11 +422,16 @@ __global__ void __launch_bounds__(512) k_erode(GridArgs g, const uint16_t *__res
     }
 }
 
+__global__ void __launch_bounds__(512) k_erode(GridArgs g, const uint16_t *__restrict__ occ0,
+                                               const int32_t *__restrict__ list, const int32_t *__restrict__ slot,
+                                               DevStatus *__restrict__ st, uint8_t *__restrict__ blk,
+                                               uint8_t *__restrict__ brick_blk, uint8_t *__restrict__ super_blk) { b_erode(g, occ0, list, slot, st, blk, brick_blk, super_blk, blockIdx.x, gridDim.x); }
+
 // Averaging step on dense grids (levels >= 3): parent = floor((sum of the
 // children inside the grid + 4) / 8), parent dims = ceil(child dims / 2).
-__global__ void k_mip_avg(const uint16_t *__restrict__ src, int sx, int sy, int sz, uint16_t *__restrict__ dst, int dx,
-                          int dy, int dz) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void b_mip_avg(const uint16_t *__restrict__ src, int sx, int sy, int sz, uint16_t *__restrict__ dst, int dx,
+                          int dy, int dz, unsigned bid_, unsigned nblk_) {
+    int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     if (i >= (int64_t)dx * dy * dz) return;
     int x = (int)(i % dx), y = (int)((i / dx) % dy), z = (int)(i / ((int64_t)dx * dy));
     unsigned s = 0;
@@ -404,63 +442,82 @@ __global__ void k_mip_avg(const uint16_t *__restrict__ src, int sx, int sy, int 
     dst[i] = (uint16_t)((s + 4u) >> 3);
 }
 
+__global__ void k_mip_avg(const uint16_t *__restrict__ src, int sx, int sy, int sz, uint16_t *__restrict__ dst, int dx,
+                          int dy, int dz) { b_mip_avg(src, sx, sy, sz, dst, dx, dy, dz, blockIdx.x, gridDim.x); }
+
 }  // namespace
+
+// Arguments of every voxelization kernel for one frame of context c.
+struct VoxPlan {
+    int64_t nb, ns, nv;
+    bool fp16;
+    GridArgs g;
+    IngestArgs ia;
+    CountArgs ca;
+};
+
+static VoxPlan make_vox_plan(const vrt_ctx *c, const vrt_lines *L, float s_q) {
+    const Arenas &A = c->a;
+    VoxPlan p;
+    for (int k = 0; k < 3; ++k) {
+        p.g.G[k] = c->dims[k];
+        p.g.nb[k] = c->dims[k] / 8;
+        p.g.ns[k] = (c->dims[k] + 63) / 64;
+    }
+    p.nb = (int64_t)p.g.nb[0] * p.g.nb[1] * p.g.nb[2];
+    p.ns = (int64_t)p.g.ns[0] * p.g.ns[1] * p.g.ns[2];
+    p.nv = L->n_vertices;
+    p.fp16 = c->desc.form == VRT_FORM_FP16;
+    p.ia.xyz = L->xyz;
+    p.ia.off = L->poly_offsets;
+    p.ia.np = L->n_polylines;
+    p.ia.nv = L->n_vertices;
+    for (int k = 0; k < 3; ++k) p.ia.o[k] = c->origin[k];
+    p.ia.s = s_q;
+    p.ca.vrec = A.vrec;
+    p.ca.nv = L->n_vertices;
+    p.ca.rq = c->rq;
+    const int64_t rcl = c->rq > kRMinQ ? c->rq : kRMinQ;
+    const double ratio = (double)c->rq / (double)rcl;
+    p.ca.rc = (float)rcl;
+    p.ca.corr = (float)(ratio * ratio);
+    for (int k = 0; k < 3; ++k) p.ca.G[k] = c->dims[k];
+    p.ca.nbx = c->dims[0] / 8;
+    p.ca.nby = c->dims[1] / 8;
+    p.ca.words = A.words;
+    p.ca.brick_flag = A.brick_flag;
+    return p;
+}
 
 hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *L, float s_q, hipStream_t st) {
     Arenas &A = c->a;
-    const int64_t nb = (int64_t)(c->dims[0] / 8) * (c->dims[1] / 8) * (c->dims[2] / 8);
+    const VoxPlan p = make_vox_plan(c, L, s_q);
+    const unsigned eb = (unsigned)((p.nv + 255) / 256);
     VRT_LAUNCH(c, "k_clear_prev", st, k_clear_prev<<<2048, 128, 0, st>>>(A.words, A.brick_list, A.status));
-    GridArgs g;
-    for (int k = 0; k < 3; ++k) {
-        g.G[k] = c->dims[k];
-        g.nb[k] = c->dims[k] / 8;
-        g.ns[k] = (c->dims[k] + 63) / 64;
-    }
-    const int64_t ns = (int64_t)g.ns[0] * g.ns[1] * g.ns[2];
     VRT_LAUNCH(c, "k_reset", st,
-               k_reset<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(A.occ3, A.brick_blk, nb, A.super_blk, ns,
-                                                                     A.status));
-    IngestArgs ia;
-    ia.xyz = L->xyz;
-    ia.off = L->poly_offsets;
-    ia.np = L->n_polylines;
-    ia.nv = L->n_vertices;
-    for (int k = 0; k < 3; ++k) ia.o[k] = c->origin[k];
-    ia.s = s_q;
-    VRT_LAUNCH(c, "k_ingest", st, k_ingest<<<(unsigned)((L->n_vertices + 255) / 256), 256, 0, st>>>(ia, A.vrec, A.status));
-    CountArgs ca;
-    ca.vrec = A.vrec;
-    ca.nv = L->n_vertices;
-    ca.rq = c->rq;
-    int64_t rcl = c->rq > kRMinQ ? c->rq : kRMinQ;
-    double ratio = (double)c->rq / (double)rcl;
-    ca.rc = (float)rcl;
-    ca.corr = (float)(ratio * ratio);
-    for (int k = 0; k < 3; ++k) ca.G[k] = c->dims[k];
-    ca.nbx = c->dims[0] / 8;
-    ca.nby = c->dims[1] / 8;
-    ca.words = A.words;
-    ca.brick_flag = A.brick_flag;
-    if (c->desc.form == VRT_FORM_FP16)
-        VRT_LAUNCH(c, "k_pack16", st,
-                   k_pack16<<<(unsigned)((L->n_vertices + 255) / 256), 256, 0, st>>>(A.vrec, L->n_vertices, A.srec16));
-    VRT_LAUNCH(c, "k_vox_count", st, k_vox_count<<<(unsigned)((L->n_vertices + 255) / 256), 256, 0, st>>>(ca, A.status));
-    VRT_LAUNCH(c, "k_brick_compact", st, k_brick_compact<<<1, 1024, 0, st>>>(A.brick_flag, nb, A.brick_list, A.brick_slot, A.status));
+               k_reset<<<(unsigned)((p.nb + 255) / 256), 256, 0, st>>>(A.occ3, A.brick_blk, p.nb, A.super_blk, p.ns,
+                                                                       A.status));
+    VRT_LAUNCH(c, "k_ingest", st, k_ingest<<<eb, 256, 0, st>>>(p.ia, A.vrec, A.status));
+    if (p.fp16) VRT_LAUNCH(c, "k_pack16", st, k_pack16<<<eb, 256, 0, st>>>(A.vrec, p.nv, A.srec16));
+    VRT_LAUNCH(c, "k_vox_count", st, k_vox_count<<<eb, 256, 0, st>>>(p.ca, A.status));
+    VRT_LAUNCH(c, "k_brick_compact", st,
+               k_brick_compact<<<1, 1024, 0, st>>>(A.brick_flag, p.nb, A.brick_list, A.brick_slot, A.status));
     VRT_LAUNCH(c, "k_occ_brick", st,
                k_occ_brick<<<4096, 512, 0, st>>>(A.words, A.brick_list, A.status, A.occ0, A.occ1, A.occ2, A.occ3,
                                                  A.occ_list));
     VRT_LAUNCH(c, "k_erode", st,
-               k_erode<<<4096, 512, 0, st>>>(g, A.occ0, A.brick_list, A.brick_slot, A.status, A.blk, A.brick_blk,
+               k_erode<<<4096, 512, 0, st>>>(p.g, A.occ0, A.brick_list, A.brick_slot, A.status, A.blk, A.brick_blk,
                                              A.super_blk));
     // levels >= 4 from the dense level 3
     const uint16_t *src = A.occ3;
-    int sx = c->dims[0] / 8, sy = c->dims[1] / 8, sz = c->dims[2] / 8;
+    int sx = p.g.nb[0], sy = p.g.nb[1], sz = p.g.nb[2];
     for (int L4 = 4; L4 < c->n_levels; ++L4) {
         const Level &lv = c->levels[L4];
         uint16_t *dst = A.occ_hi + lv.offset;
-        int64_t n = (int64_t)lv.dims[0] * lv.dims[1] * lv.dims[2];
-        VRT_LAUNCH(c, "k_mip_avg", st, k_mip_avg<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, sx, sy, sz, dst, lv.dims[0], lv.dims[1],
-                                                               lv.dims[2]));
+        const int64_t n = (int64_t)lv.dims[0] * lv.dims[1] * lv.dims[2];
+        VRT_LAUNCH(c, "k_mip_avg", st,
+                   k_mip_avg<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, sx, sy, sz, dst, lv.dims[0], lv.dims[1],
+                                                                          lv.dims[2]));
         src = dst;
         sx = lv.dims[0];
         sy = lv.dims[1];

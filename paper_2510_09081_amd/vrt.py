@@ -21,11 +21,13 @@ VRT_ERR_CAPACITY, VRT_ERR_COUNT_OVERFLOW, VRT_ERR_HIP = 4, 5, 6
 CULL_NONE, CULL_OPAQUE, CULL_ALPHA = 0, 1, 2
 TRACE_OPAQUE, TRACE_TRANSPARENT = 0, 1
 FORM_PLAIN, FORM_FP16 = 0, 1
+BATCH_PERSISTENT, BATCH_SEQUENTIAL = 0, 1
 
 EXPORTED = ["vrt_create", "vrt_destroy", "vrt_voxelize", "vrt_cull", "vrt_trace", "vrt_frame_status",
             "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_last_hip_error", "vrt_status_string",
             "vrt_profile_enable", "vrt_profile_read", "vrt_trace_stats_run", "vrt_graph_create",
-            "vrt_graph_launch", "vrt_graph_destroy"]
+            "vrt_graph_launch", "vrt_graph_destroy", "vrt_batch_create", "vrt_batch_run", "vrt_batch_context",
+            "vrt_batch_destroy"]
 
 
 class VrtError(RuntimeError):
@@ -74,6 +76,11 @@ class vrt_as_view(C.Structure):
                 ("ids", C.c_void_p)]
 
 
+class vrt_batch_item(C.Structure):
+    _fields_ = [("lines", vrt_lines), ("grid", vrt_grid), ("view", vrt_view), ("cam", vrt_camera),
+                ("image", vrt_image)]
+
+
 class vrt_kernel_time(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
@@ -108,6 +115,10 @@ def load():
         L.vrt_graph_create.argtypes = [P, C.POINTER(vrt_lines), C.POINTER(vrt_grid), C.POINTER(vrt_view),
                                        C.POINTER(vrt_camera), C.POINTER(vrt_image), C.c_int32, C.POINTER(P)]
         L.vrt_graph_launch.argtypes = [P, P]
+        L.vrt_batch_create.argtypes = [C.POINTER(vrt_desc), C.c_int32, C.POINTER(P)]
+        L.vrt_batch_run.argtypes = [P, C.POINTER(vrt_batch_item), C.c_int32, C.c_int32, P]
+        L.vrt_batch_context.argtypes = [P, C.c_int32, C.POINTER(P)]
+        L.vrt_batch_destroy.argtypes = [P]
         L.vrt_graph_destroy.argtypes = [P]
         L.vrt_trace_stats_run.argtypes = [P, C.POINTER(vrt_camera), C.POINTER(vrt_image), C.POINTER(vrt_trace_stats), P]
         L.vrt_profile_read.argtypes = [P, C.POINTER(vrt_kernel_time), C.c_int32, C.POINTER(C.c_int32)]
@@ -117,7 +128,8 @@ def load():
         for name in ["vrt_create", "vrt_destroy", "vrt_voxelize", "vrt_cull", "vrt_trace", "vrt_frame_status",
                      "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_profile_enable",
                      "vrt_profile_read", "vrt_trace_stats_run", "vrt_graph_create", "vrt_graph_launch",
-                     "vrt_graph_destroy"]:
+                     "vrt_graph_destroy", "vrt_batch_create", "vrt_batch_run", "vrt_batch_context",
+                     "vrt_batch_destroy"]:
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -271,6 +283,63 @@ class FrameGraph:
     def close(self):
         if self._h and self._h.value:
             _check(load().vrt_graph_destroy(self._h), "vrt_graph_destroy")
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+
+class _Borrowed(Context):
+    """A context owned by a batch (not destroyed by Python)."""
+
+    def __init__(self, handle):  # noqa: D401 - no allocation here
+        self._h = handle
+        self.device = 0
+        self.max_fragments = 0
+
+    def close(self):
+        self._h = C.c_void_p()
+
+
+class Batch:
+    """Many line sets built and traced together (one persistent launch, or set by set)."""
+
+    def __init__(self, capacities, device=0, form=FORM_PLAIN):
+        """capacities: list of (max_vertices, max_fragments, max_dim, max_pixels), one per set."""
+        n = len(capacities)
+        descs = (vrt_desc * n)()
+        for i, (mv, mf, md, mp) in enumerate(capacities):
+            descs[i] = vrt_desc(int(mv), int(mf), int(md), int(device), int(mp), int(form), 0)
+        h = C.c_void_p()
+        _check(load().vrt_batch_create(descs, n, C.byref(h)), "vrt_batch_create")
+        self._h = h
+        self.n = n
+
+    def run(self, items, mode=BATCH_PERSISTENT, stream=None):
+        """items: list of dicts with xyz, offsets, radius, origin, voxel_size, dims, view=(eye, mode, alpha, tau),
+        camera (vrt_camera), rgba, depth, first_id."""
+        arr = (vrt_batch_item * self.n)()
+        for i, it in enumerate(items):
+            x, o = it["xyz"], it["offsets"]
+            eye, cm, al, tau = it["view"]
+            arr[i] = vrt_batch_item(
+                vrt_lines(_ptr(x), _ptr(o), int(x.shape[0]), int(o.shape[0] - 1), float(it["radius"])),
+                vrt_grid(_f3(it["origin"]), float(it["voxel_size"]), (C.c_int32 * 3)(*[int(v) for v in it["dims"]])),
+                vrt_view(_f3(eye), int(cm), float(al), float(tau)), it["camera"],
+                vrt_image(_ptr(it["rgba"]), _ptr(it.get("depth")), _ptr(it.get("first_id"))))
+        _check(load().vrt_batch_run(self._h, arr, self.n, int(mode), _stream_ptr(stream)), "vrt_batch_run")
+
+    def context(self, i):
+        h = C.c_void_p()
+        _check(load().vrt_batch_context(self._h, int(i), C.byref(h)), "vrt_batch_context")
+        return _Borrowed(h)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(load().vrt_batch_destroy(self._h), "vrt_batch_destroy")
             self._h = C.c_void_p()
 
     def __del__(self):
