@@ -48,6 +48,122 @@ def kernel_bytes(name, n):
     return None
 
 
+def bench_dynamic(torch, vrt, synth, warmup):
+    """Dynamic pathlines: every frame re-advects the line set and rebuilds everything; the whole
+    frame (voxelize, alpha cull, lists, transparent trace) is one captured HIP graph replayed per
+    frame, against the same frames issued eagerly."""
+    frames = synth.pathline_frames()
+    traj, origin, vs, dims, radius = frames
+    S, L, F = traj.shape[0], 100, 120
+    traj_d = torch.from_numpy(traj.astype(np.float32)).cuda()
+    ls0 = synth.pathline_frame(frames, 0)
+    cam = synth.grid_camera(ls0, 1280, 720)
+    P = cam.width * cam.height
+    xyz = torch.from_numpy(ls0.xyz).cuda()
+    off = torch.from_numpy(ls0.offsets).cuda()
+    rgba = torch.empty(4 * P, device="cuda")
+    depth = torch.empty(P, device="cuda")
+    fid = torch.empty(P, dtype=torch.int32, device="cuda")
+    eye = np.asarray(cam.eye, np.float32)
+    cam_a = vrt.make_camera(cam.eye, cam.target, cam.up, cam.fovy_deg, cam.width, cam.height,
+                            vrt.TRACE_TRANSPARENT, 0.3)
+    ctx = vrt.Context(max_vertices=ls0.n_vertices, max_fragments=16 * ls0.n_segments, max_dim=max(dims),
+                      max_pixels=P)
+    view = (eye, vrt.CULL_ALPHA, 0.3, 1.0 / 256.0)
+    graph = ctx.frame_graph(xyz, off, radius, origin, vs, dims, [(view, cam_a, rgba, depth, fid)])
+    xv = xyz.view(S, L + 1, 3)
+
+    def load(f):
+        xv.copy_(traj_d[:, 2 * f:2 * f + L + 1])
+
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for f in range(warmup):
+        load(f)
+        graph.launch()
+    torch.cuda.synchronize()
+    ev0.record()
+    for f in range(F):
+        load(f)
+        graph.launch()
+    ev1.record()
+    torch.cuda.synchronize()
+    t_graph = ev0.elapsed_time(ev1) / F
+    st = ctx.frame_status()
+    ev0.record()
+    for f in range(F):
+        load(f)
+        ctx.voxelize(xyz, off, radius, origin, vs, dims)
+        ctx.cull(*view)
+        ctx.trace(cam_a, rgba, depth, fid)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_eager = ev0.elapsed_time(ev1) / F
+    if ctx.frame_status()["device_status"] != 0 or st["device_status"] != 0:
+        raise SystemExit("device status error in the dynamic frames")
+    graph.close()
+    ctx.close()
+    return {"workload": "pathlines_abc_2m: 20k seeds x 100 RK4 segments (2M segments/frame), 120 frames, "
+                        "256^3, 1280x720, alpha 0.3, alpha culling",
+            "frames": F, "graph_ms_per_frame": round(t_graph, 4), "eager_ms_per_frame": round(t_eager, 4),
+            "graph_speedup": round(t_eager / t_graph, 4), "mrays_s_graph": round(P / (t_graph * 1e-3) / 1e6, 2),
+            "fragments_last_frame": st["n_fragments"], "listed_last_frame": st["n_listed"]}
+
+
+def bench_batched(torch, vrt, synth, steps, warmup):
+    """64 uneven line sets (1k-1M segments, 64^3-256^3 grids, 512x512 each, opaque, culled):
+    one persistent launch against the plain calls set by set."""
+    ws = synth.batch_sets()
+    items, capsl = [], []
+    for w in ws:
+        ls, cam = w.lines, w.camera
+        n = cam.width * cam.height
+        items.append(dict(xyz=torch.from_numpy(ls.xyz).cuda(), offsets=torch.from_numpy(ls.offsets).cuda(),
+                          radius=ls.radius, origin=ls.origin, voxel_size=ls.voxel_size, dims=ls.dims,
+                          view=(np.asarray(cam.eye, np.float32), vrt.CULL_OPAQUE, 1.0, 1.0 / 256.0),
+                          camera=vrt.make_camera(cam.eye, cam.target, cam.up, cam.fovy_deg, cam.width, cam.height),
+                          rgba=torch.empty(4 * n, device="cuda"), depth=torch.empty(n, device="cuda"),
+                          first_id=torch.empty(n, dtype=torch.int32, device="cuda")))
+        capsl.append((ls.n_vertices, 16 * ls.n_segments, max(ls.dims), n))
+    b = vrt.Batch(capsl)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for label, mode in (("persistent", vrt.BATCH_PERSISTENT), ("sequential", vrt.BATCH_SEQUENTIAL)):
+        for _ in range(warmup):
+            b.run(items, mode)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(steps):
+            b.run(items, mode)
+        ev1.record()
+        torch.cuda.synchronize()
+        res[label] = ev0.elapsed_time(ev1) / steps
+        res[label + "_ids"] = [it["first_id"].clone() for it in items]
+    same = all(torch.equal(a, c) for a, c in zip(res["persistent_ids"], res["sequential_ids"]))
+    bad = [i for i in range(len(ws)) if b.context(i).frame_status()["device_status"] != 0]
+    b.close()
+    if bad:
+        raise SystemExit(f"device status error in batch sets {bad}")
+    rays = sum(w.camera.width * w.camera.height for w in ws)
+    return {"workload": "batch64: 64 sets, log-uniform 1k-1M segments, random-walk and bundle generators, "
+                        "64^3-256^3 grids, 512x512 each, opaque with opaque culling",
+            "sets": len(ws), "segments": int(sum(w.lines.n_segments for w in ws)), "rays": rays,
+            "persistent_ms": round(res["persistent"], 4), "sequential_ms": round(res["sequential"], 4),
+            "persistent_speedup": round(res["sequential"] / res["persistent"], 4),
+            "mrays_s_persistent": round(rays / (res["persistent"] * 1e-3) / 1e6, 2),
+            "first_ids_identical": bool(same)}
+
+
+def autotune_passes(ctx, passes, rgba, depth, fid, args, key):
+    """Autotunes the launch shape of each pass's trace on its own culled structure (outside the timed region)."""
+    res = {}
+    for label, view, cm in passes:
+        ctx.cull(*view)
+        r = ctx.autotune(cm, rgba, depth, fid, reps=3, warmup=1, sweeps=2, cache_path=args.tune_cache, key=key)
+        res[label] = {"best": r["best"], "best_ms": round(r["best_ms"], 4), "start_ms": round(r["start_ms"], 4),
+                      "evaluated": r["evaluated"], "from_cache": r["from_cache"]}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +173,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-pixels", type=int, default=20000)
     ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--no-dynamic", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="trace with the default launch shapes")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: none, search every run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path has no multi-GPU leg)",
@@ -127,6 +247,9 @@ def main():
     vis0a = vrt.copy_to_host(v.vis[0], top * 512, np.uint8, top * 512).reshape(top, 512)[bricks]
     V_v_a = int((vis0a > 0).sum())
     NB = (ls.dims[0] // 8) * (ls.dims[1] // 8) * (ls.dims[2] // 8)
+    tune_passes = [("opaque", (eye, opq.cull_mode, opq.alpha, opq.tau), cam_o),
+                   ("transparent", (eye, alp.cull_mode, alp.alpha, alp.tau), cam_a)]
+    tune = None if args.no_tune else autotune_passes(ctx, tune_passes, rgba, depth, fid, args, w.name)
 
     for _ in range(args.warmup):
         frame()
@@ -220,6 +343,7 @@ def main():
         "counts": counts,
         "trace_work": {"opaque": ts_o, "alpha": ts_a},
         "roofline": roofline,
+        "tune": tune,
         "wall_s_timed": round(wall, 3),
     }
 
@@ -278,6 +402,9 @@ def main():
             if stage_events:
                 ev[5].record()
 
+        ctx16.voxelize(xyz, off, ls.radius, ls.origin, ls.voxel_size, ls.dims)
+        tune16 = None if args.no_tune else autotune_passes(ctx16, tune_passes, rgba16, depth16, fid16, args,
+                                                           w.name)
         for _ in range(args.warmup):
             frame16()
         torch.cuda.synchronize()
@@ -316,7 +443,11 @@ def main():
                        "stage_ms": {k: round(v, 4) for k, v in zip(
                            ["voxelize", "cull_opaque", "trace_opaque", "cull_alpha", "trace_alpha"], s16)},
                        "trace_speedup_vs_plain": round((stage_ms[2] + stage_ms[4]) / (s16[2] + s16[4]), 4),
-                       "agreement_with_plain": agree}
+                       "agreement_with_plain": agree, "tune": tune16}
+    if not args.no_dynamic:
+        out["dynamic_pathlines"] = bench_dynamic(torch, vrt, synth, args.warmup)
+    if not args.no_batched:
+        out["batched"] = bench_batched(torch, vrt, synth, args.steps, args.warmup)
     print(json.dumps(out))
 
 

@@ -227,6 +227,63 @@ vrt_status vrt_batch_run(vrt_batch *b, const vrt_batch_item *items, int32_t n, i
 vrt_status vrt_batch_context(vrt_batch *b, int32_t i, vrt_ctx **ctx);
 vrt_status vrt_batch_destroy(vrt_batch *b);
 
+/* Launch shape of the tracer (one per trace mode and context).  Every point
+ * gives identical images; only the time differs.
+ *   march_threads  threads per block of the march phase: 128, 256 or 512
+ *                  (a block covers 16 x march_threads/16 pixels);
+ *   shade_group    lanes that share one ray in the shade phase: 8, 16 or 32;
+ *   shade_batch    list entries per lane whose records are fetched together: 2 or 4;
+ *   lane_keys      transparent hits a lane keeps per pass over a list (k): 4 or 8;
+ *   shade_blocks   256-thread blocks of the shade launch: 256 .. 65535.
+ * Default {256, 16, 4, 4, 4096}.  The batched form always uses the default. */
+typedef struct {
+    int32_t march_threads;
+    int32_t shade_group;
+    int32_t shade_batch;
+    int32_t lane_keys;
+    int32_t shade_blocks;
+    int32_t reserved[3]; /* zero */
+} vrt_tune;
+
+/* Sets / reads the launch shape used by vrt_trace (and graphs captured
+ * afterwards) for trace mode `mode`.  Errors: VRT_ERR_INVALID_ARG for a null
+ * pointer, a bad mode or a value outside the sets above (nothing changes). */
+vrt_status vrt_set_tune(vrt_ctx *ctx, int32_t mode, const vrt_tune *tune);
+vrt_status vrt_get_tune(vrt_ctx *ctx, int32_t mode, vrt_tune *tune);
+
+/* Host-timed search of the launch shape for the context's current
+ * acceleration structure and one camera (its mode selects which shape is
+ * tuned): coordinate descent from the current shape over the sets above, one
+ * parameter at a time, for `sweeps` sweeps or until a sweep changes nothing.
+ * Each point is traced `warmup` times untimed, then `reps` times between two
+ * HIP events on `stream`; its time is the mean.  The best shape is set on
+ * the context.  With a cache file, the result is looked up first under the
+ * key "<gfx arch>|<form>|<mode>|<grid dims>|<W>x<H>|<n_vertices>|<key>" and
+ * stored after a search (a JSON object, one entry per line, rewritten
+ * through a temporary file).  Writes the image buffers; synchronizes.
+ * Errors: as vrt_trace; VRT_ERR_INVALID_ARG for reps < 1, warmup < 0,
+ * sweeps < 1; a cache file that cannot be read or written is ignored. */
+typedef struct {
+    const vrt_camera *cam;
+    const vrt_image *image;  /* device buffers written by every timed trace */
+    int32_t reps;
+    int32_t warmup;
+    int32_t sweeps;
+    int32_t reserved;
+    const char *cache_path;  /* NULL: no cache */
+    const char *key;         /* caller's workload name (NULL: empty) */
+} vrt_tune_space;
+
+typedef struct {
+    vrt_tune best;
+    float best_ms;      /* mean trace time of the best shape */
+    float start_ms;     /* mean trace time of the shape the search started from */
+    int32_t evaluated;  /* shapes timed (0 on a cache hit) */
+    int32_t from_cache; /* 1 when the shape came from the cache file */
+} vrt_tune_result;
+
+vrt_status vrt_autotune(vrt_ctx *ctx, const vrt_tune_space *space, vrt_tune_result *out, void *stream);
+
 /* Synchronizes the context's last stream, reads the device status word and
  * the frame totals, and clears the latched error. */
 vrt_status vrt_frame_status(vrt_ctx *ctx, vrt_frame_info *out);

@@ -61,7 +61,7 @@ __device__ unsigned part_blocks(int ph, int part, const SetDesc &d) {
     case P_OFFSETS: return part == 0 ? st->n_bricks : 0u;
     case P_SCATTER: return part == 0 ? cdiv(d.cp.nv, T) : (part == 1 ? 1u : 0u);
     case P_MARCH: return part == 0 ? d.march_blocks : 0u;
-    case P_SHADE: return part == 0 ? cdiv(st->n_queue, T / kGroup) : 0u;
+    case P_SHADE: return part == 0 ? cdiv(st->n_queue, T / DefaultShade::kGroup) : 0u;
     default: return 0u;
     }
 }

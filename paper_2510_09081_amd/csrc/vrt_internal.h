@@ -123,6 +123,7 @@ struct vrt_ctx {
     float voxel_size = 1;
     hipStream_t last_stream = nullptr;
     vrt::Profiler prof;
+    vrt_tune tune[2] = {{256, 16, 4, 4, 4096, {0, 0, 0}}, {256, 16, 4, 4, 4096, {0, 0, 0}}};  // per trace mode
 };
 
 namespace vrt {
@@ -170,6 +171,7 @@ struct TraceParams {
 };
 hipError_t launch_trace(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st);
 hipError_t launch_trace_stats(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st);
+bool tune_valid(const vrt_tune &t);
 hipError_t launch_debug_rays(const TraceParams &p, const int64_t *pix, int64_t n, float *dirs, hipStream_t st);
 
 // ------------------------------------------------------------------------

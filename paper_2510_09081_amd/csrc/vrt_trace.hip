@@ -4,9 +4,16 @@
 namespace vrt {
 namespace {
 
-constexpr int kBatch = 4;  // list entries per lane whose vertex records are fetched together
-constexpr int kGroup = 16;    // lanes that share one ray in the shade phase
-constexpr int kLaneKeys = 4;  // accepted (t, id) keys a lane keeps per pass (transparent)
+// Shade-phase launch shape (all points give identical images):
+//   G  lanes that share one ray (8, 16 or 32),
+//   B  list entries per lane whose vertex records are fetched together (2 or 4),
+//   K  accepted (t, id) keys a lane keeps per pass in transparent mode (4 or 8).
+template <int G, int B, int K>
+struct ShadeCfg {
+    static constexpr int kGroup = G, kBatch = B, kLaneKeys = K;
+    static_assert(G == 8 || G == 16 || G == 32, "group");
+};
+using DefaultShade = ShadeCfg<16, 4, 4>;
 
 // Primary ray through the centre of pixel (px, py), row 0 at the top, as a
 // fixed binary32 sequence (no contraction): u = 2(x + .5)/W - 1,
@@ -356,12 +363,13 @@ __device__ __forceinline__ LocalSeg load_seg(const TraceArgs &a, uint32_t id, in
 // lane `gl` of a kGroup-lane group (entries gl, gl + kGroup, ...).  The
 // records of kBatch entries are fetched before any of them is tested, so each
 // lane keeps several independent loads in flight.
-template <bool kStats, int kForm, class F>
+template <bool kStats, int kForm, class Cfg, class F>
 __device__ __forceinline__ void for_each_entry(const TraceArgs &a, const Walk &w, int gl, Counters &cn, F &&f) {
     // after a capacity overflow the lists are undefined but reads stay inside ids
     const uint32_t start = (uint32_t)w.cd, cnt = (uint32_t)(w.cd >> 32);
     const uint32_t end = (int64_t)start + cnt <= a.capacity ? start + cnt : start;
     const int cx = w.v[0], cy = w.v[1], cz = w.v[2];
+    constexpr int kGroup = Cfg::kGroup, kBatch = Cfg::kBatch;
     for (uint32_t k = start + gl; k < end; k += kGroup * kBatch) {
         uint32_t id[kBatch];
         LocalSeg g[kBatch];
@@ -389,6 +397,7 @@ constexpr unsigned long long kNoKey = ~0ull;
 
 // Minimum over the kGroup lanes of this lane's group (xor offsets stay inside
 // an aligned group).
+template <int kGroup>
 __device__ __forceinline__ unsigned long long group_min(unsigned long long k) {
     for (int o = kGroup / 2; o > 0; o >>= 1) {
         const unsigned long long y = __shfl_xor(k, o, 64);
@@ -396,6 +405,7 @@ __device__ __forceinline__ unsigned long long group_min(unsigned long long k) {
     }
     return k;
 }
+template <int kGroup>
 __device__ __forceinline__ bool group_any(bool p, int lane) {
     const unsigned long long m = __ballot(p);
     return ((m >> (lane & ~(kGroup - 1))) & ((1ull << kGroup) - 1ull)) != 0ull;
@@ -412,9 +422,10 @@ struct Shade {
 // Processes the current voxel's list with the kGroup lanes of the ray's group;
 // true when the ray is finished (opaque: a hit in this voxel; transparent:
 // transmittance below tau).  Every lane of the group returns the same result.
-template <bool kStats, int kForm>
+template <bool kStats, int kForm, class Cfg>
 __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, const Walk &w, Shade &sh, Counters &cn,
                                             int lane) {
+    constexpr int kGroup = Cfg::kGroup, kLaneKeys = Cfg::kLaneKeys;
     const int gl = lane & (kGroup - 1);
     const float3 D = make_float3(r.D[0], r.D[1], r.D[2]);
     const float3 ro = make_float3(fmaf(w.tcur, D.x, r.O[0] - (float)w.v[0]), fmaf(w.tcur, D.y, r.O[1] - (float)w.v[1]),
@@ -428,14 +439,14 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
     }
     if (a.p.mode == VRT_TRACE_OPAQUE) {
         unsigned long long best = kNoKey;
-        for_each_entry<kStats, kForm>(a, w, gl, cn, [&](uint32_t id, const LocalSeg &g) {
+        for_each_entry<kStats, kForm, Cfg>(a, w, gl, cn, [&](uint32_t id, const LocalSeg &g) {
             float s;
             if (voxel_hit(g, radius, ro, D, tl, s)) {
                 const unsigned long long key = hit_key(s, id);
                 best = key < best ? key : best;
             }
         });
-        best = group_min(best);
+        best = group_min<kGroup>(best);
         if (best == kNoKey) return false;
         const uint32_t id = (uint32_t)best;
         sh.first = (int)id;
@@ -457,7 +468,7 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
         for (int j = 0; j < kLaneKeys; ++j) kk[j] = kNoKey;
         int nacc = 0;
         if (kStats && gl == 0) ++cn.pass;
-        for_each_entry<kStats, kForm>(a, w, gl, cn, [&](uint32_t id, const LocalSeg &g) {
+        for_each_entry<kStats, kForm, Cfg>(a, w, gl, cn, [&](uint32_t id, const LocalSeg &g) {
             float s;
             if (!voxel_hit(g, radius, ro, D, tl, s)) return;
             unsigned long long key = hit_key(s, id);
@@ -473,11 +484,11 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
         const bool dropped = nacc > kLaneKeys;
         bool rescan = false;
         for (;;) {
-            if (group_any(dropped && kk[0] == kNoKey, lane)) {
+            if (group_any<kGroup>(dropped && kk[0] == kNoKey, lane)) {
                 rescan = true;
                 break;
             }
-            const unsigned long long m = group_min(kk[0]);
+            const unsigned long long m = group_min<kGroup>(kk[0]);
             if (m == kNoKey) break;
             if (kk[0] == m) {  // keys are unique (one per segment), so exactly one lane pops
 #pragma unroll
@@ -587,13 +598,14 @@ __device__ __forceinline__ void b_trace_march(TraceArgs a, unsigned bid_, unsign
 }
 
 template <bool kStats>
-__global__ void __launch_bounds__(256) k_trace_march(TraceArgs a) { b_trace_march<kStats>(a, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(512) k_trace_march(TraceArgs a) { b_trace_march<kStats>(a, blockIdx.x, gridDim.x); }
 
 // Phase 2, one kGroup-lane group per queued ray: lists, capsule tests and
 // compositing, continuing the walk until the ray is finished.  All lanes of a
 // group follow the same walk; list entries are split across them.
-template <bool kStats, int kForm>
+template <bool kStats, int kForm, class Cfg = DefaultShade>
 __device__ __forceinline__ void b_trace_shade(TraceArgs a, unsigned bid_, unsigned nblk_) {
+    constexpr int kGroup = Cfg::kGroup;
     const int lane = threadIdx.x & 63;
     const unsigned n = a.st->n_queue;
     const unsigned ngroups = nblk_ * (blockDim.x / kGroup);
@@ -619,7 +631,7 @@ __device__ __forceinline__ void b_trace_shade(TraceArgs a, unsigned bid_, unsign
             Counters walk_cn;  // walk counters once per ray
             bool have = march<kStats>(a, r, w, walk_cn);  // recomputes the exit data of the queued voxel
             while (have) {
-                if (shade_voxel<kStats, kForm>(a, r, w, sh, cn, lane)) break;
+                if (shade_voxel<kStats, kForm, Cfg>(a, r, w, sh, cn, lane)) break;
                 if (!step_voxel(a, r, w)) break;
                 have = march<kStats>(a, r, w, walk_cn);
             }
@@ -645,8 +657,8 @@ __device__ __forceinline__ void b_debug_rays(TraceParams p, const int64_t *__res
     dirs[3 * i + 2] = d.z;
 }
 
-template <bool kStats, int kForm>
-__global__ void __launch_bounds__(256) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm>(a, blockIdx.x, gridDim.x); }
+template <bool kStats, int kForm, class Cfg>
+__global__ void __launch_bounds__(256) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm, Cfg>(a, blockIdx.x, gridDim.x); }
 
 __global__ void k_debug_rays(TraceParams p, const int64_t *__restrict__ pix, int64_t n, float *__restrict__ dirs) { b_debug_rays(p, pix, n, dirs, blockIdx.x, gridDim.x); }
 
@@ -728,28 +740,58 @@ static TraceArgs trace_args(vrt_ctx *c, const TraceParams &p, const vrt_image *i
     return a;
 }
 
-static constexpr unsigned kShadeBlocks = 4096;
+bool tune_valid(const vrt_tune &t) {
+    const bool mt = t.march_threads == 128 || t.march_threads == 256 || t.march_threads == 512;
+    const bool g = t.shade_group == 8 || t.shade_group == 16 || t.shade_group == 32;
+    const bool b = t.shade_batch == 2 || t.shade_batch == 4;
+    const bool k = t.lane_keys == 4 || t.lane_keys == 8;
+    const bool nb = t.shade_blocks >= 256 && t.shade_blocks <= 65535;
+    return mt && g && b && k && nb && t.reserved[0] == 0 && t.reserved[1] == 0 && t.reserved[2] == 0;
+}
+
+static unsigned march_grid(const TraceParams &p, int threads) {
+    const int rows = march_tile_rows(threads);
+    return (unsigned)(((p.W + 15) / 16) * ((p.H + rows - 1) / rows));
+}
+
+// Launches the shade kernel instance of shape (group, batch, keys).
+template <bool kStats, int kForm>
+static void launch_shade(const vrt_tune &t, const TraceArgs &a, hipStream_t st) {
+    const unsigned blocks = (unsigned)t.shade_blocks;
+#define VRT_SHADE_CASE(G, B, K)                                                                  \
+    case G * 100 + B * 10 + K:                                                                   \
+        k_trace_shade<kStats, kForm, ShadeCfg<G, B, K>><<<blocks, 256, 0, st>>>(a);              \
+        break;
+    switch (t.shade_group * 100 + t.shade_batch * 10 + t.lane_keys) {
+        VRT_SHADE_CASE(8, 2, 4) VRT_SHADE_CASE(8, 2, 8) VRT_SHADE_CASE(8, 4, 4) VRT_SHADE_CASE(8, 4, 8)
+        VRT_SHADE_CASE(16, 2, 4) VRT_SHADE_CASE(16, 2, 8) VRT_SHADE_CASE(16, 4, 4) VRT_SHADE_CASE(16, 4, 8)
+        VRT_SHADE_CASE(32, 2, 4) VRT_SHADE_CASE(32, 2, 8) VRT_SHADE_CASE(32, 4, 4) VRT_SHADE_CASE(32, 4, 8)
+        default: break;  // unreachable: the shape is validated when it is set
+    }
+#undef VRT_SHADE_CASE
+}
 
 hipError_t launch_trace(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st) {
     TraceArgs a = trace_args(c, p, img);
-    const unsigned grid = (unsigned)(((p.W + 15) / 16) * ((p.H + march_tile_rows(256) - 1) / march_tile_rows(256)));
+    const vrt_tune &t = c->tune[p.mode == VRT_TRACE_OPAQUE ? 0 : 1];
     VRT_LAUNCH(c, "k_trace_begin", st, k_trace_begin<<<1, 1, 0, st>>>(a.st));
-    VRT_LAUNCH(c, "k_trace_march", st, k_trace_march<false><<<grid, 256, 0, st>>>(a));
+    VRT_LAUNCH(c, "k_trace_march", st, k_trace_march<false><<<march_grid(p, t.march_threads), t.march_threads, 0, st>>>(a));
     if (c->desc.form == VRT_FORM_FP16)
-        VRT_LAUNCH(c, "k_trace_shade", st, k_trace_shade<false, VRT_FORM_FP16><<<kShadeBlocks, 256, 0, st>>>(a));
+        VRT_LAUNCH(c, "k_trace_shade", st, (launch_shade<false, VRT_FORM_FP16>(t, a, st)));
     else
-        VRT_LAUNCH(c, "k_trace_shade", st, k_trace_shade<false, VRT_FORM_PLAIN><<<kShadeBlocks, 256, 0, st>>>(a));
+        VRT_LAUNCH(c, "k_trace_shade", st, (launch_shade<false, VRT_FORM_PLAIN>(t, a, st)));
     return hipGetLastError();
 }
 
+// The counters are gathered with the default shape (kbuffer_passes depends on
+// the group and lane_keys; every other counter does not).
 hipError_t launch_trace_stats(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st) {
     TraceArgs a = trace_args(c, p, img);
     k_stat_clear<<<1024, 256, 0, st>>>(c->a.brick_list, c->a.status, c->n_vertices, a.stat_vox, a.stat_seg, a.stat_acc);
-    const unsigned grid = (unsigned)(((p.W + 15) / 16) * ((p.H + march_tile_rows(256) - 1) / march_tile_rows(256)));
     k_trace_begin<<<1, 1, 0, st>>>(a.st);
-    k_trace_march<true><<<grid, 256, 0, st>>>(a);
-    if (c->desc.form == VRT_FORM_FP16) k_trace_shade<true, VRT_FORM_FP16><<<kShadeBlocks, 256, 0, st>>>(a);
-    else k_trace_shade<true, VRT_FORM_PLAIN><<<kShadeBlocks, 256, 0, st>>>(a);
+    k_trace_march<true><<<march_grid(p, 256), 256, 0, st>>>(a);
+    if (c->desc.form == VRT_FORM_FP16) k_trace_shade<true, VRT_FORM_FP16, DefaultShade><<<4096, 256, 0, st>>>(a);
+    else k_trace_shade<true, VRT_FORM_PLAIN, DefaultShade><<<4096, 256, 0, st>>>(a);
     k_stat_reduce<<<1024, 256, 0, st>>>(c->a.brick_list, c->a.status, c->n_vertices, a.stat_vox, a.cell, a.stat_seg,
                                         a.stat_acc);
     return hipGetLastError();

@@ -4,4 +4,5 @@
 #include "vrt_cull.hip"
 #include "vrt_trace.hip"
 #include "vrt_api.hip"
+#include "vrt_tune.hip"
 #include "vrt_batch.hip"

@@ -27,7 +27,7 @@ EXPORTED = ["vrt_create", "vrt_destroy", "vrt_voxelize", "vrt_cull", "vrt_trace"
             "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_last_hip_error", "vrt_status_string",
             "vrt_profile_enable", "vrt_profile_read", "vrt_trace_stats_run", "vrt_graph_create",
             "vrt_graph_launch", "vrt_graph_destroy", "vrt_batch_create", "vrt_batch_run", "vrt_batch_context",
-            "vrt_batch_destroy"]
+            "vrt_batch_destroy", "vrt_set_tune", "vrt_get_tune", "vrt_autotune"]
 
 
 class VrtError(RuntimeError):
@@ -94,6 +94,25 @@ class vrt_trace_stats(C.Structure):
 _lib = None
 
 
+class vrt_tune(C.Structure):
+    _fields_ = [("march_threads", C.c_int32), ("shade_group", C.c_int32), ("shade_batch", C.c_int32),
+                ("lane_keys", C.c_int32), ("shade_blocks", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+TUNE_FIELDS = ["march_threads", "shade_group", "shade_batch", "lane_keys", "shade_blocks"]
+
+
+class vrt_tune_space(C.Structure):
+    _fields_ = [("cam", C.POINTER(vrt_camera)), ("image", C.POINTER(vrt_image)), ("reps", C.c_int32),
+                ("warmup", C.c_int32), ("sweeps", C.c_int32), ("reserved", C.c_int32), ("cache_path", C.c_char_p),
+                ("key", C.c_char_p)]
+
+
+class vrt_tune_result(C.Structure):
+    _fields_ = [("best", vrt_tune), ("best_ms", C.c_float), ("start_ms", C.c_float), ("evaluated", C.c_int32),
+                ("from_cache", C.c_int32)]
+
+
 def load():
     """Loads libvrt.so; raises if it has not been built."""
     global _lib
@@ -122,6 +141,9 @@ def load():
         L.vrt_graph_destroy.argtypes = [P]
         L.vrt_trace_stats_run.argtypes = [P, C.POINTER(vrt_camera), C.POINTER(vrt_image), C.POINTER(vrt_trace_stats), P]
         L.vrt_profile_read.argtypes = [P, C.POINTER(vrt_kernel_time), C.c_int32, C.POINTER(C.c_int32)]
+        L.vrt_set_tune.argtypes = [P, C.c_int32, C.POINTER(vrt_tune)]
+        L.vrt_get_tune.argtypes = [P, C.c_int32, C.POINTER(vrt_tune)]
+        L.vrt_autotune.argtypes = [P, C.POINTER(vrt_tune_space), C.POINTER(vrt_tune_result), P]
         L.vrt_last_hip_error.restype = C.c_int32
         L.vrt_status_string.argtypes = [C.c_int32]
         L.vrt_status_string.restype = C.c_char_p
@@ -129,7 +151,7 @@ def load():
                      "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_profile_enable",
                      "vrt_profile_read", "vrt_trace_stats_run", "vrt_graph_create", "vrt_graph_launch",
                      "vrt_graph_destroy", "vrt_batch_create", "vrt_batch_run", "vrt_batch_context",
-                     "vrt_batch_destroy"]:
+                     "vrt_batch_destroy", "vrt_set_tune", "vrt_get_tune", "vrt_autotune"]:
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -233,6 +255,34 @@ class Context:
         _check(load().vrt_frame_status(self._h, C.byref(info)), "vrt_frame_status")
         return {"device_status": info.device_status, "n_fragments": info.n_fragments, "n_listed": info.n_listed,
                 "n_bricks": info.n_bricks}
+
+    def set_tune(self, mode, **shape):
+        """Sets the tracer launch shape of trace mode `mode`; unnamed fields keep their current value."""
+        t = vrt_tune()
+        _check(load().vrt_get_tune(self._h, int(mode), C.byref(t)), "vrt_get_tune")
+        for k, v in shape.items():
+            if k not in TUNE_FIELDS:
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        _check(load().vrt_set_tune(self._h, int(mode), C.byref(t)), "vrt_set_tune")
+
+    def get_tune(self, mode):
+        t = vrt_tune()
+        _check(load().vrt_get_tune(self._h, int(mode), C.byref(t)), "vrt_get_tune")
+        return {k: int(getattr(t, k)) for k in TUNE_FIELDS}
+
+    def autotune(self, camera: vrt_camera, rgba, depth=None, first_id=None, reps=3, warmup=1, sweeps=2,
+                 cache_path=None, key=None, stream=None):
+        """Times launch shapes of the camera's trace mode on the current structure and keeps the fastest
+        (synchronizes).  Returns {"best": shape, "best_ms", "start_ms", "evaluated", "from_cache"}."""
+        img = vrt_image(_ptr(rgba), _ptr(depth), _ptr(first_id))
+        sp = vrt_tune_space(C.pointer(camera), C.pointer(img), int(reps), int(warmup), int(sweeps), 0,
+                            None if cache_path is None else os.fsencode(cache_path),
+                            None if key is None else str(key).encode())
+        res = vrt_tune_result()
+        _check(load().vrt_autotune(self._h, C.byref(sp), C.byref(res), _stream_ptr(stream)), "vrt_autotune")
+        return {"best": {k: int(getattr(res.best, k)) for k in TUNE_FIELDS}, "best_ms": float(res.best_ms),
+                "start_ms": float(res.start_ms), "evaluated": int(res.evaluated), "from_cache": bool(res.from_cache)}
 
     def profile_enable(self, enable=True):
         _check(load().vrt_profile_enable(self._h, int(bool(enable))), "vrt_profile_enable")

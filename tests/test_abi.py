@@ -45,3 +45,7 @@ def test_status_strings_and_host_validation():
     assert L.vrt_create(ctypes.byref(bad), ctypes.byref(h)) == vrt.VRT_ERR_INVALID_ARG
     assert L.vrt_voxelize(None, None, None, None) == vrt.VRT_ERR_INVALID_ARG
     assert L.vrt_copy_to_host(None, None, -1) == vrt.VRT_ERR_INVALID_ARG
+    t = vrt.vrt_tune(256, 16, 4, 4, 4096)
+    assert L.vrt_set_tune(None, 0, ctypes.byref(t)) == vrt.VRT_ERR_INVALID_ARG
+    assert L.vrt_get_tune(None, 0, ctypes.byref(t)) == vrt.VRT_ERR_INVALID_ARG
+    assert L.vrt_autotune(None, None, None, None) == vrt.VRT_ERR_INVALID_ARG
