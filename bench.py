@@ -20,6 +20,53 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "per-frame AS build ms + Mrays/s at 1080p, 5M segs; batched/FP16 vs plain"
+TUNE_CACHE = os.path.join(ROOT, "paper_2510_09081_amd", "tune_cache.json")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_bundles_5m_plain.md")
+
+
+def source_digest():
+    """sha256 over the library sources and build flags: HBM counters taken for another digest are stale."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2510_09081_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(ROOT, "paper_2510_09081_amd", "build.py"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, tune):
+    """HBM bytes per launch of `kernel` from the committed PMC summary (FETCH_SIZE + WRITE_SIZE, each scaled by
+    the copy-kernel calibration), or None when the summary is missing or was taken for other sources or shapes."""
+    import re
+    try:
+        with open(PMC_SUMMARY) as f:
+            m = re.search(r"<!-- pmc (\{.*\}) -->", f.read())
+    except OSError:
+        return None
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    k = d.get("kernels", {}).get(kernel)
+    if k is None or d.get("source_sha256") != source_digest() or d.get("tune") != tune:
+        return None
+    return {"bytes_per_launch": int(k["fetch_bytes"] + k["write_bytes"]), "fetch_bytes": int(k["fetch_bytes"]),
+            "write_bytes": int(k["write_bytes"])}
+
+
+def calibrate_copy():
+    """A plain device copy of known size (for scaling the FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+    n = 64 << 20
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 4 * n, "copies": 3}))
 HBM_PEAK_GBS = 8000.0
 VREC_BYTES = 32  # quantized position, flags, clip normal per vertex
 
@@ -36,8 +83,11 @@ def kernel_bytes(name, n):
                               for p in passes]))
     if name == "k_ingest":      # xyz + offsets in, records out
         return 12 * n["N_v"] + 4 * n["N_p"] + VREC_BYTES * n["N_v"]
-    if name == "k_cull_vis":    # words in, visibility out, over occupied bricks
-        return 5 * 512 * n["bricks"]
+    if name == "k_cull_walk":   # occupied-voxel list in, visibility byte out; voxel blocking bits of the
+        # occupied bricks, brick bits and 64^3-cell flags once each
+        return 5 * n["V_o"] + 64 * n["bricks"] + n["NB"] / 8 + n["NB"] / 512
+    if name == "k_cull_brick":  # per occupied brick: words, visibility read + written, mips 1-3, brick total
+        return (2048 + 1024 + 64 + 8 + 1 + 4) * n["bricks"]
     if name == "k_trace_march":  # every pixel: brick table once, miss outputs (RGBA + depth + id)
         return 24 * n["P"] + n["NB"]
     if name == "k_trace_shade":  # per pass: distinct voxel descriptors (8 B), list entries (4 B) and segments
@@ -176,8 +226,15 @@ def main():
     ap.add_argument("--no-dynamic", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="trace with the default launch shapes")
-    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: none, search every run)")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="autotuner cache file ('' to search every run); default: the shipped MI355X table")
+    ap.add_argument("--calibrate-copy", action="store_true", help="only run a 256 MiB device copy three times")
     args = ap.parse_args()
+    if args.tune_cache == "":
+        args.tune_cache = None
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path has no multi-GPU leg)",
               file=sys.stderr)
@@ -313,8 +370,10 @@ def main():
     roofline = None
     if b is not None:
         ach = b / (per_kernel[dom]["avg_ms"] * 1e-3) / 1e9
+        tr = measured_traffic(dom, tune)
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "bytes_per_launch": int(b)}
+                    "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None if tr is None else tr["bytes_per_launch"],
+                    "traffic_detail": tr, "bytes_per_launch": int(b)}
 
     as_build_ms = stage_ms[0] + stage_ms[1]
     out = {

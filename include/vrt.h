@@ -284,6 +284,24 @@ typedef struct {
 
 vrt_status vrt_autotune(vrt_ctx *ctx, const vrt_tune_space *space, vrt_tune_result *out, void *stream);
 
+/* Host-timed choice of the grid resolution for one line set.  The grid only
+ * narrows the search for hits (voxelization and culling are conservative), so
+ * every grid yields the same hits up to binary32 rounding of the hit
+ * parameters; fragment counts, list lengths and walk lengths change with it.
+ * For each of the n_grids candidates: one frame (vrt_voxelize, then vrt_cull
+ * and vrt_trace for each of the n_passes (view, camera, image) triples),
+ * vrt_frame_status, `warmup` untimed frames and `reps` frames between two HIP
+ * events on `stream`.  ms[i] (host, n_grids entries) receives the mean frame
+ * time, or +inf when the candidate latched a device error (e.g. it needs
+ * more than max_fragments); *best the index of the fastest.  The context
+ * holds the last candidate's structure afterwards.  Writes the image buffers;
+ * synchronizes.  Errors: VRT_ERR_INVALID_ARG (null pointers, counts < 1,
+ * warmup < 0), any error of the frame's calls (e.g. an invalid grid), or the
+ * device error of the last candidate when none fits. */
+vrt_status vrt_autotune_grid(vrt_ctx *ctx, const vrt_lines *lines, const vrt_grid *grids, int32_t n_grids,
+                             const vrt_view *views, const vrt_camera *cams, const vrt_image *imgs, int32_t n_passes,
+                             int32_t reps, int32_t warmup, int32_t *best, float *ms, void *stream);
+
 /* Synchronizes the context's last stream, reads the device status word and
  * the frame totals, and clears the latched error. */
 vrt_status vrt_frame_status(vrt_ctx *ctx, vrt_frame_info *out);

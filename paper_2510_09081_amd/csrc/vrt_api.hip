@@ -28,7 +28,7 @@ hipError_t alloc(T *&p, int64_t n) {
 }
 
 void free_all(Arenas &a) {
-    void *ptrs[] = {a.vrec, a.words, a.occ0, a.occ1, a.occ2, a.occ3, a.occ_hi, a.blk, a.brick_blk, a.super_blk,
+    void *ptrs[] = {a.vrec, a.words, a.occ0, a.occ1, a.occ2, a.occ3, a.occ_hi, a.blk, a.blk_bits, a.brick_bits, a.super_blk,
                     a.occ_list, a.vis0,
                     a.vis1, a.vis2,  a.vis3, a.vis_hi, a.cursor, a.cell, a.queue, a.srec16, a.ids, a.brick_flag, a.brick_list, a.brick_slot,
                     a.brick_total, a.brick_base, a.status, a.stat_vox, a.stat_seg, a.stat_acc};
@@ -117,7 +117,8 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     ALLOC(a.occ3, mb);
     ALLOC(a.occ_hi, c->hi_elems);
     ALLOC(a.blk, mb * kBrickVox);
-    ALLOC(a.brick_blk, mb);
+    ALLOC(a.blk_bits, mb * 8);
+    ALLOC(a.brick_bits, (mb + 31) / 32);
     ALLOC(a.super_blk, c->max_supers);
     ALLOC(a.occ_list, mb * kBrickVox);
     ALLOC(a.vis0, mb * kBrickVox);

@@ -108,7 +108,7 @@ __device__ void run_part(int ph, int part, const SetDesc &d, unsigned vb, unsign
     switch (ph) {
     case P_CLEAR:
         if (part == 0) b_clear_prev(A.words, A.brick_list, A.status, vb, nvb);
-        else b_reset(A.occ3, A.brick_blk, d.vp.nb, A.super_blk, d.vp.ns, A.status, vb, nvb);
+        else b_reset(A.occ3, A.brick_bits, d.vp.nb, A.super_blk, d.vp.ns, A.status, vb, nvb);
         break;
     case P_INGEST: b_ingest(d.vp.ia, A.vrec, A.status, vb, nvb); break;
     case P_COUNT:
@@ -119,11 +119,12 @@ __device__ void run_part(int ph, int part, const SetDesc &d, unsigned vb, unsign
     case P_OCC: b_occ_brick(A.words, A.brick_list, A.status, A.occ0, A.occ1, A.occ2, A.occ3, A.occ_list, vb, nvb); break;
     case P_ERODE:
         if (part == 0)
-            b_erode(d.vp.g, A.occ0, A.brick_list, A.brick_slot, A.status, A.blk, A.brick_blk, A.super_blk, vb, nvb);
+            b_erode(d.vp.g, A.occ0, A.brick_list, A.brick_slot, A.status, A.blk, A.blk_bits, A.brick_bits, A.super_blk,
+                    vb, nvb);
         else if (part == 1) mip_avg_chain(d);
         else b_cull_reset(A.vis3, d.cp.nb, A.status, vb, nvb);
         break;
-    case P_WALK: b_cull_walk(d.cp.ca, d.cp.cells, A.occ_list, A.status, A.vis0, vb, nvb); break;
+    case P_WALK: b_cull_walk<false>(d.cp.ca, d.cp.cells, A.occ_list, A.status, A.vis0, vb, nvb); break;
     case P_CBRICK:
         b_cull_brick(d.cp.limit, d.cp.g, A.words, A.brick_list, A.status, A.vis0, A.vis1, A.vis2, A.vis3,
                      A.brick_total, vb, nvb);

@@ -22,20 +22,32 @@ __global__ void k_cull_reset(uint8_t *__restrict__ vis3, int64_t nb, DevStatus *
 
 // Blocking lookups for the culling walk: 64^3 cells and bricks holding a
 // blocking voxel, and the level-0 blocking flags (defined in occupied bricks).
+// Blocking flags the culling walk reads: one byte per 64^3 cell, one bit per
+// brick and one bit per voxel (brick-major, 64 voxels per word).
 struct CullCells {
-    const uint8_t *super_blk, *brick_blk, *blk;
+    const uint8_t *super_blk;
+    const uint32_t *brick_bits;
+    const uint64_t *blk_bits;
     int nb0, nb1, ns0, ns1;
-    __host__ __device__ bool super_empty(int x, int y, int z) const {
-        return !super_blk[((int64_t)(z >> 6) * ns1 + (y >> 6)) * ns0 + (x >> 6)];
+    __device__ bool super_empty(int x, int y, int z) const {
+        return !super_blk[((z >> 6) * ns1 + (y >> 6)) * ns0 + (x >> 6)];
     }
-    __host__ __device__ bool brick_empty(int x, int y, int z) const {
-        return !brick_blk[((int64_t)(z >> 3) * nb1 + (y >> 3)) * nb0 + (x >> 3)];
+    __device__ bool brick_empty(int x, int y, int z) const {
+        const unsigned b = (unsigned)(((z >> 3) * nb1 + (y >> 3)) * nb0 + (x >> 3));
+        return !((brick_bits[b >> 5] >> (b & 31u)) & 1u);
     }
-    __host__ __device__ bool blocking(int x, int y, int z) const {
+    __device__ bool blocking(int x, int y, int z) const {
         const int64_t b = ((int64_t)(z >> 3) * nb1 + (y >> 3)) * nb0 + (x >> 3);
-        return blk[b * kBrickVox + (((z & 7) << 6) | ((y & 7) << 3) | (x & 7))] != 0;
+        const int l = ((z & 7) << 6) | ((y & 7) << 3) | (x & 7);
+        return (blk_bits[b * 8 + (l >> 6)] >> (l & 63)) & 1ull;
     }
 };
+
+// Bytes of the brick bits and cell flags when staged in LDS.
+__host__ __device__ inline size_t cull_lds_bytes(int64_t nbricks, int64_t nsupers) {
+    return (size_t)((nbricks + 31) / 32) * 4 + (size_t)nsupers;
+}
+constexpr size_t kCullLdsMax = 48 * 1024;  // larger grids read the flags from global memory
 
 struct CullArgs {
     GridArgs g;
@@ -46,10 +58,25 @@ struct CullArgs {
 // One thread per occupied voxel (Section 3.2): visible iff its culling ray
 // meets fewer than `limit` blocking voxels.  Writes level-0 visibility of
 // occupied voxels only; k_cull_brick completes the rest of the brick.
+// With kLds the block first copies the brick bits and cell flags into LDS
+// (cull_lds_bytes of dynamic shared memory), so that only the voxel bits are
+// global loads inside the walk.
+extern __shared__ __align__(16) uint32_t vrt_cull_lds[];
+
+template <bool kLds>
 __device__ __forceinline__ void b_cull_walk(CullArgs a, CullCells cells, const uint32_t *__restrict__ occ_list,
                                                    const DevStatus *__restrict__ st, uint8_t *__restrict__ vis0, unsigned bid_, unsigned nblk_) {
     __shared__ int bbox[6];
     if (threadIdx.x < 6) bbox[threadIdx.x] = st->bbox[threadIdx.x];
+    if (kLds) {
+        const int64_t nb = (int64_t)a.g.nb[0] * a.g.nb[1] * a.g.nb[2];
+        const int nw = (int)((nb + 31) / 32), ns = a.g.ns[0] * a.g.ns[1] * a.g.ns[2];
+        for (int i = threadIdx.x; i < nw; i += blockDim.x) vrt_cull_lds[i] = cells.brick_bits[i];
+        uint8_t *s_super = reinterpret_cast<uint8_t *>(vrt_cull_lds + nw);
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) s_super[i] = cells.super_blk[i];
+        cells.brick_bits = vrt_cull_lds;
+        cells.super_blk = s_super;
+    }
     __syncthreads();
     const unsigned n = st->n_occ;
     for (unsigned i = bid_ * blockDim.x + threadIdx.x; i < n; i += nblk_ * blockDim.x) {
@@ -64,8 +91,9 @@ __device__ __forceinline__ void b_cull_walk(CullArgs a, CullCells cells, const u
     }
 }
 
-__global__ void __launch_bounds__(256) k_cull_walk(CullArgs a, CullCells cells, const uint32_t *__restrict__ occ_list,
-                                                   const DevStatus *__restrict__ st, uint8_t *__restrict__ vis0) { b_cull_walk(a, cells, occ_list, st, vis0, blockIdx.x, gridDim.x); }
+template <bool kLds>
+__global__ void __launch_bounds__(512) k_cull_walk(CullArgs a, CullCells cells, const uint32_t *__restrict__ occ_list,
+                                                   const DevStatus *__restrict__ st, uint8_t *__restrict__ vis0) { b_cull_walk<kLds>(a, cells, occ_list, st, vis0, blockIdx.x, gridDim.x); }
 
 // One workgroup per occupied brick: final level-0 visibility (unoccupied
 // voxels are invisible; without culling every occupied voxel is visible), the
@@ -278,6 +306,10 @@ __global__ void __launch_bounds__(256) k_scatter(ScatterArgs a) { b_scatter(a, b
 
 }  // namespace
 
+// Blocks of the LDS-staged walk: each copies the flags once, then takes
+// occupied voxels grid-stride (four blocks per compute unit).
+static constexpr unsigned kCullWalkBlocks = 1024;
+
 // Arguments of every culling and list kernel for one view of context c.
 struct CullPlan {
     int64_t nb, nv;
@@ -303,8 +335,8 @@ static CullPlan make_cull_plan(const vrt_ctx *c, const int64_t E[3], int64_t lim
     for (int k = 0; k < 3; ++k) p.ca.E[k] = E[k];
     p.ca.limit = p.limit;
     p.cells.super_blk = A.super_blk;
-    p.cells.brick_blk = A.brick_blk;
-    p.cells.blk = A.blk;
+    p.cells.brick_bits = A.brick_bits;
+    p.cells.blk_bits = A.blk_bits;
     p.cells.nb0 = p.g.nb[0];
     p.cells.nb1 = p.g.nb[1];
     p.cells.ns0 = p.g.ns[0];
@@ -329,8 +361,15 @@ hipError_t launch_cull(vrt_ctx *c, const int64_t E[3], int64_t limit, hipStream_
     const CullPlan p = make_cull_plan(c, E, limit);
     VRT_LAUNCH(c, "k_cull_reset", st,
                k_cull_reset<<<(unsigned)((p.nb + 255) / 256), 256, 0, st>>>(A.vis3, p.nb, A.status));
-    if (p.limit >= 0)
-        VRT_LAUNCH(c, "k_cull_walk", st, k_cull_walk<<<8192, 256, 0, st>>>(p.ca, p.cells, A.occ_list, A.status, A.vis0));
+    if (p.limit >= 0) {
+        const size_t lds = cull_lds_bytes(p.nb, (int64_t)p.g.ns[0] * p.g.ns[1] * p.g.ns[2]);
+        if (lds <= kCullLdsMax)
+            VRT_LAUNCH(c, "k_cull_walk", st,
+                       k_cull_walk<true><<<kCullWalkBlocks, 512, lds, st>>>(p.ca, p.cells, A.occ_list, A.status, A.vis0));
+        else
+            VRT_LAUNCH(c, "k_cull_walk", st,
+                       k_cull_walk<false><<<8192, 512, 0, st>>>(p.ca, p.cells, A.occ_list, A.status, A.vis0));
+    }
     VRT_LAUNCH(c, "k_cull_brick", st,
                k_cull_brick<<<4096, 512, 0, st>>>(p.limit, p.g, A.words, A.brick_list, A.status, A.vis0, A.vis1, A.vis2,
                                                   A.vis3, A.brick_total));

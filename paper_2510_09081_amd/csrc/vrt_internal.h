@@ -46,6 +46,7 @@ struct DevStatus {
     unsigned int n_occ;  // occupied voxels (entries of occ_list)
     int vbox[6];         // visible-brick bounds: min bx,by,bz then max (bricks)
     unsigned int n_queue;  // rays queued by the trace's march phase
+    unsigned long long count_sum;  // sum of the 16-bit count fields of all words (== n_fragments unless one wrapped)
 };
 
 struct Arenas {
@@ -57,7 +58,8 @@ struct Arenas {
     uint16_t *occ3 = nullptr;       // [max_bricks]
     uint16_t *occ_hi = nullptr;     // levels >= 4
     uint8_t *blk = nullptr;         // [max_bricks * 512]
-    uint8_t *brick_blk = nullptr;   // [max_bricks]
+    uint64_t *blk_bits = nullptr;   // [max_bricks * 8] blocking voxels, one bit each, 64 voxels per word
+    uint32_t *brick_bits = nullptr; // [(max_bricks + 31) / 32] bricks holding a blocking voxel, one bit each
     uint8_t *super_blk = nullptr;   // [max_supers] 64^3 cells holding a blocking voxel
     uint32_t *occ_list = nullptr;   // [max_bricks * 512] brick-major index of every occupied voxel
     uint8_t *vis0 = nullptr;        // [max_bricks * 512]

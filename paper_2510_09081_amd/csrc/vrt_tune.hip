@@ -1,10 +1,16 @@
-// vrt_tune.hip -- launch-shape setting and the host-timed autotuner of the tracer.
+// vrt_tune.hip -- launch-shape setting and the host-timed autotuners.
 //
 // The tracer's launch shape (march block size, lanes per ray, records fetched
 // together, keys per lane, shade grid) changes only the time of a trace, not
 // its image: every shape computes the same (t, id) keys and composites them in
-// the same order.  The autotuner times shapes on the caller's own frame and
-// keeps the fastest; results can be kept in a small JSON cache file.
+// the same order.  The shape autotuner times shapes on the caller's own frame
+// and keeps the fastest; results can be kept in a small JSON cache file.
+//
+// The grid resolution is the other free parameter: the grid only narrows the
+// search for hits (voxelization and culling are conservative), so every grid
+// yields the same hits up to binary32 rounding of the hit parameters, while
+// list lengths, fragment counts and walk lengths change.  The grid autotuner
+// times whole frames for caller-given candidate grids.
 #include <unistd.h>
 
 #include <cstdio>
@@ -125,8 +131,9 @@ vrt_status search(vrt_ctx *c, const TraceParams &p, const vrt_tune_space *sp, hi
         bool changed = false;
         for (int k = 0; k < 5; ++k) {
             if (k == 3 && p.mode == VRT_TRACE_OPAQUE) continue;  // keys per lane: transparent only
+            const int32_t timed = *tune_field(cur, k);  // the value cur_ms was measured with
             for (int j = 0; j < 5 && kValues[k][j]; ++j) {
-                if (kValues[k][j] == *tune_field(cur, k)) continue;
+                if (kValues[k][j] == timed) continue;
                 vrt_tune cand = cur;
                 *tune_field(cand, k) = kValues[k][j];
                 float ms = 0.0f;
@@ -148,9 +155,91 @@ vrt_status search(vrt_ctx *c, const TraceParams &p, const vrt_tune_space *sp, hi
     return VRT_OK;
 }
 
+// One frame: voxelize, then cull and trace every pass.
+vrt_status grid_frame(vrt_ctx *c, const vrt_lines *L, const vrt_grid *g, const vrt_view *views,
+                      const vrt_camera *cams, const vrt_image *imgs, int n_passes, void *stream) {
+    vrt_status s = vrt_voxelize(c, L, g, stream);
+    for (int i = 0; s == VRT_OK && i < n_passes; ++i) {
+        s = vrt_cull(c, &views[i], stream);
+        if (s == VRT_OK) s = vrt_trace(c, &cams[i], &imgs[i], stream);
+    }
+    return s;
+}
+
+vrt_status grid_search(vrt_ctx *c, const vrt_lines *L, const vrt_grid *grids, int n, const vrt_view *views,
+                       const vrt_camera *cams, const vrt_image *imgs, int n_passes, int reps, int warmup,
+                       hipEvent_t e0, hipEvent_t e1, int32_t *best, float *ms, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    float best_ms = INFINITY;
+    vrt_status unfit = VRT_ERR_CAPACITY;  // returned when no candidate fits
+    *best = -1;
+    for (int i = 0; i < n; ++i) {
+        ms[i] = INFINITY;
+        vrt_status s = grid_frame(c, L, &grids[i], views, cams, imgs, n_passes, stream);
+        if (s != VRT_OK) return s;
+        vrt_frame_info info;
+        s = vrt_frame_status(c, &info);
+        if (s != VRT_OK) return s;
+        if (info.device_status != VRT_OK) {  // does not fit the context's capacities
+            unfit = info.device_status;
+            continue;
+        }
+        for (int k = 0; k < warmup; ++k) {
+            s = grid_frame(c, L, &grids[i], views, cams, imgs, n_passes, stream);
+            if (s != VRT_OK) return s;
+        }
+        VRT_HIP(hipEventRecord(e0, st));
+        for (int k = 0; k < reps; ++k) {
+            s = grid_frame(c, L, &grids[i], views, cams, imgs, n_passes, stream);
+            if (s != VRT_OK) return s;
+        }
+        VRT_HIP(hipEventRecord(e1, st));
+        VRT_HIP(hipEventSynchronize(e1));
+        float total = 0.0f;
+        VRT_HIP(hipEventElapsedTime(&total, e0, e1));
+        s = vrt_frame_status(c, &info);
+        if (s != VRT_OK) return s;
+        if (info.device_status != VRT_OK) {
+            unfit = info.device_status;
+            continue;
+        }
+        ms[i] = total / (float)reps;
+        if (ms[i] < best_ms) {
+            best_ms = ms[i];
+            *best = i;
+        }
+    }
+    return *best >= 0 ? VRT_OK : unfit;
+}
+
 }  // namespace
 
 extern "C" {
+
+vrt_status vrt_autotune_grid(vrt_ctx *c, const vrt_lines *lines, const vrt_grid *grids, int32_t n_grids,
+                             const vrt_view *views, const vrt_camera *cams, const vrt_image *imgs, int32_t n_passes,
+                             int32_t reps, int32_t warmup, int32_t *best, float *ms, void *stream) {
+    if (!c || !lines || !grids || n_grids < 1 || !views || !cams || !imgs || n_passes < 1 || reps < 1 ||
+        warmup < 0 || !best || !ms)
+        return VRT_ERR_INVALID_ARG;
+    VRT_HIP(hipSetDevice(c->desc.device));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    VRT_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he);
+    }
+    const bool prof = c->prof.enabled;
+    c->prof.enabled = false;
+    const vrt_status s =
+        grid_search(c, lines, grids, n_grids, views, cams, imgs, n_passes, reps, warmup, e0, e1, best, ms, stream);
+    c->prof.enabled = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return s;
+}
+
 
 vrt_status vrt_set_tune(vrt_ctx *c, int32_t mode, const vrt_tune *t) {
     if (!c || !t || (mode != VRT_TRACE_OPAQUE && mode != VRT_TRACE_TRANSPARENT) || !tune_valid(*t))

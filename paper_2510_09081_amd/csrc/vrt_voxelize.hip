@@ -22,24 +22,23 @@ __global__ void k_clear_prev(uint32_t *__restrict__ words, const int32_t *__rest
 
 // Clears the per-frame brick-level state: level-3 occupancy, blocking flags
 // of bricks and 64^3 cells, the blocking box and the frame counters.
-__device__ __forceinline__ void b_reset(uint16_t *__restrict__ occ3, uint8_t *__restrict__ brick_blk, int64_t nbricks,
+__device__ __forceinline__ void b_reset(uint16_t *__restrict__ occ3, uint32_t *__restrict__ brick_bits, int64_t nbricks,
                         uint8_t *__restrict__ super_blk, int64_t nsupers, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
     int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
-    if (i < nbricks) {
-        occ3[i] = 0;
-        brick_blk[i] = 0;
-    }
+    if (i < nbricks) occ3[i] = 0;
+    if (i < (nbricks + 31) / 32) brick_bits[i] = 0u;
     if (i < nsupers) super_blk[i] = 0;
     if (i == 0) {
         st->n_fragments = 0;
+        st->count_sum = 0;
         st->n_occ = 0;
         st->bbox[0] = st->bbox[1] = st->bbox[2] = INT_MAX;
         st->bbox[3] = st->bbox[4] = st->bbox[5] = INT_MIN;
     }
 }
 
-__global__ void k_reset(uint16_t *__restrict__ occ3, uint8_t *__restrict__ brick_blk, int64_t nbricks,
-                        uint8_t *__restrict__ super_blk, int64_t nsupers, DevStatus *__restrict__ st) { b_reset(occ3, brick_blk, nbricks, super_blk, nsupers, st, blockIdx.x, gridDim.x); }
+__global__ void k_reset(uint16_t *__restrict__ occ3, uint32_t *__restrict__ brick_bits, int64_t nbricks,
+                        uint8_t *__restrict__ super_blk, int64_t nsupers, DevStatus *__restrict__ st) { b_reset(occ3, brick_bits, nbricks, super_blk, nsupers, st, blockIdx.x, gridDim.x); }
 
 // fixed-point coordinate: rint((x - origin) * s) as two binary32 operations
 __device__ __forceinline__ bool quantize1(float x, float o, float s, int &q) {
@@ -200,6 +199,9 @@ struct CountArgs {
 
 // Pass 1: one thread per segment walks its voxel set and adds
 // 1 + (q << 16) to each voxel's packed word (count low, occupancy high).
+// The adds return nothing: a count field that wraps past 65535 is found
+// afterwards, because the count fields then sum to less than the number of
+// fragments (each wrap loses exactly 65536).
 __device__ __forceinline__ void b_vox_count(CountArgs a, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
     int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     unsigned long long nfrag = 0;
@@ -213,18 +215,15 @@ __device__ __forceinline__ void b_vox_count(CountArgs a, DevStatus *__restrict__
             } else {
                 SlabSpan s = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), a.rq, a.G);
                 int64_t last_b = -1;
-                bool over = false;
                 nfrag = for_each_voxel(s, [&](int x, int y, int z) {
                     int q = occupancy_quantum(A, B, a.rc, a.corr, x, y, z);
                     int64_t b = brick_index_of(x, y, z, a.nbx, a.nby);
-                    uint32_t old = atomicAdd(&a.words[b * kBrickVox + local_of(x, y, z)], 1u + ((uint32_t)q << 16));
-                    over |= (old & 0xFFFFu) == 0xFFFFu;
+                    atomicAdd(&a.words[b * kBrickVox + local_of(x, y, z)], 1u + ((uint32_t)q << 16));
                     if (b != last_b) {
                         a.brick_flag[b] = 1;
                         last_b = b;
                     }
                 });
-                if (over) set_err(st, kErrCount);
             }
         }
     }
@@ -312,10 +311,12 @@ __device__ __forceinline__ void b_occ_brick(const uint32_t *__restrict__ words,
     __shared__ unsigned base;
     const unsigned nbk = st->n_bricks;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    unsigned long long csum = 0;  // count fields seen by this thread
     for (unsigned sl = bid_; sl < nbk; sl += nblk_) {
         int64_t b = list[sl];
         uint32_t wd = words[b * kBrickVox + t];
         uint32_t cnt = wd & 0xFFFFu, sum = wd >> 16;
+        csum += cnt;
         uint16_t o = (uint16_t)(cnt >= 256u ? 256u : (sum > 256u ? 256u : sum));
         occ0[b * kBrickVox + t] = o;
         s0[t] = o;
@@ -361,6 +362,8 @@ __device__ __forceinline__ void b_occ_brick(const uint32_t *__restrict__ words,
         }
         __syncthreads();
     }
+    csum = wave_sum_u64(csum);
+    if (lane == 0 && csum) atomicAdd(&st->count_sum, csum);
 }
 
 __global__ void __launch_bounds__(512) k_occ_brick(const uint32_t *__restrict__ words,
@@ -384,10 +387,13 @@ __device__ __forceinline__ unsigned occ_at(const GridArgs &g, const uint16_t *__
 __device__ __forceinline__ void b_erode(GridArgs g, const uint16_t *__restrict__ occ0,
                                                const int32_t *__restrict__ list, const int32_t *__restrict__ slot,
                                                DevStatus *__restrict__ st, uint8_t *__restrict__ blk,
-                                               uint8_t *__restrict__ brick_blk, uint8_t *__restrict__ super_blk, unsigned bid_, unsigned nblk_) {
+                                               uint64_t *__restrict__ blk_bits, uint32_t *__restrict__ brick_bits,
+                                               uint8_t *__restrict__ super_blk, unsigned bid_, unsigned nblk_) {
     __shared__ int bb[6];
     const unsigned nbk = st->n_bricks;
     const int t = threadIdx.x;
+    // pass 1 is complete: a count field wrapped iff the fields sum to less than the fragments
+    if (bid_ == 0 && t == 0 && st->count_sum != st->n_fragments) set_err(st, kErrCount);
     for (unsigned sl = bid_; sl < nbk; sl += nblk_) {
         int64_t b = list[sl];
         if (t < 3) bb[t] = INT_MAX;
@@ -407,13 +413,15 @@ __device__ __forceinline__ void b_erode(GridArgs g, const uint16_t *__restrict__
         }
         bool blocking = e >= 256u;
         blk[b * kBrickVox + t] = blocking ? 1 : 0;
+        const unsigned long long bits = __ballot(blocking);  // the wave holds local voxels 64w .. 64w + 63
+        if ((t & 63) == 0) blk_bits[b * 8 + (t >> 6)] = bits;
         if (blocking) {
             atomicMin(&bb[0], x); atomicMin(&bb[1], y); atomicMin(&bb[2], z);
             atomicMax(&bb[3], x); atomicMax(&bb[4], y); atomicMax(&bb[5], z);
         }
         int any = __syncthreads_or(blocking ? 1 : 0);
         if (t == 0 && any) {
-            brick_blk[b] = 1;
+            atomicOr(&brick_bits[b >> 5], 1u << (b & 31));
             super_blk[((int64_t)(bz >> 3) * g.ns[1] + (by >> 3)) * g.ns[0] + (bx >> 3)] = 1;
             atomicMin(&st->bbox[0], bb[0]); atomicMin(&st->bbox[1], bb[1]); atomicMin(&st->bbox[2], bb[2]);
             atomicMax(&st->bbox[3], bb[3]); atomicMax(&st->bbox[4], bb[4]); atomicMax(&st->bbox[5], bb[5]);
@@ -425,7 +433,8 @@ __device__ __forceinline__ void b_erode(GridArgs g, const uint16_t *__restrict__
 __global__ void __launch_bounds__(512) k_erode(GridArgs g, const uint16_t *__restrict__ occ0,
                                                const int32_t *__restrict__ list, const int32_t *__restrict__ slot,
                                                DevStatus *__restrict__ st, uint8_t *__restrict__ blk,
-                                               uint8_t *__restrict__ brick_blk, uint8_t *__restrict__ super_blk) { b_erode(g, occ0, list, slot, st, blk, brick_blk, super_blk, blockIdx.x, gridDim.x); }
+                                               uint64_t *__restrict__ blk_bits, uint32_t *__restrict__ brick_bits,
+                                               uint8_t *__restrict__ super_blk) { b_erode(g, occ0, list, slot, st, blk, blk_bits, brick_bits, super_blk, blockIdx.x, gridDim.x); }
 
 // Averaging step on dense grids (levels >= 3): parent = floor((sum of the
 // children inside the grid + 4) / 8), parent dims = ceil(child dims / 2).
@@ -495,7 +504,7 @@ hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *L, float s_q, hipStream_
     const unsigned eb = (unsigned)((p.nv + 255) / 256);
     VRT_LAUNCH(c, "k_clear_prev", st, k_clear_prev<<<2048, 128, 0, st>>>(A.words, A.brick_list, A.status));
     VRT_LAUNCH(c, "k_reset", st,
-               k_reset<<<(unsigned)((p.nb + 255) / 256), 256, 0, st>>>(A.occ3, A.brick_blk, p.nb, A.super_blk, p.ns,
+               k_reset<<<(unsigned)((p.nb + 255) / 256), 256, 0, st>>>(A.occ3, A.brick_bits, p.nb, A.super_blk, p.ns,
                                                                        A.status));
     VRT_LAUNCH(c, "k_ingest", st, k_ingest<<<eb, 256, 0, st>>>(p.ia, A.vrec, A.status));
     if (p.fp16) VRT_LAUNCH(c, "k_pack16", st, k_pack16<<<eb, 256, 0, st>>>(A.vrec, p.nv, A.srec16));
@@ -506,8 +515,8 @@ hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *L, float s_q, hipStream_
                k_occ_brick<<<4096, 512, 0, st>>>(A.words, A.brick_list, A.status, A.occ0, A.occ1, A.occ2, A.occ3,
                                                  A.occ_list));
     VRT_LAUNCH(c, "k_erode", st,
-               k_erode<<<4096, 512, 0, st>>>(p.g, A.occ0, A.brick_list, A.brick_slot, A.status, A.blk, A.brick_blk,
-                                             A.super_blk));
+               k_erode<<<4096, 512, 0, st>>>(p.g, A.occ0, A.brick_list, A.brick_slot, A.status, A.blk, A.blk_bits,
+                                             A.brick_bits, A.super_blk));
     // levels >= 4 from the dense level 3
     const uint16_t *src = A.occ3;
     int sx = p.g.nb[0], sy = p.g.nb[1], sz = p.g.nb[2];

@@ -27,7 +27,7 @@ EXPORTED = ["vrt_create", "vrt_destroy", "vrt_voxelize", "vrt_cull", "vrt_trace"
             "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_last_hip_error", "vrt_status_string",
             "vrt_profile_enable", "vrt_profile_read", "vrt_trace_stats_run", "vrt_graph_create",
             "vrt_graph_launch", "vrt_graph_destroy", "vrt_batch_create", "vrt_batch_run", "vrt_batch_context",
-            "vrt_batch_destroy", "vrt_set_tune", "vrt_get_tune", "vrt_autotune"]
+            "vrt_batch_destroy", "vrt_set_tune", "vrt_get_tune", "vrt_autotune", "vrt_autotune_grid"]
 
 
 class VrtError(RuntimeError):
@@ -144,6 +144,9 @@ def load():
         L.vrt_set_tune.argtypes = [P, C.c_int32, C.POINTER(vrt_tune)]
         L.vrt_get_tune.argtypes = [P, C.c_int32, C.POINTER(vrt_tune)]
         L.vrt_autotune.argtypes = [P, C.POINTER(vrt_tune_space), C.POINTER(vrt_tune_result), P]
+        L.vrt_autotune_grid.argtypes = [P, C.POINTER(vrt_lines), C.POINTER(vrt_grid), C.c_int32,
+                                        C.POINTER(vrt_view), C.POINTER(vrt_camera), C.POINTER(vrt_image), C.c_int32,
+                                        C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float), P]
         L.vrt_last_hip_error.restype = C.c_int32
         L.vrt_status_string.argtypes = [C.c_int32]
         L.vrt_status_string.restype = C.c_char_p
@@ -151,7 +154,7 @@ def load():
                      "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_profile_enable",
                      "vrt_profile_read", "vrt_trace_stats_run", "vrt_graph_create", "vrt_graph_launch",
                      "vrt_graph_destroy", "vrt_batch_create", "vrt_batch_run", "vrt_batch_context",
-                     "vrt_batch_destroy", "vrt_set_tune", "vrt_get_tune", "vrt_autotune"]:
+                     "vrt_batch_destroy", "vrt_set_tune", "vrt_get_tune", "vrt_autotune", "vrt_autotune_grid"]:
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -284,6 +287,35 @@ class Context:
         return {"best": {k: int(getattr(res.best, k)) for k in TUNE_FIELDS}, "best_ms": float(res.best_ms),
                 "start_ms": float(res.start_ms), "evaluated": int(res.evaluated), "from_cache": bool(res.from_cache)}
 
+    def autotune_grid(self, xyz, offsets, radius, grids, passes, reps=3, warmup=1, stream=None):
+        """Times whole frames for each candidate grid (origin, voxel_size, dims); passes as in frame_graph.
+        Returns (index of the fastest grid, [mean frame ms per grid, inf where it did not fit]).  Synchronizes;
+        the context holds the last candidate's structure afterwards."""
+        lines = vrt_lines(_ptr(xyz), _ptr(offsets), int(xyz.shape[0]), int(offsets.shape[0] - 1), float(radius))
+        gs = (vrt_grid * len(grids))()
+        for i, (origin, voxel_size, dims) in enumerate(grids):
+            gs[i] = vrt_grid(_f3(origin), float(voxel_size), (C.c_int32 * 3)(*[int(x) for x in dims]))
+        views, cams, imgs = self._passes(passes)
+        best = C.c_int32()
+        ms = (C.c_float * len(grids))()
+        _check(load().vrt_autotune_grid(self._h, C.byref(lines), gs, len(grids), views, cams, imgs, len(passes),
+                                        int(reps), int(warmup), C.byref(best), ms, _stream_ptr(stream)),
+               "vrt_autotune_grid")
+        return int(best.value), [float(x) for x in ms]
+
+    @staticmethod
+    def _passes(passes):
+        n = len(passes)
+        views = (vrt_view * max(n, 1))()
+        cams = (vrt_camera * max(n, 1))()
+        imgs = (vrt_image * max(n, 1))()
+        for i, (view, cam, rgba, depth, fid) in enumerate(passes):
+            eye, mode, alpha, tau = view
+            views[i] = vrt_view(_f3(eye), int(mode), float(alpha), float(tau))
+            cams[i] = cam
+            imgs[i] = vrt_image(_ptr(rgba), _ptr(depth), _ptr(fid))
+        return views, cams, imgs
+
     def profile_enable(self, enable=True):
         _check(load().vrt_profile_enable(self._h, int(bool(enable))), "vrt_profile_enable")
 
@@ -300,14 +332,7 @@ class Context:
         lines = vrt_lines(_ptr(xyz), _ptr(offsets), int(xyz.shape[0]), int(offsets.shape[0] - 1), float(radius))
         grid = vrt_grid(_f3(origin), float(voxel_size), (C.c_int32 * 3)(*[int(x) for x in dims]))
         n = len(passes)
-        views = (vrt_view * max(n, 1))()
-        cams = (vrt_camera * max(n, 1))()
-        imgs = (vrt_image * max(n, 1))()
-        for i, (view, cam, rgba, depth, fid) in enumerate(passes):
-            eye, mode, alpha, tau = view
-            views[i] = vrt_view(_f3(eye), int(mode), float(alpha), float(tau))
-            cams[i] = cam
-            imgs[i] = vrt_image(_ptr(rgba), _ptr(depth), _ptr(fid))
+        views, cams, imgs = self._passes(passes)
         h = C.c_void_p()
         _check(load().vrt_graph_create(self._h, C.byref(lines), C.byref(grid), views, cams, imgs, n, C.byref(h)),
                "vrt_graph_create")

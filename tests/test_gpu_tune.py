@@ -29,7 +29,8 @@ def _need_gpu():
 
 
 def _passes(w):
-    return [(p.cull_mode, vrt.TRACE_OPAQUE if p.mode == synth.MODE_OPAQUE else vrt.TRACE_TRANSPARENT, p.alpha)
+    return [(p.cull_mode, vrt.TRACE_OPAQUE if p.trace_mode == synth.MODE_OPAQUE else vrt.TRACE_TRANSPARENT,
+             p.alpha)
             for p in w.passes]
 
 
@@ -115,5 +116,58 @@ def test_autotune_sets_a_shape_and_uses_its_cache(tmp_path):
         assert len(json.loads(cache.read_text())) == 2
         with pytest.raises(vrt.VrtError):
             ctx.autotune(cs, rgba, reps=0)
+    finally:
+        ctx.close()
+
+
+def test_autotune_grid_times_fitting_grids():
+    import torch
+    _need_gpu()
+    w = synth.workload("bundles_small")
+    ls, cam = w.lines, w.camera
+    n = cam.width * cam.height
+    base = ls.dims[0]
+    grids = [(ls.origin, ls.voxel_size * base / g, (g, g, g)) for g in (64, 128, 256)]
+    eye = np.asarray(cam.eye, np.float32)
+    xyz, off = G.to_device(ls)
+    out = [(torch.empty(4 * n, device="cuda"), torch.empty(n, device="cuda"),
+            torch.empty(n, dtype=torch.int32, device="cuda")) for _ in range(2)]
+    passes = [((eye, vrt.CULL_OPAQUE, 1.0, 1 / 256), G.camera_struct(cam, vrt.TRACE_OPAQUE), *out[0]),
+              ((eye, vrt.CULL_ALPHA, 0.2, 1 / 256), G.camera_struct(cam, vrt.TRACE_TRANSPARENT, 0.2), *out[1])]
+    big = vrt.Context(max_vertices=ls.n_vertices, max_fragments=80 * ls.n_segments, max_dim=256)
+    need, ids = [], []
+    try:
+        for origin, vs, dims in grids:
+            big.voxelize(xyz, off, ls.radius, origin, vs, dims)
+            req = 0
+            for view, cm, r, d, f in passes:
+                big.cull(*view)
+                big.trace(cm, r, d, f)
+                st = big.frame_status()
+                assert st["device_status"] == 0
+                req = max(req, st["n_listed"])
+            need.append(req)
+            ids.append(out[0][2].cpu().numpy().copy())
+    finally:
+        big.close()
+    # the grid only narrows the search: the opaque first hits agree across grids up to rounding near ties
+    hit = ids[1] >= 0
+    assert hit.sum() > 1000
+    for other in (ids[0], ids[2]):
+        assert (other == ids[1]).mean() >= 0.999
+    assert need[2] > max(need[0], need[1])  # the finest grid needs the most list entries
+    ctx = vrt.Context(max_vertices=ls.n_vertices, max_fragments=max(need[0], need[1]), max_dim=256)
+    try:
+        best, ms = ctx.autotune_grid(xyz, off, ls.radius, grids, passes, reps=2, warmup=1)
+        assert ms[2] == float("inf")  # does not fit the capacity
+        assert all(0 < m < float("inf") for m in ms[:2])
+        assert best in (0, 1) and ms[best] == min(ms)
+        assert ctx.frame_status()["device_status"] == 0
+        with pytest.raises(vrt.VrtError) as e:
+            ctx.autotune_grid(xyz, off, ls.radius, [(ls.origin, ls.voxel_size, (12, 12, 12))], passes)
+        assert e.value.status == vrt.VRT_ERR_INVALID_ARG
+        with pytest.raises(vrt.VrtError) as e:
+            ctx.autotune_grid(xyz, off, ls.radius, grids[2:], passes)
+        assert e.value.status == vrt.VRT_ERR_CAPACITY
     finally:
         ctx.close()
