@@ -29,17 +29,22 @@ struct CullCells {
     const uint32_t *brick_bits;
     const uint64_t *blk_bits;
     int nb0, nb1, ns0, ns1;
+    // indices below 2^24 (at most 128^3 bricks): 24-bit multiplies
+    __device__ unsigned brick_of(int x, int y, int z) const {
+        return __umul24(__umul24((unsigned)(z >> 3), (unsigned)nb1) + (unsigned)(y >> 3), (unsigned)nb0) +
+               (unsigned)(x >> 3);
+    }
     __device__ bool super_empty(int x, int y, int z) const {
-        return !super_blk[((z >> 6) * ns1 + (y >> 6)) * ns0 + (x >> 6)];
+        return !super_blk[__umul24(__umul24((unsigned)(z >> 6), (unsigned)ns1) + (unsigned)(y >> 6), (unsigned)ns0) +
+                          (unsigned)(x >> 6)];
     }
     __device__ bool brick_empty(int x, int y, int z) const {
-        const unsigned b = (unsigned)(((z >> 3) * nb1 + (y >> 3)) * nb0 + (x >> 3));
+        const unsigned b = brick_of(x, y, z);
         return !((brick_bits[b >> 5] >> (b & 31u)) & 1u);
     }
     __device__ bool blocking(int x, int y, int z) const {
-        const int64_t b = ((int64_t)(z >> 3) * nb1 + (y >> 3)) * nb0 + (x >> 3);
-        const int l = ((z & 7) << 6) | ((y & 7) << 3) | (x & 7);
-        return (blk_bits[b * 8 + (l >> 6)] >> (l & 63)) & 1ull;
+        const unsigned l = (unsigned)(((z & 7) << 6) | ((y & 7) << 3) | (x & 7));
+        return (blk_bits[brick_of(x, y, z) * 8u + (l >> 6)] >> (l & 63u)) & 1ull;
     }
 };
 

@@ -6,23 +6,17 @@
 
 namespace vrt {
 
-// floor(n / m) for m > 0 (exact; binary64 estimate corrected in integers)
-__host__ __device__ inline long long walk_floor_div(long long n, long long m) {
-    long long q = (long long)floor((double)n / (double)m);
-    while (q * m > n) --q;
-    while ((q + 1) * m <= n) ++q;
+// floor((num) / den) for 0 <= num < 64 * den (den > 0): an estimate from a
+// binary32 reciprocal, corrected exactly in integers.
+__host__ __device__ inline long long walk_small_quot(long long num, long long den) {
+#ifdef __HIP_DEVICE_COMPILE__
+    long long q = (long long)((float)num * __builtin_amdgcn_rcpf((float)den));
+#else
+    long long q = num / den;
+#endif
+    while (q > 0 && q * den > num) --q;
+    while ((q + 1) * den <= num) ++q;
     return q;
-}
-
-// Element k (0..2) of a three-vector held in registers (no indexed memory).
-template <class T>
-__host__ __device__ inline T wpick(const T (&v)[3], int k) {
-    return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]);
-}
-
-// Product of two non-negative values below 2^32 (one 32x32->64 multiply).
-__host__ __device__ inline long long wmul(long long a, long long b) {
-    return (long long)((unsigned long long)(uint32_t)a * (unsigned long long)(uint32_t)b);
 }
 
 // Counts the blocking voxels met by the open segment from the centre of voxel
@@ -31,25 +25,26 @@ __host__ __device__ inline long long wmul(long long a, long long b) {
 // The walk is the exact integer grid walk of Section 3.2's culling rays: with
 // c the start, D = E - c, and g_a the distance from c to the next voxel
 // boundary ahead on axis a, the next crossing is the axis minimizing
-// g_a / |D_a| (compared as g_a |D_b| < g_b |D_a|); tied axes step together, so
-// voxels met only along an edge or at a corner are not visited.  It stops at
-// the grid boundary, at the eye, or once it is past the bounding box of all
-// blocking voxels.
+// g_a / |D_a|; tied axes step together, so voxels met only along an edge or at
+// a corner are not visited.  It stops at the grid boundary, at the eye, or once
+// it is past the bounding box of all blocking voxels.
+//
+// Crossing times are kept as integers T_a = g_a * L_a, where L_a is the product
+// of |D_b| over the other moving axes: T_a < T_b exactly when
+// g_a / |D_a| < g_b / |D_b|, crossing axis a adds dT_a = Q L_a, and the eye is
+// reached once the smallest T is at least P = |D_a| L_a (the product of all
+// moving |D|).  A step is then additions and comparisons only.  Magnitudes:
+// |D| < 2^22.1 (the eye within 2^22 of the grid corner), g below 2^18.1
+// (1024 voxels), so T < 2^62.3; P is clamped to 2^63 - 1 when larger (the eye
+// then lies beyond every reachable crossing).
 //
 // Cells of S^3 voxels (S = 64, then 8) that hold no blocking voxel are crossed
-// in one jump: the exit time t = gb_m / |D_m| is the first crossing of the
-// cell's far faces; on the exit axes the walk enters the next cell, on every
-// other axis a it enters the voxel containing c_a + t D_a, half-open in the
-// direction of travel:
-//   D_a > 0: floor((c_a |D_m| + gb_m D_a) / (Q |D_m|)),
-//   D_a < 0: floor((c_a |D_m| + gb_m D_a - 1) / (Q |D_m|)),
-// which is the voxel the unskipped walk occupies right after t.  Skipped voxels
-// hold no blocker, so the count is unchanged.
-//
-// Magnitudes: positions below 2^18 (1024 voxels), |D| below 2^23 (the eye
-// within 2^22 of the grid corner), so every g and |D| fits 32 bits and every
-// product fits 64.  Three-vectors are only indexed by loop constants or
-// through wpick, so they stay in registers.
+// in one jump: with Te the smallest time at which the walk crosses the cell's
+// far face on some axis, every moving axis a makes all its crossings with
+// T <= Te, n_a = floor((Te - T_a) / dT_a) + 1 of them (none if Te < T_a);
+// on the exit axes that is exactly into the next cell, and crossings tied
+// with Te are taken together as in the voxel walk.  Skipped voxels hold no
+// blocker, so the count is unchanged.
 //
 // Cells: `cells` provides
 //   bool super_empty(x, y, z)  -- the 64^3 cell holding voxel (x,y,z) has no blocker
@@ -59,15 +54,29 @@ template <class Cells>
 __host__ __device__ inline int culling_walk(const int *G, int x, int y, int z, const long long *E, int limit,
                                             const int *bbox, const Cells &cells) {
     constexpr long long Q = 256;
-    long long c[3], adel[3], g[3];
+    constexpr long long kNever = 0x7FFFFFFFFFFFFFFFll;
+    long long adel[3], T[3], dT[3];
     int step[3], cur[3] = {x, y, z};
+    int nmov = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        c[a] = (long long)cur[a] * Q + Q / 2;
-        const long long dl = E[a] - c[a];
+        const long long c = (long long)cur[a] * Q + Q / 2;
+        const long long dl = E[a] - c;
         step[a] = dl > 0 ? 1 : (dl < 0 ? -1 : 0);
         adel[a] = dl < 0 ? -dl : dl;
-        g[a] = Q / 2;
+        nmov += step[a] != 0;
+    }
+    if (nmov == 0) return 0;  // the eye is at this voxel's centre
+    long long P = kNever;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        long long L = 1;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            if (b != a && step[b] != 0) L *= adel[b];
+        T[a] = step[a] != 0 ? (Q / 2) * L : kNever;
+        dT[a] = step[a] != 0 ? Q * L : kNever;
+        if (step[a] != 0 && (double)adel[a] * (double)L < 9.0e18) P = adel[a] * L;
     }
     int n = 0;
     bool be = cells.brick_empty(x, y, z);  // brick_empty of the current voxel
@@ -83,69 +92,47 @@ __host__ __device__ inline int culling_walk(const int *G, int x, int y, int z, c
         int S = 1;
         if (be) S = cells.super_empty(cur[0], cur[1], cur[2]) ? 64 : 8;
         if (S == 1) {
-            int m = -1;
-            long long gm = 0, am = 0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                if (step[a] == 0) continue;
-                if (m < 0 || wmul(g[a], am) < wmul(gm, adel[a])) {
-                    m = a;
-                    gm = g[a];
-                    am = adel[a];
-                }
-            }
-            if (m < 0 || !(gm < am)) break;  // eye reached
+            long long tm = T[0] < T[1] ? T[0] : T[1];
+            tm = T[2] < tm ? T[2] : tm;
+            if (!(tm < P)) break;  // eye reached
             bool out = false;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                if (step[a] != 0 && wmul(g[a], am) == wmul(gm, adel[a])) {
+                if (T[a] == tm) {
                     cur[a] += step[a];
-                    g[a] += Q;
+                    T[a] += dT[a];
                     if (cur[a] < 0 || cur[a] >= G[a]) out = true;
                 }
             }
             if (out) break;
         } else {
-            long long gb[3];
-            int m = -1;
-            long long gm = 0, am = 0;
+            long long Tc[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                gb[a] = 0;
+                Tc[a] = kNever;
                 if (step[a] == 0) continue;
-                const long long cell = cur[a] / S;  // cur >= 0
-                const long long bnd = (step[a] > 0 ? cell + 1 : cell) * S * Q;
-                gb[a] = step[a] > 0 ? bnd - c[a] : c[a] - bnd;
-                if (m < 0 || wmul(gb[a], am) < wmul(gm, adel[a])) {
-                    m = a;
-                    gm = gb[a];
-                    am = adel[a];
-                }
+                const int cs = cur[a] / S * S;  // cur >= 0
+                const long long k = step[a] > 0 ? cs + S - 1 - cur[a] : cur[a] - cs;
+                Tc[a] = T[a] + k * dT[a];
             }
-            if (m < 0 || !(gm < am)) break;  // the eye lies inside this empty cell
+            long long te = Tc[0] < Tc[1] ? Tc[0] : Tc[1];
+            te = Tc[2] < te ? Tc[2] : te;
+            if (!(te < P)) break;  // the eye lies inside this empty cell
             bool out = false;
-            int nxt[3];
+            long long na[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                nxt[a] = cur[a];
-                if (step[a] == 0) continue;
-                if (wmul(gb[a], am) == wmul(gm, adel[a])) {
-                    const int cell = cur[a] / S;
-                    nxt[a] = step[a] > 0 ? (cell + 1) * S : cell * S - 1;
-                    if (nxt[a] < 0 || nxt[a] >= G[a]) out = true;
-                } else {
-                    const long long num = wmul(c[a], am) + (long long)step[a] * wmul(gm, adel[a]);
-                    nxt[a] = (int)walk_floor_div(step[a] > 0 ? num : num - 1, Q * am);
-                    if (nxt[a] < 0 || nxt[a] >= G[a]) out = true;  // left the grid inside a 64^3 cell
-                }
+                na[a] = 0;
+                if (step[a] == 0 || te < T[a]) continue;
+                na[a] = walk_small_quot(te - T[a], dT[a]) + 1;
+                const long long nx = cur[a] + step[a] * na[a];
+                if (nx < 0 || nx >= G[a]) out = true;
             }
             if (out) break;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                cur[a] = nxt[a];
-                if (step[a] == 0) continue;
-                const long long bnd = (step[a] > 0 ? (long long)cur[a] + 1 : (long long)cur[a]) * Q;
-                g[a] = step[a] > 0 ? bnd - c[a] : c[a] - bnd;
+                cur[a] += step[a] * (int)na[a];
+                if (na[a]) T[a] += na[a] * dT[a];
             }
         }
         be = cells.brick_empty(cur[0], cur[1], cur[2]);
