@@ -30,7 +30,7 @@ hipError_t alloc(T *&p, int64_t n) {
 void free_all(Arenas &a) {
     void *ptrs[] = {a.vrec, a.words, a.occ0, a.occ1, a.occ2, a.occ3, a.occ_hi, a.blk, a.blk_bits, a.brick_bits, a.super_blk,
                     a.occ_list, a.vis0,
-                    a.vis1, a.vis2,  a.vis3, a.vis_hi, a.cursor, a.cell, a.queue, a.srec16, a.ids, a.brick_flag, a.brick_list, a.brick_slot,
+                    a.vis1, a.vis2,  a.vis3, a.vis_hi, a.cursor, a.cell, a.queue, a.srec16, a.ids, a.brick_flag, a.bin_count, a.bin_range, a.cand, a.bins, a.long_ids, a.brick_list, a.brick_slot,
                     a.brick_total, a.brick_base, a.status, a.stat_vox, a.stat_seg, a.stat_acc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -132,6 +132,11 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     if (desc->form == VRT_FORM_FP16) ALLOC(a.srec16, desc->max_vertices);
     ALLOC(a.ids, desc->max_fragments);
     ALLOC(a.brick_flag, mb);
+    ALLOC(a.bin_count, mb);
+    ALLOC(a.bin_range, mb);
+    ALLOC(a.cand, mb);
+    ALLOC(a.bins, (int64_t)kMaxBinBricks * desc->max_vertices);
+    ALLOC(a.long_ids, desc->max_vertices);
     ALLOC(a.brick_list, mb);
     ALLOC(a.brick_slot, mb);
     ALLOC(a.brick_total, mb);
@@ -143,6 +148,7 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
 #undef ALLOC
     if (e == hipSuccess) e = hipMemset(a.words, 0, (size_t)mb * kBrickVox * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(a.brick_flag, 0, (size_t)mb);
+    if (e == hipSuccess) e = hipMemset(a.bin_count, 0, (size_t)mb * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(a.brick_slot, 0xFF, (size_t)mb * sizeof(int32_t));
     if (e == hipSuccess) e = hipMemset(a.status, 0, sizeof(DevStatus));
     if (e == hipSuccess) e = hipDeviceSynchronize();

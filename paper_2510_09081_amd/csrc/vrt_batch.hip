@@ -108,7 +108,7 @@ __device__ void run_part(int ph, int part, const SetDesc &d, unsigned vb, unsign
     switch (ph) {
     case P_CLEAR:
         if (part == 0) b_clear_prev(A.words, A.brick_list, A.status, vb, nvb);
-        else b_reset(A.occ3, A.brick_bits, d.vp.nb, A.super_blk, d.vp.ns, A.status, vb, nvb);
+        else b_reset(A.occ3, A.bin_count, A.brick_bits, d.vp.nb, A.super_blk, d.vp.ns, A.status, vb, nvb);
         break;
     case P_INGEST: b_ingest(d.vp.ia, A.vrec, A.status, vb, nvb); break;
     case P_COUNT:

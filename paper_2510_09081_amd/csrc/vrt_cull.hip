@@ -271,11 +271,11 @@ struct ScatterArgs {
     int64_t capacity;
 };
 
-// Pass 2 (Section 3.3): a segment whose capsule AABB touches no visible brick
-// is skipped; otherwise its voxel set is walked again and every visible voxel
-// gets the segment id at an atomically claimed slot of its list.
-__device__ __forceinline__ void b_scatter(ScatterArgs a, unsigned bid_, unsigned nblk_) {
-    int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
+// Pass 2 (Section 3.3) for one segment with global atomics: a segment whose
+// capsule AABB touches no visible brick is skipped; otherwise its voxel set is
+// walked again and every visible voxel gets the segment id at an atomically
+// claimed slot of its list.
+__device__ __forceinline__ void scatter_segment(const ScatterArgs &a, int64_t i) {
     if (i + 1 >= a.nv) return;
     VRec A = a.vrec[i];
     if (!(A.flags & kSegValid)) return;
@@ -307,7 +307,73 @@ __device__ __forceinline__ void b_scatter(ScatterArgs a, unsigned bid_, unsigned
     });
 }
 
+// Pass 2, one thread per segment (the batched form's path).
+__device__ __forceinline__ void b_scatter(ScatterArgs a, unsigned bid_, unsigned nblk_) {
+    scatter_segment(a, (int64_t)bid_ * blockDim.x + threadIdx.x);
+}
+
+struct ScatterBinArgs {
+    ScatterArgs sa;
+    const int32_t *cand;
+    const uint2 *bin_range;
+    const uint32_t *bins;
+    const uint32_t *long_ids;
+};
+
+// Pass 2 by brick (the per-context path): one workgroup per visible binned
+// brick walks its bin's segments inside the brick and claims list slots from
+// LDS copies of the brick's cursors, so a brick's ids land in its own
+// contiguous range of the list array; the cursors are stored back for the
+// long segments that follow.
+__device__ __forceinline__ void b_scatter_brick(ScatterBinArgs a, const DevStatus *__restrict__ st, unsigned bid_,
+                                                unsigned nblk_) {
+    __shared__ uint32_t cur[kBrickVox];
+    __shared__ uint8_t vis[kBrickVox];
+    const ScatterArgs &s = a.sa;
+    const unsigned n = st->n_cand;
+    const int t = threadIdx.x;
+    for (unsigned sl = bid_; sl < n; sl += nblk_) {
+        const int b = a.cand[sl];
+        if (!s.vis3[b]) continue;  // the whole workgroup skips
+        for (int v = t; v < kBrickVox; v += blockDim.x) {
+            vis[v] = s.vis0[(int64_t)b * kBrickVox + v];
+            cur[v] = s.cursor[(int64_t)b * kBrickVox + v];
+        }
+        __syncthreads();
+        const uint2 r = a.bin_range[b];
+        const int bx = b % s.nb[0], by = (b / s.nb[0]) % s.nb[1], bz = b / (s.nb[0] * s.nb[1]);
+        for (uint32_t k = t; k < r.y; k += blockDim.x) {
+            const uint32_t id = a.bins[r.x + k];
+            const VRec A = s.vrec[id], B = s.vrec[id + 1];
+            const SlabSpan sp = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), s.rq, s.G);
+            for_each_voxel_in_brick(sp, bx, by, bz, [&](int x, int y, int z) {
+                const int l = local_of(x, y, z);
+                if (vis[l]) {
+                    const uint32_t slot = atomicAdd(&cur[l], 1u);
+                    if ((int64_t)slot < s.capacity) s.ids[slot] = id;
+                }
+            });
+        }
+        __syncthreads();
+        for (int v = t; v < kBrickVox; v += blockDim.x) s.cursor[(int64_t)b * kBrickVox + v] = cur[v];
+        __syncthreads();
+    }
+}
+
+// Pass 2 for the long segments (after the binned bricks).
+__device__ __forceinline__ void b_scatter_long(ScatterBinArgs a, const DevStatus *__restrict__ st, unsigned bid_,
+                                               unsigned nblk_) {
+    const unsigned n = st->n_long;
+    for (unsigned k = bid_ * blockDim.x + threadIdx.x; k < n; k += nblk_ * blockDim.x) scatter_segment(a.sa, a.long_ids[k]);
+}
+
 __global__ void __launch_bounds__(256) k_scatter(ScatterArgs a) { b_scatter(a, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(256) k_scatter_brick(ScatterBinArgs a, const DevStatus *__restrict__ st) {
+    b_scatter_brick(a, st, blockIdx.x, gridDim.x);
+}
+__global__ void __launch_bounds__(256) k_scatter_long(ScatterBinArgs a, const DevStatus *__restrict__ st) {
+    b_scatter_long(a, st, blockIdx.x, gridDim.x);
+}
 
 }  // namespace
 
@@ -323,6 +389,7 @@ struct CullPlan {
     CullArgs ca;
     CullCells cells;
     ScatterArgs sa;
+    ScatterBinArgs sb;
 };
 
 static CullPlan make_cull_plan(const vrt_ctx *c, const int64_t E[3], int64_t limit) {
@@ -358,6 +425,11 @@ static CullPlan make_cull_plan(const vrt_ctx *c, const int64_t E[3], int64_t lim
     p.sa.cursor = A.cursor;
     p.sa.ids = A.ids;
     p.sa.capacity = c->desc.max_fragments;
+    p.sb.sa = p.sa;
+    p.sb.cand = A.cand;
+    p.sb.bin_range = A.bin_range;
+    p.sb.bins = A.bins;
+    p.sb.long_ids = A.long_ids;
     return p;
 }
 
@@ -397,7 +469,8 @@ hipError_t launch_cull(vrt_ctx *c, const int64_t E[3], int64_t limit, hipStream_
     VRT_LAUNCH(c, "k_list_offsets", st,
                k_list_offsets<<<4096, 512, 0, st>>>(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor,
                                                     A.cell));
-    VRT_LAUNCH(c, "k_scatter", st, k_scatter<<<(unsigned)((p.nv + 255) / 256), 256, 0, st>>>(p.sa));
+    VRT_LAUNCH(c, "k_scatter_brick", st, k_scatter_brick<<<kBrickBlocks, 256, 0, st>>>(p.sb, A.status));
+    VRT_LAUNCH(c, "k_scatter_long", st, k_scatter_long<<<256, 256, 0, st>>>(p.sb, A.status));
     return hipGetLastError();
 }
 

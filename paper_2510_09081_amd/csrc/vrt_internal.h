@@ -47,7 +47,14 @@ struct DevStatus {
     int vbox[6];         // visible-brick bounds: min bx,by,bz then max (bricks)
     unsigned int n_queue;  // rays queued by the trace's march phase
     unsigned long long count_sum;  // sum of the 16-bit count fields of all words (== n_fragments unless one wrapped)
+    unsigned int n_cand;           // bricks with a non-empty segment bin (entries of cand)
+    unsigned int n_long;           // segments too long for the bins (entries of long_ids)
+    unsigned long long bin_total;  // bin entries allocated
 };
+
+// A segment is binned into every brick of its voxel box when that box has at
+// most this many bricks; longer segments take the per-segment path.
+constexpr int kMaxBinBricks = 8;
 
 struct Arenas {
     VRec *vrec = nullptr;
@@ -73,6 +80,11 @@ struct Arenas {
     SRec16 *srec16 = nullptr;       // [max_vertices] FP16-form segment records (FP16 form only)
     uint32_t *ids = nullptr;        // [max_fragments]
     uint8_t *brick_flag = nullptr;  // [max_bricks]
+    uint32_t *bin_count = nullptr;  // [max_bricks] segments binned per brick (zero between frames)
+    uint2 *bin_range = nullptr;     // [max_bricks] (first entry, length) of a brick's bin in bins
+    int32_t *cand = nullptr;        // [max_bricks] bricks with a non-empty bin, in no particular order
+    uint32_t *bins = nullptr;       // [kMaxBinBricks * max_vertices] segment ids grouped by brick
+    uint32_t *long_ids = nullptr;   // [max_vertices] segments whose voxel box spans more bricks
     int32_t *brick_list = nullptr;  // [max_bricks]
     int32_t *brick_slot = nullptr;  // [max_bricks] slot in brick_list or -1
     uint32_t *brick_total = nullptr;// [max_bricks] visible fragments per occupied brick (by slot)
@@ -300,14 +312,22 @@ __device__ __forceinline__ void slab_range(const SlabSpan &s, int x, long long A
     rh = (int)(h < vhi ? h : vhi);
 }
 
+// The voxels of the set inside the box [lo0, hi0] x [lo1, hi1] x [lo2, hi2]
+// given on the span's axes (a0, a1, a2); each exactly once.
 template <class F>
-__device__ __forceinline__ int for_each_voxel(const SlabSpan &s, F &&f) {
+__device__ __forceinline__ int for_each_voxel_clip(const SlabSpan &s, int lo0, int hi0, int lo1, int hi1, int lo2,
+                                                   int hi2, F &&f) {
     if (s.empty) return 0;
     int n = 0;
-    for (int x = s.vlo0; x <= s.vhi0; ++x) {
+    const int x0 = s.vlo0 > lo0 ? s.vlo0 : lo0, x1 = s.vhi0 < hi0 ? s.vhi0 : hi0;
+    for (int x = x0; x <= x1; ++x) {
         int l1, h1, l2, h2;
         slab_range(s, x, s.A1, s.d1, s.W1, s.vlo1, s.vhi1, l1, h1);
         slab_range(s, x, s.A2, s.d2, s.W2, s.vlo2, s.vhi2, l2, h2);
+        l1 = l1 > lo1 ? l1 : lo1;
+        h1 = h1 < hi1 ? h1 : hi1;
+        l2 = l2 > lo2 ? l2 : lo2;
+        h2 = h2 < hi2 ? h2 : hi2;
         for (int j = l1; j <= h1; ++j)
             for (int k = l2; k <= h2; ++k) {
                 // (x, j, k) on axes (a0, a1, a2) back to (x, y, z)
@@ -321,4 +341,40 @@ __device__ __forceinline__ int for_each_voxel(const SlabSpan &s, F &&f) {
     return n;
 }
 
+template <class F>
+__device__ __forceinline__ int for_each_voxel(const SlabSpan &s, F &&f) {
+    return for_each_voxel_clip(s, s.vlo0, s.vhi0, s.vlo1, s.vhi1, s.vlo2, s.vhi2, f);
+}
+
+// The voxels of the set inside brick (bx, by, bz).
+template <class F>
+__device__ __forceinline__ int for_each_voxel_in_brick(const SlabSpan &s, int bx, int by, int bz, F &&f) {
+    const int l0 = 8 * (int)sel3(bx, by, bz, s.a0), l1 = 8 * (int)sel3(bx, by, bz, s.a1);
+    const int l2 = 8 * (int)sel3(bx, by, bz, s.a2);
+    return for_each_voxel_clip(s, l0, l0 + 7, l1, l1 + 7, l2, l2 + 7, f);
+}
+
+// Voxel box of the set on the original axes.
+__device__ __forceinline__ void span_box(const SlabSpan &s, int &lx, int &hx, int &ly, int &hy, int &lz, int &hz) {
+    lx = s.a0 == 0 ? s.vlo0 : (s.a1 == 0 ? s.vlo1 : s.vlo2);
+    hx = s.a0 == 0 ? s.vhi0 : (s.a1 == 0 ? s.vhi1 : s.vhi2);
+    ly = s.a0 == 1 ? s.vlo0 : (s.a1 == 1 ? s.vlo1 : s.vlo2);
+    hy = s.a0 == 1 ? s.vhi0 : (s.a1 == 1 ? s.vhi1 : s.vhi2);
+    lz = s.a0 == 2 ? s.vlo0 : (s.a1 == 2 ? s.vlo1 : s.vlo2);
+    hz = s.a0 == 2 ? s.vhi0 : (s.a1 == 2 ? s.vhi1 : s.vhi2);
+}
+
+// Appends `val` to list[] for every lane with p set, one counter update per
+// wave.  Called by all lanes of the wave together.
+template <class T>
+__device__ __forceinline__ void wave_append(bool p, T val, unsigned *counter, T *list) {
+    const unsigned long long m = __ballot(p);
+    if (!m) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(counter, (unsigned)__popcll(m));
+    base = __shfl(base, leader, 64);
+    if (p) list[base + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = val;
+}
 }  // namespace vrt

@@ -22,23 +22,32 @@ __global__ void k_clear_prev(uint32_t *__restrict__ words, const int32_t *__rest
 
 // Clears the per-frame brick-level state: level-3 occupancy, blocking flags
 // of bricks and 64^3 cells, the blocking box and the frame counters.
-__device__ __forceinline__ void b_reset(uint16_t *__restrict__ occ3, uint32_t *__restrict__ brick_bits, int64_t nbricks,
+__device__ __forceinline__ void b_reset(uint16_t *__restrict__ occ3, uint32_t *__restrict__ bin_count,
+                        uint32_t *__restrict__ brick_bits, int64_t nbricks,
                         uint8_t *__restrict__ super_blk, int64_t nsupers, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
     int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
-    if (i < nbricks) occ3[i] = 0;
+    if (i < nbricks) {
+        occ3[i] = 0;
+        bin_count[i] = 0u;
+    }
     if (i < (nbricks + 31) / 32) brick_bits[i] = 0u;
     if (i < nsupers) super_blk[i] = 0;
     if (i == 0) {
         st->n_fragments = 0;
         st->count_sum = 0;
+        st->n_cand = 0;
+        st->n_long = 0;
+        st->bin_total = 0;
         st->n_occ = 0;
         st->bbox[0] = st->bbox[1] = st->bbox[2] = INT_MAX;
         st->bbox[3] = st->bbox[4] = st->bbox[5] = INT_MIN;
     }
 }
 
-__global__ void k_reset(uint16_t *__restrict__ occ3, uint32_t *__restrict__ brick_bits, int64_t nbricks,
-                        uint8_t *__restrict__ super_blk, int64_t nsupers, DevStatus *__restrict__ st) { b_reset(occ3, brick_bits, nbricks, super_blk, nsupers, st, blockIdx.x, gridDim.x); }
+__global__ void k_reset(uint16_t *__restrict__ occ3, uint32_t *__restrict__ bin_count, uint32_t *__restrict__ brick_bits,
+                        int64_t nbricks, uint8_t *__restrict__ super_blk, int64_t nsupers, DevStatus *__restrict__ st) {
+    b_reset(occ3, bin_count, brick_bits, nbricks, super_blk, nsupers, st, blockIdx.x, gridDim.x);
+}
 
 // fixed-point coordinate: rint((x - origin) * s) as two binary32 operations
 __device__ __forceinline__ bool quantize1(float x, float o, float s, int &q) {
@@ -197,41 +206,246 @@ struct CountArgs {
     uint8_t *brick_flag;
 };
 
-// Pass 1: one thread per segment walks its voxel set and adds
+// Pass 1 for one segment with global atomics: walks its voxel set and adds
 // 1 + (q << 16) to each voxel's packed word (count low, occupancy high).
 // The adds return nothing: a count field that wraps past 65535 is found
 // afterwards, because the count fields then sum to less than the number of
-// fragments (each wrap loses exactly 65536).
+// fragments (each wrap loses exactly 65536).  Returns the fragments.
+__device__ __forceinline__ unsigned long long vox_count_segment(const CountArgs &a, int64_t i, DevStatus *st) {
+    if (i + 1 >= a.nv) return 0;
+    const VRec A = a.vrec[i];
+    if (!(A.flags & kSegValid)) return 0;
+    const VRec B = a.vrec[i + 1];
+    const long long dx = (long long)B.x - A.x, dy = (long long)B.y - A.y, dz = (long long)B.z - A.z;
+    if (dx >= 65536 || dx <= -65536 || dy >= 65536 || dy <= -65536 || dz >= 65536 || dz <= -65536) {
+        set_err(st, kErrRange);
+        return 0;
+    }
+    SlabSpan s = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), a.rq, a.G);
+    int64_t last_b = -1;
+    return for_each_voxel(s, [&](int x, int y, int z) {
+        int q = occupancy_quantum(A, B, a.rc, a.corr, x, y, z);
+        int64_t b = brick_index_of(x, y, z, a.nbx, a.nby);
+        atomicAdd(&a.words[b * kBrickVox + local_of(x, y, z)], 1u + ((uint32_t)q << 16));
+        if (b != last_b) {
+            a.brick_flag[b] = 1;
+            last_b = b;
+        }
+    });
+}
+
+// Pass 1, one thread per segment (the batched form's path).
 __device__ __forceinline__ void b_vox_count(CountArgs a, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
-    int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
-    unsigned long long nfrag = 0;
-    if (i + 1 < a.nv) {
-        VRec A = a.vrec[i];
-        if (A.flags & kSegValid) {
-            VRec B = a.vrec[i + 1];
-            long long dx = (long long)B.x - A.x, dy = (long long)B.y - A.y, dz = (long long)B.z - A.z;
-            if (dx >= 65536 || dx <= -65536 || dy >= 65536 || dy <= -65536 || dz >= 65536 || dz <= -65536) {
-                set_err(st, kErrRange);
-            } else {
-                SlabSpan s = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), a.rq, a.G);
-                int64_t last_b = -1;
-                nfrag = for_each_voxel(s, [&](int x, int y, int z) {
-                    int q = occupancy_quantum(A, B, a.rc, a.corr, x, y, z);
-                    int64_t b = brick_index_of(x, y, z, a.nbx, a.nby);
-                    atomicAdd(&a.words[b * kBrickVox + local_of(x, y, z)], 1u + ((uint32_t)q << 16));
-                    if (b != last_b) {
-                        a.brick_flag[b] = 1;
-                        last_b = b;
-                    }
-                });
-            }
+    unsigned long long nfrag = vox_count_segment(a, (int64_t)bid_ * blockDim.x + threadIdx.x, st);
+    nfrag = wave_sum_u64(nfrag);
+    if ((threadIdx.x & 63) == 0 && nfrag) atomicAdd(&st->n_fragments, nfrag);
+}
+
+// ------------------------------------------------------------------------
+// Pass 1 by brick (the per-context path).  Segments are first binned by the
+// bricks of their voxel box; then one workgroup per binned brick adds the
+// brick's fragments in LDS and stores its 512 words once.  Device-wide atomics
+// go from one per fragment to about one per run of consecutive segments in a
+// brick; words are written with plain coalesced stores.
+
+struct BinArgs {
+    const VRec *vrec;
+    int64_t nv;
+    long long rq;
+    int G[3];
+    int nb[3];
+    uint32_t *bin_count;
+    uint2 *bin_range;
+    int32_t *cand;
+    uint32_t *bins;
+    int64_t bin_cap;
+    uint32_t *long_ids;
+};
+
+// Brick box of segment i's voxel set; 0 bricks when the segment is not
+// valid, out of range (flagged when `flag`) or its set is empty.
+__device__ __forceinline__ int seg_brick_box(const BinArgs &a, int64_t i, DevStatus *st, bool flag, int &bx0,
+                                             int &bx1, int &by0, int &by1, int &bz0, int &bz1) {
+    if (i + 1 >= a.nv) return 0;
+    const VRec A = a.vrec[i];
+    if (!(A.flags & kSegValid)) return 0;
+    const VRec B = a.vrec[i + 1];
+    const long long dx = (long long)B.x - A.x, dy = (long long)B.y - A.y, dz = (long long)B.z - A.z;
+    if (dx >= 65536 || dx <= -65536 || dy >= 65536 || dy <= -65536 || dz >= 65536 || dz <= -65536) {
+        if (flag) set_err(st, kErrRange);
+        return 0;
+    }
+    // the voxel range of the closed capsule AABB, clipped to the grid (the box make_span computes)
+    int lo[3], hi[3];
+    const int pa[3] = {A.x, A.y, A.z}, pb[3] = {B.x, B.y, B.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const long long l = (long long)(pa[k] < pb[k] ? pa[k] : pb[k]) - a.rq - 1;
+        const long long h = (long long)(pa[k] < pb[k] ? pb[k] : pa[k]) + a.rq;
+        long long vl = l >> 8, vh = h >> 8;  // floor division by kQ = 256
+        vl = vl < 0 ? 0 : vl;
+        vh = vh > a.G[k] - 1 ? a.G[k] - 1 : vh;
+        if (vl > vh) return 0;
+        lo[k] = (int)vl >> 3;
+        hi[k] = (int)vh >> 3;
+    }
+    bx0 = lo[0], bx1 = hi[0], by0 = lo[1], by1 = hi[1], bz0 = lo[2], bz1 = hi[2];
+    return (bx1 - bx0 + 1) * (by1 - by0 + 1) * (bz1 - bz0 + 1);
+}
+
+// Brick k (0-based, x fastest) of a brick box.
+__device__ __forceinline__ int box_brick(const BinArgs &a, int k, int bx0, int bx1, int by0, int by1, int bz0) {
+    const int wx = bx1 - bx0 + 1, wy = by1 - by0 + 1;
+    const int bx = bx0 + k % wx, by = by0 + (k / wx) % wy, bz = bz0 + k / (wx * wy);
+    return (bz * a.nb[1] + by) * a.nb[0] + bx;
+}
+
+// Runs of consecutive lanes whose segment lies in one brick (key >= 0): true
+// for the first lane of a run, with the run's length.
+__device__ __forceinline__ bool run_head(int key, int lane, unsigned long long &heads, unsigned &len) {
+    const int prev = __shfl_up(key, 1, 64);
+    const bool head = key >= 0 && (lane == 0 || prev != key);
+    heads = __ballot(head);
+    const unsigned long long single = __ballot(key >= 0);
+    const unsigned long long stop = (heads | ~single) & ~((2ull << lane) - 1ull);  // lanes after this one
+    len = (unsigned)((stop ? __ffsll((long long)stop) - 1 : 64) - lane);
+    return head;
+}
+
+// Bin sizes: one thread per segment.  A brick whose count leaves zero is
+// appended to the candidate list; segments spanning more than kMaxBinBricks
+// bricks go to the long list.
+__device__ __forceinline__ void b_bin_count(BinArgs a, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
+    const int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int bx0 = 0, bx1 = 0, by0 = 0, by1 = 0, bz0 = 0, bz1 = 0;
+    const int nbr = seg_brick_box(a, i, st, true, bx0, bx1, by0, by1, bz0, bz1);
+    const int nbin = nbr <= kMaxBinBricks ? nbr : 0;
+    // the k-th bricks of consecutive segments along a polyline mostly agree:
+    // one atomic per run of equal bricks
+    for (int k = 0; __ballot(k < nbin); ++k) {
+        const int key = k < nbin ? box_brick(a, k, bx0, bx1, by0, by1, bz0) : -1;
+        unsigned long long heads;
+        unsigned len;
+        const bool head = run_head(key, lane, heads, len);
+        bool fresh = false;
+        if (head) fresh = atomicAdd(&a.bin_count[key], len) == 0u;
+        wave_append(fresh, key, &st->n_cand, a.cand);
+    }
+    wave_append(nbr > kMaxBinBricks, (uint32_t)i, &st->n_long, a.long_ids);
+}
+
+// Bin ranges: per wave, an inclusive scan of the candidates' counts and one
+// atomic on the running total.
+__device__ __forceinline__ void b_bin_alloc(BinArgs a, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
+    const unsigned n = st->n_cand;
+    const int lane = threadIdx.x & 63;
+    const unsigned stride = nblk_ * blockDim.x;
+    for (unsigned base = bid_ * blockDim.x + (threadIdx.x & ~63u); base < n; base += stride) {
+        const unsigned k = base + lane;
+        int b = -1;
+        unsigned c = 0;
+        if (k < n) {
+            b = a.cand[k];
+            c = a.bin_count[b];
+        }
+        unsigned incl = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        unsigned long long start = 0;
+        if (lane == 63) start = atomicAdd(&st->bin_total, (unsigned long long)incl);
+        start = __shfl(start, 63, 64);
+        if (k < n) a.bin_range[b] = make_uint2((uint32_t)(start + incl - c), c);
+    }
+}
+
+// Bin entries: the same enumeration as b_bin_count; each run (or brick of a
+// multi-brick segment) takes its slots by counting its bin back down to zero.
+__device__ __forceinline__ void b_bin_fill(BinArgs a, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
+    const int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int bx0 = 0, bx1 = 0, by0 = 0, by1 = 0, bz0 = 0, bz1 = 0;
+    const int nbr = seg_brick_box(a, i, st, false, bx0, bx1, by0, by1, bz0, bz1);
+    const int nbin = nbr <= kMaxBinBricks ? nbr : 0;
+    for (int k = 0; __ballot(k < nbin); ++k) {
+        const int key = k < nbin ? box_brick(a, k, bx0, bx1, by0, by1, bz0) : -1;
+        unsigned long long heads;
+        unsigned len;
+        const bool head = run_head(key, lane, heads, len);
+        unsigned old = 0;
+        if (head) old = atomicSub(&a.bin_count[key], len);
+        // each lane of a run takes its slot from the run's head (the last head at or below it)
+        const int h = key >= 0 ? 63 - __clzll((long long)(heads & ((2ull << lane) - 1ull))) : lane;
+        const unsigned old_h = __shfl(old, h, 64), len_h = __shfl(len, h, 64);
+        if (key >= 0) {
+            const uint64_t slot = (uint64_t)a.bin_range[key].x + (old_h - len_h) + (unsigned)(lane - h);
+            if ((int64_t)slot < a.bin_cap) a.bins[slot] = (uint32_t)i;
         }
     }
+}
+
+struct AccumArgs {
+    CountArgs ca;
+    const int32_t *cand;
+    const uint2 *bin_range;
+    const uint32_t *bins;
+};
+
+// Words of the binned bricks: one workgroup per brick adds its bin's
+// fragments in LDS, then stores all 512 words and the brick's flag.
+__device__ __forceinline__ void b_brick_accum(AccumArgs a, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
+    __shared__ uint32_t w[kBrickVox];
+    const CountArgs &c = a.ca;
+    const unsigned n = st->n_cand;
+    const int t = threadIdx.x;
+    unsigned long long nfrag = 0;
+    for (unsigned sl = bid_; sl < n; sl += nblk_) {
+        const int b = a.cand[sl];
+        const uint2 r = a.bin_range[b];
+        for (int v = t; v < kBrickVox; v += blockDim.x) w[v] = 0u;
+        __syncthreads();
+        const int bx = b % c.nbx, by = (b / c.nbx) % c.nby, bz = b / (c.nbx * c.nby);
+        for (uint32_t k = t; k < r.y; k += blockDim.x) {
+            const uint32_t id = a.bins[r.x + k];
+            const VRec A = c.vrec[id], B = c.vrec[id + 1];
+            const SlabSpan s = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), c.rq, c.G);
+            nfrag += for_each_voxel_in_brick(s, bx, by, bz, [&](int x, int y, int z) {
+                const int q = occupancy_quantum(A, B, c.rc, c.corr, x, y, z);
+                atomicAdd(&w[local_of(x, y, z)], 1u + ((uint32_t)q << 16));
+            });
+        }
+        __syncthreads();
+        unsigned any = 0;
+        for (int v = t; v < kBrickVox; v += blockDim.x) {
+            const uint32_t wd = w[v];
+            c.words[(int64_t)b * kBrickVox + v] = wd;
+            any |= wd & 0xFFFFu;
+        }
+        if (__syncthreads_or(any != 0u) && t == 0) c.brick_flag[b] = 1;
+    }
+    nfrag = wave_sum_u64(nfrag);
+    if ((t & 63) == 0 && nfrag) atomicAdd(&st->n_fragments, nfrag);
+}
+
+// Pass 1 for the long segments, after the binned bricks' words are stored.
+__device__ __forceinline__ void b_vox_long(CountArgs a, const uint32_t *__restrict__ long_ids, DevStatus *__restrict__ st,
+                                           unsigned bid_, unsigned nblk_) {
+    const unsigned n = st->n_long;
+    unsigned long long nfrag = 0;
+    for (unsigned k = bid_ * blockDim.x + threadIdx.x; k < n; k += nblk_ * blockDim.x)
+        nfrag += vox_count_segment(a, long_ids[k], st);
     nfrag = wave_sum_u64(nfrag);
     if ((threadIdx.x & 63) == 0 && nfrag) atomicAdd(&st->n_fragments, nfrag);
 }
 
 __global__ void __launch_bounds__(256) k_vox_count(CountArgs a, DevStatus *__restrict__ st) { b_vox_count(a, st, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(256) k_bin_count(BinArgs a, DevStatus *__restrict__ st) { b_bin_count(a, st, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(256) k_bin_alloc(BinArgs a, DevStatus *__restrict__ st) { b_bin_alloc(a, st, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(256) k_bin_fill(BinArgs a, DevStatus *__restrict__ st) { b_bin_fill(a, st, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(256) k_brick_accum(AccumArgs a, DevStatus *__restrict__ st) { b_brick_accum(a, st, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(256) k_vox_long(CountArgs a, const uint32_t *__restrict__ long_ids, DevStatus *__restrict__ st) { b_vox_long(a, long_ids, st, blockIdx.x, gridDim.x); }
 
 // Single workgroup: compacts the touched-brick flags into the ascending list
 // of occupied bricks, writes each brick's slot (or -1), clears the flags.
@@ -463,6 +677,8 @@ struct VoxPlan {
     GridArgs g;
     IngestArgs ia;
     CountArgs ca;
+    BinArgs ba;
+    AccumArgs aa;
 };
 
 static VoxPlan make_vox_plan(const vrt_ctx *c, const vrt_lines *L, float s_q) {
@@ -495,8 +711,28 @@ static VoxPlan make_vox_plan(const vrt_ctx *c, const vrt_lines *L, float s_q) {
     p.ca.nby = c->dims[1] / 8;
     p.ca.words = A.words;
     p.ca.brick_flag = A.brick_flag;
+    p.ba.vrec = A.vrec;
+    p.ba.nv = L->n_vertices;
+    p.ba.rq = c->rq;
+    for (int k = 0; k < 3; ++k) {
+        p.ba.G[k] = p.g.G[k];
+        p.ba.nb[k] = p.g.nb[k];
+    }
+    p.ba.bin_count = A.bin_count;
+    p.ba.bin_range = A.bin_range;
+    p.ba.cand = A.cand;
+    p.ba.bins = A.bins;
+    p.ba.bin_cap = (int64_t)kMaxBinBricks * c->desc.max_vertices;
+    p.ba.long_ids = A.long_ids;
+    p.aa.ca = p.ca;
+    p.aa.cand = A.cand;
+    p.aa.bin_range = A.bin_range;
+    p.aa.bins = A.bins;
     return p;
 }
+
+// Workgroups of the per-brick passes (grid-stride over the binned bricks).
+static constexpr unsigned kBrickBlocks = 8192;
 
 hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *L, float s_q, hipStream_t st) {
     Arenas &A = c->a;
@@ -504,11 +740,15 @@ hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *L, float s_q, hipStream_
     const unsigned eb = (unsigned)((p.nv + 255) / 256);
     VRT_LAUNCH(c, "k_clear_prev", st, k_clear_prev<<<2048, 128, 0, st>>>(A.words, A.brick_list, A.status));
     VRT_LAUNCH(c, "k_reset", st,
-               k_reset<<<(unsigned)((p.nb + 255) / 256), 256, 0, st>>>(A.occ3, A.brick_bits, p.nb, A.super_blk, p.ns,
-                                                                       A.status));
+               k_reset<<<(unsigned)((p.nb + 255) / 256), 256, 0, st>>>(A.occ3, A.bin_count, A.brick_bits, p.nb,
+                                                                       A.super_blk, p.ns, A.status));
     VRT_LAUNCH(c, "k_ingest", st, k_ingest<<<eb, 256, 0, st>>>(p.ia, A.vrec, A.status));
     if (p.fp16) VRT_LAUNCH(c, "k_pack16", st, k_pack16<<<eb, 256, 0, st>>>(A.vrec, p.nv, A.srec16));
-    VRT_LAUNCH(c, "k_vox_count", st, k_vox_count<<<eb, 256, 0, st>>>(p.ca, A.status));
+    VRT_LAUNCH(c, "k_bin_count", st, k_bin_count<<<eb, 256, 0, st>>>(p.ba, A.status));
+    VRT_LAUNCH(c, "k_bin_alloc", st, k_bin_alloc<<<64, 256, 0, st>>>(p.ba, A.status));
+    VRT_LAUNCH(c, "k_bin_fill", st, k_bin_fill<<<eb, 256, 0, st>>>(p.ba, A.status));
+    VRT_LAUNCH(c, "k_brick_accum", st, k_brick_accum<<<kBrickBlocks, 256, 0, st>>>(p.aa, A.status));
+    VRT_LAUNCH(c, "k_vox_long", st, k_vox_long<<<256, 256, 0, st>>>(p.ca, A.long_ids, A.status));
     VRT_LAUNCH(c, "k_brick_compact", st,
                k_brick_compact<<<1, 1024, 0, st>>>(A.brick_flag, p.nb, A.brick_list, A.brick_slot, A.status));
     VRT_LAUNCH(c, "k_occ_brick", st,

@@ -182,6 +182,12 @@ EDGE_SETS = {
     # thin lines: radius below the PWAA minimum, radius zero
     "thin": lambda: _make([[[1.3, 2.7, 3.1], [14.2, 12.9, 6.6], [3.3, 9.9, 14.4]]], 16, 0.05),
     "zero_radius": lambda: _make([[[1.3, 2.7, 3.1], [14.2, 12.9, 6.6]]], 16, 0.0),
+    # segments whose voxel box spans more than 8 bricks, sharing bricks with short polylines laid along them
+    "long_and_short": lambda: _make(
+        [[[2.5, 3.1, 4.2], [60.3, 41.7, 55.9], [10.2, 58.8, 30.1]], [[63.5, 0.5, 32.0], [0.5, 63.5, 32.0]]]
+        + [[list(np.add(np.array([2.5, 3.1, 4.2]) + np.subtract([60.3, 41.7, 55.9], [2.5, 3.1, 4.2]) * t, d))
+            for t in (0.40, 0.41, 0.42, 0.43, 0.44)] for d in ((0.2, 0.0, 0.1), (-0.3, 0.25, 0.0))]
+        + [[[31.0 + 0.45 * k, 32.6 - 0.45 * k, 32.2] for k in range(12)]], 64, 0.7),
     # non-cubic grid
     "non_cubic": lambda: synth.LineSet(**{**synth.random_walk_set(seed=5, n_poly=30, n_seg=20, G=24).__dict__,
                                           "dims": (24, 16, 40)}),
