@@ -11,10 +11,11 @@ namespace {
 __device__ __forceinline__ void b_cull_reset(uint8_t *__restrict__ vis3, int64_t nb, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
     int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     if (i < nb) vis3[i] = 0;
-    if (i == 0) {
-        st->n_listed = 0;
-        st->vbox[0] = st->vbox[1] = st->vbox[2] = INT_MAX;
-        st->vbox[3] = st->vbox[4] = st->vbox[5] = INT_MIN;
+    if (i == 0) st->n_listed = 0;
+    if (i < kStripes) {
+        int *p = st->stripe[i].vbox;
+        p[0] = p[1] = p[2] = INT_MAX;
+        p[3] = p[4] = p[5] = INT_MIN;
     }
 }
 
@@ -72,7 +73,15 @@ template <bool kLds>
 __device__ __forceinline__ void b_cull_walk(CullArgs a, CullCells cells, const uint32_t *__restrict__ occ_list,
                                                    const DevStatus *__restrict__ st, uint8_t *__restrict__ vis0, unsigned bid_, unsigned nblk_) {
     __shared__ int bbox[6];
-    if (threadIdx.x < 6) bbox[threadIdx.x] = st->bbox[threadIdx.x];
+    if (threadIdx.x < 6) {  // combine the stripes of the blocking box
+        const int k = threadIdx.x;
+        int v = k < 3 ? INT_MAX : INT_MIN;
+        for (int s = 0; s < kStripes; ++s) {
+            const int u = st->stripe[s].bbox[k];
+            v = k < 3 ? (u < v ? u : v) : (u > v ? u : v);
+        }
+        bbox[k] = v;
+    }
     if (kLds) {
         const int64_t nb = (int64_t)a.g.nb[0] * a.g.nb[1] * a.g.nb[2];
         const int nw = (int)((nb + 31) / 32), ns = a.g.ns[0] * a.g.ns[1] * a.g.ns[2];
@@ -154,8 +163,9 @@ __device__ __forceinline__ void b_cull_brick(int limit, GridArgs g, const uint32
             if (o) {
                 const int bx = (int)(b % g.nb[0]), by = (int)((b / g.nb[0]) % g.nb[1]);
                 const int bz = (int)(b / ((int64_t)g.nb[0] * g.nb[1]));
-                atomicMin(&st->vbox[0], bx); atomicMin(&st->vbox[1], by); atomicMin(&st->vbox[2], bz);
-                atomicMax(&st->vbox[3], bx); atomicMax(&st->vbox[4], by); atomicMax(&st->vbox[5], bz);
+                int *p = st->stripe[bid_ % kStripes].vbox;
+                atomicMin(&p[0], bx); atomicMin(&p[1], by); atomicMin(&p[2], bz);
+                atomicMax(&p[3], bx); atomicMax(&p[4], by); atomicMax(&p[5], bz);
             }
         }
         __syncthreads();

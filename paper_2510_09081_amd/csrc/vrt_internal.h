@@ -37,19 +37,29 @@ struct __align__(16) SRec16 {
 };
 static_assert(sizeof(SRec16) == 32, "SRec16 is 32 bytes");
 
+// Device-wide atomics on one cache line serialize (about 11 ns each on
+// MI355X), so per-block tallies go to the stripe of their block (one 128-byte
+// line each) and the readers combine the stripes.
+constexpr int kStripes = 64;
+struct alignas(128) StatStripe {
+    unsigned long long frag;  // pass-1 fragments
+    unsigned long long csum;  // sum of the 16-bit count fields
+    int bbox[6];              // blocking-voxel bounds
+    int vbox[6];              // visible-brick bounds
+};
+
 struct DevStatus {
     unsigned int err;
     unsigned int n_bricks;
-    unsigned long long n_fragments;
+    unsigned long long n_fragments;  // final value (sum of the stripes, written after pass 1)
     unsigned long long n_listed;
-    int bbox[6];  // blocking-voxel bounds: min x,y,z then max x,y,z (voxels)
     unsigned int n_occ;  // occupied voxels (entries of occ_list)
-    int vbox[6];         // visible-brick bounds: min bx,by,bz then max (bricks)
+    int vbox[6];         // visible-brick bounds: min bx,by,bz then max (bricks), combined at trace start
     unsigned int n_queue;  // rays queued by the trace's march phase
-    unsigned long long count_sum;  // sum of the 16-bit count fields of all words (== n_fragments unless one wrapped)
     unsigned int n_cand;           // bricks with a non-empty segment bin (entries of cand)
     unsigned int n_long;           // segments too long for the bins (entries of long_ids)
     unsigned long long bin_total;  // bin entries allocated
+    StatStripe stripe[kStripes];
 };
 
 // A segment is binned into every brick of its voxel box when that box has at

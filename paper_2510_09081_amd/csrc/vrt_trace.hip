@@ -1,4 +1,6 @@
 // vrt_trace.hip -- Section 3.5: voxel ray tracing through the per-voxel lists.
+#include <climits>
+
 #include "vrt_internal.h"
 
 namespace vrt {
@@ -405,10 +407,15 @@ __device__ __forceinline__ unsigned long long group_min(unsigned long long k) {
     }
     return k;
 }
+// The kGroup bits of this lane's group in a wave-wide ballot (bit j = lane j of the group).
+template <int kGroup>
+__device__ __forceinline__ unsigned long long group_ballot(bool p, int lane) {
+    const unsigned long long m = __ballot(p);
+    return (m >> (lane & ~(kGroup - 1))) & (kGroup == 64 ? ~0ull : ((1ull << kGroup) - 1ull));
+}
 template <int kGroup>
 __device__ __forceinline__ bool group_any(bool p, int lane) {
-    const unsigned long long m = __ballot(p);
-    return ((m >> (lane & ~(kGroup - 1))) & ((1ull << kGroup) - 1ull)) != 0ull;
+    return group_ballot<kGroup>(p, lane) != 0ull;
 }
 
 // Result of one ray.
@@ -457,15 +464,20 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
         return true;
     }
     // Transparent: each lane keeps its kLaneKeys smallest accepted keys above
-    // the threshold; the group composites the smallest head key of all lanes
-    // while it is safe, i.e. while no lane that dropped keys has run dry;
-    // otherwise it rescans above the last composited key.
+    // the threshold, each with its segment's colour; the group composites the
+    // smallest head key of all lanes while it is safe, i.e. while no lane that
+    // dropped keys has run dry; otherwise it rescans above the last composited
+    // key.
     unsigned long long thr = 0ull;
     bool have_thr = false;
     for (;;) {
         unsigned long long kk[kLaneKeys];
+        float kr[kLaneKeys], kg[kLaneKeys], kb[kLaneKeys];  // colours of the keys
 #pragma unroll
-        for (int j = 0; j < kLaneKeys; ++j) kk[j] = kNoKey;
+        for (int j = 0; j < kLaneKeys; ++j) {
+            kk[j] = kNoKey;
+            kr[j] = kg[j] = kb[j] = 0.0f;
+        }
         int nacc = 0;
         if (kStats && gl == 0) ++cn.pass;
         for_each_entry<kStats, kForm, Cfg>(a, w, gl, cn, [&](uint32_t id, const LocalSeg &g) {
@@ -474,11 +486,21 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
             unsigned long long key = hit_key(s, id);
             if (have_thr && !(key > thr)) return;
             ++nacc;
+            const float3 col = seg_colour(g.pa, g.pb);
+            float cr = col.x, cg = col.y, cb = col.z;
 #pragma unroll
             for (int j = 0; j < kLaneKeys; ++j) {  // sorted insert, the largest falls off the end
-                const unsigned long long lo = key < kk[j] ? key : kk[j];
-                key = key < kk[j] ? kk[j] : key;
+                const bool less = key < kk[j];
+                const unsigned long long lo = less ? key : kk[j];
+                key = less ? kk[j] : key;
                 kk[j] = lo;
+                const float r0 = less ? cr : kr[j], g0 = less ? cg : kg[j], b0 = less ? cb : kb[j];
+                cr = less ? kr[j] : cr;
+                cg = less ? kg[j] : cg;
+                cb = less ? kb[j] : cb;
+                kr[j] = r0;
+                kg[j] = g0;
+                kb[j] = b0;
             }
         });
         const bool dropped = nacc > kLaneKeys;
@@ -490,9 +512,18 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
             }
             const unsigned long long m = group_min<kGroup>(kk[0]);
             if (m == kNoKey) break;
-            if (kk[0] == m) {  // keys are unique (one per segment), so exactly one lane pops
+            // keys are unique (one per segment), so exactly one lane holds m: it pops, and its colour is used
+            const bool own = kk[0] == m;
+            const int src = (lane & ~(kGroup - 1)) + __ffsll((long long)group_ballot<kGroup>(own, lane)) - 1;
+            const float3 c = make_float3(__shfl(kr[0], src, 64), __shfl(kg[0], src, 64), __shfl(kb[0], src, 64));
+            if (own) {
 #pragma unroll
-                for (int j = 0; j + 1 < kLaneKeys; ++j) kk[j] = kk[j + 1];
+                for (int j = 0; j + 1 < kLaneKeys; ++j) {
+                    kk[j] = kk[j + 1];
+                    kr[j] = kr[j + 1];
+                    kg[j] = kg[j + 1];
+                    kb[j] = kb[j + 1];
+                }
                 kk[kLaneKeys - 1] = kNoKey;
             }
             const uint32_t id = (uint32_t)m;
@@ -500,8 +531,6 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
                 sh.first = (int)id;
                 sh.first_t = w.tcur + __uint_as_float((uint32_t)(m >> 32));
             }
-            const LocalSeg g = load_seg<kForm>(a, id, cx, cy, cz);
-            const float3 c = seg_colour(g.pa, g.pb);
             const float wgt = sh.T * a.p.alpha;
             sh.col.x += wgt * c.x;
             sh.col.y += wgt * c.y;
@@ -546,7 +575,19 @@ __device__ __forceinline__ void flush_counters(const TraceArgs &a, const Counter
     if (lane == 0 && mx) atomicMax(&a.stat_acc[7], mx);
 }
 
-__device__ __forceinline__ void b_trace_begin(DevStatus *st, unsigned bid_, unsigned nblk_) { st->n_queue = 0; }
+// Clears the ray queue and combines the stripes of the visible-brick box.
+__device__ __forceinline__ void b_trace_begin(DevStatus *st, unsigned bid_, unsigned nblk_) {
+    const int k = threadIdx.x;
+    if (k == 0) st->n_queue = 0;
+    if (k < 6) {
+        int v = k < 3 ? INT_MAX : INT_MIN;
+        for (int s = 0; s < kStripes; ++s) {
+            const int u = st->stripe[s].vbox[k];
+            v = k < 3 ? (u < v ? u : v) : (u > v ? u : v);
+        }
+        st->vbox[k] = v;
+    }
+}
 
 __global__ void k_trace_begin(DevStatus *st) { b_trace_begin(st, blockIdx.x, gridDim.x); }
 
@@ -580,18 +621,24 @@ __device__ __forceinline__ void b_trace_march(TraceArgs a, unsigned bid_, unsign
         w.fresh = true;
         found = march<kStats>(a, r, w, cn);
     }
+    // one queue append per block (same-address atomics serialize)
+    __shared__ unsigned s_wcnt[16];
+    __shared__ unsigned s_base;
     const unsigned long long mask = __ballot(found);
-    if (mask) {
-        const int leader = __ffsll((long long)mask) - 1;
-        unsigned base = 0;
-        if (lane == leader) base = atomicAdd(&a.st->n_queue, (unsigned)__popcll(mask));
-        base = __shfl(base, leader, 64);
-        if (found) {
-            const unsigned pos = base + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
-            const uint32_t pix = (uint32_t)(py * a.p.W + px);
-            const uint32_t vp = (uint32_t)w.v[0] | ((uint32_t)w.v[1] << 10) | ((uint32_t)w.v[2] << 20);
-            a.queue[pos] = make_uint4(pix, vp, __float_as_uint(w.tcur), __float_as_uint(w.tout));
-        }
+    if (lane == 0) s_wcnt[wv] = (unsigned)__popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned tot = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tot += s_wcnt[k];
+        s_base = tot ? atomicAdd(&a.st->n_queue, tot) : 0u;
+    }
+    __syncthreads();
+    if (found) {
+        unsigned pos = s_base + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+        for (int k = 0; k < wv; ++k) pos += s_wcnt[k];
+        const uint32_t pix = (uint32_t)(py * a.p.W + px);
+        const uint32_t vp = (uint32_t)w.v[0] | ((uint32_t)w.v[1] << 10) | ((uint32_t)w.v[2] << 20);
+        a.queue[pos] = make_uint4(pix, vp, __float_as_uint(w.tcur), __float_as_uint(w.tout));
     }
     flush_counters<kStats>(a, cn, false, lane, 1);
     if (live && !found) write_pixel(a, (int64_t)py * a.p.W + px, Shade());
@@ -629,7 +676,8 @@ __device__ __forceinline__ void b_trace_shade(TraceArgs a, unsigned bid_, unsign
             w.tout = __uint_as_float(q.w);
             w.fresh = true;
             Counters walk_cn;  // walk counters once per ray
-            bool have = march<kStats>(a, r, w, walk_cn);  // recomputes the exit data of the queued voxel
+            // recomputes the exit data of the queued voxel
+            bool have = march<kStats>(a, r, w, walk_cn);
             while (have) {
                 if (shade_voxel<kStats, kForm, Cfg>(a, r, w, sh, cn, lane)) break;
                 if (!step_voxel(a, r, w)) break;
@@ -774,7 +822,7 @@ static void launch_shade(const vrt_tune &t, const TraceArgs &a, hipStream_t st) 
 hipError_t launch_trace(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st) {
     TraceArgs a = trace_args(c, p, img);
     const vrt_tune &t = c->tune[p.mode == VRT_TRACE_OPAQUE ? 0 : 1];
-    VRT_LAUNCH(c, "k_trace_begin", st, k_trace_begin<<<1, 1, 0, st>>>(a.st));
+    VRT_LAUNCH(c, "k_trace_begin", st, k_trace_begin<<<1, 64, 0, st>>>(a.st));
     VRT_LAUNCH(c, "k_trace_march", st, k_trace_march<false><<<march_grid(p, t.march_threads), t.march_threads, 0, st>>>(a));
     if (c->desc.form == VRT_FORM_FP16)
         VRT_LAUNCH(c, "k_trace_shade", st, (launch_shade<false, VRT_FORM_FP16>(t, a, st)));
@@ -788,7 +836,7 @@ hipError_t launch_trace(vrt_ctx *c, const TraceParams &p, const vrt_image *img, 
 hipError_t launch_trace_stats(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st) {
     TraceArgs a = trace_args(c, p, img);
     k_stat_clear<<<1024, 256, 0, st>>>(c->a.brick_list, c->a.status, c->n_vertices, a.stat_vox, a.stat_seg, a.stat_acc);
-    k_trace_begin<<<1, 1, 0, st>>>(a.st);
+    k_trace_begin<<<1, 64, 0, st>>>(a.st);
     k_trace_march<true><<<march_grid(p, 256), 256, 0, st>>>(a);
     if (c->desc.form == VRT_FORM_FP16) k_trace_shade<true, VRT_FORM_FP16, DefaultShade><<<4096, 256, 0, st>>>(a);
     else k_trace_shade<true, VRT_FORM_PLAIN, DefaultShade><<<4096, 256, 0, st>>>(a);

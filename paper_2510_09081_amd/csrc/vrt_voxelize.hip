@@ -34,13 +34,17 @@ __device__ __forceinline__ void b_reset(uint16_t *__restrict__ occ3, uint32_t *_
     if (i < nsupers) super_blk[i] = 0;
     if (i == 0) {
         st->n_fragments = 0;
-        st->count_sum = 0;
         st->n_cand = 0;
         st->n_long = 0;
         st->bin_total = 0;
         st->n_occ = 0;
-        st->bbox[0] = st->bbox[1] = st->bbox[2] = INT_MAX;
-        st->bbox[3] = st->bbox[4] = st->bbox[5] = INT_MIN;
+    }
+    if (i < kStripes) {
+        StatStripe &p = st->stripe[i];
+        p.frag = 0;
+        p.csum = 0;
+        p.bbox[0] = p.bbox[1] = p.bbox[2] = INT_MAX;
+        p.bbox[3] = p.bbox[4] = p.bbox[5] = INT_MIN;
     }
 }
 
@@ -238,7 +242,7 @@ __device__ __forceinline__ unsigned long long vox_count_segment(const CountArgs 
 __device__ __forceinline__ void b_vox_count(CountArgs a, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
     unsigned long long nfrag = vox_count_segment(a, (int64_t)bid_ * blockDim.x + threadIdx.x, st);
     nfrag = wave_sum_u64(nfrag);
-    if ((threadIdx.x & 63) == 0 && nfrag) atomicAdd(&st->n_fragments, nfrag);
+    if ((threadIdx.x & 63) == 0 && nfrag) atomicAdd(&st->stripe[bid_ % kStripes].frag, nfrag);
 }
 
 // ------------------------------------------------------------------------
@@ -426,7 +430,7 @@ __device__ __forceinline__ void b_brick_accum(AccumArgs a, DevStatus *__restrict
         if (__syncthreads_or(any != 0u) && t == 0) c.brick_flag[b] = 1;
     }
     nfrag = wave_sum_u64(nfrag);
-    if ((t & 63) == 0 && nfrag) atomicAdd(&st->n_fragments, nfrag);
+    if ((t & 63) == 0 && nfrag) atomicAdd(&st->stripe[bid_ % kStripes].frag, nfrag);
 }
 
 // Pass 1 for the long segments, after the binned bricks' words are stored.
@@ -437,7 +441,7 @@ __device__ __forceinline__ void b_vox_long(CountArgs a, const uint32_t *__restri
     for (unsigned k = bid_ * blockDim.x + threadIdx.x; k < n; k += nblk_ * blockDim.x)
         nfrag += vox_count_segment(a, long_ids[k], st);
     nfrag = wave_sum_u64(nfrag);
-    if ((threadIdx.x & 63) == 0 && nfrag) atomicAdd(&st->n_fragments, nfrag);
+    if ((threadIdx.x & 63) == 0 && nfrag) atomicAdd(&st->stripe[bid_ % kStripes].frag, nfrag);
 }
 
 __global__ void __launch_bounds__(256) k_vox_count(CountArgs a, DevStatus *__restrict__ st) { b_vox_count(a, st, blockIdx.x, gridDim.x); }
@@ -525,8 +529,25 @@ __device__ __forceinline__ void b_occ_brick(const uint32_t *__restrict__ words,
     __shared__ unsigned base;
     const unsigned nbk = st->n_bricks;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    // this block's bricks: one contiguous range of slots, so that the occupied
+    // list takes one atomic per block (same-address atomics serialize)
+    const unsigned per = (nbk + nblk_ - 1) / nblk_;
+    const unsigned sl0 = bid_ * per < nbk ? bid_ * per : nbk, sl1 = sl0 + per < nbk ? sl0 + per : nbk;
+    if (sl0 >= sl1) return;  // the whole block
+    unsigned occ_t = 0;
+    for (unsigned sl = sl0; sl < sl1; ++sl) occ_t += (words[(int64_t)list[sl] * kBrickVox + t] & 0xFFFFu) != 0u;
+    occ_t = (unsigned)wave_sum_u64(occ_t);
+    if (lane == 0) wcnt[w] = occ_t;
+    __syncthreads();
+    if (t == 0) {
+        unsigned tot = 0;
+        for (int k = 0; k < 8; ++k) tot += wcnt[k];
+        base = tot ? atomicAdd(&st->n_occ, tot) : 0u;
+    }
+    __syncthreads();
+    unsigned run = base;  // the block's next occupied-list position (same in every thread)
     unsigned long long csum = 0;  // count fields seen by this thread
-    for (unsigned sl = bid_; sl < nbk; sl += nblk_) {
+    for (unsigned sl = sl0; sl < sl1; ++sl) {
         int64_t b = list[sl];
         uint32_t wd = words[b * kBrickVox + t];
         uint32_t cnt = wd & 0xFFFFu, sum = wd >> 16;
@@ -538,17 +559,12 @@ __device__ __forceinline__ void b_occ_brick(const uint32_t *__restrict__ words,
         const unsigned long long m = __ballot(cnt != 0u);
         if (lane == 0) wcnt[w] = (unsigned)__popcll(m);
         __syncthreads();
-        if (t == 0) {
-            unsigned tot = 0;
-            for (int k = 0; k < 8; ++k) tot += wcnt[k];
-            base = tot ? atomicAdd(&st->n_occ, tot) : 0u;
-        }
-        __syncthreads();
         if (cnt) {
-            unsigned pos = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+            unsigned pos = run + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
             for (int k = 0; k < w; ++k) pos += wcnt[k];
             occ_list[pos] = (uint32_t)(b * kBrickVox + t);
         }
+        for (int k = 0; k < 8; ++k) run += wcnt[k];
         if (t < 64) {
             int X = t & 3, Y = (t >> 2) & 3, Z = t >> 4;
             unsigned s = 0;
@@ -577,7 +593,7 @@ __device__ __forceinline__ void b_occ_brick(const uint32_t *__restrict__ words,
         __syncthreads();
     }
     csum = wave_sum_u64(csum);
-    if (lane == 0 && csum) atomicAdd(&st->count_sum, csum);
+    if (lane == 0 && csum) atomicAdd(&st->stripe[bid_ % kStripes].csum, csum);
 }
 
 __global__ void __launch_bounds__(512) k_occ_brick(const uint32_t *__restrict__ words,
@@ -606,8 +622,16 @@ __device__ __forceinline__ void b_erode(GridArgs g, const uint16_t *__restrict__
     __shared__ int bb[6];
     const unsigned nbk = st->n_bricks;
     const int t = threadIdx.x;
-    // pass 1 is complete: a count field wrapped iff the fields sum to less than the fragments
-    if (bid_ == 0 && t == 0 && st->count_sum != st->n_fragments) set_err(st, kErrCount);
+    // pass 1 is complete: total the fragment stripes; a count field wrapped iff
+    // the fields sum to less than the fragments
+    if (bid_ == 0 && t < 64) {
+        const unsigned long long f = wave_sum_u64(t < kStripes ? st->stripe[t].frag : 0ull);
+        const unsigned long long c = wave_sum_u64(t < kStripes ? st->stripe[t].csum : 0ull);
+        if (t == 0) {
+            st->n_fragments = f;
+            if (c != f) set_err(st, kErrCount);
+        }
+    }
     for (unsigned sl = bid_; sl < nbk; sl += nblk_) {
         int64_t b = list[sl];
         if (t < 3) bb[t] = INT_MAX;
@@ -637,8 +661,9 @@ __device__ __forceinline__ void b_erode(GridArgs g, const uint16_t *__restrict__
         if (t == 0 && any) {
             atomicOr(&brick_bits[b >> 5], 1u << (b & 31));
             super_blk[((int64_t)(bz >> 3) * g.ns[1] + (by >> 3)) * g.ns[0] + (bx >> 3)] = 1;
-            atomicMin(&st->bbox[0], bb[0]); atomicMin(&st->bbox[1], bb[1]); atomicMin(&st->bbox[2], bb[2]);
-            atomicMax(&st->bbox[3], bb[3]); atomicMax(&st->bbox[4], bb[4]); atomicMax(&st->bbox[5], bb[5]);
+            int *p = st->stripe[bid_ % kStripes].bbox;
+            atomicMin(&p[0], bb[0]); atomicMin(&p[1], bb[1]); atomicMin(&p[2], bb[2]);
+            atomicMax(&p[3], bb[3]); atomicMax(&p[4], bb[4]); atomicMax(&p[5], bb[5]);
         }
         __syncthreads();
     }
@@ -752,7 +777,7 @@ hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *L, float s_q, hipStream_
     VRT_LAUNCH(c, "k_brick_compact", st,
                k_brick_compact<<<1, 1024, 0, st>>>(A.brick_flag, p.nb, A.brick_list, A.brick_slot, A.status));
     VRT_LAUNCH(c, "k_occ_brick", st,
-               k_occ_brick<<<4096, 512, 0, st>>>(A.words, A.brick_list, A.status, A.occ0, A.occ1, A.occ2, A.occ3,
+               k_occ_brick<<<1024, 512, 0, st>>>(A.words, A.brick_list, A.status, A.occ0, A.occ1, A.occ2, A.occ3,
                                                  A.occ_list));
     VRT_LAUNCH(c, "k_erode", st,
                k_erode<<<4096, 512, 0, st>>>(p.g, A.occ0, A.brick_list, A.brick_slot, A.status, A.blk, A.blk_bits,
