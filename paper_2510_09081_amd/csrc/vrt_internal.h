@@ -59,12 +59,25 @@ struct DevStatus {
     unsigned int n_cand;           // bricks with a non-empty segment bin (entries of cand)
     unsigned int n_long;           // segments too long for the bins (entries of long_ids)
     unsigned long long bin_total;  // bin entries allocated
+    unsigned int n_items;          // (brick, chunk) work items of the per-brick passes
     StatStripe stripe[kStripes];
 };
 
 // A segment is binned into every brick of its voxel box when that box has at
 // most this many bricks; longer segments take the per-segment path.
 constexpr int kMaxBinBricks = 8;
+// Bins are processed in chunks of at most this many segments (one workgroup
+// each), so that crowded bricks are spread over several workgroups.
+constexpr int kBinChunk = 1024;
+
+// Index of the k-th item of a chunk in the order its workgroup reads it:
+// within every group of 64, lane L takes entry 8 (L % 8) + L / 8, so that the
+// lanes of a wave take segments eight apart in the bin (consecutive segments
+// of a polyline share voxels, and LDS atomics on one address serialize).
+__device__ __forceinline__ uint32_t spread64(uint32_t u) {
+    const uint32_t l = u & 63u;
+    return (u & ~63u) | ((l & 7u) << 3) | (l >> 3);
+}
 
 struct Arenas {
     VRec *vrec = nullptr;
@@ -95,6 +108,7 @@ struct Arenas {
     int32_t *cand = nullptr;        // [max_bricks] bricks with a non-empty bin, in no particular order
     uint32_t *bins = nullptr;       // [kMaxBinBricks * max_vertices] segment ids grouped by brick
     uint32_t *long_ids = nullptr;   // [max_vertices] segments whose voxel box spans more bricks
+    uint2 *items = nullptr;         // (brick, chunk) work items of the per-brick passes
     int32_t *brick_list = nullptr;  // [max_bricks]
     int32_t *brick_slot = nullptr;  // [max_bricks] slot in brick_list or -1
     uint32_t *brick_total = nullptr;// [max_bricks] visible fragments per occupied brick (by slot)
@@ -206,12 +220,16 @@ __device__ __forceinline__ int64_t brick_index_of(int x, int y, int z, int nbx, 
 }
 __device__ __forceinline__ int local_of(int x, int y, int z) { return ((z & 7) << 6) | ((y & 7) << 3) | (x & 7); }
 
-// floor(n / m) for m > 0, exact: a binary64 estimate corrected in integers.
+// floor(n / m) for 0 < m, |n| + m < 2^52 and |n / m| < 2^20 (voxel indices),
+// exact: n, m and every product q * m below are exact binary64 values, so an
+// estimate from the hardware reciprocal (off by less than one at these
+// quotients) is corrected with exact comparisons.
 __device__ __forceinline__ long long floor_div(long long n, long long m) {
-    long long q = (long long)floor((double)n / (double)m);
-    while (q * m > n) --q;
-    while ((q + 1) * m <= n) ++q;
-    return q;
+    const double dn = (double)n, dm = (double)m;
+    double q = floor(dn * __builtin_amdgcn_rcp(dm));
+    if (q * dm > dn) q -= 1.0;
+    else if ((q + 1.0) * dm <= dn) q += 1.0;
+    return (long long)q;
 }
 
 // smallest w >= 0 with w*w >= n
@@ -276,9 +294,9 @@ __device__ __forceinline__ SlabSpan make_span(int3 a, int3 b, long long rq, cons
     const long long lox = (a.x < b.x ? a.x : b.x) - rq, hix = (a.x < b.x ? b.x : a.x) + rq;
     const long long loy = (a.y < b.y ? a.y : b.y) - rq, hiy = (a.y < b.y ? b.y : a.y) + rq;
     const long long loz = (a.z < b.z ? a.z : b.z) - rq, hiz = (a.z < b.z ? b.z : a.z) + rq;
-    long long vlx = floor_div(lox - 1, kQ), vhx = floor_div(hix, kQ);
-    long long vly = floor_div(loy - 1, kQ), vhy = floor_div(hiy, kQ);
-    long long vlz = floor_div(loz - 1, kQ), vhz = floor_div(hiz, kQ);
+    long long vlx = (lox - 1) >> 8, vhx = hix >> 8;  // floor division by kQ = 256
+    long long vly = (loy - 1) >> 8, vhy = hiy >> 8;
+    long long vlz = (loz - 1) >> 8, vhz = hiz >> 8;
     vlx = vlx < 0 ? 0 : vlx;
     vly = vly < 0 ? 0 : vly;
     vlz = vlz < 0 ? 0 : vlz;

@@ -37,6 +37,7 @@ __device__ __forceinline__ void b_reset(uint16_t *__restrict__ occ3, uint32_t *_
         st->n_cand = 0;
         st->n_long = 0;
         st->bin_total = 0;
+        st->n_items = 0;
         st->n_occ = 0;
     }
     if (i < kStripes) {
@@ -264,6 +265,7 @@ struct BinArgs {
     uint32_t *bins;
     int64_t bin_cap;
     uint32_t *long_ids;
+    uint2 *items;
 };
 
 // Brick box of segment i's voxel set; 0 bricks when the segment is not
@@ -339,8 +341,8 @@ __device__ __forceinline__ void b_bin_count(BinArgs a, DevStatus *__restrict__ s
     wave_append(nbr > kMaxBinBricks, (uint32_t)i, &st->n_long, a.long_ids);
 }
 
-// Bin ranges: per wave, an inclusive scan of the candidates' counts and one
-// atomic on the running total.
+// Bin ranges and work items: per wave, inclusive scans of the candidates'
+// counts and chunk counts and one atomic on each running total.
 __device__ __forceinline__ void b_bin_alloc(BinArgs a, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
     const unsigned n = st->n_cand;
     const int lane = threadIdx.x & 63;
@@ -353,15 +355,27 @@ __device__ __forceinline__ void b_bin_alloc(BinArgs a, DevStatus *__restrict__ s
             b = a.cand[k];
             c = a.bin_count[b];
         }
-        unsigned incl = c;
+        const unsigned nch = (c + kBinChunk - 1) / kBinChunk;
+        unsigned incl = c, inch = nch;
         for (int o = 1; o < 64; o <<= 1) {
-            const unsigned u = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += u;
+            const unsigned u = __shfl_up(incl, o, 64), v = __shfl_up(inch, o, 64);
+            if (lane >= o) {
+                incl += u;
+                inch += v;
+            }
         }
         unsigned long long start = 0;
-        if (lane == 63) start = atomicAdd(&st->bin_total, (unsigned long long)incl);
+        unsigned first = 0;
+        if (lane == 63) {
+            start = atomicAdd(&st->bin_total, (unsigned long long)incl);
+            first = atomicAdd(&st->n_items, inch);
+        }
         start = __shfl(start, 63, 64);
-        if (k < n) a.bin_range[b] = make_uint2((uint32_t)(start + incl - c), c);
+        first = __shfl(first, 63, 64);
+        if (k < n) {
+            a.bin_range[b] = make_uint2((uint32_t)(start + incl - c), c);
+            for (unsigned j = 0; j < nch; ++j) a.items[first + inch - nch + j] = make_uint2((uint32_t)b, j);
+        }
     }
 }
 
@@ -392,27 +406,34 @@ __device__ __forceinline__ void b_bin_fill(BinArgs a, DevStatus *__restrict__ st
 
 struct AccumArgs {
     CountArgs ca;
-    const int32_t *cand;
+    const uint2 *items;
     const uint2 *bin_range;
     const uint32_t *bins;
 };
 
-// Words of the binned bricks: one workgroup per brick adds its bin's
-// fragments in LDS, then stores all 512 words and the brick's flag.
+// Words of the binned bricks: one workgroup per (brick, chunk) item adds the
+// chunk's fragments in LDS, then stores the brick's 512 words (a brick of one
+// chunk) or adds them to the words (every word is zero at the start of a
+// frame: the previous frame's occupied bricks are cleared), and flags the
+// brick when it holds a fragment.
 __device__ __forceinline__ void b_brick_accum(AccumArgs a, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
     __shared__ uint32_t w[kBrickVox];
     const CountArgs &c = a.ca;
-    const unsigned n = st->n_cand;
+    const unsigned n = st->n_items;
     const int t = threadIdx.x;
     unsigned long long nfrag = 0;
-    for (unsigned sl = bid_; sl < n; sl += nblk_) {
-        const int b = a.cand[sl];
+    for (unsigned it = bid_; it < n; it += nblk_) {
+        const uint2 item = a.items[it];
+        const int b = (int)item.x;
         const uint2 r = a.bin_range[b];
+        const uint32_t k0 = item.y * kBinChunk, len = min(r.y - k0, (uint32_t)kBinChunk);
         for (int v = t; v < kBrickVox; v += blockDim.x) w[v] = 0u;
         __syncthreads();
         const int bx = b % c.nbx, by = (b / c.nbx) % c.nby, bz = b / (c.nbx * c.nby);
-        for (uint32_t k = t; k < r.y; k += blockDim.x) {
-            const uint32_t id = a.bins[r.x + k];
+        for (uint32_t u = t; u < ((len + 63u) & ~63u); u += blockDim.x) {
+            const uint32_t kk = spread64(u);
+            if (kk >= len) continue;
+            const uint32_t id = a.bins[r.x + k0 + kk];
             const VRec A = c.vrec[id], B = c.vrec[id + 1];
             const SlabSpan s = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), c.rq, c.G);
             nfrag += for_each_voxel_in_brick(s, bx, by, bz, [&](int x, int y, int z) {
@@ -421,10 +442,12 @@ __device__ __forceinline__ void b_brick_accum(AccumArgs a, DevStatus *__restrict
             });
         }
         __syncthreads();
+        const bool whole = r.y <= (uint32_t)kBinChunk;
         unsigned any = 0;
         for (int v = t; v < kBrickVox; v += blockDim.x) {
             const uint32_t wd = w[v];
-            c.words[(int64_t)b * kBrickVox + v] = wd;
+            if (whole) c.words[(int64_t)b * kBrickVox + v] = wd;
+            else if (wd) atomicAdd(&c.words[(int64_t)b * kBrickVox + v], wd);
             any |= wd & 0xFFFFu;
         }
         if (__syncthreads_or(any != 0u) && t == 0) c.brick_flag[b] = 1;
@@ -749,8 +772,9 @@ static VoxPlan make_vox_plan(const vrt_ctx *c, const vrt_lines *L, float s_q) {
     p.ba.bins = A.bins;
     p.ba.bin_cap = (int64_t)kMaxBinBricks * c->desc.max_vertices;
     p.ba.long_ids = A.long_ids;
+    p.ba.items = A.items;
     p.aa.ca = p.ca;
-    p.aa.cand = A.cand;
+    p.aa.items = A.items;
     p.aa.bin_range = A.bin_range;
     p.aa.bins = A.bins;
     return p;

@@ -188,6 +188,10 @@ EDGE_SETS = {
         + [[list(np.add(np.array([2.5, 3.1, 4.2]) + np.subtract([60.3, 41.7, 55.9], [2.5, 3.1, 4.2]) * t, d))
             for t in (0.40, 0.41, 0.42, 0.43, 0.44)] for d in ((0.2, 0.0, 0.1), (-0.3, 0.25, 0.0))]
         + [[[31.0 + 0.45 * k, 32.6 - 0.45 * k, 32.2] for k in range(12)]], 64, 0.7),
+    # more than one work chunk (1024 segments) in one brick: 3300 short segments crowded into brick (0, 0, 0)
+    "crowded_brick": lambda: _make(
+        [list(1.0 + np.cumsum(np.random.default_rng(7 + p).uniform(-0.3, 0.3, (12, 3)), axis=0).clip(-0.5, 5.5)
+              + np.random.default_rng(1000 + p).uniform(0.0, 1.0, 3)) for p in range(300)], 16, 0.3),
     # non-cubic grid
     "non_cubic": lambda: synth.LineSet(**{**synth.random_walk_set(seed=5, n_poly=30, n_seg=20, G=24).__dict__,
                                           "dims": (24, 16, 40)}),
