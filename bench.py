@@ -161,7 +161,7 @@ def bench_dynamic(torch, vrt, synth, warmup):
 
 def bench_batched(torch, vrt, synth, steps, warmup):
     """64 uneven line sets (1k-1M segments, 64^3-256^3 grids, 512x512 each, opaque, culled):
-    one persistent launch against the plain calls set by set."""
+    one persistent launch and one launch per phase against the plain calls set by set."""
     ws = synth.batch_sets()
     items, capsl = [], []
     for w in ws:
@@ -177,7 +177,8 @@ def bench_batched(torch, vrt, synth, steps, warmup):
     b = vrt.Batch(capsl)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     res = {}
-    for label, mode in (("persistent", vrt.BATCH_PERSISTENT), ("sequential", vrt.BATCH_SEQUENTIAL)):
+    for label, mode in (("persistent", vrt.BATCH_PERSISTENT), ("staged", vrt.BATCH_STAGED),
+                        ("sequential", vrt.BATCH_SEQUENTIAL)):
         for _ in range(warmup):
             b.run(items, mode)
         torch.cuda.synchronize()
@@ -188,7 +189,8 @@ def bench_batched(torch, vrt, synth, steps, warmup):
         torch.cuda.synchronize()
         res[label] = ev0.elapsed_time(ev1) / steps
         res[label + "_ids"] = [it["first_id"].clone() for it in items]
-    same = all(torch.equal(a, c) for a, c in zip(res["persistent_ids"], res["sequential_ids"]))
+    same = all(torch.equal(a, c) and torch.equal(s, c)
+               for a, s, c in zip(res["persistent_ids"], res["staged_ids"], res["sequential_ids"]))
     bad = [i for i in range(len(ws)) if b.context(i).frame_status()["device_status"] != 0]
     b.close()
     if bad:
@@ -197,9 +199,12 @@ def bench_batched(torch, vrt, synth, steps, warmup):
     return {"workload": "batch64: 64 sets, log-uniform 1k-1M segments, random-walk and bundle generators, "
                         "64^3-256^3 grids, 512x512 each, opaque with opaque culling",
             "sets": len(ws), "segments": int(sum(w.lines.n_segments for w in ws)), "rays": rays,
-            "persistent_ms": round(res["persistent"], 4), "sequential_ms": round(res["sequential"], 4),
+            "persistent_ms": round(res["persistent"], 4), "staged_ms": round(res["staged"], 4),
+            "sequential_ms": round(res["sequential"], 4),
             "persistent_speedup": round(res["sequential"] / res["persistent"], 4),
+            "staged_speedup": round(res["sequential"] / res["staged"], 4),
             "mrays_s_persistent": round(rays / (res["persistent"] * 1e-3) / 1e6, 2),
+            "mrays_s_staged": round(rays / (res["staged"] * 1e-3) / 1e6, 2),
             "first_ids_identical": bool(same)}
 
 

@@ -204,14 +204,17 @@ vrt_status vrt_graph_destroy(vrt_graph *g);
  * every stage of every set in ONE cooperative launch: the frame's stages are
  * phases separated by grid barriers, and inside a phase the resident blocks
  * take (set, stage, block) work items from a counter, largest sets first.
- * VRT_BATCH_SEQUENTIAL issues the plain vrt_voxelize / vrt_cull / vrt_trace
- * calls set after set (the reference the persistent form is compared with).
- * Both give identical results.  Set i uses the arenas of a context created
+ * VRT_BATCH_STAGED runs the same phases as one launch each (kernel boundaries
+ * instead of grid barriers; each phase kernel is compiled for its own stages,
+ * so it keeps their register budget).  VRT_BATCH_SEQUENTIAL issues the plain
+ * vrt_voxelize / vrt_cull / vrt_trace calls set after set (the reference the
+ * batched forms are compared with).  All give identical results.  Set i uses the arenas of a context created
  * from descs[i] (reachable with vrt_batch_context for vrt_frame_status and
  * vrt_query_as); all sets share one device.  vrt_batch_run validates every set
  * on the host before anything is enqueued and never allocates. */
 #define VRT_BATCH_PERSISTENT 0
 #define VRT_BATCH_SEQUENTIAL 1
+#define VRT_BATCH_STAGED 2
 
 typedef struct {
     vrt_lines lines;

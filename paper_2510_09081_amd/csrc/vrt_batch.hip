@@ -103,7 +103,7 @@ __device__ void mip_or_chain(const SetDesc &d) {
 }
 
 // Virtual block vb of nvb of stage `part` of phase `ph` for set d.
-__device__ void run_part(int ph, int part, const SetDesc &d, unsigned vb, unsigned nvb) {
+__device__ __forceinline__ void run_part(int ph, int part, const SetDesc &d, unsigned vb, unsigned nvb) {
     const Arenas &A = d.a;
     switch (ph) {
     case P_CLEAR:
@@ -147,41 +147,78 @@ __device__ void run_part(int ph, int part, const SetDesc &d, unsigned vb, unsign
     }
 }
 
-// The persistent batch kernel.  tickets[ph] counts the virtual blocks of phase
-// ph handed out; block 0 clears the next phase's counter during each phase (it
-// is not read before the barrier), so the counters are zero at every launch.
+// One phase of the batch: the resident blocks take the phase's virtual blocks
+// of every set from the ticket counter tickets[ph]; block 0 clears the next
+// phase's counter (it is not read before this phase has ended), so the
+// counters are zero at every launch.
+__device__ __forceinline__ void batch_phase(int ph, const SetDesc *__restrict__ sets, int nsets,
+                                            unsigned *__restrict__ tickets, unsigned *pre, unsigned &ticket) {
+    const int nk = nsets * kParts;
+    if (blockIdx.x == 0 && threadIdx.x == 0) tickets[(ph + 1) % kPhases] = 0u;
+    for (int k = threadIdx.x; k < nk; k += blockDim.x) pre[k + 1] = part_blocks(ph, k % kParts, sets[k / kParts]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        pre[0] = 0u;
+        for (int k = 1; k <= nk; ++k) pre[k] += pre[k - 1];
+    }
+    __syncthreads();
+    const unsigned total = pre[nk];
+    for (;;) {
+        if (threadIdx.x == 0) ticket = atomicAdd(&tickets[ph], 1u);
+        __syncthreads();
+        const unsigned t = ticket;
+        __syncthreads();
+        if (t >= total) break;
+        int lo = 0, hi = nk - 1;  // the (set, stage) whose range holds ticket t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        run_part(ph, lo % kParts, sets[lo / kParts], t - pre[lo], pre[lo + 1] - pre[lo]);
+        __syncthreads();
+    }
+}
+
+// The persistent batch kernel: every phase, separated by grid barriers.
 __global__ void __launch_bounds__(kBatchThreads) k_batch(const SetDesc *__restrict__ sets, int nsets,
                                                          unsigned *__restrict__ tickets) {
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
     __shared__ unsigned pre[kMaxBatch * kParts + 1];
     __shared__ unsigned ticket;
-    const int nk = nsets * kParts;
     for (int ph = 0; ph < kPhases; ++ph) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) tickets[(ph + 1) % kPhases] = 0u;
-        for (int k = threadIdx.x; k < nk; k += blockDim.x) pre[k + 1] = part_blocks(ph, k % kParts, sets[k / kParts]);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            pre[0] = 0u;
-            for (int k = 1; k <= nk; ++k) pre[k] += pre[k - 1];
-        }
-        __syncthreads();
-        const unsigned total = pre[nk];
-        for (;;) {
-            if (threadIdx.x == 0) ticket = atomicAdd(&tickets[ph], 1u);
-            __syncthreads();
-            const unsigned t = ticket;
-            __syncthreads();
-            if (t >= total) break;
-            int lo = 0, hi = nk - 1;  // the (set, stage) whose range holds ticket t
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (pre[mid] <= t) lo = mid;
-                else hi = mid - 1;
-            }
-            run_part(ph, lo % kParts, sets[lo / kParts], t - pre[lo], pre[lo + 1] - pre[lo]);
-            __syncthreads();
-        }
+        batch_phase(ph, sets, nsets, tickets, pre, ticket);
         grid.sync();
+    }
+}
+
+// The staged form: one launch per phase (kernel boundaries instead of grid
+// barriers), each compiled for its own phase only, so it keeps the register
+// budget of that phase's bodies.
+template <int kPh>
+__global__ void __launch_bounds__(kBatchThreads) k_batch_phase(const SetDesc *__restrict__ sets, int nsets,
+                                                               unsigned *__restrict__ tickets) {
+    __shared__ unsigned pre[kMaxBatch * kParts + 1];
+    __shared__ unsigned ticket;
+    batch_phase(kPh, sets, nsets, tickets, pre, ticket);
+}
+
+// Host handle of the staged kernel of phase ph.
+const void *phase_kernel(int ph) {
+    switch (ph) {
+    case P_CLEAR: return (const void *)k_batch_phase<P_CLEAR>;
+    case P_INGEST: return (const void *)k_batch_phase<P_INGEST>;
+    case P_COUNT: return (const void *)k_batch_phase<P_COUNT>;
+    case P_COMPACT: return (const void *)k_batch_phase<P_COMPACT>;
+    case P_OCC: return (const void *)k_batch_phase<P_OCC>;
+    case P_ERODE: return (const void *)k_batch_phase<P_ERODE>;
+    case P_WALK: return (const void *)k_batch_phase<P_WALK>;
+    case P_CBRICK: return (const void *)k_batch_phase<P_CBRICK>;
+    case P_SCAN: return (const void *)k_batch_phase<P_SCAN>;
+    case P_OFFSETS: return (const void *)k_batch_phase<P_OFFSETS>;
+    case P_SCATTER: return (const void *)k_batch_phase<P_SCATTER>;
+    case P_MARCH: return (const void *)k_batch_phase<P_MARCH>;
+    default: return (const void *)k_batch_phase<P_SHADE>;
     }
 }
 
@@ -197,7 +234,8 @@ struct vrt_batch {
     unsigned *d_tickets = nullptr;
     hipEvent_t copied = nullptr;
     bool copy_pending = false;
-    unsigned grid = 0;
+    unsigned grid = 0;                     // resident blocks of the persistent kernel
+    unsigned phase_grid[vrt::kPhases] = {}; // resident blocks of each staged phase kernel
 };
 
 extern "C" {
@@ -232,6 +270,11 @@ vrt_status vrt_batch_create(const vrt_desc *descs, int32_t n, vrt_batch **out) {
     if (st == VRT_OK && e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kBatchThreads, 0);
     if (st == VRT_OK && e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device);
+    for (int ph = 0; ph < kPhases && st == VRT_OK && e == hipSuccess; ++ph) {
+        int pc = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, phase_kernel(ph), kBatchThreads, 0);
+        b->phase_grid[ph] = (unsigned)((pc > 0 ? pc : 1) * ncu);
+    }
     if (st == VRT_OK && e == hipSuccess) e = hipDeviceSynchronize();
     if (st == VRT_OK && e != hipSuccess) st = hip_fail(e);
     if (st == VRT_OK && per_cu < 1) st = VRT_ERR_INVALID_ARG;
@@ -247,7 +290,8 @@ vrt_status vrt_batch_create(const vrt_desc *descs, int32_t n, vrt_batch **out) {
 vrt_status vrt_batch_run(vrt_batch *b, const vrt_batch_item *items, int32_t n, int32_t mode, void *stream) {
     using namespace vrt;
     if (!b || !items || n != b->n) return VRT_ERR_INVALID_ARG;
-    if (mode != VRT_BATCH_PERSISTENT && mode != VRT_BATCH_SEQUENTIAL) return VRT_ERR_INVALID_ARG;
+    if (mode != VRT_BATCH_PERSISTENT && mode != VRT_BATCH_SEQUENTIAL && mode != VRT_BATCH_STAGED)
+        return VRT_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     VRT_HIP(hipSetDevice(b->device));
     if (mode == VRT_BATCH_SEQUENTIAL) {
@@ -303,6 +347,11 @@ vrt_status vrt_batch_run(vrt_batch *b, const vrt_batch_item *items, int32_t n, i
     int nsets = n;
     unsigned *tickets = b->d_tickets;
     void *args[] = {(void *)&sets, (void *)&nsets, (void *)&tickets};
+    if (mode == VRT_BATCH_STAGED) {
+        for (int ph = 0; ph < kPhases; ++ph)
+            VRT_HIP(hipLaunchKernel(phase_kernel(ph), dim3(b->phase_grid[ph]), dim3(kBatchThreads), args, 0, st));
+        return VRT_OK;
+    }
     VRT_HIP(hipLaunchCooperativeKernel((const void *)k_batch, dim3(b->grid), dim3(kBatchThreads), args, 0, st));
     return VRT_OK;
 }

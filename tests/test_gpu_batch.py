@@ -58,20 +58,23 @@ def test_persistent_batch_equals_sequential(orc):
     if not torch.cuda.is_available():
         pytest.fail("no GPU: the gpu tests need an MI355X")
     sets = small_batch()
-    pb, sb = vrt.Batch(caps(sets)), vrt.Batch(caps(sets))
+    pb, sb, tb = vrt.Batch(caps(sets)), vrt.Batch(caps(sets)), vrt.Batch(caps(sets))
     try:
-        ip, isq = make_items(sets), make_items(sets)
+        ip, isq, ist = make_items(sets), make_items(sets), make_items(sets)
         for rep in range(3):  # repeated launches reuse the arenas and the ticket counters
             pb.run(ip, vrt.BATCH_PERSISTENT)
             sb.run(isq, vrt.BATCH_SEQUENTIAL)
+            tb.run(ist, vrt.BATCH_STAGED)
             torch.cuda.synchronize()
             for i in range(len(sets)):
-                sp, ss = pb.context(i).frame_status(), sb.context(i).frame_status()
-                assert sp["device_status"] == ss["device_status"] == 0
+                sp, ss, s3 = pb.context(i).frame_status(), sb.context(i).frame_status(), tb.context(i).frame_status()
+                assert sp["device_status"] == ss["device_status"] == s3["device_status"] == 0
                 assert (sp["n_fragments"], sp["n_listed"], sp["n_bricks"]) == \
-                       (ss["n_fragments"], ss["n_listed"], ss["n_bricks"]), (rep, i)
+                       (ss["n_fragments"], ss["n_listed"], ss["n_bricks"]) == \
+                       (s3["n_fragments"], s3["n_listed"], s3["n_bricks"]), (rep, i)
                 for key in ("rgba", "depth", "first_id"):
                     assert torch.equal(ip[i][key], isq[i][key]), (rep, i, key)
+                    assert torch.equal(ist[i][key], isq[i][key]), (rep, i, key)
         # one set of the persistent batch against the oracle
         k = 4
         ls, cam, cull, mode = sets[k]
@@ -86,3 +89,4 @@ def test_persistent_batch_equals_sequential(orc):
     finally:
         pb.close()
         sb.close()
+        tb.close()
