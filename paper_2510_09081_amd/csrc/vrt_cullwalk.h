@@ -78,17 +78,19 @@ __host__ __device__ inline int culling_walk(const int *G, int x, int y, int z, c
         dT[a] = step[a] != 0 ? Q * L : kNever;
         if (step[a] != 0 && (double)adel[a] * (double)L < 9.0e18) P = adel[a] * L;
     }
+    // The walk is monotone on every axis, so it can stop as soon as it leaves
+    // the grid or the box of blocking voxels: lim[a] is the last coordinate
+    // worth visiting in the direction of travel.
+    int lim[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (step[a] == 0 && (cur[a] < bbox[a] || cur[a] > bbox[3 + a])) return 0;
+        lim[a] = step[a] > 0 ? (G[a] - 1 < bbox[3 + a] ? G[a] - 1 : bbox[3 + a]) : (bbox[a] > 0 ? bbox[a] : 0);
+        if ((step[a] > 0 && cur[a] > lim[a]) || (step[a] < 0 && cur[a] < lim[a])) return 0;
+    }
     int n = 0;
     bool be = cells.brick_empty(x, y, z);  // brick_empty of the current voxel
     for (;;) {
-        bool gone = false;  // past the blocking box for good
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (step[a] > 0 && cur[a] > bbox[3 + a]) gone = true;
-            if (step[a] < 0 && cur[a] < bbox[a]) gone = true;
-            if (step[a] == 0 && (cur[a] < bbox[a] || cur[a] > bbox[3 + a])) gone = true;
-        }
-        if (gone) break;
         int S = 1;
         if (be) S = cells.super_empty(cur[0], cur[1], cur[2]) ? 64 : 8;
         if (S == 1) {
@@ -101,19 +103,20 @@ __host__ __device__ inline int culling_walk(const int *G, int x, int y, int z, c
                 if (T[a] == tm) {
                     cur[a] += step[a];
                     T[a] += dT[a];
-                    if (cur[a] < 0 || cur[a] >= G[a]) out = true;
+                    if (step[a] > 0 ? cur[a] > lim[a] : cur[a] < lim[a]) out = true;
                 }
             }
             if (out) break;
         } else {
             long long Tc[3];
+            const int sh = S == 64 ? 6 : 3;  // S = 2^sh
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 Tc[a] = kNever;
                 if (step[a] == 0) continue;
-                const int cs = cur[a] / S * S;  // cur >= 0
-                const long long k = step[a] > 0 ? cs + S - 1 - cur[a] : cur[a] - cs;
-                Tc[a] = T[a] + k * dT[a];
+                const int cs = (cur[a] >> sh) << sh;  // cur >= 0
+                const unsigned k = (unsigned)(step[a] > 0 ? cs + S - 1 - cur[a] : cur[a] - cs);
+                Tc[a] = T[a] + (long long)((unsigned long long)dT[a] * k);
             }
             long long te = Tc[0] < Tc[1] ? Tc[0] : Tc[1];
             te = Tc[2] < te ? Tc[2] : te;
@@ -126,13 +129,13 @@ __host__ __device__ inline int culling_walk(const int *G, int x, int y, int z, c
                 if (step[a] == 0 || te < T[a]) continue;
                 na[a] = walk_small_quot(te - T[a], dT[a]) + 1;
                 const long long nx = cur[a] + step[a] * na[a];
-                if (nx < 0 || nx >= G[a]) out = true;
+                if (step[a] > 0 ? nx > lim[a] : nx < lim[a]) out = true;
             }
             if (out) break;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 cur[a] += step[a] * (int)na[a];
-                if (na[a]) T[a] += na[a] * dT[a];
+                if (na[a]) T[a] += (long long)((unsigned long long)dT[a] * (unsigned)na[a]);
             }
         }
         be = cells.brick_empty(cur[0], cur[1], cur[2]);
