@@ -40,15 +40,22 @@ __device__ __forceinline__ float dot3(float3 a, float3 b) {
 }
 __device__ __forceinline__ float3 sub3(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
 
+// Hit geometry uses the hardware reciprocal and square root (about one ulp
+// each): hit parameters only need to stay within the binary32 error margins
+// that decide which pixels are compared exactly, while the primary rays keep
+// the correctly rounded sequence.
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ float fsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+
 // Entry root of |oc + t D| = r (unit D): smaller root, stable form.
 __device__ __forceinline__ float sphere_entry(float3 oc, float3 D, float r2) {
     float b = dot3(oc, D);
     float c = dot3(oc, oc) - r2;
     float h = b * b - c;
     if (h < 0.0f) return -INFINITY;
-    float sq = sqrtf(h);
+    float sq = fsqrt(h);
     float q = b >= 0.0f ? -(b + sq) : (sq - b);
-    return b >= 0.0f ? q : c / q;
+    return b >= 0.0f ? q : fdiv(c, q);
 }
 
 __device__ __forceinline__ float3 cross3(float3 a, float3 b) {
@@ -82,8 +89,8 @@ __device__ __forceinline__ float capsule_entry(float3 ro, float3 D, float3 pa, f
     const float g = r2 * ww - ow * ow;
     if (g < 0.0f) return -INFINITY;  // misses the infinite cylinder, hence the capsule
     const float b = dot3(w, u);
-    const float sq = sqrtf(baba * g);
-    const float t = b >= 0.0f ? -(b + sq) / ww : c / (sq - b);
+    const float sq = fsqrt(baba * g);
+    const float t = b >= 0.0f ? fdiv(-(b + sq), ww) : fdiv(c, sq - b);
     const float y = baoa + t * bard;
     if (y > 0.0f && y < baba) return t;
     return sphere_entry(y <= 0.0f ? oa : sub3(ro, pb), D, r2);
@@ -171,9 +178,10 @@ __device__ __forceinline__ bool voxel_hit(const LocalSeg &g, float radius, float
 // the FP16 offsets are exact).
 __device__ __forceinline__ float3 seg_colour(float3 pa, float3 pb) {
     const float dx = pb.x - pa.x, dy = pb.y - pa.y, dz = pb.z - pa.z;
-    const float len = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float len = fsqrt(dx * dx + dy * dy + dz * dz);
     if (len == 0.0f) return make_float3(0.0f, 0.0f, 0.0f);
-    return make_float3(fabsf(dx) / len, fabsf(dy) / len, fabsf(dz) / len);
+    const float il = __builtin_amdgcn_rcpf(len);
+    return make_float3(fabsf(dx) * il, fabsf(dy) * il, fabsf(dz) * il);
 }
 
 __device__ __forceinline__ bool key_less(float s0, uint32_t i0, float s1, uint32_t i1) {
@@ -251,7 +259,7 @@ __device__ __forceinline__ bool skip_cell(const Ray &r, const int *G, int S, int
     int cellk[3];
     float tb[3];
     for (int k = 0; k < 3; ++k) {
-        cellk[k] = v[k] / S;
+        cellk[k] = v[k] >> (S == 64 ? 6 : 3);  // S is 64 or 8, v >= 0
         tb[k] = r.step[k] == 0 ? INFINITY : tcross(S * (cellk[k] + (r.step[k] > 0)), r.O[k], r.inv[k]);
     }
     int m = 0;
