@@ -50,100 +50,139 @@ __host__ __device__ inline long long walk_small_quot(long long num, long long de
 //   bool super_empty(x, y, z)  -- the 64^3 cell holding voxel (x,y,z) has no blocker
 //   bool brick_empty(x, y, z)  -- the 8^3 brick holding voxel (x,y,z) has no blocker
 //   bool blocking(x, y, z)     -- the voxel blocks (only asked in non-empty bricks)
+// State of one culling walk between steps (everything in registers).
+struct CullWalk {
+    int cur[3], step[3], lim[3];
+    long long T[3], dT[3], P;
+    int n;      // blocking voxels met so far
+    bool be;    // the current voxel's brick holds no blocker
+    bool done;  // n is the result
+};
+
+// Sets up the walk from voxel (x, y, z); done at once when the eye is at the
+// voxel's centre or no blocking voxel can lie ahead.
 template <class Cells>
-__host__ __device__ inline int culling_walk(const int *G, int x, int y, int z, const long long *E, int limit,
-                                            const int *bbox, const Cells &cells) {
+__host__ __device__ inline void walk_begin(CullWalk &w, const int *G, int x, int y, int z, const long long *E,
+                                           const int *bbox, const Cells &cells) {
     constexpr long long Q = 256;
     constexpr long long kNever = 0x7FFFFFFFFFFFFFFFll;
-    long long adel[3], T[3], dT[3];
-    int step[3], cur[3] = {x, y, z};
+    long long adel[3];
+    w.cur[0] = x;
+    w.cur[1] = y;
+    w.cur[2] = z;
+    w.n = 0;
+    w.done = false;
     int nmov = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const long long c = (long long)cur[a] * Q + Q / 2;
+        const long long c = (long long)w.cur[a] * Q + Q / 2;
         const long long dl = E[a] - c;
-        step[a] = dl > 0 ? 1 : (dl < 0 ? -1 : 0);
+        w.step[a] = dl > 0 ? 1 : (dl < 0 ? -1 : 0);
         adel[a] = dl < 0 ? -dl : dl;
-        nmov += step[a] != 0;
+        nmov += w.step[a] != 0;
     }
-    if (nmov == 0) return 0;  // the eye is at this voxel's centre
-    long long P = kNever;
+    w.P = kNever;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         long long L = 1;
 #pragma unroll
         for (int b = 0; b < 3; ++b)
-            if (b != a && step[b] != 0) L *= adel[b];
-        T[a] = step[a] != 0 ? (Q / 2) * L : kNever;
-        dT[a] = step[a] != 0 ? Q * L : kNever;
-        if (step[a] != 0 && (double)adel[a] * (double)L < 9.0e18) P = adel[a] * L;
+            if (b != a && w.step[b] != 0) L *= adel[b];
+        w.T[a] = w.step[a] != 0 ? (Q / 2) * L : kNever;
+        w.dT[a] = w.step[a] != 0 ? Q * L : kNever;
+        if (w.step[a] != 0 && (double)adel[a] * (double)L < 9.0e18) w.P = adel[a] * L;
     }
     // The walk is monotone on every axis, so it can stop as soon as it leaves
     // the grid or the box of blocking voxels: lim[a] is the last coordinate
     // worth visiting in the direction of travel.
-    int lim[3];
+    bool none = nmov == 0;  // the eye is at this voxel's centre
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (step[a] == 0 && (cur[a] < bbox[a] || cur[a] > bbox[3 + a])) return 0;
-        lim[a] = step[a] > 0 ? (G[a] - 1 < bbox[3 + a] ? G[a] - 1 : bbox[3 + a]) : (bbox[a] > 0 ? bbox[a] : 0);
-        if ((step[a] > 0 && cur[a] > lim[a]) || (step[a] < 0 && cur[a] < lim[a])) return 0;
+        const int st = w.step[a];
+        if (st == 0 && (w.cur[a] < bbox[a] || w.cur[a] > bbox[3 + a])) none = true;
+        w.lim[a] = st > 0 ? (G[a] - 1 < bbox[3 + a] ? G[a] - 1 : bbox[3 + a]) : (bbox[a] > 0 ? bbox[a] : 0);
+        if ((st > 0 && w.cur[a] > w.lim[a]) || (st < 0 && w.cur[a] < w.lim[a])) none = true;
     }
-    int n = 0;
-    bool be = cells.brick_empty(x, y, z);  // brick_empty of the current voxel
-    for (;;) {
-        int S = 1;
-        if (be) S = cells.super_empty(cur[0], cur[1], cur[2]) ? 64 : 8;
-        if (S == 1) {
-            long long tm = T[0] < T[1] ? T[0] : T[1];
-            tm = T[2] < tm ? T[2] : tm;
-            if (!(tm < P)) break;  // eye reached
-            bool out = false;
+    w.done = none;
+    w.be = none ? true : cells.brick_empty(x, y, z);
+}
+
+// One step of the walk: a voxel, or an empty cell crossed in one jump; then
+// the blocking test of the voxel entered.  Sets done when the walk ends.
+template <class Cells>
+__host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &cells) {
+    constexpr long long kNever = 0x7FFFFFFFFFFFFFFFll;
+    int S = 1;
+    if (w.be) S = cells.super_empty(w.cur[0], w.cur[1], w.cur[2]) ? 64 : 8;
+    if (S == 1) {
+        long long tm = w.T[0] < w.T[1] ? w.T[0] : w.T[1];
+        tm = w.T[2] < tm ? w.T[2] : tm;
+        if (!(tm < w.P)) {  // eye reached
+            w.done = true;
+            return;
+        }
+        bool out = false;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                if (T[a] == tm) {
-                    cur[a] += step[a];
-                    T[a] += dT[a];
-                    if (step[a] > 0 ? cur[a] > lim[a] : cur[a] < lim[a]) out = true;
-                }
-            }
-            if (out) break;
-        } else {
-            long long Tc[3];
-            const int sh = S == 64 ? 6 : 3;  // S = 2^sh
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                Tc[a] = kNever;
-                if (step[a] == 0) continue;
-                const int cs = (cur[a] >> sh) << sh;  // cur >= 0
-                const unsigned k = (unsigned)(step[a] > 0 ? cs + S - 1 - cur[a] : cur[a] - cs);
-                Tc[a] = T[a] + (long long)((unsigned long long)dT[a] * k);
-            }
-            long long te = Tc[0] < Tc[1] ? Tc[0] : Tc[1];
-            te = Tc[2] < te ? Tc[2] : te;
-            if (!(te < P)) break;  // the eye lies inside this empty cell
-            bool out = false;
-            long long na[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                na[a] = 0;
-                if (step[a] == 0 || te < T[a]) continue;
-                na[a] = walk_small_quot(te - T[a], dT[a]) + 1;
-                const long long nx = cur[a] + step[a] * na[a];
-                if (step[a] > 0 ? nx > lim[a] : nx < lim[a]) out = true;
-            }
-            if (out) break;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                cur[a] += step[a] * (int)na[a];
-                if (na[a]) T[a] += (long long)((unsigned long long)dT[a] * (unsigned)na[a]);
+        for (int a = 0; a < 3; ++a) {
+            if (w.T[a] == tm) {
+                w.cur[a] += w.step[a];
+                w.T[a] += w.dT[a];
+                if (w.step[a] > 0 ? w.cur[a] > w.lim[a] : w.cur[a] < w.lim[a]) out = true;
             }
         }
-        be = cells.brick_empty(cur[0], cur[1], cur[2]);
-        if (!be && cells.blocking(cur[0], cur[1], cur[2])) {
-            if (++n >= limit) break;
+        if (out) {
+            w.done = true;
+            return;
+        }
+    } else {
+        long long Tc[3];
+        const int sh = S == 64 ? 6 : 3;  // S = 2^sh
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Tc[a] = kNever;
+            if (w.step[a] == 0) continue;
+            const int cs = (w.cur[a] >> sh) << sh;  // cur >= 0
+            const unsigned k = (unsigned)(w.step[a] > 0 ? cs + S - 1 - w.cur[a] : w.cur[a] - cs);
+            Tc[a] = w.T[a] + (long long)((unsigned long long)w.dT[a] * k);
+        }
+        long long te = Tc[0] < Tc[1] ? Tc[0] : Tc[1];
+        te = Tc[2] < te ? Tc[2] : te;
+        if (!(te < w.P)) {  // the eye lies inside this empty cell
+            w.done = true;
+            return;
+        }
+        bool out = false;
+        long long na[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            na[a] = 0;
+            if (w.step[a] == 0 || te < w.T[a]) continue;
+            na[a] = walk_small_quot(te - w.T[a], w.dT[a]) + 1;
+            const long long nx = w.cur[a] + w.step[a] * na[a];
+            if (w.step[a] > 0 ? nx > w.lim[a] : nx < w.lim[a]) out = true;
+        }
+        if (out) {
+            w.done = true;
+            return;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            w.cur[a] += w.step[a] * (int)na[a];
+            if (na[a]) w.T[a] += (long long)((unsigned long long)w.dT[a] * (unsigned)na[a]);
         }
     }
-    return n;
+    w.be = cells.brick_empty(w.cur[0], w.cur[1], w.cur[2]);
+    if (!w.be && cells.blocking(w.cur[0], w.cur[1], w.cur[2]) && ++w.n >= limit) w.done = true;
+}
+
+// The whole walk: the number of blocking voxels met, at most `limit`.
+template <class Cells>
+__host__ __device__ inline int culling_walk(const int *G, int x, int y, int z, const long long *E, int limit,
+                                            const int *bbox, const Cells &cells) {
+    CullWalk w;
+    walk_begin(w, G, x, y, z, E, bbox, cells);
+    while (!w.done) walk_step(w, limit, cells);
+    return w.n;
 }
 
 }  // namespace vrt
