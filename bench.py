@@ -38,9 +38,10 @@ def source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, tune):
+def measured_traffic(kernel, shapes):
     """HBM bytes per launch of `kernel` from the committed PMC summary (FETCH_SIZE + WRITE_SIZE, each scaled by
-    the copy-kernel calibration), or None when the summary is missing or was taken for other sources or shapes."""
+    the copy-kernel calibration), or None when the summary is missing or was taken for other sources or launch
+    shapes."""
     import re
     try:
         with open(PMC_SUMMARY) as f:
@@ -51,7 +52,7 @@ def measured_traffic(kernel, tune):
         return None
     d = json.loads(m.group(1))
     k = d.get("kernels", {}).get(kernel)
-    if k is None or d.get("source_sha256") != source_digest() or d.get("tune") != tune:
+    if k is None or d.get("source_sha256") != source_digest() or d.get("shapes") != shapes:
         return None
     return {"bytes_per_launch": int(k["fetch_bytes"] + k["write_bytes"]), "fetch_bytes": int(k["fetch_bytes"]),
             "write_bytes": int(k["write_bytes"])}
@@ -313,6 +314,7 @@ def main():
                    ("transparent", (eye, alp.cull_mode, alp.alpha, alp.tau), cam_a)]
     tune = None if args.no_tune else autotune_passes(ctx, tune_passes, rgba, depth, fid, args, w.name)
 
+    ctx_shapes = (ctx.get_tune(vrt.TRACE_OPAQUE), ctx.get_tune(vrt.TRACE_TRANSPARENT))
     for _ in range(args.warmup):
         frame()
     torch.cuda.synchronize()
@@ -375,7 +377,8 @@ def main():
     roofline = None
     if b is not None:
         ach = b / (per_kernel[dom]["avg_ms"] * 1e-3) / 1e9
-        tr = measured_traffic(dom, tune)
+        shapes = {"opaque": ctx_shapes[0], "transparent": ctx_shapes[1]}
+        tr = measured_traffic(dom, shapes)
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None if tr is None else tr["bytes_per_launch"],
                     "traffic_detail": tr, "bytes_per_launch": int(b)}

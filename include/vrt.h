@@ -238,7 +238,7 @@ vrt_status vrt_batch_destroy(vrt_batch *b);
  *   shade_batch    list entries per lane whose records are fetched together: 2 or 4;
  *   lane_keys      transparent hits a lane keeps per pass over a list (k): 4 or 8;
  *   shade_blocks   256-thread blocks of the shade launch: 256 .. 65535.
- * Default {256, 16, 4, 4, 4096}.  The batched form always uses the default. */
+ * Default {256, 16, 2, 4, 4096}.  The batched forms always use the default. */
 typedef struct {
     int32_t march_threads;
     int32_t shade_group;

@@ -161,7 +161,7 @@ struct vrt_ctx {
     float voxel_size = 1;
     hipStream_t last_stream = nullptr;
     vrt::Profiler prof;
-    vrt_tune tune[2] = {{256, 16, 4, 4, 4096, {0, 0, 0}}, {256, 16, 4, 4, 4096, {0, 0, 0}}};  // per trace mode
+    vrt_tune tune[2] = {{256, 16, 2, 4, 4096, {0, 0, 0}}, {256, 16, 2, 4, 4096, {0, 0, 0}}};  // per trace mode
 };
 
 namespace vrt {

@@ -15,7 +15,7 @@ struct ShadeCfg {
     static constexpr int kGroup = G, kBatch = B, kLaneKeys = K;
     static_assert(G == 8 || G == 16 || G == 32, "group");
 };
-using DefaultShade = ShadeCfg<16, 4, 4>;
+using DefaultShade = ShadeCfg<16, 2, 4>;
 
 // Primary ray through the centre of pixel (px, py), row 0 at the top, as a
 // fixed binary32 sequence (no contraction): u = 2(x + .5)/W - 1,

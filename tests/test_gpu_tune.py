@@ -94,7 +94,7 @@ def test_autotune_sets_a_shape_and_uses_its_cache(tmp_path):
         assert r1["best"] == ctx.get_tune(vrt.TRACE_TRANSPARENT)
         assert 0 < r1["best_ms"] <= r1["start_ms"] * 1.0001
         # the opaque shape is untouched
-        assert ctx.get_tune(vrt.TRACE_OPAQUE) == dict(march_threads=256, shade_group=16, shade_batch=4, lane_keys=4,
+        assert ctx.get_tune(vrt.TRACE_OPAQUE) == dict(march_threads=256, shade_group=16, shade_batch=2, lane_keys=4,
                                                       shade_blocks=4096)
         got = G.run_trace(ctx, cam, vrt.TRACE_TRANSPARENT, 0.2)
         for a, b in zip(got, ref):
