@@ -713,8 +713,11 @@ __device__ __forceinline__ void b_debug_rays(TraceParams p, const int64_t *__res
     dirs[3 * i + 2] = d.z;
 }
 
+// Four waves per SIMD (at most 128 registers): the shade phase is bound by
+// memory latency, and the fourth wave hides more of it than the few spilled
+// registers cost.
 template <bool kStats, int kForm, class Cfg>
-__global__ void __launch_bounds__(256) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm, Cfg>(a, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm, Cfg>(a, blockIdx.x, gridDim.x); }
 
 __global__ void k_debug_rays(TraceParams p, const int64_t *__restrict__ pix, int64_t n, float *__restrict__ dirs) { b_debug_rays(p, pix, n, dirs, blockIdx.x, gridDim.x); }
 

@@ -471,7 +471,8 @@ __global__ void __launch_bounds__(256) k_vox_count(CountArgs a, DevStatus *__res
 __global__ void __launch_bounds__(256) k_bin_count(BinArgs a, DevStatus *__restrict__ st) { b_bin_count(a, st, blockIdx.x, gridDim.x); }
 __global__ void __launch_bounds__(256) k_bin_alloc(BinArgs a, DevStatus *__restrict__ st) { b_bin_alloc(a, st, blockIdx.x, gridDim.x); }
 __global__ void __launch_bounds__(256) k_bin_fill(BinArgs a, DevStatus *__restrict__ st) { b_bin_fill(a, st, blockIdx.x, gridDim.x); }
-__global__ void __launch_bounds__(256) k_brick_accum(AccumArgs a, DevStatus *__restrict__ st) { b_brick_accum(a, st, blockIdx.x, gridDim.x); }
+// six waves per SIMD (at most 80 registers, a few spilled): more bins in flight
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_brick_accum(AccumArgs a, DevStatus *__restrict__ st) { b_brick_accum(a, st, blockIdx.x, gridDim.x); }
 __global__ void __launch_bounds__(256) k_vox_long(CountArgs a, const uint32_t *__restrict__ long_ids, DevStatus *__restrict__ st) { b_vox_long(a, long_ids, st, blockIdx.x, gridDim.x); }
 
 // Single workgroup: compacts the touched-brick flags into the ascending list
