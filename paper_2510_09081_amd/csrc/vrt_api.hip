@@ -30,7 +30,7 @@ hipError_t alloc(T *&p, int64_t n) {
 void free_all(Arenas &a) {
     void *ptrs[] = {a.vrec, a.words, a.occ0, a.occ1, a.occ2, a.occ3, a.occ_hi, a.blk, a.blk_bits, a.brick_bits, a.super_blk,
                     a.occ_list, a.vis0,
-                    a.vis1, a.vis2,  a.vis3, a.vis_hi, a.cursor, a.cell, a.queue, a.srec16, a.ids, a.brick_flag, a.bin_count, a.bin_range, a.cand, a.bins, a.long_ids, a.items, a.brick_list, a.brick_slot,
+                    a.vis1, a.vis2,  a.vis3, a.vis_hi, a.cursor, a.cell, a.queue, a.srec16, a.ids, a.brick_flag, a.bin_count, a.bin_range, a.cand, a.bins, a.long_ids, a.items, a.chunk_cnt, a.brick_list, a.brick_slot,
                     a.brick_total, a.brick_base, a.status, a.stat_vox, a.stat_seg, a.stat_acc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -138,6 +138,7 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     ALLOC(a.bins, (int64_t)kMaxBinBricks * desc->max_vertices);
     ALLOC(a.long_ids, desc->max_vertices);
     ALLOC(a.items, mb + (int64_t)kMaxBinBricks * desc->max_vertices / kBinChunk + 1);
+    ALLOC(a.chunk_cnt, mb / (1024 * 16) + 1);
     ALLOC(a.brick_list, mb);
     ALLOC(a.brick_slot, mb);
     ALLOC(a.brick_total, mb);

@@ -109,6 +109,7 @@ struct Arenas {
     uint32_t *bins = nullptr;       // [kMaxBinBricks * max_vertices] segment ids grouped by brick
     uint32_t *long_ids = nullptr;   // [max_vertices] segments whose voxel box spans more bricks
     uint2 *items = nullptr;         // (brick, chunk) work items of the per-brick passes
+    uint32_t *chunk_cnt = nullptr;  // touched bricks per compaction chunk
     int32_t *brick_list = nullptr;  // [max_bricks]
     int32_t *brick_slot = nullptr;  // [max_bricks] slot in brick_list or -1
     uint32_t *brick_total = nullptr;// [max_bricks] visible fragments per occupied brick (by slot)

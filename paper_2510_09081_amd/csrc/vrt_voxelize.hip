@@ -475,19 +475,21 @@ __global__ void __launch_bounds__(256) k_bin_fill(BinArgs a, DevStatus *__restri
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_brick_accum(AccumArgs a, DevStatus *__restrict__ st) { b_brick_accum(a, st, blockIdx.x, gridDim.x); }
 __global__ void __launch_bounds__(256) k_vox_long(CountArgs a, const uint32_t *__restrict__ long_ids, DevStatus *__restrict__ st) { b_vox_long(a, long_ids, st, blockIdx.x, gridDim.x); }
 
-// Single workgroup: compacts the touched-brick flags into the ascending list
-// of occupied bricks, writes each brick's slot (or -1), clears the flags.
-// Rounds of 16 flags per thread (coalesced), a block-wide exclusive scan of
-// the per-thread counts and a running carry keep the list in brick order.
-__device__ __forceinline__ void b_brick_compact(uint8_t *__restrict__ flag, int64_t nb,
-                                                int32_t *__restrict__ list, int32_t *__restrict__ slot,
-                                                DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
+// One workgroup compacts the touched-brick flags of bricks [first, last) into
+// the ascending list of occupied bricks, starting at list position carry0;
+// writes each brick's slot (or -1) and clears the flags.  Rounds of 16 flags
+// per thread (coalesced), a block-wide exclusive scan of the per-thread counts
+// and a running carry keep the list in brick order.  Returns the position
+// after the range (in every thread).
+__device__ __forceinline__ unsigned compact_range(uint8_t *__restrict__ flag, int64_t nb, int64_t first, int64_t last,
+                                                  unsigned carry0, int32_t *__restrict__ list,
+                                                  int32_t *__restrict__ slot) {
     __shared__ unsigned wtot[16];
     __shared__ unsigned carry;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
-    if (t == 0) carry = 0;
+    if (t == 0) carry = carry0;
     __syncthreads();
-    for (int64_t base = 0; base < nb; base += (int64_t)blockDim.x * 16) {
+    for (int64_t base = first; base < last; base += (int64_t)blockDim.x * 16) {
         const int64_t b0 = base + (int64_t)t * 16;
         uint8_t f[16];
         if (b0 + 16 <= nb) {
@@ -531,12 +533,61 @@ __device__ __forceinline__ void b_brick_compact(uint8_t *__restrict__ flag, int6
         if (t == 0) carry += round;
         __syncthreads();
     }
-    if (t == 0) st->n_bricks = carry;
+    return carry;
 }
 
-__global__ void __launch_bounds__(1024) k_brick_compact(uint8_t *__restrict__ flag, int64_t nb,
+// Single workgroup over all bricks (the batched form's path).
+__device__ __forceinline__ void b_brick_compact(uint8_t *__restrict__ flag, int64_t nb,
+                                                int32_t *__restrict__ list, int32_t *__restrict__ slot,
+                                                DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
+    const unsigned n = compact_range(flag, nb, 0, nb, 0u, list, slot);
+    if (threadIdx.x == 0) st->n_bricks = n;
+}
+
+// The per-context path: one workgroup per chunk of kCompactChunk bricks,
+// first counting each chunk's touched bricks, then compacting every chunk at
+// the position after the chunks before it.
+constexpr int kCompactChunk = 1024 * 16;
+
+__global__ void __launch_bounds__(1024) k_compact_count(const uint8_t *__restrict__ flag, int64_t nb,
+                                                        uint32_t *__restrict__ chunk_cnt) {
+    __shared__ unsigned wsum[16];
+    const int64_t b0 = (int64_t)blockIdx.x * kCompactChunk + (int64_t)threadIdx.x * 16;
+    unsigned cnt = 0;
+    if (b0 + 16 <= nb) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(flag + b0);
+        const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cnt += ((qq[k >> 2] >> (8 * (k & 3))) & 0xFFu) ? 1u : 0u;
+    } else {
+        for (int k = 0; k < 16; ++k) cnt += (b0 + k < nb && flag[b0 + k]) ? 1u : 0u;
+    }
+    cnt = (unsigned)wave_sum_u64(cnt);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned tot = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tot += wsum[k];
+        chunk_cnt[blockIdx.x] = tot;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_compact_write(uint8_t *__restrict__ flag, int64_t nb,
+                                                        const uint32_t *__restrict__ chunk_cnt,
                                                         int32_t *__restrict__ list, int32_t *__restrict__ slot,
-                                                        DevStatus *__restrict__ st) { b_brick_compact(flag, nb, list, slot, st, blockIdx.x, gridDim.x); }
+                                                        DevStatus *__restrict__ st) {
+    __shared__ unsigned base;
+    if (threadIdx.x == 0) {
+        unsigned s = 0;
+        for (unsigned k = 0; k < blockIdx.x; ++k) s += chunk_cnt[k];
+        base = s;
+    }
+    __syncthreads();
+    const int64_t first = (int64_t)blockIdx.x * kCompactChunk;
+    const int64_t last = first + kCompactChunk < nb ? first + kCompactChunk : nb;
+    const unsigned end = compact_range(flag, nb, first, last, base, list, slot);
+    if (threadIdx.x == 0 && blockIdx.x + 1 == gridDim.x) st->n_bricks = end;
+}
 
 // One workgroup (512 threads) per occupied brick: level-0 occupancy (saturated
 // at 1.0; a voxel with 256 or more fragments is full) and the in-brick mips
@@ -799,8 +850,12 @@ hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *L, float s_q, hipStream_
     VRT_LAUNCH(c, "k_bin_fill", st, k_bin_fill<<<eb, 256, 0, st>>>(p.ba, A.status));
     VRT_LAUNCH(c, "k_brick_accum", st, k_brick_accum<<<kBrickBlocks, 256, 0, st>>>(p.aa, A.status));
     VRT_LAUNCH(c, "k_vox_long", st, k_vox_long<<<256, 256, 0, st>>>(p.ca, A.long_ids, A.status));
-    VRT_LAUNCH(c, "k_brick_compact", st,
-               k_brick_compact<<<1, 1024, 0, st>>>(A.brick_flag, p.nb, A.brick_list, A.brick_slot, A.status));
+    const unsigned nchunks = (unsigned)((p.nb + kCompactChunk - 1) / kCompactChunk);
+    VRT_LAUNCH(c, "k_compact_count", st,
+               k_compact_count<<<nchunks, 1024, 0, st>>>(A.brick_flag, p.nb, A.chunk_cnt));
+    VRT_LAUNCH(c, "k_compact_write", st,
+               k_compact_write<<<nchunks, 1024, 0, st>>>(A.brick_flag, p.nb, A.chunk_cnt, A.brick_list, A.brick_slot,
+                                                         A.status));
     VRT_LAUNCH(c, "k_occ_brick", st,
                k_occ_brick<<<1024, 512, 0, st>>>(A.words, A.brick_list, A.status, A.occ0, A.occ1, A.occ2, A.occ3,
                                                  A.occ_list));
