@@ -472,20 +472,15 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
         return true;
     }
     // Transparent: each lane keeps its kLaneKeys smallest accepted keys above
-    // the threshold, each with its segment's colour; the group composites the
-    // smallest head key of all lanes while it is safe, i.e. while no lane that
-    // dropped keys has run dry; otherwise it rescans above the last composited
-    // key.
+    // the threshold; the group composites the smallest head key of all lanes
+    // while it is safe, i.e. while no lane that dropped keys has run dry;
+    // otherwise it rescans above the last composited key.
     unsigned long long thr = 0ull;
     bool have_thr = false;
     for (;;) {
         unsigned long long kk[kLaneKeys];
-        float kr[kLaneKeys], kg[kLaneKeys], kb[kLaneKeys];  // colours of the keys
 #pragma unroll
-        for (int j = 0; j < kLaneKeys; ++j) {
-            kk[j] = kNoKey;
-            kr[j] = kg[j] = kb[j] = 0.0f;
-        }
+        for (int j = 0; j < kLaneKeys; ++j) kk[j] = kNoKey;
         int nacc = 0;
         if (kStats && gl == 0) ++cn.pass;
         for_each_entry<kStats, kForm, Cfg>(a, w, gl, cn, [&](uint32_t id, const LocalSeg &g) {
@@ -494,21 +489,12 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
             unsigned long long key = hit_key(s, id);
             if (have_thr && !(key > thr)) return;
             ++nacc;
-            const float3 col = seg_colour(g.pa, g.pb);
-            float cr = col.x, cg = col.y, cb = col.z;
 #pragma unroll
             for (int j = 0; j < kLaneKeys; ++j) {  // sorted insert, the largest falls off the end
                 const bool less = key < kk[j];
                 const unsigned long long lo = less ? key : kk[j];
                 key = less ? kk[j] : key;
                 kk[j] = lo;
-                const float r0 = less ? cr : kr[j], g0 = less ? cg : kg[j], b0 = less ? cb : kb[j];
-                cr = less ? kr[j] : cr;
-                cg = less ? kg[j] : cg;
-                cb = less ? kb[j] : cb;
-                kr[j] = r0;
-                kg[j] = g0;
-                kb[j] = b0;
             }
         });
         const bool dropped = nacc > kLaneKeys;
@@ -522,18 +508,13 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
             if (m == kNoKey) break;
             // keys are unique (one per segment), so exactly one lane holds m: it pops, and its colour is used
             const bool own = kk[0] == m;
-            const int src = (lane & ~(kGroup - 1)) + __ffsll((long long)group_ballot<kGroup>(own, lane)) - 1;
-            const float3 c = make_float3(__shfl(kr[0], src, 64), __shfl(kg[0], src, 64), __shfl(kb[0], src, 64));
             if (own) {
 #pragma unroll
-                for (int j = 0; j + 1 < kLaneKeys; ++j) {
-                    kk[j] = kk[j + 1];
-                    kr[j] = kr[j + 1];
-                    kg[j] = kg[j + 1];
-                    kb[j] = kb[j + 1];
-                }
+                for (int j = 0; j + 1 < kLaneKeys; ++j) kk[j] = kk[j + 1];
                 kk[kLaneKeys - 1] = kNoKey;
             }
+            const LocalSeg gc = load_seg<kForm>(a, (uint32_t)m, cx, cy, cz);
+            const float3 c = seg_colour(gc.pa, gc.pb);
             const uint32_t id = (uint32_t)m;
             if (sh.first < 0) {
                 sh.first = (int)id;
