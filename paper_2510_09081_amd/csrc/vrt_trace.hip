@@ -303,6 +303,7 @@ struct Walk {
     float texit;    // exit parameter of the current voxel
     int64_t vi;     // brick-major index of the current voxel
     uint64_t cd;    // its list descriptor
+    int64_t bvis = -1;  // a brick already found visible (its culling flags need no second look)
 };
 
 // Steps past the current voxel along its exit axis; false when the ray leaves the grid.
@@ -324,18 +325,21 @@ __device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w,
     const int max_iter = 3 * (a.G[0] + a.G[1] + a.G[2]) + 16;
     for (int it = 0; it < max_iter; ++it) {
         if (!(w.tcur < w.tout)) return false;
-        if (a.vis6 && !a.vis6[((int64_t)(w.v[2] >> 6) * a.n6[1] + (w.v[1] >> 6)) * a.n6[0] + (w.v[0] >> 6)]) {
-            if (kStats) ++cn.skip64;
-            if (!skip_cell(r, a.G, 64, w.v, w.tcur)) return false;
-            w.fresh = true;
-            continue;
-        }
         const int64_t b = ((int64_t)(w.v[2] >> 3) * a.nb[1] + (w.v[1] >> 3)) * a.nb[0] + (w.v[0] >> 3);
-        if (!a.vis3[b]) {
-            if (kStats) ++cn.skip8;
-            if (!skip_cell(r, a.G, 8, w.v, w.tcur)) return false;
-            w.fresh = true;
-            continue;
+        if (b != w.bvis) {  // a new brick: its 64^3 cell and its own culling flag
+            if (a.vis6 && !a.vis6[((int64_t)(w.v[2] >> 6) * a.n6[1] + (w.v[1] >> 6)) * a.n6[0] + (w.v[0] >> 6)]) {
+                if (kStats) ++cn.skip64;
+                if (!skip_cell(r, a.G, 64, w.v, w.tcur)) return false;
+                w.fresh = true;
+                continue;
+            }
+            if (!a.vis3[b]) {
+                if (kStats) ++cn.skip8;
+                if (!skip_cell(r, a.G, 8, w.v, w.tcur)) return false;
+                w.fresh = true;
+                continue;
+            }
+            w.bvis = b;
         }
         if (w.fresh) {
             for (int k = 0; k < 3; ++k)
