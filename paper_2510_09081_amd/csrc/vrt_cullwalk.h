@@ -6,16 +6,21 @@
 
 namespace vrt {
 
-// floor((num) / den) for 0 <= num < 64 * den (den > 0): an estimate from a
-// binary32 reciprocal, corrected exactly in integers.
-__host__ __device__ inline long long walk_small_quot(long long num, long long den) {
-#ifdef __HIP_DEVICE_COMPILE__
-    long long q = (long long)((float)num * __builtin_amdgcn_rcpf((float)den));
-#else
-    long long q = num / den;
-#endif
-    while (q > 0 && q * den > num) --q;
-    while ((q + 1) * den <= num) ++q;
+// q = floor(num / den) for 0 <= num < 64 * den (den > 0, 64 * den < 2^63),
+// bit by bit from the top: additions and comparisons only.  Also returns
+// q * den in `qd`.
+__host__ __device__ inline int walk_small_quot(long long num, long long den, long long &qd) {
+    int q = 0;
+    long long acc = 0;
+#pragma unroll
+    for (int s = 5; s >= 0; --s) {
+        const long long t = acc + (den << s);
+        if (t <= num) {
+            acc = t;
+            q |= 1 << s;
+        }
+    }
+    qd = acc;
     return q;
 }
 
@@ -152,13 +157,16 @@ __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &c
             return;
         }
         bool out = false;
-        long long na[3];
+        int na[3];
+        long long nd[3];  // na * dT
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             na[a] = 0;
+            nd[a] = 0;
             if (w.step[a] == 0 || te < w.T[a]) continue;
-            na[a] = walk_small_quot(te - w.T[a], w.dT[a]) + 1;
-            const long long nx = w.cur[a] + w.step[a] * na[a];
+            na[a] = walk_small_quot(te - w.T[a], w.dT[a], nd[a]) + 1;
+            nd[a] += w.dT[a];
+            const int nx = w.cur[a] + w.step[a] * na[a];
             if (w.step[a] > 0 ? nx > w.lim[a] : nx < w.lim[a]) out = true;
         }
         if (out) {
@@ -167,8 +175,8 @@ __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &c
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            w.cur[a] += w.step[a] * (int)na[a];
-            if (na[a]) w.T[a] += (long long)((unsigned long long)w.dT[a] * (unsigned)na[a]);
+            w.cur[a] += w.step[a] * na[a];
+            w.T[a] += nd[a];
         }
     }
     w.be = cells.brick_empty(w.cur[0], w.cur[1], w.cur[2]);
