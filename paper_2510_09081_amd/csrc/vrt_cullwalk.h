@@ -7,13 +7,23 @@
 namespace vrt {
 
 // q = floor(num / den) for 0 <= num < 64 * den (den > 0, 64 * den < 2^63),
-// bit by bit from the top: additions and comparisons only.  Also returns
-// q * den in `qd`.
-__host__ __device__ inline int walk_small_quot(long long num, long long den, long long &qd) {
+// bit by bit from the top: additions and comparisons only; the top three bits
+// only when `wide` (else num < 8 * den).  Also returns q * den in `qd`.
+__host__ __device__ inline int walk_small_quot(long long num, long long den, bool wide, long long &qd) {
     int q = 0;
     long long acc = 0;
+    if (wide) {
 #pragma unroll
-    for (int s = 5; s >= 0; --s) {
+        for (int s = 5; s >= 3; --s) {
+            const long long t = acc + (den << s);
+            if (t <= num) {
+                acc = t;
+                q |= 1 << s;
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 2; s >= 0; --s) {
         const long long t = acc + (den << s);
         if (t <= num) {
             acc = t;
@@ -164,7 +174,7 @@ __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &c
             na[a] = 0;
             nd[a] = 0;
             if (w.step[a] == 0 || te < w.T[a]) continue;
-            na[a] = walk_small_quot(te - w.T[a], w.dT[a], nd[a]) + 1;
+            na[a] = walk_small_quot(te - w.T[a], w.dT[a], S == 64, nd[a]) + 1;
             nd[a] += w.dT[a];
             const int nx = w.cur[a] + w.step[a] * na[a];
             if (w.step[a] > 0 ? nx > w.lim[a] : nx < w.lim[a]) out = true;
