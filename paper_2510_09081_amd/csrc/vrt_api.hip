@@ -117,7 +117,7 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     ALLOC(a.occ3, mb);
     ALLOC(a.occ_hi, c->hi_elems);
     ALLOC(a.blk, mb * kBrickVox);
-    ALLOC(a.blk_bits, mb * 8);
+    ALLOC(a.blk_bits, mb * 16);
     ALLOC(a.brick_bits, (mb + 31) / 32);
     ALLOC(a.super_blk, c->max_supers);
     ALLOC(a.occ_list, mb * kBrickVox);

@@ -6,32 +6,41 @@
 
 namespace vrt {
 
-// q = floor(num / den) for 0 <= num < 64 * den (den > 0, 64 * den < 2^63),
-// bit by bit from the top: additions and comparisons only; the top three bits
-// only when `wide` (else num < 8 * den).  Also returns q * den in `qd`.
-__host__ __device__ inline int walk_small_quot(long long num, long long den, bool wide, long long &qd) {
+// One bit of a long division: q gets bit s if (q + 2^s) den <= num.
+__host__ __device__ inline void walk_quot_bit(int s, long long num, long long den, long long &acc, int &q) {
+    const long long t = acc + (den << s);
+    if (t <= num) {
+        acc = t;
+        q |= 1 << s;
+    }
+}
+
+// q = floor(num / den) for 0 <= num < 2^sh den, sh in {1, 2, 3, 6} (den > 0,
+// 64 den < 2^63), bit by bit from the top: additions and comparisons only,
+// sh bits.  Also returns q * den in `qd`.
+__host__ __device__ inline int walk_small_quot(long long num, long long den, int sh, long long &qd) {
     int q = 0;
     long long acc = 0;
-    if (wide) {
-#pragma unroll
-        for (int s = 5; s >= 3; --s) {
-            const long long t = acc + (den << s);
-            if (t <= num) {
-                acc = t;
-                q |= 1 << s;
-            }
-        }
+    if (sh > 3) {
+        walk_quot_bit(5, num, den, acc, q);
+        walk_quot_bit(4, num, den, acc, q);
+        walk_quot_bit(3, num, den, acc, q);
     }
-#pragma unroll
-    for (int s = 2; s >= 0; --s) {
-        const long long t = acc + (den << s);
-        if (t <= num) {
-            acc = t;
-            q |= 1 << s;
-        }
-    }
+    if (sh > 2) walk_quot_bit(2, num, den, acc, q);
+    if (sh > 1) walk_quot_bit(1, num, den, acc, q);
+    walk_quot_bit(0, num, den, acc, q);
     qd = acc;
     return q;
+}
+
+// Within a brick: index of the 2^3 cell holding voxel (x, y, z), and the mask
+// of the eight 2^3 cells of its 4^3 cell, in a brick's 64-bit mask of
+// 2^3 cells (bit 16 Z + 4 Y + X for cell (X, Y, Z), 0 <= X, Y, Z < 4).
+__host__ __device__ inline int walk_cell2(int x, int y, int z) {
+    return (((z & 7) >> 1) << 4) | (((y & 7) >> 1) << 2) | ((x & 7) >> 1);
+}
+__host__ __device__ inline uint64_t walk_cell4_mask(int x, int y, int z) {
+    return 0x00330033ull << ((((z & 7) >> 2) << 5) | (((y & 7) >> 2) << 3) | (((x & 7) >> 2) << 1));
 }
 
 // Counts the blocking voxels met by the open segment from the centre of voxel
@@ -53,8 +62,9 @@ __host__ __device__ inline int walk_small_quot(long long num, long long den, boo
 // (1024 voxels), so T < 2^62.3; P is clamped to 2^63 - 1 when larger (the eye
 // then lies beyond every reachable crossing).
 //
-// Cells of S^3 voxels (S = 64, then 8) that hold no blocking voxel are crossed
-// in one jump: with Te the smallest time at which the walk crosses the cell's
+// Cells of S^3 voxels that hold no blocking voxel are crossed in one jump (S =
+// 64 or 8 in bricks without a blocker, else 4 or 2 from the brick's mask of
+// 2^3 cells): with Te the smallest time at which the walk crosses the cell's
 // far face on some axis, every moving axis a makes all its crossings with
 // T <= Te, n_a = floor((Te - T_a) / dT_a) + 1 of them (none if Te < T_a);
 // on the exit axes that is exactly into the next cell, and crossings tied
@@ -64,15 +74,39 @@ __host__ __device__ inline int walk_small_quot(long long num, long long den, boo
 // Cells: `cells` provides
 //   bool super_empty(x, y, z)  -- the 64^3 cell holding voxel (x,y,z) has no blocker
 //   bool brick_empty(x, y, z)  -- the 8^3 brick holding voxel (x,y,z) has no blocker
-//   bool blocking(x, y, z)     -- the voxel blocks (only asked in non-empty bricks)
+//   uint64_t sub_mask(x, y, z) -- the 2^3 cells of that brick holding a blocker
+//                                 (only asked in non-empty bricks)
+//   bool blocking(x, y, z)     -- the voxel blocks (only asked in non-empty 2^3 cells)
+//
 // State of one culling walk between steps (everything in registers).
 struct CullWalk {
     int cur[3], step[3], lim[3];
     long long T[3], dT[3], P;
-    int n;      // blocking voxels met so far
-    bool be;    // the current voxel's brick holds no blocker
-    bool done;  // n is the result
+    uint64_t m2;  // sub_mask of the brick with key k2
+    int k2;       // packed brick coordinates of m2, or -1
+    int n;        // blocking voxels met so far
+    bool be;      // the current voxel's brick holds no blocker
+    bool done;    // n is the result
 };
+
+// Brick key of voxel (x, y, z): brick coordinates below 2^10 each.
+__host__ __device__ inline int walk_brick_key(int x, int y, int z) {
+    return ((z >> 3) << 20) | ((y >> 3) << 10) | (x >> 3);
+}
+
+// The brick flag of the current voxel, the 2^3-cell mask of its brick when
+// that holds a blocker, and whether the current voxel's 2^3 cell does.
+template <class Cells>
+__host__ __device__ inline bool walk_enter(CullWalk &w, const Cells &cells) {
+    w.be = cells.brick_empty(w.cur[0], w.cur[1], w.cur[2]);
+    if (w.be) return false;
+    const int key = walk_brick_key(w.cur[0], w.cur[1], w.cur[2]);
+    if (key != w.k2) {
+        w.m2 = cells.sub_mask(w.cur[0], w.cur[1], w.cur[2]);
+        w.k2 = key;
+    }
+    return (w.m2 >> walk_cell2(w.cur[0], w.cur[1], w.cur[2])) & 1ull;
+}
 
 // Sets up the walk from voxel (x, y, z); done at once when the eye is at the
 // voxel's centre or no blocking voxel can lie ahead.
@@ -119,7 +153,10 @@ __host__ __device__ inline void walk_begin(CullWalk &w, const int *G, int x, int
         if ((st > 0 && w.cur[a] > w.lim[a]) || (st < 0 && w.cur[a] < w.lim[a])) none = true;
     }
     w.done = none;
-    w.be = none ? true : cells.brick_empty(x, y, z);
+    w.k2 = -1;
+    w.m2 = 0;
+    w.be = true;
+    if (!none) walk_enter(w, cells);
 }
 
 // One step of the walk: a voxel, or an empty cell crossed in one jump; then
@@ -127,9 +164,13 @@ __host__ __device__ inline void walk_begin(CullWalk &w, const int *G, int x, int
 template <class Cells>
 __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &cells) {
     constexpr long long kNever = 0x7FFFFFFFFFFFFFFFll;
-    int S = 1;
-    if (w.be) S = cells.super_empty(w.cur[0], w.cur[1], w.cur[2]) ? 64 : 8;
-    if (S == 1) {
+    int sh = 0;  // the cell crossed has S = 2^sh voxels a side
+    if (w.be) {
+        sh = cells.super_empty(w.cur[0], w.cur[1], w.cur[2]) ? 6 : 3;
+    } else if (!((w.m2 >> walk_cell2(w.cur[0], w.cur[1], w.cur[2])) & 1ull)) {
+        sh = (w.m2 & walk_cell4_mask(w.cur[0], w.cur[1], w.cur[2])) ? 1 : 2;
+    }
+    if (sh == 0) {
         long long tm = w.T[0] < w.T[1] ? w.T[0] : w.T[1];
         tm = w.T[2] < tm ? w.T[2] : tm;
         if (!(tm < w.P)) {  // eye reached
@@ -151,13 +192,13 @@ __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &c
         }
     } else {
         long long Tc[3];
-        const int sh = S == 64 ? 6 : 3;  // S = 2^sh
+        const int s1 = (1 << sh) - 1;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             Tc[a] = kNever;
             if (w.step[a] == 0) continue;
-            const int cs = (w.cur[a] >> sh) << sh;  // cur >= 0
-            const unsigned k = (unsigned)(w.step[a] > 0 ? cs + S - 1 - w.cur[a] : w.cur[a] - cs);
+            const int cs = w.cur[a] & ~s1;  // cur >= 0
+            const unsigned k = (unsigned)(w.step[a] > 0 ? cs + s1 - w.cur[a] : w.cur[a] - cs);
             Tc[a] = w.T[a] + (long long)((unsigned long long)w.dT[a] * k);
         }
         long long te = Tc[0] < Tc[1] ? Tc[0] : Tc[1];
@@ -174,7 +215,7 @@ __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &c
             na[a] = 0;
             nd[a] = 0;
             if (w.step[a] == 0 || te < w.T[a]) continue;
-            na[a] = walk_small_quot(te - w.T[a], w.dT[a], S == 64, nd[a]) + 1;
+            na[a] = walk_small_quot(te - w.T[a], w.dT[a], sh, nd[a]) + 1;
             nd[a] += w.dT[a];
             const int nx = w.cur[a] + w.step[a] * na[a];
             if (w.step[a] > 0 ? nx > w.lim[a] : nx < w.lim[a]) out = true;
@@ -189,8 +230,7 @@ __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &c
             w.T[a] += nd[a];
         }
     }
-    w.be = cells.brick_empty(w.cur[0], w.cur[1], w.cur[2]);
-    if (!w.be && cells.blocking(w.cur[0], w.cur[1], w.cur[2]) && ++w.n >= limit) w.done = true;
+    if (walk_enter(w, cells) && cells.blocking(w.cur[0], w.cur[1], w.cur[2]) && ++w.n >= limit) w.done = true;
 }
 
 // The whole walk: the number of blocking voxels met, at most `limit`.

@@ -88,7 +88,8 @@ struct Arenas {
     uint16_t *occ3 = nullptr;       // [max_bricks]
     uint16_t *occ_hi = nullptr;     // levels >= 4
     uint8_t *blk = nullptr;         // [max_bricks * 512]
-    uint64_t *blk_bits = nullptr;   // [max_bricks * 8] blocking voxels, one bit each, 64 voxels per word
+    uint64_t *blk_bits = nullptr;   // [max_bricks * 16] per brick: words 0..7 blocking voxels, one bit each
+                                    // (64 voxels per word), word 8 its 2^3 cells holding a blocker
     uint32_t *brick_bits = nullptr; // [(max_bricks + 31) / 32] bricks holding a blocking voxel, one bit each
     uint8_t *super_blk = nullptr;   // [max_supers] 64^3 cells holding a blocking voxel
     uint32_t *occ_list = nullptr;   // [max_bricks * 512] brick-major index of every occupied voxel

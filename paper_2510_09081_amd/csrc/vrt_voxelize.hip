@@ -695,6 +695,7 @@ __device__ __forceinline__ void b_erode(GridArgs g, const uint16_t *__restrict__
                                                uint64_t *__restrict__ blk_bits, uint32_t *__restrict__ brick_bits,
                                                uint8_t *__restrict__ super_blk, unsigned bid_, unsigned nblk_) {
     __shared__ int bb[6];
+    __shared__ unsigned m2[8];
     const unsigned nbk = st->n_bricks;
     const int t = threadIdx.x;
     // pass 1 is complete: total the fragment stripes; a count field wrapped iff
@@ -727,13 +728,23 @@ __device__ __forceinline__ void b_erode(GridArgs g, const uint16_t *__restrict__
         bool blocking = e >= 256u;
         blk[b * kBrickVox + t] = blocking ? 1 : 0;
         const unsigned long long bits = __ballot(blocking);  // the wave holds local voxels 64w .. 64w + 63
-        if ((t & 63) == 0) blk_bits[b * 8 + (t >> 6)] = bits;
+        if ((t & 63) == 0) blk_bits[b * 16 + (t >> 6)] = bits;
+        {  // the slice's 2x2 squares holding a blocker: bit 4 Y + X for square (X, Y)
+            unsigned long long c = bits | (bits >> 1);
+            c |= c >> 8;  // bit 16 Y + 2 X: the square's OR
+            const int lane = t & 63;
+            const unsigned long long sq = __ballot(lane < 16 && ((c >> (16 * (lane >> 2) + 2 * (lane & 3))) & 1ull));
+            if (lane == 0) m2[t >> 6] = (unsigned)sq & 0xFFFFu;
+        }
         if (blocking) {
             atomicMin(&bb[0], x); atomicMin(&bb[1], y); atomicMin(&bb[2], z);
             atomicMax(&bb[3], x); atomicMax(&bb[4], y); atomicMax(&bb[5], z);
         }
         int any = __syncthreads_or(blocking ? 1 : 0);
         if (t == 0 && any) {
+            uint64_t cells = 0;  // bit 16 Z + 4 Y + X for the 2^3 cell (X, Y, Z)
+            for (int Z = 0; Z < 4; ++Z) cells |= (uint64_t)(m2[2 * Z] | m2[2 * Z + 1]) << (16 * Z);
+            blk_bits[b * 16 + 8] = cells;
             atomicOr(&brick_bits[b >> 5], 1u << (b & 31));
             super_blk[((int64_t)(bz >> 3) * g.ns[1] + (by >> 3)) * g.ns[0] + (bx >> 3)] = 1;
             int *p = st->stripe[bid_ % kStripes].bbox;
