@@ -118,8 +118,12 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     ALLOC(a.occ_hi, c->hi_elems);
     ALLOC(a.blk, mb * kBrickVox);
     ALLOC(a.blk_bits, mb * 16);
-    ALLOC(a.brick_bits, (mb + 31) / 32);
-    ALLOC(a.super_blk, c->max_supers);
+    {
+        const int nbm[3] = {(int)nbd, (int)nbd, (int)nbd};
+        const CellFlagLayout cl = cell_flag_layout(nbm);
+        ALLOC(a.brick_bits, cl.words);
+        ALLOC(a.super_blk, cl.bytes);
+    }
     ALLOC(a.occ_list, mb * kBrickVox);
     ALLOC(a.vis0, mb * kBrickVox);
     ALLOC(a.vis1, mb * 64);

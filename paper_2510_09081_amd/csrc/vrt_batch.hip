@@ -46,7 +46,7 @@ __device__ unsigned part_blocks(int ph, int part, const SetDesc &d) {
     const DevStatus *st = d.a.status;
     const unsigned T = kBatchThreads;
     switch (ph) {
-    case P_CLEAR: return part == 0 ? st->n_bricks : (part == 1 ? cdiv(d.vp.nb, T) : 0u);
+    case P_CLEAR: return part == 0 ? st->n_bricks : (part == 1 ? cdiv(reset_items(d.vp.nb, d.vp.nw, d.vp.nf), T) : 0u);
     case P_INGEST: return part == 0 ? cdiv(d.vp.nv, T) : 0u;
     case P_COUNT: return part == 0 ? (d.fp16 ? cdiv(d.vp.nv, T) : 0u) : (part == 1 ? cdiv(d.vp.nv, T) : 0u);
     case P_COMPACT: return part == 0 ? 1u : 0u;
@@ -108,7 +108,7 @@ __device__ __forceinline__ void run_part(int ph, int part, const SetDesc &d, uns
     switch (ph) {
     case P_CLEAR:
         if (part == 0) b_clear_prev(A.words, A.brick_list, A.status, vb, nvb);
-        else b_reset(A.occ3, A.bin_count, A.brick_bits, d.vp.nb, A.super_blk, d.vp.ns, A.status, vb, nvb);
+        else b_reset(A.occ3, A.bin_count, A.brick_bits, d.vp.nb, d.vp.nw, A.super_blk, d.vp.nf, A.status, vb, nvb);
         break;
     case P_INGEST: b_ingest(d.vp.ia, A.vrec, A.status, vb, nvb); break;
     case P_COUNT:

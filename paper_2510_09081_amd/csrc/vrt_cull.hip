@@ -21,23 +21,32 @@ __device__ __forceinline__ void b_cull_reset(uint8_t *__restrict__ vis3, int64_t
 
 __global__ void k_cull_reset(uint8_t *__restrict__ vis3, int64_t nb, DevStatus *__restrict__ st) { b_cull_reset(vis3, nb, st, blockIdx.x, gridDim.x); }
 
-// Blocking lookups for the culling walk: 64^3 cells and bricks holding a
-// blocking voxel, and the level-0 blocking flags (defined in occupied bricks).
-// Blocking flags the culling walk reads: one byte per 64^3 cell, one bit per
-// brick and one bit per voxel (brick-major, 64 voxels per word).
+// Blocking flags the culling walk reads: one byte per 64^3 and 32^3 cell, one
+// bit per 16^3 cell and brick, and per brick holding a blocker one bit per
+// voxel (64 voxels per word) and one per 2^3 cell.
 struct CullCells {
-    const uint8_t *super_blk;
-    const uint32_t *brick_bits;
+    const uint8_t *super_blk, *c32_blk;
+    const uint32_t *brick_bits, *c16_bits;
     const uint64_t *blk_bits;
     int nb0, nb1, ns0, ns1;
+    int n16x, n16y, n32x, n32y;
     // indices below 2^24 (at most 128^3 bricks): 24-bit multiplies
     __device__ unsigned brick_of(int x, int y, int z) const {
         return __umul24(__umul24((unsigned)(z >> 3), (unsigned)nb1) + (unsigned)(y >> 3), (unsigned)nb0) +
                (unsigned)(x >> 3);
     }
-    __device__ bool super_empty(int x, int y, int z) const {
-        return !super_blk[__umul24(__umul24((unsigned)(z >> 6), (unsigned)ns1) + (unsigned)(y >> 6), (unsigned)ns0) +
-                          (unsigned)(x >> 6)];
+    // log2 of the largest of the 64^3, 32^3, 16^3 cells and the brick holding
+    // voxel (x, y, z) with no blocker, the brick being empty
+    __device__ int empty_shift(int x, int y, int z) const {
+        const bool e64 = !super_blk[__umul24(__umul24((unsigned)(z >> 6), (unsigned)ns1) + (unsigned)(y >> 6),
+                                             (unsigned)ns0) + (unsigned)(x >> 6)];
+        const unsigned c32 = __umul24(__umul24((unsigned)(z >> 5), (unsigned)n32y) + (unsigned)(y >> 5), (unsigned)n32x) +
+                             (unsigned)(x >> 5);
+        const unsigned c16 = __umul24(__umul24((unsigned)(z >> 4), (unsigned)n16y) + (unsigned)(y >> 4), (unsigned)n16x) +
+                             (unsigned)(x >> 4);
+        const bool e32 = !c32_blk[c32];
+        const bool e16 = !((c16_bits[c16 >> 5] >> (c16 & 31u)) & 1u);
+        return e64 ? 6 : (e32 ? 5 : (e16 ? 4 : 3));
     }
     __device__ bool brick_empty(int x, int y, int z) const {
         const unsigned b = brick_of(x, y, z);
@@ -50,9 +59,9 @@ struct CullCells {
     }
 };
 
-// Bytes of the brick bits and cell flags when staged in LDS.
-__host__ __device__ inline size_t cull_lds_bytes(int64_t nbricks, int64_t nsupers) {
-    return (size_t)((nbricks + 31) / 32) * 4 + (size_t)nsupers;
+// Bytes of the brick and cell flags when staged in LDS.
+__host__ __device__ inline size_t cull_lds_bytes(int64_t nwords, int64_t nflags) {
+    return (size_t)nwords * 4 + (size_t)nflags;
 }
 constexpr size_t kCullLdsMax = 48 * 1024;  // larger grids read the flags from global memory
 
@@ -84,13 +93,15 @@ __device__ __forceinline__ void b_cull_walk(CullArgs a, CullCells cells, const u
         bbox[k] = v;
     }
     if (kLds) {
-        const int64_t nb = (int64_t)a.g.nb[0] * a.g.nb[1] * a.g.nb[2];
-        const int nw = (int)((nb + 31) / 32), ns = a.g.ns[0] * a.g.ns[1] * a.g.ns[2];
+        const CellFlagLayout cl = cell_flag_layout(a.g.nb);
+        const int nw = (int)cl.words, nf = (int)cl.bytes;
         for (int i = threadIdx.x; i < nw; i += blockDim.x) vrt_cull_lds[i] = cells.brick_bits[i];
-        uint8_t *s_super = reinterpret_cast<uint8_t *>(vrt_cull_lds + nw);
-        for (int i = threadIdx.x; i < ns; i += blockDim.x) s_super[i] = cells.super_blk[i];
+        uint8_t *s_flags = reinterpret_cast<uint8_t *>(vrt_cull_lds + nw);
+        for (int i = threadIdx.x; i < nf; i += blockDim.x) s_flags[i] = cells.super_blk[i];
         cells.brick_bits = vrt_cull_lds;
-        cells.super_blk = s_super;
+        cells.c16_bits = vrt_cull_lds + cl.w16;
+        cells.super_blk = s_flags;
+        cells.c32_blk = s_flags + cl.b32;
     }
     __syncthreads();
     const unsigned n = st->n_occ;
@@ -395,6 +406,7 @@ static constexpr unsigned kCullWalkBlocks = 1024;
 // Arguments of every culling and list kernel for one view of context c.
 struct CullPlan {
     int64_t nb, nv;
+    int64_t nw, nf;  // words of the brick and 16^3 cell bits, bytes of the 64^3 and 32^3 cell flags
     int limit;  // < 0: no culling
     GridArgs g;
     CullArgs ca;
@@ -417,13 +429,22 @@ static CullPlan make_cull_plan(const vrt_ctx *c, const int64_t E[3], int64_t lim
     p.ca.g = p.g;
     for (int k = 0; k < 3; ++k) p.ca.E[k] = E[k];
     p.ca.limit = p.limit;
+    const CellFlagLayout cl = cell_flag_layout(p.g.nb);
+    p.nw = cl.words;
+    p.nf = cl.bytes;
     p.cells.super_blk = A.super_blk;
+    p.cells.c32_blk = A.super_blk + cl.b32;
     p.cells.brick_bits = A.brick_bits;
+    p.cells.c16_bits = A.brick_bits + cl.w16;
     p.cells.blk_bits = A.blk_bits;
     p.cells.nb0 = p.g.nb[0];
     p.cells.nb1 = p.g.nb[1];
     p.cells.ns0 = p.g.ns[0];
     p.cells.ns1 = p.g.ns[1];
+    p.cells.n16x = cl.n16[0];
+    p.cells.n16y = cl.n16[1];
+    p.cells.n32x = cl.n32[0];
+    p.cells.n32y = cl.n32[1];
     p.sa.vrec = A.vrec;
     p.sa.nv = c->n_vertices;
     p.sa.rq = c->rq;
@@ -450,7 +471,7 @@ hipError_t launch_cull(vrt_ctx *c, const int64_t E[3], int64_t limit, hipStream_
     VRT_LAUNCH(c, "k_cull_reset", st,
                k_cull_reset<<<(unsigned)((p.nb + 255) / 256), 256, 0, st>>>(A.vis3, p.nb, A.status));
     if (p.limit >= 0) {
-        const size_t lds = cull_lds_bytes(p.nb, (int64_t)p.g.ns[0] * p.g.ns[1] * p.g.ns[2]);
+        const size_t lds = cull_lds_bytes(p.nw, p.nf);
         if (lds <= kCullLdsMax)
             VRT_LAUNCH(c, "k_cull_walk", st,
                        k_cull_walk<true><<<kCullWalkBlocks, 512, lds, st>>>(p.ca, p.cells, A.occ_list, A.status, A.vis0));

@@ -15,17 +15,15 @@ __host__ __device__ inline void walk_quot_bit(int s, long long num, long long de
     }
 }
 
-// q = floor(num / den) for 0 <= num < 2^sh den, sh in {1, 2, 3, 6} (den > 0,
+// q = floor(num / den) for 0 <= num < 2^sh den, 1 <= sh <= 6 (den > 0,
 // 64 den < 2^63), bit by bit from the top: additions and comparisons only,
 // sh bits.  Also returns q * den in `qd`.
 __host__ __device__ inline int walk_small_quot(long long num, long long den, int sh, long long &qd) {
     int q = 0;
     long long acc = 0;
-    if (sh > 3) {
-        walk_quot_bit(5, num, den, acc, q);
-        walk_quot_bit(4, num, den, acc, q);
-        walk_quot_bit(3, num, den, acc, q);
-    }
+    if (sh > 5) walk_quot_bit(5, num, den, acc, q);
+    if (sh > 4) walk_quot_bit(4, num, den, acc, q);
+    if (sh > 3) walk_quot_bit(3, num, den, acc, q);
     if (sh > 2) walk_quot_bit(2, num, den, acc, q);
     if (sh > 1) walk_quot_bit(1, num, den, acc, q);
     walk_quot_bit(0, num, den, acc, q);
@@ -63,8 +61,8 @@ __host__ __device__ inline uint64_t walk_cell4_mask(int x, int y, int z) {
 // then lies beyond every reachable crossing).
 //
 // Cells of S^3 voxels that hold no blocking voxel are crossed in one jump (S =
-// 64 or 8 in bricks without a blocker, else 4 or 2 from the brick's mask of
-// 2^3 cells): with Te the smallest time at which the walk crosses the cell's
+// 64, 32, 16 or 8 in bricks without a blocker, else 4 or 2 from the brick's
+// mask of 2^3 cells): with Te the smallest time at which the walk crosses the cell's
 // far face on some axis, every moving axis a makes all its crossings with
 // T <= Te, n_a = floor((Te - T_a) / dT_a) + 1 of them (none if Te < T_a);
 // on the exit axes that is exactly into the next cell, and crossings tied
@@ -72,8 +70,10 @@ __host__ __device__ inline uint64_t walk_cell4_mask(int x, int y, int z) {
 // blocker, so the count is unchanged.
 //
 // Cells: `cells` provides
-//   bool super_empty(x, y, z)  -- the 64^3 cell holding voxel (x,y,z) has no blocker
 //   bool brick_empty(x, y, z)  -- the 8^3 brick holding voxel (x,y,z) has no blocker
+//   int empty_shift(x, y, z)   -- log2 of the largest of the 64^3, 32^3 and 16^3
+//                                 cells and the brick holding it with no blocker
+//                                 (only asked in empty bricks)
 //   uint64_t sub_mask(x, y, z) -- the 2^3 cells of that brick holding a blocker
 //                                 (only asked in non-empty bricks)
 //   bool blocking(x, y, z)     -- the voxel blocks (only asked in non-empty 2^3 cells)
@@ -166,7 +166,7 @@ __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &c
     constexpr long long kNever = 0x7FFFFFFFFFFFFFFFll;
     int sh = 0;  // the cell crossed has S = 2^sh voxels a side
     if (w.be) {
-        sh = cells.super_empty(w.cur[0], w.cur[1], w.cur[2]) ? 6 : 3;
+        sh = cells.empty_shift(w.cur[0], w.cur[1], w.cur[2]);
     } else if (!((w.m2 >> walk_cell2(w.cur[0], w.cur[1], w.cur[2])) & 1ull)) {
         sh = (w.m2 & walk_cell4_mask(w.cur[0], w.cur[1], w.cur[2])) ? 1 : 2;
     }

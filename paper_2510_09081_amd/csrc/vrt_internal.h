@@ -90,8 +90,8 @@ struct Arenas {
     uint8_t *blk = nullptr;         // [max_bricks * 512]
     uint64_t *blk_bits = nullptr;   // [max_bricks * 16] per brick: words 0..7 blocking voxels, one bit each
                                     // (64 voxels per word), word 8 its 2^3 cells holding a blocker
-    uint32_t *brick_bits = nullptr; // [(max_bricks + 31) / 32] bricks holding a blocking voxel, one bit each
-    uint8_t *super_blk = nullptr;   // [max_supers] 64^3 cells holding a blocking voxel
+    uint32_t *brick_bits = nullptr; // [cell_flag_layout(max).words] bricks and 16^3 cells holding a blocker, one bit each
+    uint8_t *super_blk = nullptr;   // [cell_flag_layout(max).bytes] 64^3 and 32^3 cells holding a blocker
     uint32_t *occ_list = nullptr;   // [max_bricks * 512] brick-major index of every occupied voxel
     uint8_t *vis0 = nullptr;        // [max_bricks * 512]
     uint8_t *vis1 = nullptr;        // [max_bricks * 64]
@@ -128,6 +128,34 @@ struct GridArgs {
     int nb[3];  // bricks per axis
     int ns[3];  // 64^3 cells per axis
 };
+
+// Blocker flags above the voxel level, each array x fastest.  Bits, in one
+// word array: one per brick, then one per 16^3 cell (2^3 bricks) from word
+// w16.  Bytes, in one byte array: one per 64^3 cell, then one per 32^3 cell
+// (4^3 bricks) from byte b32.
+struct CellFlagLayout {
+    int n16[3], n32[3], n64[3];
+    int64_t w16, words;
+    int64_t b32, bytes;
+};
+__host__ __device__ inline CellFlagLayout cell_flag_layout(const int *nb) {
+    CellFlagLayout c;
+    int64_t tb = 1, t16 = 1, t32 = 1, t64 = 1;
+    for (int k = 0; k < 3; ++k) {
+        c.n16[k] = (nb[k] + 1) / 2;
+        c.n32[k] = (nb[k] + 3) / 4;
+        c.n64[k] = (nb[k] + 7) / 8;
+        tb *= nb[k];
+        t16 *= c.n16[k];
+        t32 *= c.n32[k];
+        t64 *= c.n64[k];
+    }
+    c.w16 = (tb + 31) / 32;
+    c.words = c.w16 + (t16 + 31) / 32;
+    c.b32 = t64;
+    c.bytes = t64 + t32;
+    return c;
+}
 
 // Event-pair profiler (host side); disabled unless vrt_profile_enable.
 struct Profiler {

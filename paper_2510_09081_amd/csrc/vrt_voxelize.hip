@@ -22,16 +22,22 @@ __global__ void k_clear_prev(uint32_t *__restrict__ words, const int32_t *__rest
 
 // Clears the per-frame brick-level state: level-3 occupancy, blocking flags
 // of bricks and 64^3 cells, the blocking box and the frame counters.
+// Threads of the per-frame reset: bricks, flag words and flag bytes.
+__host__ __device__ inline int64_t reset_items(int64_t nb, int64_t nw, int64_t nf) {
+    const int64_t m = nb > nw ? nb : nw;
+    return m > nf ? m : nf;
+}
+
 __device__ __forceinline__ void b_reset(uint16_t *__restrict__ occ3, uint32_t *__restrict__ bin_count,
-                        uint32_t *__restrict__ brick_bits, int64_t nbricks,
-                        uint8_t *__restrict__ super_blk, int64_t nsupers, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
+                        uint32_t *__restrict__ brick_bits, int64_t nbricks, int64_t nwords,
+                        uint8_t *__restrict__ super_blk, int64_t nflags, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
     int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     if (i < nbricks) {
         occ3[i] = 0;
         bin_count[i] = 0u;
     }
-    if (i < (nbricks + 31) / 32) brick_bits[i] = 0u;
-    if (i < nsupers) super_blk[i] = 0;
+    if (i < nwords) brick_bits[i] = 0u;
+    if (i < nflags) super_blk[i] = 0;
     if (i == 0) {
         st->n_fragments = 0;
         st->n_cand = 0;
@@ -50,8 +56,9 @@ __device__ __forceinline__ void b_reset(uint16_t *__restrict__ occ3, uint32_t *_
 }
 
 __global__ void k_reset(uint16_t *__restrict__ occ3, uint32_t *__restrict__ bin_count, uint32_t *__restrict__ brick_bits,
-                        int64_t nbricks, uint8_t *__restrict__ super_blk, int64_t nsupers, DevStatus *__restrict__ st) {
-    b_reset(occ3, bin_count, brick_bits, nbricks, super_blk, nsupers, st, blockIdx.x, gridDim.x);
+                        int64_t nbricks, int64_t nwords, uint8_t *__restrict__ super_blk, int64_t nflags,
+                        DevStatus *__restrict__ st) {
+    b_reset(occ3, bin_count, brick_bits, nbricks, nwords, super_blk, nflags, st, blockIdx.x, gridDim.x);
 }
 
 // fixed-point coordinate: rint((x - origin) * s) as two binary32 operations
@@ -746,7 +753,11 @@ __device__ __forceinline__ void b_erode(GridArgs g, const uint16_t *__restrict__
             for (int Z = 0; Z < 4; ++Z) cells |= (uint64_t)(m2[2 * Z] | m2[2 * Z + 1]) << (16 * Z);
             blk_bits[b * 16 + 8] = cells;
             atomicOr(&brick_bits[b >> 5], 1u << (b & 31));
+            const CellFlagLayout cl = cell_flag_layout(g.nb);
+            const int64_t c16 = ((int64_t)(bz >> 1) * cl.n16[1] + (by >> 1)) * cl.n16[0] + (bx >> 1);
+            atomicOr(&brick_bits[cl.w16 + (c16 >> 5)], 1u << (c16 & 31));
             super_blk[((int64_t)(bz >> 3) * g.ns[1] + (by >> 3)) * g.ns[0] + (bx >> 3)] = 1;
+            super_blk[cl.b32 + ((int64_t)(bz >> 2) * cl.n32[1] + (by >> 2)) * cl.n32[0] + (bx >> 2)] = 1;
             int *p = st->stripe[bid_ % kStripes].bbox;
             atomicMin(&p[0], bb[0]); atomicMin(&p[1], bb[1]); atomicMin(&p[2], bb[2]);
             atomicMax(&p[3], bb[3]); atomicMax(&p[4], bb[4]); atomicMax(&p[5], bb[5]);
@@ -784,6 +795,7 @@ __global__ void k_mip_avg(const uint16_t *__restrict__ src, int sx, int sy, int 
 // Arguments of every voxelization kernel for one frame of context c.
 struct VoxPlan {
     int64_t nb, ns, nv;
+    int64_t nw, nf;  // words of the brick and 16^3 cell bits, bytes of the 64^3 and 32^3 cell flags
     bool fp16;
     GridArgs g;
     IngestArgs ia;
@@ -802,6 +814,9 @@ static VoxPlan make_vox_plan(const vrt_ctx *c, const vrt_lines *L, float s_q) {
     }
     p.nb = (int64_t)p.g.nb[0] * p.g.nb[1] * p.g.nb[2];
     p.ns = (int64_t)p.g.ns[0] * p.g.ns[1] * p.g.ns[2];
+    const CellFlagLayout cl = cell_flag_layout(p.g.nb);
+    p.nw = cl.words;
+    p.nf = cl.bytes;
     p.nv = L->n_vertices;
     p.fp16 = c->desc.form == VRT_FORM_FP16;
     p.ia.xyz = L->xyz;
@@ -852,8 +867,8 @@ hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *L, float s_q, hipStream_
     const unsigned eb = (unsigned)((p.nv + 255) / 256);
     VRT_LAUNCH(c, "k_clear_prev", st, k_clear_prev<<<2048, 128, 0, st>>>(A.words, A.brick_list, A.status));
     VRT_LAUNCH(c, "k_reset", st,
-               k_reset<<<(unsigned)((p.nb + 255) / 256), 256, 0, st>>>(A.occ3, A.bin_count, A.brick_bits, p.nb,
-                                                                       A.super_blk, p.ns, A.status));
+               k_reset<<<(unsigned)((reset_items(p.nb, p.nw, p.nf) + 255) / 256), 256, 0, st>>>(
+                   A.occ3, A.bin_count, A.brick_bits, p.nb, p.nw, A.super_blk, p.nf, A.status));
     VRT_LAUNCH(c, "k_ingest", st, k_ingest<<<eb, 256, 0, st>>>(p.ia, A.vrec, A.status));
     if (p.fp16) VRT_LAUNCH(c, "k_pack16", st, k_pack16<<<eb, 256, 0, st>>>(A.vrec, p.nv, A.srec16));
     VRT_LAUNCH(c, "k_bin_count", st, k_bin_count<<<eb, 256, 0, st>>>(p.ba, A.status));
