@@ -35,6 +35,7 @@ struct SetDesc {
     int64_t capacity;
     int n_levels;
     Level levels[kMaxLevels];
+    int64_t n_hi;  // elements of the levels >= 4
     unsigned march_blocks;
     int fp16;
 };
@@ -53,11 +54,11 @@ __device__ unsigned part_blocks(int ph, int part, const SetDesc &d) {
     case P_OCC: return part == 0 ? st->n_bricks : 0u;
     case P_ERODE:
         if (part == 0) return st->n_bricks;
-        if (part == 1) return d.n_levels > 4 ? 1u : 0u;
-        return cdiv(d.cp.nb, T);
-    case P_WALK: return part == 0 && d.cp.limit >= 0 ? cdiv(st->n_occ, T) : 0u;
+        if (part == 1) return d.n_levels > 4 ? mip_tree_regions(d.levels) : 0u;
+        return cdiv(d.cp.nb > d.n_hi ? d.cp.nb : d.n_hi, T);
+    case P_WALK: return part == 0 ? (d.cp.limit >= 0 ? cdiv(st->n_occ, T) : 0u) : (part == 1 && d.n_levels > 8 ? 1u : 0u);
     case P_CBRICK: return part == 0 ? st->n_bricks : 0u;
-    case P_SCAN: return part == 0 ? (d.n_levels > 4 ? 1u : 0u) : (part == 1 ? 1u : 0u);
+    case P_SCAN: return part == 0 ? 1u : 0u;
     case P_OFFSETS: return part == 0 ? st->n_bricks : 0u;
     case P_SCATTER: return part == 0 ? cdiv(d.cp.nv, T) : (part == 1 ? 1u : 0u);
     case P_MARCH: return part == 0 ? d.march_blocks : 0u;
@@ -66,41 +67,7 @@ __device__ unsigned part_blocks(int ph, int part, const SetDesc &d) {
     }
 }
 
-// Occupancy levels >= 4 by one block, level after level.
-__device__ void mip_avg_chain(const SetDesc &d) {
-    const uint16_t *src = d.a.occ3;
-    int sx = d.vp.g.nb[0], sy = d.vp.g.nb[1], sz = d.vp.g.nb[2];
-    for (int L = 4; L < d.n_levels; ++L) {
-        const Level &lv = d.levels[L];
-        uint16_t *dst = d.a.occ_hi + lv.offset;
-        const int64_t n = (int64_t)lv.dims[0] * lv.dims[1] * lv.dims[2];
-        for (unsigned vb = 0; (int64_t)vb * blockDim.x < n; ++vb)
-            b_mip_avg(src, sx, sy, sz, dst, lv.dims[0], lv.dims[1], lv.dims[2], vb, 0u);
-        __syncthreads();
-        src = dst;
-        sx = lv.dims[0];
-        sy = lv.dims[1];
-        sz = lv.dims[2];
-    }
-}
 
-// Culling levels >= 4 by one block, level after level.
-__device__ void mip_or_chain(const SetDesc &d) {
-    const uint8_t *src = d.a.vis3;
-    int sx = d.cp.g.nb[0], sy = d.cp.g.nb[1], sz = d.cp.g.nb[2];
-    for (int L = 4; L < d.n_levels; ++L) {
-        const Level &lv = d.levels[L];
-        uint8_t *dst = d.a.vis_hi + lv.offset;
-        const int64_t n = (int64_t)lv.dims[0] * lv.dims[1] * lv.dims[2];
-        for (unsigned vb = 0; (int64_t)vb * blockDim.x < n; ++vb)
-            b_mip_or(src, sx, sy, sz, dst, lv.dims[0], lv.dims[1], lv.dims[2], vb, 0u);
-        __syncthreads();
-        src = dst;
-        sx = lv.dims[0];
-        sy = lv.dims[1];
-        sz = lv.dims[2];
-    }
-}
 
 // Virtual block vb of nvb of stage `part` of phase `ph` for set d.
 __device__ __forceinline__ void run_part(int ph, int part, const SetDesc &d, unsigned vb, unsigned nvb) {
@@ -121,18 +88,18 @@ __device__ __forceinline__ void run_part(int ph, int part, const SetDesc &d, uns
         if (part == 0)
             b_erode(d.vp.g, A.occ0, A.brick_list, A.brick_slot, A.status, A.blk, A.blk_bits, A.brick_bits, A.super_blk,
                     vb, nvb);
-        else if (part == 1) mip_avg_chain(d);
-        else b_cull_reset(A.vis3, d.cp.nb, A.status, vb, nvb);
+        else if (part == 1) b_mip_avg_tree(A.occ3, d.vp.g.nb, A.occ_hi, d.levels, d.n_levels, vb);
+        else b_cull_reset(A.vis3, d.cp.nb, A.vis_hi, d.n_hi, A.status, vb, nvb);
         break;
-    case P_WALK: b_cull_walk<false>(d.cp.ca, d.cp.cells, A.occ_list, A.status, A.vis0, vb, nvb); break;
+    case P_WALK:
+        if (part == 0) b_cull_walk<false>(d.cp.ca, d.cp.cells, A.occ_list, A.status, A.vis0, vb, nvb);
+        else b_mip_avg_top(A.occ_hi, d.levels, d.n_levels);
+        break;
     case P_CBRICK:
-        b_cull_brick(d.cp.limit, d.cp.g, A.words, A.brick_list, A.status, A.vis0, A.vis1, A.vis2, A.vis3,
-                     A.brick_total, vb, nvb);
+        b_cull_brick(d.cp.limit, d.cp.g, A.words, A.brick_list, A.status, A.vis0, A.vis1, A.vis2, A.vis3, A.vis_hi,
+                     d.levels, d.n_levels, A.brick_total, vb, nvb);
         break;
-    case P_SCAN:
-        if (part == 0) mip_or_chain(d);
-        else b_scan_bricks(A.brick_total, A.brick_base, A.status, d.capacity, 0u, 1u);
-        break;
+    case P_SCAN: b_scan_bricks(A.brick_total, A.brick_base, A.status, d.capacity, A.vis_hi, d.levels, d.n_levels, 0u, 1u); break;
     case P_OFFSETS: b_list_offsets(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor, A.cell, vb, nvb); break;
     case P_SCATTER:
         if (part == 0) b_scatter(d.cp.sa, vb, nvb);
@@ -335,6 +302,7 @@ vrt_status vrt_batch_run(vrt_batch *b, const vrt_batch_item *items, int32_t n, i
         d.capacity = c->desc.max_fragments;
         d.n_levels = c->n_levels;
         for (int L = 0; L < kMaxLevels; ++L) d.levels[L] = c->levels[L];
+        d.n_hi = hi_used(c);
         d.march_blocks = (unsigned)(((tp[i].W + 15) / 16) *
                                     ((tp[i].H + march_tile_rows(kBatchThreads) - 1) / march_tile_rows(kBatchThreads)));
         d.fp16 = c->desc.form == VRT_FORM_FP16;

@@ -8,9 +8,11 @@
 namespace vrt {
 namespace {
 
-__device__ __forceinline__ void b_cull_reset(uint8_t *__restrict__ vis3, int64_t nb, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
+__device__ __forceinline__ void b_cull_reset(uint8_t *__restrict__ vis3, int64_t nb, uint8_t *__restrict__ vis_hi,
+                                             int64_t n_hi, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
     int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     if (i < nb) vis3[i] = 0;
+    if (i < n_hi) vis_hi[i] = 0;
     if (i == 0) st->n_listed = 0;
     if (i < kStripes) {
         int *p = st->stripe[i].vbox;
@@ -19,7 +21,10 @@ __device__ __forceinline__ void b_cull_reset(uint8_t *__restrict__ vis3, int64_t
     }
 }
 
-__global__ void k_cull_reset(uint8_t *__restrict__ vis3, int64_t nb, DevStatus *__restrict__ st) { b_cull_reset(vis3, nb, st, blockIdx.x, gridDim.x); }
+__global__ void k_cull_reset(uint8_t *__restrict__ vis3, int64_t nb, uint8_t *__restrict__ vis_hi, int64_t n_hi,
+                             DevStatus *__restrict__ st) {
+    b_cull_reset(vis3, nb, vis_hi, n_hi, st, blockIdx.x, gridDim.x);
+}
 
 // Blocking flags the culling walk reads: one byte per 64^3 and 32^3 cell, one
 // bit per 16^3 cell and brick, and per brick holding a blocker one bit per
@@ -124,11 +129,16 @@ __global__ void __launch_bounds__(512) k_cull_walk(CullArgs a, CullCells cells, 
 // One workgroup per occupied brick: final level-0 visibility (unoccupied
 // voxels are invisible; without culling every occupied voxel is visible), the
 // in-brick culling mips 1..3 (parent = OR of children), and the brick's
-// visible-fragment total.
+// visible-fragment total.  The coarser culling levels are ORs too: a visible
+// brick sets its cell on levels 4 .. kMarkTop (cleared by the reset); the few
+// cells above are left to the brick scan.
+constexpr int kMarkTop = 6;  // highest culling level set brick by brick
+
 __device__ __forceinline__ void b_cull_brick(int limit, GridArgs g, const uint32_t *__restrict__ words,
                                                     const int32_t *__restrict__ list, DevStatus *__restrict__ st,
                                                     uint8_t *__restrict__ vis0, uint8_t *__restrict__ vis1,
                                                     uint8_t *__restrict__ vis2, uint8_t *__restrict__ vis3,
+                                                    uint8_t *__restrict__ vis_hi, const Level *levels, int n_levels,
                                                     uint32_t *__restrict__ brick_total, unsigned bid_, unsigned nblk_) {
     __shared__ uint8_t s0[512];
     __shared__ uint8_t s1[64];
@@ -178,6 +188,11 @@ __device__ __forceinline__ void b_cull_brick(int limit, GridArgs g, const uint32
                 int *p = st->stripe[bid_ % kStripes].vbox;
                 atomicMin(&p[0], bx); atomicMin(&p[1], by); atomicMin(&p[2], bz);
                 atomicMax(&p[3], bx); atomicMax(&p[4], by); atomicMax(&p[5], bz);
+                for (int L = 4; L < n_levels && L <= kMarkTop; ++L) {
+                    const int s = L - 3;
+                    const Level &lv = levels[L];
+                    vis_hi[lv.offset + ((int64_t)(bz >> s) * lv.dims[1] + (by >> s)) * lv.dims[0] + (bx >> s)] = 1;
+                }
             }
         }
         __syncthreads();
@@ -188,28 +203,45 @@ __global__ void __launch_bounds__(512) k_cull_brick(int limit, GridArgs g, const
                                                     const int32_t *__restrict__ list, DevStatus *__restrict__ st,
                                                     uint8_t *__restrict__ vis0, uint8_t *__restrict__ vis1,
                                                     uint8_t *__restrict__ vis2, uint8_t *__restrict__ vis3,
-                                                    uint32_t *__restrict__ brick_total) { b_cull_brick(limit, g, words, list, st, vis0, vis1, vis2, vis3, brick_total, blockIdx.x, gridDim.x); }
-
-__device__ __forceinline__ void b_mip_or(const uint8_t *__restrict__ src, int sx, int sy, int sz, uint8_t *__restrict__ dst, int dx,
-                         int dy, int dz, unsigned bid_, unsigned nblk_) {
-    int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)dx * dy * dz) return;
-    int x = (int)(i % dx), y = (int)((i / dx) % dy), z = (int)(i / ((int64_t)dx * dy));
-    uint8_t o = 0;
-    for (int k = 0; k < 8; ++k) {
-        int cx = 2 * x + (k & 1), cy = 2 * y + ((k >> 1) & 1), cz = 2 * z + (k >> 2);
-        if (cx < sx && cy < sy && cz < sz) o |= src[((int64_t)cz * sy + cy) * sx + cx];
-    }
-    dst[i] = o;
+                                                    uint8_t *__restrict__ vis_hi, LevelChain ch,
+                                                    uint32_t *__restrict__ brick_total) {
+    b_cull_brick(limit, g, words, list, st, vis0, vis1, vis2, vis3, vis_hi, ch.lv, ch.n, brick_total, blockIdx.x,
+                 gridDim.x);
 }
 
-__global__ void k_mip_or(const uint8_t *__restrict__ src, int sx, int sy, int sz, uint8_t *__restrict__ dst, int dx,
-                         int dy, int dz) { b_mip_or(src, sx, sy, sz, dst, dx, dy, dz, blockIdx.x, gridDim.x); }
+// Culling levels L0, L0 + 1, ... from level L0 - 1 (src, sx x sy x sz) by one
+// block, level after level: parent = OR of its children inside the grid.
+__device__ void mip_or_levels(int L0, const uint8_t *src, int sx, int sy, int sz, uint8_t *hi, const Level *levels,
+                              int n_levels) {
+    for (int L = L0; L < n_levels; ++L) {
+        const Level &lv = levels[L];
+        uint8_t *dst = hi + lv.offset;
+        const int64_t n = (int64_t)lv.dims[0] * lv.dims[1] * lv.dims[2];
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const int x = (int)(i % lv.dims[0]), y = (int)((i / lv.dims[0]) % lv.dims[1]);
+            const int z = (int)(i / ((int64_t)lv.dims[0] * lv.dims[1]));
+            uint8_t o = 0;
+            for (int k = 0; k < 8; ++k) {
+                const int cx = 2 * x + (k & 1), cy = 2 * y + ((k >> 1) & 1), cz = 2 * z + (k >> 2);
+                if (cx < sx && cy < sy && cz < sz) o |= src[((int64_t)cz * sy + cy) * sx + cx];
+            }
+            dst[i] = o;
+        }
+        __syncthreads();
+        src = dst;
+        sx = lv.dims[0];
+        sy = lv.dims[1];
+        sz = lv.dims[2];
+    }
+}
 
 // Single workgroup: exclusive scan of the per-brick visible totals in
-// ascending brick order; the grand total is the number of listed fragments.
+// ascending brick order (the grand total is the number of listed fragments),
+// then the culling levels above kMarkTop.
 __device__ __forceinline__ void b_scan_bricks(const uint32_t *__restrict__ tot, uint32_t *__restrict__ base,
-                                                      DevStatus *__restrict__ st, int64_t capacity, unsigned bid_, unsigned nblk_) {
+                                                      DevStatus *__restrict__ st, int64_t capacity,
+                                                      uint8_t *__restrict__ vis_hi, const Level *levels, int n_levels,
+                                                      unsigned bid_, unsigned nblk_) {
     __shared__ unsigned long long wt[16];
     __shared__ unsigned long long carry;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -238,10 +270,17 @@ __device__ __forceinline__ void b_scan_bricks(const uint32_t *__restrict__ tot, 
         st->n_listed = carry;
         if ((long long)carry > capacity) atomicOr(&st->err, kErrCapacity);
     }
+    if (n_levels > kMarkTop + 1) {
+        const Level &l = levels[kMarkTop];
+        mip_or_levels(kMarkTop + 1, vis_hi + l.offset, l.dims[0], l.dims[1], l.dims[2], vis_hi, levels, n_levels);
+    }
 }
 
 __global__ void __launch_bounds__(1024) k_scan_bricks(const uint32_t *__restrict__ tot, uint32_t *__restrict__ base,
-                                                      DevStatus *__restrict__ st, int64_t capacity) { b_scan_bricks(tot, base, st, capacity, blockIdx.x, gridDim.x); }
+                                                      DevStatus *__restrict__ st, int64_t capacity,
+                                                      uint8_t *__restrict__ vis_hi, LevelChain ch) {
+    b_scan_bricks(tot, base, st, capacity, vis_hi, ch.lv, ch.n, blockIdx.x, gridDim.x);
+}
 
 // One workgroup per occupied brick: list start of every voxel = brick base +
 // exclusive prefix of visible counts inside the brick (x fastest).
@@ -468,8 +507,13 @@ static CullPlan make_cull_plan(const vrt_ctx *c, const int64_t E[3], int64_t lim
 hipError_t launch_cull(vrt_ctx *c, const int64_t E[3], int64_t limit, hipStream_t st) {
     Arenas &A = c->a;
     const CullPlan p = make_cull_plan(c, E, limit);
+    LevelChain ch;
+    ch.n = c->n_levels;
+    for (int L = 0; L < kMaxLevels; ++L) ch.lv[L] = c->levels[L];
+    const int64_t n_hi = hi_used(c);
     VRT_LAUNCH(c, "k_cull_reset", st,
-               k_cull_reset<<<(unsigned)((p.nb + 255) / 256), 256, 0, st>>>(A.vis3, p.nb, A.status));
+               k_cull_reset<<<(unsigned)(((p.nb > n_hi ? p.nb : n_hi) + 255) / 256), 256, 0, st>>>(A.vis3, p.nb, A.vis_hi,
+                                                                                              n_hi, A.status));
     if (p.limit >= 0) {
         const size_t lds = cull_lds_bytes(p.nw, p.nf);
         if (lds <= kCullLdsMax)
@@ -481,23 +525,10 @@ hipError_t launch_cull(vrt_ctx *c, const int64_t E[3], int64_t limit, hipStream_
     }
     VRT_LAUNCH(c, "k_cull_brick", st,
                k_cull_brick<<<4096, 512, 0, st>>>(p.limit, p.g, A.words, A.brick_list, A.status, A.vis0, A.vis1, A.vis2,
-                                                  A.vis3, A.brick_total));
-    const uint8_t *src = A.vis3;
-    int sx = p.g.nb[0], sy = p.g.nb[1], sz = p.g.nb[2];
-    for (int L = 4; L < c->n_levels; ++L) {
-        const Level &lv = c->levels[L];
-        uint8_t *dst = A.vis_hi + lv.offset;
-        const int64_t n = (int64_t)lv.dims[0] * lv.dims[1] * lv.dims[2];
-        VRT_LAUNCH(c, "k_mip_or", st,
-                   k_mip_or<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, sx, sy, sz, dst, lv.dims[0], lv.dims[1],
-                                                                         lv.dims[2]));
-        src = dst;
-        sx = lv.dims[0];
-        sy = lv.dims[1];
-        sz = lv.dims[2];
-    }
+                                                  A.vis3, A.vis_hi, ch, A.brick_total));
     VRT_LAUNCH(c, "k_scan_bricks", st,
-               k_scan_bricks<<<1, 1024, 0, st>>>(A.brick_total, A.brick_base, A.status, c->desc.max_fragments));
+               k_scan_bricks<<<1, 1024, 0, st>>>(A.brick_total, A.brick_base, A.status, c->desc.max_fragments, A.vis_hi,
+                                                 ch));
     VRT_LAUNCH(c, "k_list_offsets", st,
                k_list_offsets<<<4096, 512, 0, st>>>(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor,
                                                     A.cell));

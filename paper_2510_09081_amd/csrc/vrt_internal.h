@@ -172,6 +172,12 @@ struct Level {
     int64_t offset;  // element offset into occ_hi / vis_hi (levels >= 4)
 };
 
+// The level table, passed to kernels by value.
+struct LevelChain {
+    int n;
+    Level lv[kMaxLevels];
+};
+
 }  // namespace vrt
 
 struct vrt_ctx {
@@ -193,6 +199,15 @@ struct vrt_ctx {
     vrt::Profiler prof;
     vrt_tune tune[2] = {{256, 16, 2, 4, 4096, {0, 0, 0}}, {256, 16, 2, 4, 4096, {0, 0, 0}}};  // per trace mode
 };
+
+namespace vrt {
+// Elements of occ_hi / vis_hi that the current grid's levels >= 4 use.
+inline int64_t hi_used(const vrt_ctx *c) {
+    if (c->n_levels <= 4) return 0;
+    const Level &l = c->levels[c->n_levels - 1];
+    return l.offset + (int64_t)l.dims[0] * l.dims[1] * l.dims[2];
+}
+}  // namespace vrt
 
 namespace vrt {
 

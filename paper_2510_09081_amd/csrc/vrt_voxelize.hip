@@ -787,8 +787,96 @@ __device__ __forceinline__ void b_mip_avg(const uint16_t *__restrict__ src, int 
     dst[i] = (uint16_t)((s + 4u) >> 3);
 }
 
-__global__ void k_mip_avg(const uint16_t *__restrict__ src, int sx, int sy, int sz, uint16_t *__restrict__ dst, int dx,
-                          int dy, int dz) { b_mip_avg(src, sx, sy, sz, dst, dx, dy, dz, blockIdx.x, gridDim.x); }
+// Occupancy levels L0, L0 + 1, ... from level L0 - 1 (src, sx x sy x sz), by
+// one block, level after level.
+__device__ void mip_avg_levels(int L0, const uint16_t *src, int sx, int sy, int sz, uint16_t *hi,
+                               const Level *levels, int n_levels) {
+    for (int L = L0; L < n_levels; ++L) {
+        const Level &lv = levels[L];
+        uint16_t *dst = hi + lv.offset;
+        const int64_t n = (int64_t)lv.dims[0] * lv.dims[1] * lv.dims[2];
+        for (unsigned vb = 0; (int64_t)vb * blockDim.x < n; ++vb)
+            b_mip_avg(src, sx, sy, sz, dst, lv.dims[0], lv.dims[1], lv.dims[2], vb, 0u);
+        __syncthreads();
+        src = dst;
+        sx = lv.dims[0];
+        sy = lv.dims[1];
+        sz = lv.dims[2];
+    }
+}
+
+// Regions of the occupancy tree: one per 8^3 cells of level 4.
+__host__ __device__ inline unsigned mip_tree_regions(const Level *levels) {
+    const Level &l4 = levels[4];
+    return (unsigned)(((l4.dims[0] + 7) / 8) * ((l4.dims[1] + 7) / 8) * ((l4.dims[2] + 7) / 8));
+}
+
+// Occupancy levels 4..7 from the dense level 3 (nb bricks per axis).  Block
+// vb (of mip_tree_regions) takes an 8^3 region of level 4 and averages it up
+// to level 7 in LDS: the regions of level 4 + k are aligned (8 >> k)^3 blocks
+// of cells, so every parent's children lie in its block.  Levels above 7 are
+// left to mip_avg_levels.
+__device__ void b_mip_avg_tree(const uint16_t *__restrict__ occ3, const int *nb, uint16_t *__restrict__ hi,
+                               const Level *levels, int n_levels, unsigned vb) {
+    __shared__ uint16_t s[512 + 64 + 8];
+    const Level &l4 = levels[4];
+    const int nrx = (l4.dims[0] + 7) / 8, nry = (l4.dims[1] + 7) / 8;
+    const int ox = (int)(vb % nrx), oy = (int)((vb / nrx) % nry), oz = (int)(vb / ((unsigned)nrx * nry));
+    for (int t = threadIdx.x; t < 512; t += blockDim.x) {
+        const int x = ox * 8 + (t & 7), y = oy * 8 + ((t >> 3) & 7), z = oz * 8 + (t >> 6);
+        unsigned v = 0;
+        if (x < l4.dims[0] && y < l4.dims[1] && z < l4.dims[2]) {
+            unsigned sum = 0;
+            for (int k = 0; k < 8; ++k) {
+                const int cx = 2 * x + (k & 1), cy = 2 * y + ((k >> 1) & 1), cz = 2 * z + (k >> 2);
+                if (cx < nb[0] && cy < nb[1] && cz < nb[2]) sum += occ3[((int64_t)cz * nb[1] + cy) * nb[0] + cx];
+            }
+            v = (sum + 4u) >> 3;
+            hi[l4.offset + ((int64_t)z * l4.dims[1] + y) * l4.dims[0] + x] = (uint16_t)v;
+        }
+        s[t] = (uint16_t)v;
+    }
+    __syncthreads();
+    int in = 0, out = 512;  // LDS offsets of the child and parent cells
+    for (int k = 1; k <= 3 && 4 + k < n_levels; ++k) {
+        const int m = 8 >> k, cm = 2 * m;  // cells per region axis: parent, child
+        const Level &lc = levels[3 + k], &lv = levels[4 + k];
+        for (int t = threadIdx.x; t < m * m * m; t += blockDim.x) {
+            const int lx = t % m, ly = (t / m) % m, lz = t / (m * m);
+            const int x = ox * m + lx, y = oy * m + ly, z = oz * m + lz;
+            unsigned v = 0;
+            if (x < lv.dims[0] && y < lv.dims[1] && z < lv.dims[2]) {
+                unsigned sum = 0;
+                for (int c = 0; c < 8; ++c) {
+                    const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+                    if (2 * x + dx < lc.dims[0] && 2 * y + dy < lc.dims[1] && 2 * z + dz < lc.dims[2])
+                        sum += s[in + ((2 * lz + dz) * cm + (2 * ly + dy)) * cm + 2 * lx + dx];
+                }
+                v = (sum + 4u) >> 3;
+                hi[lv.offset + ((int64_t)z * lv.dims[1] + y) * lv.dims[0] + x] = (uint16_t)v;
+            }
+            s[out + t] = (uint16_t)v;
+        }
+        __syncthreads();
+        in = out;
+        out += m * m * m;
+    }
+}
+
+__global__ void __launch_bounds__(512) k_mip_avg_tree(const uint16_t *__restrict__ occ3, GridArgs g,
+                                                      uint16_t *__restrict__ hi, LevelChain ch) {
+    b_mip_avg_tree(occ3, g.nb, hi, ch.lv, ch.n, blockIdx.x);
+}
+
+// Occupancy levels above 7, from level 7, by one block.
+__device__ void b_mip_avg_top(uint16_t *__restrict__ hi, const Level *levels, int n_levels) {
+    const Level &l7 = levels[7];
+    mip_avg_levels(8, hi + l7.offset, l7.dims[0], l7.dims[1], l7.dims[2], hi, levels, n_levels);
+}
+
+__global__ void __launch_bounds__(1024) k_mip_avg_top(uint16_t *__restrict__ hi, LevelChain ch) {
+    b_mip_avg_top(hi, ch.lv, ch.n);
+}
 
 }  // namespace
 
@@ -889,19 +977,13 @@ hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *L, float s_q, hipStream_
                k_erode<<<4096, 512, 0, st>>>(p.g, A.occ0, A.brick_list, A.brick_slot, A.status, A.blk, A.blk_bits,
                                              A.brick_bits, A.super_blk));
     // levels >= 4 from the dense level 3
-    const uint16_t *src = A.occ3;
-    int sx = p.g.nb[0], sy = p.g.nb[1], sz = p.g.nb[2];
-    for (int L4 = 4; L4 < c->n_levels; ++L4) {
-        const Level &lv = c->levels[L4];
-        uint16_t *dst = A.occ_hi + lv.offset;
-        const int64_t n = (int64_t)lv.dims[0] * lv.dims[1] * lv.dims[2];
-        VRT_LAUNCH(c, "k_mip_avg", st,
-                   k_mip_avg<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, sx, sy, sz, dst, lv.dims[0], lv.dims[1],
-                                                                          lv.dims[2]));
-        src = dst;
-        sx = lv.dims[0];
-        sy = lv.dims[1];
-        sz = lv.dims[2];
+    if (c->n_levels > 4) {
+        LevelChain ch;
+        ch.n = c->n_levels;
+        for (int L = 0; L < kMaxLevels; ++L) ch.lv[L] = c->levels[L];
+        VRT_LAUNCH(c, "k_mip_avg_tree", st,
+                   k_mip_avg_tree<<<mip_tree_regions(ch.lv), 512, 0, st>>>(A.occ3, p.g, A.occ_hi, ch));
+        if (c->n_levels > 8) VRT_LAUNCH(c, "k_mip_avg_top", st, k_mip_avg_top<<<1, 1024, 0, st>>>(A.occ_hi, ch));
     }
     return hipGetLastError();
 }
