@@ -289,7 +289,8 @@ __device__ __forceinline__ void b_list_offsets(const uint32_t *__restrict__ word
                                                       const int32_t *__restrict__ list,
                                                       const uint32_t *__restrict__ base,
                                                       const DevStatus *__restrict__ st,
-                                                      uint32_t *__restrict__ cursor, uint64_t *__restrict__ cell, unsigned bid_, unsigned nblk_) {
+                                                      uint32_t *__restrict__ cursor, uint64_t *__restrict__ cell,
+                                                      uint64_t *__restrict__ lmask, unsigned bid_, unsigned nblk_) {
     __shared__ unsigned wt[8];
     const unsigned nbk = st->n_bricks;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -308,6 +309,8 @@ __device__ __forceinline__ void b_list_offsets(const uint32_t *__restrict__ word
         const uint32_t start = base[sl] + wb + incl - c;
         cursor[b * kBrickVox + t] = start;
         cell[b * kBrickVox + t] = (uint64_t)start | ((uint64_t)c << 32);
+        const unsigned long long nonempty = __ballot(c != 0u);  // the wave holds local voxels 64w .. 64w + 63
+        if (lane == 0) lmask[b * 8 + w] = nonempty;
         __syncthreads();
     }
 }
@@ -317,7 +320,10 @@ __global__ void __launch_bounds__(512) k_list_offsets(const uint32_t *__restrict
                                                       const int32_t *__restrict__ list,
                                                       const uint32_t *__restrict__ base,
                                                       const DevStatus *__restrict__ st,
-                                                      uint32_t *__restrict__ cursor, uint64_t *__restrict__ cell) { b_list_offsets(words, vis0, list, base, st, cursor, cell, blockIdx.x, gridDim.x); }
+                                                      uint32_t *__restrict__ cursor, uint64_t *__restrict__ cell,
+                                                      uint64_t *__restrict__ lmask) {
+    b_list_offsets(words, vis0, list, base, st, cursor, cell, lmask, blockIdx.x, gridDim.x);
+}
 
 struct ScatterArgs {
     const VRec *vrec;
@@ -531,7 +537,7 @@ hipError_t launch_cull(vrt_ctx *c, const int64_t E[3], int64_t limit, hipStream_
                                                  ch));
     VRT_LAUNCH(c, "k_list_offsets", st,
                k_list_offsets<<<4096, 512, 0, st>>>(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor,
-                                                    A.cell));
+                                                    A.cell, A.lmask));
     VRT_LAUNCH(c, "k_scatter_brick", st, k_scatter_brick<<<kBrickBlocks, 256, 0, st>>>(p.sb, A.status));
     VRT_LAUNCH(c, "k_scatter_long", st, k_scatter_long<<<256, 256, 0, st>>>(p.sb, A.status));
     return hipGetLastError();

@@ -16,6 +16,7 @@ struct ShadeCfg {
     static_assert(G == 8 || G == 16 || G == 32, "group");
 };
 using DefaultShade = ShadeCfg<16, 2, 4>;
+constexpr int kMaxShadeGroups = 64;  // groups per block: at most 512 threads of 8-lane groups
 
 // Primary ray through the centre of pixel (px, py), row 0 at the top, as a
 // fixed binary32 sequence (no contraction): u = 2(x + .5)/W - 1,
@@ -104,6 +105,7 @@ struct TraceArgs {
     const uint8_t *vis6;      // culling level 6, or null when the grid has no such level
     const uint8_t *vis3;      // culling level 3 (bricks)
     const uint64_t *cell;     // per voxel: list start | visible count << 32
+    const uint64_t *lmask;    // per brick: voxels with a non-empty list (8 words, z-slice w in word w)
     DevStatus *st;            // visible-brick box, ray-queue length
     const uint32_t *ids;
     const VRec *vrec;
@@ -318,10 +320,41 @@ __device__ __forceinline__ bool step_voxel(const TraceArgs &a, const Ray &r, Wal
     return true;
 }
 
+// The list mask of the brick a walk is in (its z-slice words), held by the
+// walker: in registers (one ray per lane) or in LDS (one ray per group of
+// lanes, which all hold the same values).
+struct MaskRegs {
+    uint64_t m[8];
+    __device__ void set(const uint64_t *src) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) m[k] = src[k];
+    }
+    __device__ uint64_t slice(int z) const {  // selects, not an indexed register read
+        const uint64_t a0 = (z & 1) ? m[1] : m[0], a1 = (z & 1) ? m[3] : m[2];
+        const uint64_t a2 = (z & 1) ? m[5] : m[4], a3 = (z & 1) ? m[7] : m[6];
+        const uint64_t b0 = (z & 2) ? a1 : a0, b1 = (z & 2) ? a3 : a2;
+        return (z & 4) ? b1 : b0;
+    }
+};
+struct MaskLds {
+    uint64_t *p;  // word k at p[k * stride]
+    int stride;
+    __device__ void set(const uint64_t *src) {
+        uint64_t m[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) m[k] = src[k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) p[k * stride] = m[k];
+    }
+    __device__ uint64_t slice(int z) const { return p[(z & 7) * stride]; }
+};
+
 // Advances from the current voxel (included) to the first visible voxel with
-// a non-empty list, skipping empty 64^3 cells and bricks; false if none.
-template <bool kStats>
-__device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w, Counters &cn) {
+// a non-empty list, skipping empty 64^3 cells and bricks; false if none.  In a
+// visible brick, voxels without a list are passed on the brick's list mask,
+// loaded once when the walk enters the brick.
+template <bool kStats, class Mask>
+__device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w, Counters &cn, Mask &mk) {
     const int max_iter = 3 * (a.G[0] + a.G[1] + a.G[2]) + 16;
     for (int it = 0; it < max_iter; ++it) {
         if (!(w.tcur < w.tout)) return false;
@@ -339,6 +372,7 @@ __device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w,
                 w.fresh = true;
                 continue;
             }
+            mk.set(a.lmask + b * 8);
             w.bvis = b;
         }
         if (w.fresh) {
@@ -357,10 +391,13 @@ __device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w,
             tm = w.tnext[2];
         }
         w.texit = fmaxf(tm, w.tcur);
-        w.vi = b * kBrickVox + local_of(w.v[0], w.v[1], w.v[2]);
-        w.cd = a.cell[w.vi];
         if (kStats) ++cn.vox;
-        if (w.cd >> 32) return true;
+        const int l = local_of(w.v[0], w.v[1], w.v[2]);
+        if ((mk.slice(w.v[2]) >> (l & 63)) & 1ull) {
+            w.vi = b * kBrickVox + l;
+            w.cd = a.cell[w.vi];
+            return true;
+        }
         if (!step_voxel(a, r, w)) return false;
     }
     return false;
@@ -612,7 +649,8 @@ __device__ __forceinline__ void b_trace_march(TraceArgs a, unsigned bid_, unsign
             w.v[k] = vk < lo ? lo : (vk > hi ? hi : vk);
         }
         w.fresh = true;
-        found = march<kStats>(a, r, w, cn);
+        MaskRegs mk;
+        found = march<kStats>(a, r, w, cn, mk);
     }
     // one queue append per block (same-address atomics serialize)
     __shared__ unsigned s_wcnt[16];
@@ -650,6 +688,8 @@ __device__ __forceinline__ void b_trace_shade(TraceArgs a, unsigned bid_, unsign
     const unsigned n = a.st->n_queue;
     const unsigned ngroups = nblk_ * (blockDim.x / kGroup);
     const unsigned grp = bid_ * (blockDim.x / kGroup) + threadIdx.x / kGroup;
+    __shared__ uint64_t s_mask[8 * kMaxShadeGroups];  // the list mask of each group's brick
+    MaskLds mk{s_mask + threadIdx.x / kGroup, (int)(blockDim.x / kGroup)};
     // every group runs the same number of rounds so counters can be reduced per wave
     const unsigned rounds = (n + ngroups - 1) / ngroups;
     for (unsigned rd = 0; rd < rounds; ++rd) {
@@ -670,11 +710,11 @@ __device__ __forceinline__ void b_trace_shade(TraceArgs a, unsigned bid_, unsign
             w.fresh = true;
             Counters walk_cn;  // walk counters once per ray
             // recomputes the exit data of the queued voxel
-            bool have = march<kStats>(a, r, w, walk_cn);
+            bool have = march<kStats>(a, r, w, walk_cn, mk);
             while (have) {
                 if (shade_voxel<kStats, kForm, Cfg>(a, r, w, sh, cn, lane)) break;
                 if (!step_voxel(a, r, w)) break;
-                have = march<kStats>(a, r, w, walk_cn);
+                have = march<kStats>(a, r, w, walk_cn, mk);
             }
             if ((lane & (kGroup - 1)) == 0) {
                 write_pixel(a, (int64_t)q.x, sh);
@@ -768,6 +808,7 @@ static TraceArgs trace_args(vrt_ctx *c, const TraceParams &p, const vrt_image *i
         for (int k = 0; k < 3; ++k) a.n6[k] = l6.dims[k];
     }
     a.cell = c->a.cell;
+    a.lmask = c->a.lmask;
     a.st = c->a.status;
     a.ids = c->a.ids;
     a.vrec = c->a.vrec;
