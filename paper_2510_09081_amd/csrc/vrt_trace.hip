@@ -359,16 +359,18 @@ __device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w,
     for (int it = 0; it < max_iter; ++it) {
         if (!(w.tcur < w.tout)) return false;
         const int64_t b = ((int64_t)(w.v[2] >> 3) * a.nb[1] + (w.v[1] >> 3)) * a.nb[0] + (w.v[0] >> 3);
-        if (b != w.bvis) {  // a new brick: its 64^3 cell and its own culling flag
-            if (a.vis6 && !a.vis6[((int64_t)(w.v[2] >> 6) * a.n6[1] + (w.v[1] >> 6)) * a.n6[0] + (w.v[0] >> 6)]) {
-                if (kStats) ++cn.skip64;
-                if (!skip_cell(r, a.G, 64, w.v, w.tcur)) return false;
-                w.fresh = true;
-                continue;
-            }
-            if (!a.vis3[b]) {
-                if (kStats) ++cn.skip8;
-                if (!skip_cell(r, a.G, 8, w.v, w.tcur)) return false;
+        if (b != w.bvis) {  // a new brick: its own culling flag, and its 64^3 cell's
+            // both read at once; a 64^3 cell is visible iff one of its bricks is
+            const uint8_t v3 = a.vis3[b];
+            const uint8_t v6 =
+                a.vis6 ? a.vis6[((int64_t)(w.v[2] >> 6) * a.n6[1] + (w.v[1] >> 6)) * a.n6[0] + (w.v[0] >> 6)] : 1;
+            if (!v3) {
+                const int S = v6 ? 8 : 64;
+                if (kStats) {
+                    if (v6) ++cn.skip8;
+                    else ++cn.skip64;
+                }
+                if (!skip_cell(r, a.G, S, w.v, w.tcur)) return false;
                 w.fresh = true;
                 continue;
             }
