@@ -324,10 +324,15 @@ __device__ __forceinline__ bool step_voxel(const TraceArgs &a, const Ray &r, Wal
 // walker: in registers (one ray per lane) or in LDS (one ray per group of
 // lanes, which all hold the same values).
 struct MaskRegs {
+    static constexpr bool kEarly = false;  // many rays meet invisible bricks: load only for visible ones
     uint64_t m[8];
     __device__ void set(const uint64_t *src) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) m[k] = src[k];
+    }
+    __device__ void put(const uint64_t *v) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) m[k] = v[k];
     }
     __device__ uint64_t slice(int z) const {  // selects, not an indexed register read
         const uint64_t a0 = (z & 1) ? m[1] : m[0], a1 = (z & 1) ? m[3] : m[2];
@@ -337,14 +342,18 @@ struct MaskRegs {
     }
 };
 struct MaskLds {
+    static constexpr bool kEarly = true;  // read beside the culling flags, before they are known
     uint64_t *p;  // word k at p[k * stride]
     int stride;
     __device__ void set(const uint64_t *src) {
         uint64_t m[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) m[k] = src[k];
+        put(m);
+    }
+    __device__ void put(const uint64_t *v) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) p[k * stride] = m[k];
+        for (int k = 0; k < 8; ++k) p[k * stride] = v[k];
     }
     __device__ uint64_t slice(int z) const { return p[(z & 7) * stride]; }
 };
@@ -361,6 +370,11 @@ __device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w,
         const int64_t b = ((int64_t)(w.v[2] >> 3) * a.nb[1] + (w.v[1] >> 3)) * a.nb[0] + (w.v[0] >> 3);
         if (b != w.bvis) {  // a new brick: its own culling flag, and its 64^3 cell's
             // both read at once; a 64^3 cell is visible iff one of its bricks is
+            uint64_t m[8];  // the brick's list mask, read early by walkers that keep it
+            if (Mask::kEarly) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) m[k] = a.lmask[b * 8 + k];
+            }
             const uint8_t v3 = a.vis3[b];
             const uint8_t v6 =
                 a.vis6 ? a.vis6[((int64_t)(w.v[2] >> 6) * a.n6[1] + (w.v[1] >> 6)) * a.n6[0] + (w.v[0] >> 6)] : 1;
@@ -374,7 +388,8 @@ __device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w,
                 w.fresh = true;
                 continue;
             }
-            mk.set(a.lmask + b * 8);
+            if (Mask::kEarly) mk.put(m);
+            else mk.set(a.lmask + b * 8);
             w.bvis = b;
         }
         if (w.fresh) {
