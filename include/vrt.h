@@ -237,7 +237,8 @@ vrt_status vrt_batch_destroy(vrt_batch *b);
  *   shade_group    lanes that share one ray in the shade phase: 8, 16 or 32;
  *   shade_batch    list entries per lane whose records are fetched together: 2 or 4;
  *   lane_keys      transparent hits a lane keeps per pass over a list (k): 4 or 8;
- *   shade_blocks   256-thread blocks of the shade launch: 256 .. 65535.
+ *   shade_blocks   size of the shade launch in units of 256 threads: 256 .. 65535
+ *                  (launched as single-wave workgroups, four per unit).
  * Default {256, 16, 2, 4, 4096}.  The batched forms always use the default. */
 typedef struct {
     int32_t march_threads;

@@ -859,10 +859,12 @@ static unsigned march_grid(const TraceParams &p, int threads) {
 // Launches the shade kernel instance of shape (group, batch, keys).
 template <bool kStats, int kForm>
 static void launch_shade(const vrt_tune &t, const TraceArgs &a, hipStream_t st) {
-    const unsigned blocks = (unsigned)t.shade_blocks;
+    // single-wave workgroups (shade_blocks counts 256 threads): a wave's slot is
+    // free as soon as the wave is done, not when the slowest wave of its block is
+    const unsigned blocks = (unsigned)t.shade_blocks * 4u;
 #define VRT_SHADE_CASE(G, B, K)                                                                  \
     case G * 100 + B * 10 + K:                                                                   \
-        k_trace_shade<kStats, kForm, ShadeCfg<G, B, K>><<<blocks, 256, 0, st>>>(a);              \
+        k_trace_shade<kStats, kForm, ShadeCfg<G, B, K>><<<blocks, 64, 0, st>>>(a);               \
         break;
     switch (t.shade_group * 100 + t.shade_batch * 10 + t.lane_keys) {
         VRT_SHADE_CASE(8, 2, 4) VRT_SHADE_CASE(8, 2, 8) VRT_SHADE_CASE(8, 4, 4) VRT_SHADE_CASE(8, 4, 8)
