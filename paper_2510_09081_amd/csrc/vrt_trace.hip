@@ -101,8 +101,8 @@ struct TraceArgs {
     TraceParams p;
     int G[3];
     int nb[3];
-    int n6[3];                // 64^3 cells per axis (culling level 6)
-    const uint8_t *vis6;      // culling level 6, or null when the grid has no such level
+    int n4[3], n5[3], n6[3];  // 16^3, 32^3 and 64^3 cells per axis (culling levels 4, 5, 6)
+    const uint8_t *vis4, *vis5, *vis6;  // culling levels 4..6, each null when the grid has no such level
     const uint8_t *vis3;      // culling level 3 (bricks)
     const uint64_t *cell;     // per voxel: list start | visible count << 32
     const uint64_t *lmask;    // per brick: voxels with a non-empty list (8 words, z-slice w in word w)
@@ -253,15 +253,22 @@ __device__ __forceinline__ bool clip_visible(const TraceArgs &a, const Ray &r, f
     return tin < tout;
 }
 
-// Crosses the empty S^3 cell holding voxel v: returns false when the ray
-// leaves the grid; else v becomes the voxel entered after the cell's exit
-// face (monotone in the direction of travel, clamped to the cell on the other
-// axes) and tcur the exit parameter.
-__device__ __forceinline__ bool skip_cell(const Ray &r, const int *G, int S, int *v, float &tcur) {
+// Index of the cell of culling level L (2^L voxels a side, n cells per axis)
+// holding voxel v.
+__device__ __forceinline__ int64_t coarse_index(const int *v, int L, const int *n) {
+    return ((int64_t)(v[2] >> L) * n[1] + (v[1] >> L)) * n[0] + (v[0] >> L);
+}
+
+// Crosses the empty S^3 cell (S = 2^sh) holding voxel v: returns false when
+// the ray leaves the grid; else v becomes the voxel entered after the cell's
+// exit face (monotone in the direction of travel, clamped to the cell on the
+// other axes) and tcur the exit parameter.
+__device__ __forceinline__ bool skip_cell(const Ray &r, const int *G, int sh, int *v, float &tcur) {
+    const int S = 1 << sh;
     int cellk[3];
     float tb[3];
     for (int k = 0; k < 3; ++k) {
-        cellk[k] = v[k] >> (S == 64 ? 6 : 3);  // S is 64 or 8, v >= 0
+        cellk[k] = v[k] >> sh;  // v >= 0
         tb[k] = r.step[k] == 0 ? INFINITY : tcross(S * (cellk[k] + (r.step[k] > 0)), r.O[k], r.inv[k]);
     }
     int m = 0;
@@ -376,15 +383,16 @@ __device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w,
                 for (int k = 0; k < 8; ++k) m[k] = a.lmask[b * 8 + k];
             }
             const uint8_t v3 = a.vis3[b];
-            const uint8_t v6 =
-                a.vis6 ? a.vis6[((int64_t)(w.v[2] >> 6) * a.n6[1] + (w.v[1] >> 6)) * a.n6[0] + (w.v[0] >> 6)] : 1;
-            if (!v3) {
-                const int S = v6 ? 8 : 64;
+            const uint8_t v4 = a.vis4 ? a.vis4[coarse_index(w.v, 4, a.n4)] : 1;
+            const uint8_t v5 = a.vis5 ? a.vis5[coarse_index(w.v, 5, a.n5)] : 1;
+            const uint8_t v6 = a.vis6 ? a.vis6[coarse_index(w.v, 6, a.n6)] : 1;
+            if (!v3) {  // the largest invisible cell holding the brick is crossed in one jump
+                const int sh = !v6 ? 6 : (!v5 ? 5 : (!v4 ? 4 : 3));
                 if (kStats) {
-                    if (v6) ++cn.skip8;
-                    else ++cn.skip64;
+                    if (sh == 6) ++cn.skip64;
+                    else ++cn.skip8;
                 }
-                if (!skip_cell(r, a.G, S, w.v, w.tcur)) return false;
+                if (!skip_cell(r, a.G, sh, w.v, w.tcur)) return false;
                 w.fresh = true;
                 continue;
             }
@@ -817,12 +825,16 @@ static TraceArgs trace_args(vrt_ctx *c, const TraceParams &p, const vrt_image *i
         a.nb[k] = c->dims[k] / 8;
     }
     a.vis3 = c->a.vis3;
-    a.vis6 = nullptr;
-    a.n6[0] = a.n6[1] = a.n6[2] = 0;
-    if (c->n_levels > 6) {
-        const Level &l6 = c->levels[6];
-        a.vis6 = c->a.vis_hi + l6.offset;
-        for (int k = 0; k < 3; ++k) a.n6[k] = l6.dims[k];
+    const uint8_t **hv[3] = {&a.vis4, &a.vis5, &a.vis6};
+    int *hn[3] = {a.n4, a.n5, a.n6};
+    for (int L = 4; L <= 6; ++L) {
+        *hv[L - 4] = nullptr;
+        for (int k = 0; k < 3; ++k) hn[L - 4][k] = 0;
+        if (c->n_levels > L) {
+            const Level &l = c->levels[L];
+            *hv[L - 4] = c->a.vis_hi + l.offset;
+            for (int k = 0; k < 3; ++k) hn[L - 4][k] = l.dims[k];
+        }
     }
     a.cell = c->a.cell;
     a.lmask = c->a.lmask;
