@@ -90,15 +90,20 @@ struct IngestArgs {
 // One thread per vertex: polyline lookup by binary search over the offsets,
 // quantization, segment/interior flags and the central-difference clip normal.
 __device__ __forceinline__ void b_ingest(IngestArgs a, VRec *__restrict__ out, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
-    int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
-    if (i >= a.nv) return;
-    if (i == 0 && (a.off[0] != 0 || a.off[a.np] != a.nv)) set_err(st, kErrInvalid);
-    int64_t lo = 0, hi = a.np - 1;  // largest p with off[p] <= i
+    const int64_t i0 = (int64_t)bid_ * blockDim.x;  // the block's first vertex
+    int64_t i = i0 + threadIdx.x;
+    if (i0 >= a.nv) return;
+    // polyline of the block's first vertex (largest p with off[p] <= i0), the
+    // same search in every lane; each lane then scans forward to its own
+    int64_t lo = 0, hi = a.np - 1;
     while (lo < hi) {
         int64_t mid = (lo + hi + 1) >> 1;
-        if ((int64_t)a.off[mid] <= i) lo = mid;
+        if ((int64_t)a.off[mid] <= i0) lo = mid;
         else hi = mid - 1;
     }
+    if (i >= a.nv) return;
+    if (i == 0 && (a.off[0] != 0 || a.off[a.np] != a.nv)) set_err(st, kErrInvalid);
+    while (lo + 1 < a.np && (int64_t)a.off[lo + 1] <= i) ++lo;
     int64_t pa = a.off[lo], pb = a.off[lo + 1];
     VRec r;
     int q[3];
