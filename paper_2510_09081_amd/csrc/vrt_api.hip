@@ -137,7 +137,7 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     if (desc->form == VRT_FORM_FP16) ALLOC(a.srec16, desc->max_vertices);
     ALLOC(a.ids, desc->max_fragments);
     ALLOC(a.brick_flag, mb);
-    ALLOC(a.bin_count, mb);
+    ALLOC(a.bin_count, mb * kBinStride);
     ALLOC(a.bin_range, mb);
     ALLOC(a.cand, mb);
     ALLOC(a.bins, (int64_t)kMaxBinBricks * desc->max_vertices);
@@ -155,7 +155,7 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
 #undef ALLOC
     if (e == hipSuccess) e = hipMemset(a.words, 0, (size_t)mb * kBrickVox * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(a.brick_flag, 0, (size_t)mb);
-    if (e == hipSuccess) e = hipMemset(a.bin_count, 0, (size_t)mb * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(a.bin_count, 0, (size_t)mb * kBinStride * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(a.brick_slot, 0xFF, (size_t)mb * sizeof(int32_t));
     if (e == hipSuccess) e = hipMemset(a.status, 0, sizeof(DevStatus));
     if (e == hipSuccess) e = hipDeviceSynchronize();

@@ -69,6 +69,10 @@ constexpr int kMaxBinBricks = 8;
 // Bins are processed in chunks of at most this many segments (one workgroup
 // each), so that crowded bricks are spread over several workgroups.
 constexpr int kBinChunk = 1024;
+// Words between the bin counters of consecutive bricks: each counter has a
+// 128-byte line of its own, so that device atomics on different bricks'
+// counters do not queue behind each other.
+constexpr int kBinStride = 32;
 
 // Index of the k-th item of a chunk in the order its workgroup reads it:
 // within every group of 64, lane L takes entry 8 (L % 8) + L / 8, so that the
@@ -105,7 +109,7 @@ struct Arenas {
     SRec16 *srec16 = nullptr;       // [max_vertices] FP16-form segment records (FP16 form only)
     uint32_t *ids = nullptr;        // [max_fragments]
     uint8_t *brick_flag = nullptr;  // [max_bricks]
-    uint32_t *bin_count = nullptr;  // [max_bricks] segments binned per brick (zero between frames)
+    uint32_t *bin_count = nullptr;  // [max_bricks * kBinStride] segments binned per brick, brick b at b * kBinStride (zero between frames)
     uint2 *bin_range = nullptr;     // [max_bricks] (first entry, length) of a brick's bin in bins
     int32_t *cand = nullptr;        // [max_bricks] bricks with a non-empty bin, in no particular order
     uint32_t *bins = nullptr;       // [kMaxBinBricks * max_vertices] segment ids grouped by brick

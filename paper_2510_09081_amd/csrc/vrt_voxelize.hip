@@ -34,7 +34,7 @@ __device__ __forceinline__ void b_reset(uint16_t *__restrict__ occ3, uint32_t *_
     int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     if (i < nbricks) {
         occ3[i] = 0;
-        bin_count[i] = 0u;
+        bin_count[i * kBinStride] = 0u;
     }
     if (i < nwords) brick_bits[i] = 0u;
     if (i < nflags) super_blk[i] = 0;
@@ -347,7 +347,7 @@ __device__ __forceinline__ void b_bin_count(BinArgs a, DevStatus *__restrict__ s
         unsigned len;
         const bool head = run_head(key, lane, heads, len);
         bool fresh = false;
-        if (head) fresh = atomicAdd(&a.bin_count[key], len) == 0u;
+        if (head) fresh = atomicAdd(&a.bin_count[(int64_t)key * kBinStride], len) == 0u;
         wave_append(fresh, key, &st->n_cand, a.cand);
     }
     wave_append(nbr > kMaxBinBricks, (uint32_t)i, &st->n_long, a.long_ids);
@@ -365,7 +365,7 @@ __device__ __forceinline__ void b_bin_alloc(BinArgs a, DevStatus *__restrict__ s
         unsigned c = 0;
         if (k < n) {
             b = a.cand[k];
-            c = a.bin_count[b];
+            c = a.bin_count[(int64_t)b * kBinStride];
         }
         const unsigned nch = (c + kBinChunk - 1) / kBinChunk;
         unsigned incl = c, inch = nch;
@@ -405,7 +405,7 @@ __device__ __forceinline__ void b_bin_fill(BinArgs a, DevStatus *__restrict__ st
         unsigned len;
         const bool head = run_head(key, lane, heads, len);
         unsigned old = 0;
-        if (head) old = atomicSub(&a.bin_count[key], len);
+        if (head) old = atomicSub(&a.bin_count[(int64_t)key * kBinStride], len);
         // each lane of a run takes its slot from the run's head (the last head at or below it)
         const int h = key >= 0 ? 63 - __clzll((long long)(heads & ((2ull << lane) - 1ull))) : lane;
         const unsigned old_h = __shfl(old, h, 64), len_h = __shfl(len, h, 64);
