@@ -720,11 +720,13 @@ __device__ __forceinline__ void b_erode(GridArgs g, const uint16_t *__restrict__
             if (c != f) set_err(st, kErrCount);
         }
     }
+    // box of the blocking voxels of all this workgroup's bricks, added to the
+    // stripes once at the end
+    if (t < 3) bb[t] = INT_MAX;
+    else if (t < 6) bb[t] = INT_MIN;
+    __syncthreads();
     for (unsigned sl = bid_; sl < nbk; sl += nblk_) {
         int64_t b = list[sl];
-        if (t < 3) bb[t] = INT_MAX;
-        else if (t < 6) bb[t] = INT_MIN;
-        __syncthreads();
         int bx = (int)(b % g.nb[0]), by = (int)((b / g.nb[0]) % g.nb[1]), bz = (int)(b / ((int64_t)g.nb[0] * g.nb[1]));
         int x = bx * 8 + (t & 7), y = by * 8 + ((t >> 3) & 7), z = bz * 8 + (t >> 6);
         unsigned e = occ0[b * kBrickVox + t];
@@ -748,9 +750,21 @@ __device__ __forceinline__ void b_erode(GridArgs g, const uint16_t *__restrict__
             const unsigned long long sq = __ballot(lane < 16 && ((c >> (16 * (lane >> 2) + 2 * (lane & 3))) & 1ull));
             if (lane == 0) m2[t >> 6] = (unsigned)sq & 0xFFFFu;
         }
-        if (blocking) {
-            atomicMin(&bb[0], x); atomicMin(&bb[1], y); atomicMin(&bb[2], z);
-            atomicMax(&bb[3], x); atomicMax(&bb[4], y); atomicMax(&bb[5], z);
+        if (bits) {  // the wave's box first, then one LDS update per wave
+            int v[6] = {blocking ? x : INT_MAX, blocking ? y : INT_MAX, blocking ? z : INT_MAX,
+                        blocking ? x : INT_MIN, blocking ? y : INT_MIN, blocking ? z : INT_MIN};
+            for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int lo = __shfl_xor(v[k], o, 64), hi = __shfl_xor(v[3 + k], o, 64);
+                    v[k] = lo < v[k] ? lo : v[k];
+                    v[3 + k] = hi > v[3 + k] ? hi : v[3 + k];
+                }
+            }
+            if ((t & 63) == 0) {
+                atomicMin(&bb[0], v[0]); atomicMin(&bb[1], v[1]); atomicMin(&bb[2], v[2]);
+                atomicMax(&bb[3], v[3]); atomicMax(&bb[4], v[4]); atomicMax(&bb[5], v[5]);
+            }
         }
         int any = __syncthreads_or(blocking ? 1 : 0);
         if (t == 0 && any) {
@@ -763,11 +777,13 @@ __device__ __forceinline__ void b_erode(GridArgs g, const uint16_t *__restrict__
             atomicOr(&brick_bits[cl.w16 + (c16 >> 5)], 1u << (c16 & 31));
             super_blk[((int64_t)(bz >> 3) * g.ns[1] + (by >> 3)) * g.ns[0] + (bx >> 3)] = 1;
             super_blk[cl.b32 + ((int64_t)(bz >> 2) * cl.n32[1] + (by >> 2)) * cl.n32[0] + (bx >> 2)] = 1;
-            int *p = st->stripe[bid_ % kStripes].bbox;
-            atomicMin(&p[0], bb[0]); atomicMin(&p[1], bb[1]); atomicMin(&p[2], bb[2]);
-            atomicMax(&p[3], bb[3]); atomicMax(&p[4], bb[4]); atomicMax(&p[5], bb[5]);
         }
         __syncthreads();
+    }
+    if (t == 0 && bb[0] <= bb[3]) {
+        int *p = st->stripe[bid_ % kStripes].bbox;
+        atomicMin(&p[0], bb[0]); atomicMin(&p[1], bb[1]); atomicMin(&p[2], bb[2]);
+        atomicMax(&p[3], bb[3]); atomicMax(&p[4], bb[4]); atomicMax(&p[5], bb[5]);
     }
 }
 
