@@ -84,9 +84,10 @@ def kernel_bytes(name, n):
                               for p in passes]))
     if name == "k_ingest":      # xyz + offsets in, records out
         return 12 * n["N_v"] + 4 * n["N_p"] + VREC_BYTES * n["N_v"]
-    if name == "k_cull_walk":   # occupied-voxel list in, visibility byte out; voxel blocking bits of the
-        # occupied bricks, brick bits and 64^3-cell flags once each
-        return 5 * n["V_o"] + 64 * n["bricks"] + n["NB"] / 8 + n["NB"] / 512
+    if name == "k_cull_walk":   # occupied-voxel list in, visibility byte out; per occupied brick its voxel
+        # blocking bits and 2^3-cell mask (9 words), the brick and 16^3-cell bits and the 32^3- and
+        # 64^3-cell flags once each
+        return 5 * n["V_o"] + 72 * n["bricks"] + n["NB"] / 8 + n["NB"] / 64 + n["NB"] / 64 + n["NB"] / 512
     if name == "k_cull_brick":  # per occupied brick: words, visibility read + written, mips 1-3, brick total
         return (2048 + 1024 + 64 + 8 + 1 + 4) * n["bricks"]
     if name == "k_trace_march":  # every pixel: brick table once, miss outputs (RGBA + depth + id)

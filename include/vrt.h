@@ -339,7 +339,7 @@ typedef struct {
     int64_t rays;               /* W * H */
     int64_t rays_hit;           /* rays with a first hit */
     int64_t cell_skips_64;      /* empty 64^3 cells crossed in one step */
-    int64_t cell_skips_8;       /* empty bricks crossed in one step */
+    int64_t cell_skips_8;       /* invisible bricks, 16^3 and 32^3 cells crossed in one step */
     int64_t voxel_steps;        /* voxels visited in non-empty bricks */
     int64_t list_visits;        /* visits of voxels with a non-empty list */
     int64_t capsule_tests;      /* ray-capsule tests, repeats included */
