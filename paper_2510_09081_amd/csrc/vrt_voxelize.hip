@@ -94,12 +94,33 @@ __device__ __forceinline__ void b_ingest(IngestArgs a, VRec *__restrict__ out, D
     int64_t i = i0 + threadIdx.x;
     if (i0 >= a.nv) return;
     // polyline of the block's first vertex (largest p with off[p] <= i0), the
-    // same search in every lane; each lane then scans forward to its own
-    int64_t lo = 0, hi = a.np - 1;
-    while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
+    // same search in every lane: from the proportional guess, doubling steps
+    // until the polyline is bracketed, then halving; each lane then scans
+    // forward to its own
+    int64_t g = (int64_t)((double)i0 * (double)a.np / (double)a.nv);
+    g = g < 0 ? 0 : (g > a.np - 1 ? a.np - 1 : g);
+    int64_t lo, hi;  // off[lo] <= i0 (or lo = 0), and hi = np or off[hi] > i0
+    if ((int64_t)a.off[g] <= i0) {
+        lo = g;
+        hi = g + 1;
+        for (int64_t s = 1; hi < a.np && (int64_t)a.off[hi] <= i0; s <<= 1) {
+            lo = hi;
+            hi = lo + 2 * s;
+        }
+        hi = hi > a.np ? a.np : hi;
+    } else {
+        hi = g;
+        lo = g - 1;
+        for (int64_t s = 1; lo > 0 && (int64_t)a.off[lo] > i0; s <<= 1) {
+            hi = lo;
+            lo = hi - 2 * s;
+        }
+        lo = lo < 0 ? 0 : lo;
+    }
+    while (lo + 1 < hi) {
+        const int64_t mid = (lo + hi) >> 1;
         if ((int64_t)a.off[mid] <= i0) lo = mid;
-        else hi = mid - 1;
+        else hi = mid;
     }
     if (i >= a.nv) return;
     if (i == 0 && (a.off[0] != 0 || a.off[a.np] != a.nv)) set_err(st, kErrInvalid);
