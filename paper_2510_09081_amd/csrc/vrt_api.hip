@@ -30,7 +30,7 @@ hipError_t alloc(T *&p, int64_t n) {
 void free_all(Arenas &a) {
     void *ptrs[] = {a.vrec, a.words, a.occ0, a.occ1, a.occ2, a.occ3, a.occ_hi, a.blk, a.blk_bits, a.brick_bits, a.super_blk,
                     a.occ_list, a.vis0,
-                    a.vis1, a.vis2,  a.vis3, a.vis_hi, a.cursor, a.cell, a.lmask, a.queue, a.srec16, a.ids, a.brick_flag, a.bin_count, a.bin_range, a.cand, a.bins, a.long_ids, a.items, a.chunk_cnt, a.brick_list, a.brick_slot,
+                    a.vis1, a.vis2,  a.vis3, a.vis_hi, a.cursor, a.cell, a.lmask, a.lmask2, a.queue, a.srec16, a.ids, a.brick_flag, a.bin_count, a.bin_range, a.cand, a.bins, a.long_ids, a.items, a.chunk_cnt, a.brick_list, a.brick_slot,
                     a.brick_total, a.brick_base, a.status, a.stat_vox, a.stat_seg, a.stat_acc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -133,6 +133,7 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     ALLOC(a.cursor, mb * kBrickVox);
     ALLOC(a.cell, mb * kBrickVox);
     ALLOC(a.lmask, mb * 8);
+    ALLOC(a.lmask2, mb);
     ALLOC(a.queue, desc->max_pixels);
     if (desc->form == VRT_FORM_FP16) ALLOC(a.srec16, desc->max_vertices);
     ALLOC(a.ids, desc->max_fragments);

@@ -100,7 +100,7 @@ __device__ __forceinline__ void run_part(int ph, int part, const SetDesc &d, uns
                      d.levels, d.n_levels, A.brick_total, vb, nvb);
         break;
     case P_SCAN: b_scan_bricks(A.brick_total, A.brick_base, A.status, d.capacity, A.vis_hi, d.levels, d.n_levels, 0u, 1u); break;
-    case P_OFFSETS: b_list_offsets(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor, A.cell, A.lmask, vb, nvb); break;
+    case P_OFFSETS: b_list_offsets(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor, A.cell, A.lmask, A.lmask2, vb, nvb); break;
     case P_SCATTER:
         if (part == 0) b_scatter(d.cp.sa, vb, nvb);
         else b_trace_begin(A.status, 0u, 1u);

@@ -290,8 +290,10 @@ __device__ __forceinline__ void b_list_offsets(const uint32_t *__restrict__ word
                                                       const uint32_t *__restrict__ base,
                                                       const DevStatus *__restrict__ st,
                                                       uint32_t *__restrict__ cursor, uint64_t *__restrict__ cell,
-                                                      uint64_t *__restrict__ lmask, unsigned bid_, unsigned nblk_) {
+                                                      uint64_t *__restrict__ lmask, uint64_t *__restrict__ lmask2,
+                                                      unsigned bid_, unsigned nblk_) {
     __shared__ unsigned wt[8];
+    __shared__ unsigned sq[8];
     const unsigned nbk = st->n_bricks;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     for (unsigned sl = bid_; sl < nbk; sl += nblk_) {
@@ -311,7 +313,18 @@ __device__ __forceinline__ void b_list_offsets(const uint32_t *__restrict__ word
         cell[b * kBrickVox + t] = (uint64_t)start | ((uint64_t)c << 32);
         const unsigned long long nonempty = __ballot(c != 0u);  // the wave holds local voxels 64w .. 64w + 63
         if (lane == 0) lmask[b * 8 + w] = nonempty;
+        {  // the slice's 2x2 squares holding such a voxel: bit 4 Y + X for square (X, Y)
+            unsigned long long s2 = nonempty | (nonempty >> 1);
+            s2 |= s2 >> 8;  // bit 16 Y + 2 X: the square's OR
+            const unsigned long long m = __ballot(lane < 16 && ((s2 >> (16 * (lane >> 2) + 2 * (lane & 3))) & 1ull));
+            if (lane == 0) sq[w] = (unsigned)m & 0xFFFFu;
+        }
         __syncthreads();
+        if (t == 0) {
+            uint64_t cells = 0;
+            for (int Z = 0; Z < 4; ++Z) cells |= (uint64_t)(sq[2 * Z] | sq[2 * Z + 1]) << (16 * Z);
+            lmask2[b] = cells;
+        }
     }
 }
 
@@ -321,8 +334,8 @@ __global__ void __launch_bounds__(512) k_list_offsets(const uint32_t *__restrict
                                                       const uint32_t *__restrict__ base,
                                                       const DevStatus *__restrict__ st,
                                                       uint32_t *__restrict__ cursor, uint64_t *__restrict__ cell,
-                                                      uint64_t *__restrict__ lmask) {
-    b_list_offsets(words, vis0, list, base, st, cursor, cell, lmask, blockIdx.x, gridDim.x);
+                                                      uint64_t *__restrict__ lmask, uint64_t *__restrict__ lmask2) {
+    b_list_offsets(words, vis0, list, base, st, cursor, cell, lmask, lmask2, blockIdx.x, gridDim.x);
 }
 
 struct ScatterArgs {
@@ -537,7 +550,7 @@ hipError_t launch_cull(vrt_ctx *c, const int64_t E[3], int64_t limit, hipStream_
                                                  ch));
     VRT_LAUNCH(c, "k_list_offsets", st,
                k_list_offsets<<<4096, 512, 0, st>>>(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor,
-                                                    A.cell, A.lmask));
+                                                    A.cell, A.lmask, A.lmask2));
     VRT_LAUNCH(c, "k_scatter_brick", st, k_scatter_brick<<<kBrickBlocks, 256, 0, st>>>(p.sb, A.status));
     VRT_LAUNCH(c, "k_scatter_long", st, k_scatter_long<<<256, 256, 0, st>>>(p.sb, A.status));
     return hipGetLastError();

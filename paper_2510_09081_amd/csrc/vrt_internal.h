@@ -105,6 +105,7 @@ struct Arenas {
     uint32_t *cursor = nullptr;     // [max_bricks * 512] list start, then end after pass 2
     uint64_t *cell = nullptr;       // [max_bricks * 512] list start (low 32) | visible count (high 32)
     uint64_t *lmask = nullptr;      // [max_bricks * 8] voxels with a non-empty list, one bit each (64 per word)
+    uint64_t *lmask2 = nullptr;     // [max_bricks] 2^3 cells holding such a voxel, bit 16 Z + 4 Y + X
     uint4 *queue = nullptr;         // [max_pixels] rays that reached a list
     SRec16 *srec16 = nullptr;       // [max_vertices] FP16-form segment records (FP16 form only)
     uint32_t *ids = nullptr;        // [max_fragments]

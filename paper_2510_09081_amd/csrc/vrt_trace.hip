@@ -106,6 +106,7 @@ struct TraceArgs {
     const uint8_t *vis3;      // culling level 3 (bricks)
     const uint64_t *cell;     // per voxel: list start | visible count << 32
     const uint64_t *lmask;    // per brick: voxels with a non-empty list (8 words, z-slice w in word w)
+    const uint64_t *lmask2;   // per brick: 2^3 cells holding such a voxel
     DevStatus *st;            // visible-brick box, ray-queue length
     const uint32_t *ids;
     const VRec *vrec;
@@ -332,10 +333,13 @@ __device__ __forceinline__ bool step_voxel(const TraceArgs &a, const Ray &r, Wal
 // lanes, which all hold the same values).
 struct MaskRegs {
     static constexpr bool kEarly = false;  // many rays meet invisible bricks: load only for visible ones
+    static constexpr bool kCells = true;   // one ray per lane: crosses list-free 2^3 and 4^3 cells in one jump
     uint64_t m[8];
-    __device__ void set(const uint64_t *src) {
+    uint64_t c2;  // the brick's 2^3 cells holding a list voxel
+    __device__ void set(const uint64_t *src, const uint64_t *cells) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) m[k] = src[k];
+        c2 = *cells;
     }
     __device__ void put(const uint64_t *v) {
 #pragma unroll
@@ -350,9 +354,11 @@ struct MaskRegs {
 };
 struct MaskLds {
     static constexpr bool kEarly = true;  // read beside the culling flags, before they are known
+    static constexpr bool kCells = false;  // groups walk mostly through voxels with lists
     uint64_t *p;  // word k at p[k * stride]
     int stride;
-    __device__ void set(const uint64_t *src) {
+    uint64_t c2 = 0;  // unused
+    __device__ void set(const uint64_t *src, const uint64_t *) {
         uint64_t m[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) m[k] = src[k];
@@ -397,8 +403,18 @@ __device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w,
                 continue;
             }
             if (Mask::kEarly) mk.put(m);
-            else mk.set(a.lmask + b * 8);
+            else mk.set(a.lmask + b * 8, a.lmask2 + b);
             w.bvis = b;
+        }
+        if (Mask::kCells) {  // a 2^3 or 4^3 cell of the brick without list voxels is crossed in one jump
+            const int xl = w.v[0] & 7, yl = w.v[1] & 7, zl = w.v[2] & 7;
+            if (!((mk.c2 >> (((zl >> 1) << 4) | ((yl >> 1) << 2) | (xl >> 1))) & 1ull)) {
+                const bool e4 = !(mk.c2 & (0x00330033ull << (((zl >> 2) << 5) | ((yl >> 2) << 3) | ((xl >> 2) << 1))));
+                if (kStats) ++cn.skip8;
+                if (!skip_cell(r, a.G, e4 ? 2 : 1, w.v, w.tcur)) return false;
+                w.fresh = true;
+                continue;
+            }
         }
         if (w.fresh) {
             for (int k = 0; k < 3; ++k)
@@ -838,6 +854,7 @@ static TraceArgs trace_args(vrt_ctx *c, const TraceParams &p, const vrt_image *i
     }
     a.cell = c->a.cell;
     a.lmask = c->a.lmask;
+    a.lmask2 = c->a.lmask2;
     a.st = c->a.status;
     a.ids = c->a.ids;
     a.vrec = c->a.vrec;
