@@ -328,12 +328,13 @@ __device__ __forceinline__ bool step_voxel(const TraceArgs &a, const Ray &r, Wal
     return true;
 }
 
-// The list mask of the brick a walk is in (its z-slice words), held by the
-// walker: in registers (one ray per lane) or in LDS (one ray per group of
-// lanes, which all hold the same values).
+// The list mask of the brick a walk is in (its z-slice words) and the mask of
+// its 2^3 cells holding a list voxel, held by the walker: in registers (one
+// ray per lane), or the voxel words in LDS (one ray per group of lanes, which
+// all hold the same values).
 struct MaskRegs {
     static constexpr bool kEarly = false;  // many rays meet invisible bricks: load only for visible ones
-    static constexpr bool kCells = true;   // one ray per lane: crosses list-free 2^3 and 4^3 cells in one jump
+    static constexpr bool kCells = true;   // crosses list-free 2^3 and 4^3 cells in one jump
     uint64_t m[8];
     uint64_t c2;  // the brick's 2^3 cells holding a list voxel
     __device__ void set(const uint64_t *src, const uint64_t *cells) {
@@ -354,10 +355,10 @@ struct MaskRegs {
 };
 struct MaskLds {
     static constexpr bool kEarly = true;  // read beside the culling flags, before they are known
-    static constexpr bool kCells = false;  // groups walk mostly through voxels with lists
+    static constexpr bool kCells = true;  // crosses list-free 2^3 and 4^3 cells in one jump
     uint64_t *p;  // word k at p[k * stride]
     int stride;
-    uint64_t c2 = 0;  // unused
+    uint64_t c2 = 0;  // the brick's 2^3 cells holding a list voxel (in registers)
     __device__ void set(const uint64_t *src, const uint64_t *) {
         uint64_t m[8];
 #pragma unroll
@@ -372,9 +373,10 @@ struct MaskLds {
 };
 
 // Advances from the current voxel (included) to the first visible voxel with
-// a non-empty list, skipping empty 64^3 cells and bricks; false if none.  In a
-// visible brick, voxels without a list are passed on the brick's list mask,
-// loaded once when the walk enters the brick.
+// a non-empty list, skipping invisible cells of 8^3 to 64^3 voxels; false if
+// none.  In a visible brick, list-free 4^3 and 2^3 cells are crossed in one
+// jump and single voxels without a list are passed on the brick's list mask,
+// both loaded once when the walk enters the brick.
 template <bool kStats, class Mask>
 __device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w, Counters &cn, Mask &mk) {
     const int max_iter = 3 * (a.G[0] + a.G[1] + a.G[2]) + 16;
@@ -384,9 +386,11 @@ __device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w,
         if (b != w.bvis) {  // a new brick: its own culling flag, and its 64^3 cell's
             // both read at once; a 64^3 cell is visible iff one of its bricks is
             uint64_t m[8];  // the brick's list mask, read early by walkers that keep it
+            uint64_t c2 = 0;
             if (Mask::kEarly) {
 #pragma unroll
                 for (int k = 0; k < 8; ++k) m[k] = a.lmask[b * 8 + k];
+                c2 = a.lmask2[b];
             }
             const uint8_t v3 = a.vis3[b];
             const uint8_t v4 = a.vis4 ? a.vis4[coarse_index(w.v, 4, a.n4)] : 1;
@@ -402,8 +406,12 @@ __device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w,
                 w.fresh = true;
                 continue;
             }
-            if (Mask::kEarly) mk.put(m);
-            else mk.set(a.lmask + b * 8, a.lmask2 + b);
+            if (Mask::kEarly) {
+                mk.put(m);
+                mk.c2 = c2;
+            } else {
+                mk.set(a.lmask + b * 8, a.lmask2 + b);
+            }
             w.bvis = b;
         }
         if (Mask::kCells) {  // a 2^3 or 4^3 cell of the brick without list voxels is crossed in one jump
