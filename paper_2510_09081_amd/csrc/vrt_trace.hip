@@ -791,7 +791,7 @@ __device__ __forceinline__ void b_debug_rays(TraceParams p, const int64_t *__res
 // memory latency, and the fourth wave hides more of it than the few spilled
 // registers cost.
 template <bool kStats, int kForm, class Cfg>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm, Cfg>(a, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm, Cfg>(a, blockIdx.x, gridDim.x); }
 
 __global__ void k_debug_rays(TraceParams p, const int64_t *__restrict__ pix, int64_t n, float *__restrict__ dirs) { b_debug_rays(p, pix, n, dirs, blockIdx.x, gridDim.x); }
 
@@ -931,8 +931,8 @@ hipError_t launch_trace_stats(vrt_ctx *c, const TraceParams &p, const vrt_image 
     k_stat_clear<<<1024, 256, 0, st>>>(c->a.brick_list, c->a.status, c->n_vertices, a.stat_vox, a.stat_seg, a.stat_acc);
     k_trace_begin<<<1, 64, 0, st>>>(a.st);
     k_trace_march<true><<<march_grid(p, 256), 256, 0, st>>>(a);
-    if (c->desc.form == VRT_FORM_FP16) k_trace_shade<true, VRT_FORM_FP16, DefaultShade><<<4096, 256, 0, st>>>(a);
-    else k_trace_shade<true, VRT_FORM_PLAIN, DefaultShade><<<4096, 256, 0, st>>>(a);
+    if (c->desc.form == VRT_FORM_FP16) k_trace_shade<true, VRT_FORM_FP16, DefaultShade><<<16384, 64, 0, st>>>(a);
+    else k_trace_shade<true, VRT_FORM_PLAIN, DefaultShade><<<16384, 64, 0, st>>>(a);
     k_stat_reduce<<<1024, 256, 0, st>>>(c->a.brick_list, c->a.status, c->n_vertices, a.stat_vox, a.cell, a.stat_seg,
                                         a.stat_acc);
     return hipGetLastError();
