@@ -551,8 +551,8 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
                 best = key < best ? key : best;
             }
         });
+        if (!group_any<kGroup>(best != kNoKey, lane)) return false;  // no hit: skip the reduction
         best = group_min<kGroup>(best);
-        if (best == kNoKey) return false;
         const uint32_t id = (uint32_t)best;
         sh.first = (int)id;
         sh.first_t = w.tcur + __uint_as_float((uint32_t)(best >> 32));
@@ -594,8 +594,8 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
                 rescan = true;
                 break;
             }
+            if (!group_any<kGroup>(kk[0] != kNoKey, lane)) break;  // nothing left: skip the reduction
             const unsigned long long m = group_min<kGroup>(kk[0]);
-            if (m == kNoKey) break;
             // keys are unique (one per segment), so exactly one lane holds m: it pops, and its colour is used
             const bool own = kk[0] == m;
             if (own) {
