@@ -916,6 +916,22 @@ static void segment_colour(const double *A, const double *B, double *col)
 
 typedef struct { double m, t; } near_rec; /* hit/miss or clip margin, at ray parameter t */
 
+/* Two segments with the same quantized endpoints and the same clip planes are
+ * the same capsule: every implementation computes the same hit parameter for
+ * both, so their order is decided by the id rule alone, never by rounding.
+ * Gaps between such hits are not ordering decisions. */
+static int same_capsule(const trace_in *T, int64_t a, int64_t b)
+{
+    for (int c = 0; c < 6; c++)
+        if (T->q[3 * a + c] != T->q[3 * b + c]) return 0;
+    for (int e = 0; e < 2; e++) {
+        if (T->interior[a + e] != T->interior[b + e]) return 0;
+        for (int c = 0; c < 3; c++)
+            if (T->nrm[3 * (a + e) + c] != T->nrm[3 * (b + e) + c]) return 0;
+    }
+    return 1;
+}
+
 /* Evaluates one candidate segment: records its entry hit (counted or not)
  * and the hit/miss and clip margins with the ray parameter they apply at. */
 static void eval_candidate(const trace_in *T, const double *D, int64_t s, hitbuf *B, near_rec *nr)
@@ -1056,7 +1072,8 @@ static void trace_one(const trace_in *T, const double *D, int brute, int64_t *ou
     if (T->mode == 0) {
         if (nc > 0) {
             rgba[0] = cnt[0].col[0]; rgba[1] = cnt[0].col[1]; rgba[2] = cnt[0].col[2]; rgba[3] = 1.0;
-            if (nc > 1) *m_geom = cnt[1].t - cnt[0].t;
+            for (int64_t k = 1; k < nc; k++)
+                if (!same_capsule(T, cnt[k].id, cnt[0].id)) { *m_geom = cnt[k].t - cnt[0].t; break; }
             *n_comp = 1;
         } else {
             *n_comp = 0;
@@ -1067,6 +1084,7 @@ static void trace_one(const trace_in *T, const double *D, int brute, int64_t *ou
         *n_comp = k;
         t_rel = (k < nc) ? cnt[k].t : INFINITY;
         for (int64_t i = 0; i + 1 < nc && i < k; i++) {
+            if (same_capsule(T, cnt[i + 1].id, cnt[i].id)) continue;
             double g = cnt[i + 1].t - cnt[i].t;
             if (g < *m_geom) *m_geom = g;
         }

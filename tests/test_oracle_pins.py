@@ -505,6 +505,13 @@ def test_trace_duplicate_segments_tie_to_lower_id(orc):
     cam = centre_camera((8.25, 8, 40), (8.25, 8, 8), G)
     tr, _ = trace_centre(orc, ls, cam)
     assert tr.id[0] == 6
+    # the tie between identical capsules is decided by the id rule, not by
+    # rounding: the pixel is certified (its ordering margin is the gap to the
+    # next distinct capsule, here none)
+    assert tr.m_geom[0] > 1e-3
+    trt, _ = trace_centre(orc, ls, cam, mode=1, alpha=0.3)
+    assert trt.id[0] == 6 and trt.n_comp[0] == 2 and trt.m_geom[0] > 1e-3
+    assert abs(trt.rgba[0, 0] - (1 - 0.7 ** 2)) < 1e-12
 
 
 @pytest.mark.parametrize("n", [1, 3, 10, 20])

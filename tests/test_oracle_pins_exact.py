@@ -1,0 +1,305 @@
+"""More pins of the CPU oracle, each against a fact that does not come from
+its code: an independent per-voxel evaluation of the membership rule, the
+printed Eq. (1) in the planar case where it is exact, the rounding mode of
+the fixed-point grid at exact half steps, the order of front-to-back
+compositing with two different colours, and the alpha-layer limit of culling
+rays at M - 1 and M blockers (arXiv 2510.09081, Sections 3.1, 3.2, 3.5).
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2510_09081_amd import synth
+
+from .test_oracle_pins import adversarial_segments, centre_camera, make_lineset, trace_centre
+
+Q = 256
+
+
+# ---------------------------------------------------------------------------
+# Membership, evaluated voxel by voxel (Sec. 3.1, Alg. 1 with the projected
+# radius that is conservative in 3D).  The oracle enumerates slab boxes with
+# floor divisions; here every voxel of the capsule's box is tested on its own
+# with integer inequalities, so a box one voxel too wide or narrow, a slab
+# interval taken at the wrong ends, or a half-width built from the wrong
+# direction component shows up as a set difference.
+
+
+def ceil_isqrt(n):
+    """Smallest w >= 0 with w * w >= n (exact, Python integers)."""
+    if n <= 0:
+        return 0
+    w = math.isqrt(n)
+    return w if w * w == n else w + 1
+
+
+def voxel_in_set(A, B, rq, G, v):
+    """Is voxel v in the capsule's voxel set?  One voxel, no enumeration."""
+    d = [B[c] - A[c] for c in range(3)]
+    a0 = 0
+    for c in (1, 2):
+        if abs(d[c]) > abs(d[a0]):
+            a0 = c
+    if d[a0] < 0:
+        A, B = B, A
+        d = [-x for x in d]
+    D = d[a0]
+    lo = [min(A[c], B[c]) - rq for c in range(3)]
+    hi = [max(A[c], B[c]) + rq for c in range(3)]
+    for c in range(3):
+        # the closed cube of v touches the closed capsule box, inside the grid
+        if not (0 <= v[c] < G[c] and v[c] * Q <= hi[c] and (v[c] + 1) * Q >= lo[c]):
+            return False
+    if D == 0:
+        return True  # a ball: its box
+    x = v[a0]
+    ta, tb = max(lo[a0], x * Q), min(hi[a0], (x + 1) * Q)
+    for i in range(3):
+        if i == a0:
+            continue
+        ca = A[i] * D + d[i] * (ta - A[a0])  # the line's coordinate i at ta, scaled by D
+        cb = A[i] * D + d[i] * (tb - A[a0])
+        W = ceil_isqrt(rq * rq * (D * D + d[i] * d[i]))  # r sqrt(1 + (d_i/D)^2), scaled by D, rounded up
+        if not (v[i] * Q * D <= max(ca, cb) + W and (v[i] + 1) * Q * D >= min(ca, cb) - W):
+            return False
+    return True
+
+
+def per_voxel_set(A, B, rq, G):
+    rng = [range(max(0, (min(A[c], B[c]) - rq - 1) // Q), min(G[c] - 1, (max(A[c], B[c]) + rq) // Q) + 1)
+           for c in range(3)]
+    return {(x, y, z) for x in rng[0] for y in rng[1] for z in rng[2] if voxel_in_set(A, B, rq, G, (x, y, z))}
+
+
+def test_membership_equals_per_voxel_evaluation(orc):
+    """>= 10^4 random and adversarial segments at several radii, lengths up
+    to 6 voxels, on a non-cubic grid they partly leave."""
+    G = (24, 20, 16)
+    rng = np.random.default_rng(2510)
+    segs = []
+    for rq in (0, 51, 90, 128, 200, 333):
+        for A, B in adversarial_segments(rng, 16, 0):
+            segs.append((A, B, rq))
+    while len(segs) < 10_500:
+        A = rng.integers(-2 * Q, np.array(G) * Q + 2 * Q)
+        L = rng.uniform(0, 6) * Q
+        dv = rng.normal(size=3)
+        if rng.random() < 0.3:  # exact ties between the largest components, and zero minors
+            dv = np.array([1.0, rng.choice([1.0, -1.0]), rng.choice([0.0, 1.0, -1.0])])[rng.permutation(3)]
+        dv = dv / np.linalg.norm(dv) * L
+        B = np.rint(A + dv).astype(int)
+        rq = int(rng.choice([0, 1, 51, 90, 128, 127, 129, 255, 256, 300]))
+        segs.append((tuple(int(a) for a in A), tuple(int(b) for b in B), rq))
+    n_nonempty = 0
+    for A, B, rq in segs:
+        got = orc.segment_voxels(A, B, rq, G)
+        gset = {tuple(int(c) for c in v) for v in got}
+        assert len(gset) == len(got), (A, B, rq)  # each voxel once
+        exp = per_voxel_set(A, B, rq, G)
+        assert gset == exp, (A, B, rq, sorted(gset ^ exp)[:6])
+        n_nonempty += bool(exp)
+    assert n_nonempty > 7000
+
+
+# Pythagorean directions make |d| and the printed radius rational, so Eq. (1)
+# can be evaluated exactly.  With one minor component zero (the planar case of
+# the paper's traversal figure) the printed radius r / sqrt(1 - (d_i/|d|)^2)
+# equals the conservative one, and the oracle's slab boxes must be the boxes
+# the printed radius gives: the same set.
+PLANAR = [  # (D, d_i) in whole voxels; D > |d_i|, D^2 + d_i^2 a square
+    (4, 3), (4, -3), (12, 5), (12, -5), (15, 8), (24, 7), (8, 6), (3, 0)]
+
+
+def eq1_planar_set(A, B, rq, G, i_minor):
+    """Voxel set with the slab boxes of Alg. 1 and the printed Eq. (1) radius,
+    in exact rationals (the slab ends are those of the oracle's reading: the
+    capsule box, closed at both ends)."""
+    d = [B[c] - A[c] for c in range(3)]
+    a0 = max(range(3), key=lambda c: (abs(d[c]), -c))
+    if d[a0] < 0:
+        A, B = B, A
+        d = [-x for x in d]
+    D = d[a0]
+    norm = Fraction(math.isqrt(sum(x * x for x in d)))
+    assert norm * norm == sum(x * x for x in d)
+    r = Fraction(rq, Q)
+    lo = [min(A[c], B[c]) - rq for c in range(3)]
+    hi = [max(A[c], B[c]) + rq for c in range(3)]
+    box = [range(max(0, (lo[c] - 1) // Q), min(G[c] - 1, hi[c] // Q) + 1) for c in range(3)]
+    out = set()
+    for x in box[a0]:
+        ta = Fraction(max(lo[a0], x * Q), Q)
+        tb = Fraction(min(hi[a0], (x + 1) * Q), Q)
+        ranges = {}
+        for i in range(3):
+            if i == a0:
+                continue
+            rhat = r / Fraction(math.isqrt(((norm * norm - d[i] * d[i]) / (norm * norm)).numerator),
+                                math.isqrt(((norm * norm - d[i] * d[i]) / (norm * norm)).denominator))
+            p0 = Fraction(A[i], Q) + Fraction(d[i], D) * (ta - Fraction(A[a0], Q))
+            p1 = Fraction(A[i], Q) + Fraction(d[i], D) * (tb - Fraction(A[a0], Q))
+            jlo, jhi = min(p0, p1) - rhat, max(p0, p1) + rhat
+            # voxels whose closed interval [j, j + 1] touches [jlo, jhi]
+            ranges[i] = [j for j in box[i] if j <= jhi and j + 1 >= jlo]
+        others = [c for c in range(3) if c != a0]
+        for j in ranges[others[0]]:
+            for k in ranges[others[1]]:
+                v = [0, 0, 0]
+                v[a0], v[others[0]], v[others[1]] = x, j, k
+                out.add(tuple(v))
+    return out
+
+
+@pytest.mark.parametrize("Dv,dv", PLANAR)
+@pytest.mark.parametrize("rq", [128, 90, 256])
+def test_membership_planar_case_is_equation1(orc, Dv, dv, rq):
+    G = (40, 40, 40)
+    rng = np.random.default_rng(Dv * 100 + dv + rq)
+    for trial in range(12):
+        axes = rng.permutation(3)  # major, minor with d_i, minor with zero
+        A = [int(a) for a in rng.integers(8 * Q, 16 * Q, size=3)]
+        s = int(rng.choice([32, 64, 256, 128 + 64]))  # step scale in Q units (lengths 0.5..1 of the triple)
+        d = [0, 0, 0]
+        d[axes[0]] = Dv * s * (1 if trial % 2 == 0 else -1)
+        d[axes[1]] = dv * s
+        B = [A[c] + d[c] for c in range(3)]
+        got = {tuple(int(c) for c in v) for v in orc.segment_voxels(A, B, rq, G)}
+        exp = eq1_planar_set(A, B, rq, G, axes[1])
+        assert got == exp, (A, B, rq, sorted(got ^ exp)[:6])
+
+
+# ---------------------------------------------------------------------------
+# Quantization rounding (fixed-point grid, 1/256 voxel): round to nearest, ties
+# to even, at inputs that are not on the grid.
+
+
+def quant_lineset(xs, vs, origin):
+    xyz = np.zeros((len(xs), 3), np.float32)
+    xyz[:, 0] = xs
+    xyz[:, 1] = origin[1] + np.float32(3.0) * vs  # on the grid
+    xyz[:, 2] = origin[2] + np.float32(5.0) * vs
+    return synth.LineSet(xyz=xyz, offsets=np.array([0, len(xs)], np.int32), radius=float(vs) * 0.5,
+                         origin=np.asarray(origin, np.float32), voxel_size=float(vs), dims=(64, 64, 64))
+
+
+@pytest.mark.parametrize("origin_x", [0.0, 0.25, -0.5])
+def test_quantization_round_to_nearest_even(orc, origin_x):
+    """With voxel size 2^-6 the scale is 2^14, so x = o + (q + 1/2) 2^-14 is
+    a binary32 number whose scaled offset is exactly q + 1/2: the grid value
+    must be the even neighbour.  One ulp above and below must round up and
+    down.  Truncation, floor, or ties away from zero each fail some case."""
+    vs = np.float32(2.0 ** -6)
+    origin = np.array([origin_x, 0.0, 0.0], np.float32)
+    qs = [0, 1, 2, 3, 10, 11, 1001, 1002, 4095, -1, -2, -7, -8, -1000, -1001]
+    xs, exp = [], []
+    for q in qs:
+        half = np.float32(origin_x + (q + 0.5) * 2.0 ** -14)
+        assert float(half) == origin_x + (q + 0.5) * 2.0 ** -14  # exactly representable
+        even = q if q % 2 == 0 else q + 1
+        xs += [half, np.nextafter(half, np.float32(np.inf)), np.nextafter(half, np.float32(-np.inf))]
+        exp += [even, q + 1, q]
+        off = np.float32(origin_x + q * 2.0 ** -14 + 0.3 * 2.0 ** -14)  # not a half step: nearest
+        xs.append(off)
+        exp.append(int(round((float(off) - origin_x) * 2.0 ** 14)))
+    ing = orc.ingest(quant_lineset(np.array(xs, np.float32), vs, origin))
+    assert ing.status == 0
+    assert ing.q[:, 0].tolist() == exp
+    assert ing.q[:, 1].tolist() == [3 * Q] * len(xs) and ing.q[:, 2].tolist() == [5 * Q] * len(xs)
+
+
+def test_quantization_radius_and_eye_round_half_even(orc):
+    """The radius and the eye are quantized in binary64 with ties to even:
+    r = 0.5/256 voxel -> 0 (even), 1.5/256 -> 2, 2.5/256 -> 2."""
+    vs = 2.0 ** -6
+    for r_steps, exp in ((0.5, 0), (1.5, 2), (2.5, 2), (127.5, 128), (128.5, 128), (0.49, 0), (0.51, 1)):
+        ls = quant_lineset(np.array([0.1, 0.2], np.float32), np.float32(vs), np.zeros(3, np.float32))
+        ls = synth.LineSet(xyz=ls.xyz, offsets=ls.offsets, radius=float(np.float32(r_steps * vs / Q)),
+                           origin=ls.origin, voxel_size=ls.voxel_size, dims=ls.dims)
+        assert orc.ingest(ls).rq == exp, r_steps
+    ls = quant_lineset(np.array([0.1, 0.2], np.float32), np.float32(vs), np.zeros(3, np.float32))
+    eye = np.array([(7 + 0.5) * vs / Q, (8 + 0.5) * vs / Q, -(3 + 0.5) * vs / Q], np.float32)
+    assert orc.eye_q(eye, ls).tolist() == [8, 8, -4]
+
+
+# ---------------------------------------------------------------------------
+# Compositing order (Sec. 3.5: front to back, in visibility order)
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.5, 0.8])
+def test_trace_two_colours_composite_front_to_back(orc, alpha):
+    """A red line (along x) in front of a green line (along y), seen from
+    above: C = alpha red + alpha (1 - alpha) green, A = 1 - (1 - alpha)^2.
+    Back-to-front order would swap the two weights."""
+    G = 64
+    front = [[20 + k, 32.3, 40.5] for k in range(25)]   # along x: colour (1, 0, 0)
+    back = [[32.4, 20 + k, 20.5] for k in range(25)]    # along y: colour (0, 1, 0)
+    ls = make_lineset([back, front], G, 0.5)           # the back line has the lower ids
+    cam = centre_camera((32.4, 32.3, 60), (32.4, 32.3, 0), G)
+    tr, _ = trace_centre(orc, ls, cam, mode=1, alpha=alpha)
+    assert tr.n_comp[0] == 2
+    exp = [alpha, alpha * (1 - alpha), 0.0, 1 - (1 - alpha) ** 2]
+    assert np.allclose(tr.rgba[0], exp, rtol=0, atol=1e-12), (tr.rgba[0], exp)
+    assert tr.id[0] >= 25  # the first hit is the front (red) line
+    trb, _ = trace_centre(orc, ls, cam, mode=0)
+    assert np.allclose(trb.rgba[0], [1, 0, 0, 1], rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Alpha-layer culling (Sec. 3.2 culling rays; the layer limit M(alpha))
+
+
+@pytest.mark.parametrize("alpha,M", [(0.2, 25), (0.3, 16), (0.5, 9)])
+def test_alpha_culling_hides_behind_M_blockers_only(orc, alpha, M):
+    """An occupied voxel under a column of k blocking voxels, the eye straight
+    above: visible for k = M - 1, hidden for k = M (alpha culling), hidden
+    for k = 1 (opaque culling), visible for any k without culling."""
+    lim = orc.cull_limit(orc.CULL_ALPHA, alpha)
+    assert lim == M
+    G = (8, 8, 40)
+    v = (3, 5, 1)
+    eyeq = np.array([3 * Q + 128, 5 * Q + 128, 60 * Q + 7], np.int64)
+    for k, visible in ((M - 1, True), (M, False), (M + 3, False), (0, True)):
+        words = np.zeros(G[::-1], np.uint32)
+        words[v[2], v[1], v[0]] = 1
+        blk = np.zeros(G[::-1], np.uint8)
+        blk[v[2] + 1:v[2] + 1 + k, v[1], v[0]] = 1
+        vis = orc.visibility(words, blk, eyeq, lim)
+        assert bool(vis[v[2], v[1], v[0]]) == visible, (k, M)
+        n, _ = orc.culling_ray(v, eyeq, blk, 10 ** 6)
+        assert n == k
+        if k >= 1:
+            assert orc.visibility(words, blk, eyeq, orc.cull_limit(orc.CULL_OPAQUE))[v[2], v[1], v[0]] == 0
+        assert orc.visibility(words, blk, eyeq, orc.cull_limit(orc.CULL_NONE))[v[2], v[1], v[0]] == 1
+    # blockers beside the column do not count: the ray meets only the column's interiors
+    words = np.zeros(G[::-1], np.uint8).astype(np.uint32)
+    words[v[2], v[1], v[0]] = 1
+    blk = np.ones(G[::-1], np.uint8)
+    blk[:, v[1], v[0]] = 0
+    assert orc.visibility(words, blk, eyeq, 1)[v[2], v[1], v[0]] == 1
+
+
+def test_alpha_culling_through_a_wall_of_lines(orc):
+    """The same through the whole build: under a thick wall of lines the
+    voxels behind it are culled with alpha = 0.5 (M = 9) only where the ray
+    meets at least 9 blocking voxels, which is where the wall is at least 11
+    voxels thick (erosion removes one layer on each face)."""
+    G = 32
+    polys = []
+    for z in range(4, 19):          # a wall 15 voxels thick in z under x < 16 ...
+        for y in range(2, 30):
+            polys.append([[2, y + 0.5, z + 0.5], [15.5, y + 0.5, z + 0.5]])
+    for z in range(4, 10):          # ... and 6 voxels thick under x >= 16
+        for y in range(2, 30):
+            polys.append([[16.5, y + 0.5, z + 0.5], [30, y + 0.5, z + 0.5]])
+    polys.append([[4, 16.5, 1.5], [28, 16.5, 1.5]])  # the line under the wall
+    ls = make_lineset(polys, G, 0.75)
+    eye = np.array([16.0, 16.5, 200.0], np.float32) / G  # far above: near-vertical rays
+    fr = orc.build_frame(ls, eye, orc.CULL_ALPHA, alpha=0.5)
+    assert fr.limit == 9
+    row = fr.vis[1, 16, :]
+    assert row[5:13].sum() == 0            # under the thick part: hidden
+    assert row[19:27].all()                # under the thin part: visible
+    fo = orc.build_frame(ls, eye, orc.CULL_OPAQUE)
+    assert fo.vis[1, 16, 19:27].sum() == 0  # opaque culling hides both
