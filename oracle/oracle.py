@@ -136,13 +136,23 @@ def eye_q(eye, ls) -> np.ndarray:
     return out
 
 
-def segment_voxels(A, B, rq, dims, literal=False) -> np.ndarray:
+# membership modes: the capsule voxelizer (Alg. 1 with the corrected Eq. (1)), the printed Alg. 1 + Eq. (1),
+# and the two comparison voxelizers of Table 2 (thin line, capsule AABB)
+VOX_CAPSULE, VOX_LITERAL, VOX_THIN, VOX_AABB = 0, 1, 2, 3
+
+
+def _mode(literal, mode):
+    return VOX_LITERAL if literal else int(mode)
+
+
+def segment_voxels(A, B, rq, dims, literal=False, mode=VOX_CAPSULE) -> np.ndarray:
     """Voxel set S(s) of one segment as an (n, 3) int array of (x, y, z)."""
     A, B, G = _i32(A), _i32(B), _i32(dims)
     L = lib()
-    n = L.orc_segment_voxels(_p(A), _p(B), int(rq), _p(G), None, 0, int(literal))
+    m = _mode(literal, mode)
+    n = L.orc_segment_voxels(_p(A), _p(B), int(rq), _p(G), None, 0, m)
     out = np.zeros((max(n, 1), 3), np.int32)
-    L.orc_segment_voxels(_p(A), _p(B), int(rq), _p(G), _p(out), n, int(literal))
+    L.orc_segment_voxels(_p(A), _p(B), int(rq), _p(G), _p(out), n, m)
     return out[:n]
 
 
@@ -161,14 +171,14 @@ def occupancy_q(A, B, n0, n1, a_int, b_int, rq, v) -> int:
                                      C.c_float(corr), int(v[0]), int(v[1]), int(v[2])))
 
 
-def voxelize(ing: Ingest, dims, literal=False):
+def voxelize(ing: Ingest, dims, literal=False, mode=VOX_CAPSULE):
     """Pass 1: packed words (count low 16 bits, occupancy sum high 16 bits)."""
     G = _i32(dims)
     gx, gy, gz = dims
     words = np.zeros((gz, gy, gx), np.uint32)
     nf = C.c_int64()
     st = lib().orc_voxelize(_p(ing.q), _p(ing.nrm), _p(ing.interior), _p(ing.seg_valid), ing.q.shape[0], ing.rq,
-                            _p(G), _p(words), C.byref(nf), int(literal))
+                            _p(G), _p(words), C.byref(nf), _mode(literal, mode))
     return words, st, nf.value
 
 
@@ -219,14 +229,14 @@ def visibility_pyramid(vis):
     return levels
 
 
-def csr(ing: Ingest, words, vis, literal=False):
+def csr(ing: Ingest, words, vis, literal=False, mode=VOX_CAPSULE):
     """Offsets (dense index, brick-major exclusive prefix) and ascending id lists."""
     G = _i32(words.shape[::-1])
     offsets = np.zeros(words.shape, np.uint32)
     total = lib().orc_offsets(_p(words), _p(vis), _p(G), _p(offsets))
     ids = np.zeros(max(total, 1), np.uint32)
     lib().orc_fill_lists(_p(ing.q), _p(ing.seg_valid), ing.q.shape[0], ing.rq, _p(G), _p(vis), _p(offsets),
-                         _p(ids), int(literal))
+                         _p(ids), _mode(literal, mode))
     return offsets, ids[:total], total
 
 
@@ -265,15 +275,16 @@ class Frame:
     eyeq: np.ndarray
     limit: int
     times: dict
+    mode: int = VOX_CAPSULE  # membership mode the frame was built with
 
 
-def build_frame(ls, eye, cull_mode, alpha=1.0, tau=1.0 / 256.0, literal=False) -> Frame:
+def build_frame(ls, eye, cull_mode, alpha=1.0, tau=1.0 / 256.0, literal=False, mode=VOX_CAPSULE) -> Frame:
     t = {}
     t0 = time.perf_counter()
     ing = ingest(ls)
     t["ingest"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    words, st, nf = voxelize(ing, ls.dims, literal)
+    words, st, nf = voxelize(ing, ls.dims, literal, mode)
     t["voxelize"] = time.perf_counter() - t0
     st = st or ing.status
     t0 = time.perf_counter()
@@ -291,9 +302,10 @@ def build_frame(ls, eye, cull_mode, alpha=1.0, tau=1.0 / 256.0, literal=False) -
     vlev = visibility_pyramid(vis)
     t["cull_mips"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    offsets, ids, total = csr(ing, words, vis, literal)
+    offsets, ids, total = csr(ing, words, vis, literal, mode)
     t["lists"] = time.perf_counter() - t0
-    return Frame(tuple(ls.dims), ing, words, st, nf, occ, blk, vis, vlev, offsets, ids, total, eq, lim, t)
+    return Frame(tuple(ls.dims), ing, words, st, nf, occ, blk, vis, vlev, offsets, ids, total, eq, lim, t,
+                 _mode(literal, mode))
 
 
 def recull_frame(fr: Frame, ls, eye, cull_mode, alpha=1.0, tau=1.0 / 256.0) -> Frame:
@@ -308,10 +320,10 @@ def recull_frame(fr: Frame, ls, eye, cull_mode, alpha=1.0, tau=1.0 / 256.0) -> F
     vlev = visibility_pyramid(vis)
     t["cull_mips"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    offsets, ids, total = csr(fr.ing, fr.words, vis)
+    offsets, ids, total = csr(fr.ing, fr.words, vis, mode=fr.mode)
     t["lists"] = time.perf_counter() - t0
     return Frame(fr.dims, fr.ing, fr.words, fr.status, fr.n_fragments, fr.occ, fr.blocking, vis, vlev, offsets, ids,
-                 total, eq, lim, t)
+                 total, eq, lim, t, fr.mode)
 
 
 @dataclass

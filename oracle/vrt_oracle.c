@@ -237,6 +237,95 @@ static int64_t segment_voxels_literal(const int32_t *Ai, const int32_t *Bi, int6
     return n;
 }
 
+/* The two comparison voxelizers of Section 4.1 (Table 2), from their
+ * definitions.  Neither is conservative for capsules; they are measured
+ * against the capsule voxelizer, not used for rendering.
+ *
+ * Thin line ("DDA"): the voxels whose open interior the open segment (A, B)
+ * meets, plus the voxels holding A and B (half-open cells); the radius plays
+ * no part.  Each voxel of the segment's voxel box is tested on its own: the
+ * parameters t in (0, 1) at which the segment is strictly inside the cube on
+ * one axis form an open interval (lo_c/den_c, hi_c/den_c), and the cube's
+ * interior is met iff every lower end is below every upper end (exact
+ * integer cross-multiplication). */
+static int open_segment_meets_voxel(const int64_t *A, const int64_t *d, const int64_t *v)
+{
+    int64_t ln[4] = {0, 0, 0, 0}, ld[4] = {1, 1, 1, 1};  /* lower ends n/d, d > 0 (the first is t = 0) */
+    int64_t un[4] = {1, 1, 1, 1}, ud[4] = {1, 1, 1, 1};  /* upper ends (the first is t = 1) */
+    for (int c = 0; c < 3; c++) {
+        int64_t lo = v[c] * QS, hi = (v[c] + 1) * QS;
+        if (d[c] == 0) {
+            if (!(lo < A[c] && A[c] < hi)) return 0;
+            continue;
+        }
+        int64_t n1 = lo - A[c], n2 = hi - A[c], den = d[c];
+        if (den < 0) { int64_t t = -n1; n1 = -n2; n2 = t; den = -den; }
+        ln[c + 1] = n1; ld[c + 1] = den;
+        un[c + 1] = n2; ud[c + 1] = den;
+    }
+    for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++)
+            if (!(ln[i] * ud[j] < un[j] * ld[i])) return 0;
+    return 1;
+}
+
+static int64_t segment_voxels_thin(const int32_t *Ai, const int32_t *Bi, const int32_t *G, visit_fn fn, void *ctx)
+{
+    int64_t A[3], B[3], d[3], lo[3], hi[3], ca[3], cb[3];
+    for (int c = 0; c < 3; c++) {
+        A[c] = Ai[c]; B[c] = Bi[c]; d[c] = B[c] - A[c];
+        ca[c] = floordiv(A[c], QS); cb[c] = floordiv(B[c], QS);
+        lo[c] = imax(imin(ca[c], cb[c]) - 1, 0);
+        hi[c] = imin(imax(ca[c], cb[c]) + 1, (int64_t)G[c] - 1);
+    }
+    int64_t n = 0;
+    for (int64_t z = lo[2]; z <= hi[2]; z++)
+        for (int64_t y = lo[1]; y <= hi[1]; y++)
+            for (int64_t x = lo[0]; x <= hi[0]; x++) {
+                int64_t v[3] = {x, y, z};
+                int endp = (x == ca[0] && y == ca[1] && z == ca[2]) || (x == cb[0] && y == cb[1] && z == cb[2]);
+                if (endp || open_segment_meets_voxel(A, d, v)) {
+                    if (fn) fn(ctx, x, y, z);
+                    n++;
+                }
+            }
+    return n;
+}
+
+/* Capsule AABB: every voxel that touches the capsule's closed bounding box
+ * (the range of step 2 of the capsule voxelizer). */
+static int64_t segment_voxels_aabb(const int32_t *Ai, const int32_t *Bi, int64_t rq, const int32_t *G, visit_fn fn,
+                                   void *ctx)
+{
+    int64_t vlo[3], vhi[3];
+    for (int c = 0; c < 3; c++) {
+        vlo[c] = imax(floordiv(imin(Ai[c], Bi[c]) - rq - 1, QS), 0);
+        vhi[c] = imin(floordiv(imax(Ai[c], Bi[c]) + rq, QS), (int64_t)G[c] - 1);
+        if (vlo[c] > vhi[c]) return 0;
+    }
+    int64_t n = 0;
+    for (int64_t z = vlo[2]; z <= vhi[2]; z++)
+        for (int64_t y = vlo[1]; y <= vhi[1]; y++)
+            for (int64_t x = vlo[0]; x <= vhi[0]; x++) {
+                if (fn) fn(ctx, x, y, z);
+                n++;
+            }
+    return n;
+}
+
+/* Membership by mode: 0 the capsule voxelizer (Alg. 1, corrected Eq. (1)),
+ * 1 the printed Alg. 1 + Eq. (1), 2 the thin line, 3 the capsule AABB. */
+static int64_t segment_voxels_mode(int mode, const int32_t *A, const int32_t *B, int64_t rq, const int32_t *G,
+                                   visit_fn fn, void *ctx)
+{
+    switch (mode) {
+    case 1: return segment_voxels_literal(A, B, rq, G, fn, ctx);
+    case 2: return segment_voxels_thin(A, B, G, fn, ctx);
+    case 3: return segment_voxels_aabb(A, B, rq, G, fn, ctx);
+    default: return segment_voxels_exact(A, B, rq, G, fn, ctx);
+    }
+}
+
 typedef struct { int32_t *out; int64_t cap, n; } list_ctx;
 static void visit_list(void *ctx, int64_t x, int64_t y, int64_t z)
 {
@@ -248,13 +337,12 @@ static void visit_list(void *ctx, int64_t x, int64_t y, int64_t z)
 }
 
 /* Voxel set S(s) of one segment; writes up to cap (x,y,z) triples and returns
- * the full count.  literal != 0 selects the printed Alg. 1 + Eq. (1). */
+ * the full count.  mode: see segment_voxels_mode. */
 int64_t orc_segment_voxels(const int32_t *A, const int32_t *B, int64_t rq, const int32_t *G, int32_t *out,
-                           int64_t cap, int literal)
+                           int64_t cap, int mode)
 {
     list_ctx L = {out, cap, 0};
-    if (literal) return segment_voxels_literal(A, B, rq, G, visit_list, &L);
-    return segment_voxels_exact(A, B, rq, G, visit_list, &L);
+    return segment_voxels_mode(mode, A, B, rq, G, visit_list, &L);
 }
 
 /* ------------------------------------------------------------------ */
@@ -347,10 +435,10 @@ static void visit_accumulate(void *ctx, int64_t x, int64_t y, int64_t z)
 
 /* Fills words[v] = (count + occupancy_sum * 2^16) mod 2^32.  A segment
  * longer than 2^16 steps along an axis is a range error; a voxel with more
- * than 65535 fragments is a count overflow.  literal != 0 uses the printed
- * Alg. 1 + Eq. (1) membership (for the non-conservative comparison only). */
+ * than 65535 fragments is a count overflow.  mode selects the membership
+ * (segment_voxels_mode; only 0 is conservative, the others are comparisons). */
 int orc_voxelize(const int32_t *q, const float *nrm, const uint8_t *interior, const uint8_t *seg_valid,
-                 int64_t nv, int64_t rq, const int32_t *G, uint32_t *words, int64_t *n_fragments, int literal)
+                 int64_t nv, int64_t rq, const int32_t *G, uint32_t *words, int64_t *n_fragments, int mode)
 {
     int64_t nvox = (int64_t)G[0] * G[1] * G[2];
     int64_t *count = (int64_t *)calloc((size_t)nvox, sizeof(int64_t));
@@ -367,8 +455,7 @@ int orc_voxelize(const int32_t *q, const float *nrm, const uint8_t *interior, co
             if (llabs((int64_t)q[3 * (i + 1) + c] - (int64_t)q[3 * i + c]) >= 65536) bad = 1;
         if (bad) { status = ST_RANGE; continue; }
         V.seg = i;
-        nf += literal ? segment_voxels_literal(q + 3 * i, q + 3 * (i + 1), rq, G, visit_accumulate, &V)
-                      : segment_voxels_exact(q + 3 * i, q + 3 * (i + 1), rq, G, visit_accumulate, &V);
+        nf += segment_voxels_mode(mode, q + 3 * i, q + 3 * (i + 1), rq, G, visit_accumulate, &V);
     }
     for (int64_t v = 0; v < nvox; v++) {
         if (count[v] > 65535 && status == ST_OK) status = ST_COUNT_OVERFLOW;
@@ -559,7 +646,7 @@ static void visit_fill(void *ctx, int64_t x, int64_t y, int64_t z)
 /* ids: for every visible voxel, the ascending list of segments whose voxel
  * set contains it, stored at [offsets[v], offsets[v] + count[v]). */
 void orc_fill_lists(const int32_t *q, const uint8_t *seg_valid, int64_t nv, int64_t rq, const int32_t *G,
-                    const uint8_t *vis, const uint32_t *offsets, uint32_t *ids, int literal)
+                    const uint8_t *vis, const uint32_t *offsets, uint32_t *ids, int mode)
 {
     int64_t nvox = (int64_t)G[0] * G[1] * G[2];
     uint32_t *cursor = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)nvox);
@@ -572,8 +659,7 @@ void orc_fill_lists(const int32_t *q, const uint8_t *seg_valid, int64_t nv, int6
             if (llabs((int64_t)q[3 * (i + 1) + c] - (int64_t)q[3 * i + c]) >= 65536) bad = 1;
         if (bad) continue;
         F.seg = i;
-        if (literal) segment_voxels_literal(q + 3 * i, q + 3 * (i + 1), rq, G, visit_fill, &F);
-        else segment_voxels_exact(q + 3 * i, q + 3 * (i + 1), rq, G, visit_fill, &F);
+        segment_voxels_mode(mode, q + 3 * i, q + 3 * (i + 1), rq, G, visit_fill, &F);
     }
     free(cursor);
 }

@@ -303,3 +303,122 @@ def test_alpha_culling_through_a_wall_of_lines(orc):
     assert row[19:27].all()                # under the thin part: visible
     fo = orc.build_frame(ls, eye, orc.CULL_OPAQUE)
     assert fo.vis[1, 16, 19:27].sum() == 0  # opaque culling hides both
+
+
+# ---------------------------------------------------------------------------
+# Segments and clip planes (Sec. 3.1: capsules clipped at interior joints by
+# the plane whose normal is the polyline's tangent there; Sec. 3.3: primitive
+# i is the segment from vertex i to vertex i + 1 of one polyline).
+
+
+def test_segment_flags_and_clip_normals_from_the_polyline_definition(orc):
+    """Ragged polylines (one vertex, two, many; a repeated vertex giving a zero tangent): vertex i starts a
+    segment iff vertex i + 1 belongs to the same polyline, and only vertices with a neighbour on both sides
+    and a non-zero central difference carry a clip normal, which is that difference normalized (checked in
+    binary64 against the integer positions, to the binary32 rounding of the normalization)."""
+    polys = [[[2.0, 2.0, 2.0]],
+             [[3.0, 3.0, 3.0], [5.0, 7.0, 4.0]],
+             [[1.0, 1.0, 1.0], [4.0, 2.0, 1.0], [6.5, 3.25, 2.0], [6.5, 6.0, 5.5], [2.0, 9.0, 8.0]],
+             [[8.0, 8.0, 8.0], [9.0, 8.0, 8.0], [8.0, 8.0, 8.0], [8.0, 8.0, 8.0]]]
+    ls = make_lineset(polys, 16, 0.5)
+    ing = orc.ingest(ls)
+    off = ls.offsets
+    q = ing.q.astype(np.int64)
+    for p in range(len(off) - 1):
+        for i in range(off[p], off[p + 1]):
+            assert ing.seg_valid[i] == (i + 1 < off[p + 1]), i
+            inner = off[p] < i < off[p + 1] - 1
+            T = (q[i + 1] - q[i - 1]) if inner else np.zeros(3, np.int64)
+            if inner and (T != 0).any():
+                assert ing.interior[i] == 1, i
+                n = T / math.sqrt(float((T * T).sum()))
+                assert np.abs(ing.nrm[i].astype(np.float64) - n).max() < 2e-7, i
+            else:
+                assert ing.interior[i] == 0 and (ing.nrm[i] == 0).all(), i
+    # (9, 8, 8) sits between two copies of (8, 8, 8): zero tangent, no clip; the next vertex has one
+    assert ing.interior[off[3] + 2] == 1 and ing.interior[off[3] + 1] == 0
+
+
+# ---------------------------------------------------------------------------
+# The comparison voxelizers of Sec. 4.1 (Table 2): a thin line walk ("DDA")
+# and the capsule's bounding box.  Pinned against their definitions evaluated
+# here with Python fractions, and against the capsule voxelizer they are
+# compared with.
+
+
+def _thin_reference(A, B, G):
+    """Voxels whose open interior the open segment (A, B) meets, plus the cells of A and B (Q units)."""
+    out = set()
+    ca = tuple(a // Q for a in A)
+    cb = tuple(b // Q for b in B)
+    for v in (ca, cb):
+        if all(0 <= v[c] < G for c in range(3)):
+            out.add(v)
+    lo_v = [max(min(ca[c], cb[c]) - 1, 0) for c in range(3)]
+    hi_v = [min(max(ca[c], cb[c]) + 1, G - 1) for c in range(3)]
+    for x in range(lo_v[0], hi_v[0] + 1):
+        for y in range(lo_v[1], hi_v[1] + 1):
+            for z in range(lo_v[2], hi_v[2] + 1):
+                t0, t1 = Fraction(0), Fraction(1)
+                ok = True
+                for c, vc in enumerate((x, y, z)):
+                    d = B[c] - A[c]
+                    lo, hi = vc * Q, (vc + 1) * Q
+                    if d == 0:
+                        ok &= lo < A[c] < hi
+                        continue
+                    ta, tb = Fraction(lo - A[c], d), Fraction(hi - A[c], d)
+                    t0, t1 = max(t0, min(ta, tb)), min(t1, max(ta, tb))
+                if ok and t0 < t1:
+                    out.add((x, y, z))
+    return out
+
+
+def _set(arr):
+    return {tuple(int(c) for c in v) for v in arr}
+
+
+def test_thin_line_voxels_equal_their_definition(orc):
+    rng = np.random.default_rng(41)
+    G = 12
+    segs = [((Q * 2 + 128, Q * 2 + 128, Q * 2 + 128), (Q * 9 + 128, Q * 2 + 128, Q * 2 + 128)),  # axis-aligned
+            ((Q * 1, Q * 1, Q * 1), (Q * 5, Q * 5, Q * 5)),          # through voxel corners
+            ((Q * 3, Q * 4 + 128, Q * 5 + 128), (Q * 8, Q * 4 + 128, Q * 5 + 128)),  # starts on a face
+            ((Q * 4, Q * 4, Q * 6 + 77), (Q * 7, Q * 7, Q * 6 + 77)),  # along a face diagonal, edge ties
+            ((Q * 3, Q * 5, Q * 2), (Q * 9, Q * 5, Q * 2)),          # lies on voxel faces: no interior is met
+            ((Q * 6 + 5, Q * 6 + 9, Q * 6 + 11), (Q * 6 + 5, Q * 6 + 9, Q * 6 + 11)),  # zero length
+            ((-Q * 2, Q * 3 + 7, Q * 4 + 1), (Q * 14, Q * 5 + 3, Q * 6 + 200))]  # leaves the grid
+    for _ in range(300):
+        A = rng.integers(-Q, (G + 1) * Q, 3)
+        B = A + rng.integers(-4 * Q, 4 * Q, 3)
+        if rng.uniform() < 0.3:  # snap some coordinates to voxel faces
+            A = np.where(rng.uniform(size=3) < 0.5, (A // Q) * Q, A)
+            B = np.where(rng.uniform(size=3) < 0.5, (B // Q) * Q, B)
+        segs.append((tuple(int(a) for a in A), tuple(int(b) for b in B)))
+    for A, B in segs:
+        got = _set(orc.segment_voxels(A, B, 0, (G, G, G), mode=orc.VOX_THIN))
+        assert got == _thin_reference(A, B, G), (A, B)
+    # closed forms: a straight run of voxels; the corner diagonal visits only the diagonal voxels
+    assert _set(orc.segment_voxels(*segs[0], 0, (G, G, G), mode=orc.VOX_THIN)) == {(x, 2, 2) for x in range(2, 10)}
+    assert _set(orc.segment_voxels(*segs[1], 0, (G, G, G), mode=orc.VOX_THIN)) == {(k, k, k) for k in range(1, 6)}
+    assert _set(orc.segment_voxels(*segs[4], 0, (G, G, G), mode=orc.VOX_THIN)) == {(3, 5, 2), (9, 5, 2)}
+
+
+def test_comparison_voxelizers_bracket_the_capsule(orc):
+    """thin line (radius ignored) <= capsule voxels <= capsule AABB voxels, and the AABB set is exactly the
+    voxels whose closed cube meets the capsule's closed bounding box."""
+    rng = np.random.default_rng(43)
+    G = 12
+    for _ in range(300):
+        A = rng.integers(0, G * Q, 3)
+        B = A + rng.integers(-5 * Q, 5 * Q, 3)
+        rq = int(rng.choice([0, 51, 128, 200]))
+        thin = _set(orc.segment_voxels(A, B, rq, (G, G, G), mode=orc.VOX_THIN))
+        caps = _set(orc.segment_voxels(A, B, rq, (G, G, G)))
+        box = _set(orc.segment_voxels(A, B, rq, (G, G, G), mode=orc.VOX_AABB))
+        assert thin <= caps <= box, (A, B, rq)
+        lo = np.minimum(A, B) - rq
+        hi = np.maximum(A, B) + rq
+        ref = {(x, y, z) for x in range(G) for y in range(G) for z in range(G)
+               if all(v * Q <= h and l <= (v + 1) * Q for v, l, h in zip((x, y, z), lo, hi))}
+        assert box == ref, (A, B, rq)
