@@ -862,7 +862,8 @@ typedef struct {
     const uint32_t *ids;
     double O[3];             /* eye, voxel units */
     int mode;                /* 0 opaque, 1 transparent */
-    double alpha, tau;
+    double alpha, tau;       /* alpha: opacity of a hit on a segment without its own colour */
+    const float *rgba;       /* NULL, or per segment s: colour and opacity at rgba[4 s .. 4 s + 3] */
 } trace_in;
 
 typedef struct {
@@ -871,6 +872,7 @@ typedef struct {
     int64_t vox[3];
     int counted;
     double col[3];
+    double alpha;   /* opacity of this hit when composited */
     double face_margin;
 } acc_hit;
 
@@ -959,28 +961,28 @@ static int idset_add(idset *S, int64_t id)
     return 1;
 }
 
-/* Composites hits sorted by (t, id) front to back: C += T*alpha*c,
- * T *= (1 - alpha), stopping before a hit once T < tau.  Returns the number
- * of hits composited. */
-static int64_t composite(const acc_hit *h, int64_t n, double alpha, double tau, double *rgba)
+/* Composites hits sorted by (t, id) front to back, each with its own
+ * opacity a_k: C += T*a_k*c_k, T *= (1 - a_k), stopping before a hit once
+ * T < tau.  Returns the number of hits composited. */
+static int64_t composite(const acc_hit *h, int64_t n, double tau, double *rgba)
 {
     double T = 1.0, C[3] = {0, 0, 0};
     int64_t k = 0;
     for (; k < n; k++) {
         if (T < tau) break;
-        for (int c = 0; c < 3; c++) C[c] += T * alpha * h[k].col[c];
-        T *= (1.0 - alpha);
+        for (int c = 0; c < 3; c++) C[c] += T * h[k].alpha * h[k].col[c];
+        T *= (1.0 - h[k].alpha);
     }
     rgba[0] = C[0]; rgba[1] = C[1]; rgba[2] = C[2]; rgba[3] = 1.0 - T;
     return k;
 }
 
-/* Number of hits composited before transmittance drops below tau. */
-static int64_t layers_before_tau(double alpha, double tau, int64_t n)
+/* Number of the sorted hits composited before transmittance drops below tau. */
+static int64_t layers_before_tau(const acc_hit *h, int64_t n, double tau)
 {
     double T = 1.0;
     int64_t k = 0;
-    while (k < n && !(T < tau)) { T *= (1.0 - alpha); k++; }
+    while (k < n && !(T < tau)) { T *= (1.0 - h[k].alpha); k++; }
     return k;
 }
 
@@ -994,10 +996,21 @@ static void segment_geom(const trace_in *T, int64_t s, double *A, double *B, dou
     }
 }
 
-static void segment_colour(const double *A, const double *B, double *col)
+/* Colour and opacity of a hit on segment s: the caller's per-segment RGBA
+ * (opacity clamped to [0, 1]), else the absolute unit tangent with the
+ * default opacity. */
+static void segment_colour(const trace_in *T, int64_t s, const double *A, const double *B, double *col,
+                           double *alpha)
 {
+    if (T->rgba) {
+        for (int c = 0; c < 3; c++) col[c] = (double)T->rgba[4 * s + c];
+        double a = (double)T->rgba[4 * s + 3];
+        *alpha = a < 0.0 ? 0.0 : (a > 1.0 ? 1.0 : a);
+        return;
+    }
     double d[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]}, n = sqrt(dot3(d, d));
     for (int c = 0; c < 3; c++) col[c] = n > 0 ? fabs(d[c]) / n : 0.0;
+    *alpha = T->alpha;
 }
 
 typedef struct { double m, t; } near_rec; /* hit/miss or clip margin, at ray parameter t */
@@ -1034,7 +1047,7 @@ static void eval_candidate(const trace_in *T, const double *D, int64_t s, hitbuf
     x.id = s;
     x.t = H.t;
     voxel_of(H.P, D, x.vox);
-    segment_colour(A, Bv, x.col);
+    segment_colour(T, s, A, Bv, x.col, &x.alpha);
     if (!H.accepted) return; /* a rejected entry never counts; its clip margin is in nr */
     x.counted = counted_at(T, x.vox);
     x.face_margin = face_margin(T, H.P, x.vox, s, x.counted);
@@ -1055,7 +1068,7 @@ static double result_extent(const trace_in *T, const hitbuf *B)
         qsort(c, (size_t)n, sizeof(acc_hit), cmp_hit);
         if (T->mode == 0) ext = c[0].t;
         else {
-            int64_t k = layers_before_tau(T->alpha, T->tau, n);
+            int64_t k = layers_before_tau(c, n, T->tau);
             if (k < n) ext = c[k].t;
         }
     }
@@ -1166,7 +1179,7 @@ static void trace_one(const trace_in *T, const double *D, int brute, int64_t *ou
         }
         t_rel = *out_t;
     } else {
-        int64_t k = composite(cnt, nc, T->alpha, T->tau, rgba);
+        int64_t k = composite(cnt, nc, T->tau, rgba);
         *n_comp = k;
         t_rel = (k < nc) ? cnt[k].t : INFINITY;
         for (int64_t i = 0; i + 1 < nc && i < k; i++) {
@@ -1239,13 +1252,13 @@ static void trace_invoxel(const trace_in *T, const double *D, int64_t *out_id, d
                     acc_hit x;
                     x.id = s; x.t = H.t; x.counted = 1; x.face_margin = INFINITY;
                     x.vox[0] = v[0]; x.vox[1] = v[1]; x.vox[2] = v[2];
-                    segment_colour(A, Bv, x.col);
+                    segment_colour(T, s, A, Bv, x.col, &x.alpha);
                     hb_push(&B, &x);
                 }
                 if (B.n > before) qsort(B.h + before, (size_t)(B.n - before), sizeof(acc_hit), cmp_hit);
             }
             if (T->mode == 0 && B.n > 0) break;
-            if (T->mode == 1 && layers_before_tau(T->alpha, T->tau, B.n) < B.n) break;
+            if (T->mode == 1 && layers_before_tau(B.h, B.n, T->tau) < B.n) break;
             int a = 0;
             for (int c = 1; c < 3; c++)
                 if (tnext[c] < tnext[a]) a = c;
@@ -1263,7 +1276,7 @@ static void trace_invoxel(const trace_in *T, const double *D, int64_t *out_id, d
         if (B.n > 0) { rgba[0] = B.h[0].col[0]; rgba[1] = B.h[0].col[1]; rgba[2] = B.h[0].col[2]; rgba[3] = 1.0; }
         *n_comp = B.n > 0;
     } else {
-        *n_comp = composite(B.h, B.n, T->alpha, T->tau, rgba);
+        *n_comp = composite(B.h, B.n, T->tau, rgba);
     }
     free(B.h);
 }
@@ -1278,8 +1291,8 @@ static void trace_invoxel(const trace_in *T, const double *D, int64_t *out_id, d
 void orc_trace(int32_t Gx, int32_t Gy, int32_t Gz, const int32_t *q, const float *nrm, const uint8_t *interior,
                const uint8_t *seg_valid, int64_t nv, int64_t rq, const uint8_t *vis, const uint32_t *words,
                const uint32_t *offsets, const uint32_t *ids, const int64_t *eye_q, const float *dirs,
-               int64_t npix, int mode, double alpha, double tau, int brute, int64_t *out_id, double *out_t,
-               double *out_rgba, double *m_geom, double *m_face, int64_t *n_comp)
+               int64_t npix, int mode, double alpha, double tau, const float *seg_rgba, int brute, int64_t *out_id,
+               double *out_t, double *out_rgba, double *m_geom, double *m_face, int64_t *n_comp)
 {
     trace_in T;
     T.Gx = Gx; T.Gy = Gy; T.Gz = Gz;
@@ -1287,7 +1300,7 @@ void orc_trace(int32_t Gx, int32_t Gy, int32_t Gz, const int32_t *q, const float
     T.r = (double)rq / QS;
     T.vis = vis; T.words = words; T.offsets = offsets; T.ids = ids;
     for (int c = 0; c < 3; c++) T.O[c] = (double)eye_q[c] / QS;
-    T.mode = mode; T.alpha = alpha; T.tau = tau;
+    T.mode = mode; T.alpha = alpha; T.tau = tau; T.rgba = seg_rgba;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < npix; k++) {
         double D[3] = {dirs[3 * k], dirs[3 * k + 1], dirs[3 * k + 2]};

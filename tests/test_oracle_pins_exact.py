@@ -422,3 +422,54 @@ def test_comparison_voxelizers_bracket_the_capsule(orc):
         ref = {(x, y, z) for x in range(G) for y in range(G) for z in range(G)
                if all(v * Q <= h and l <= (v + 1) * Q for v, l, h in zip((x, y, z), lo, hi))}
         assert box == ref, (A, B, rq)
+
+
+# ---------------------------------------------------------------------------
+# Per-segment colour and opacity (the boundary's optional RGBA per segment):
+# each hit is composited with its own opacity, front to back.
+
+
+def test_trace_per_segment_rgba_composite(orc):
+    """Front line (colour c1, opacity a1) over a back line (c2, a2), seen from above:
+    C = a1 c1 + (1 - a1) a2 c2, A = 1 - (1 - a1)(1 - a2); opaque shows c1 with alpha 1."""
+    G = 64
+    front = [[20 + k, 32.3, 40.5] for k in range(25)]
+    back = [[32.4, 20 + k, 20.5] for k in range(25)]
+    ls = make_lineset([back, front], G, 0.5)
+    cam = centre_camera((32.4, 32.3, 60), (32.4, 32.3, 0), G)
+    c1, a1, c2, a2 = np.array([0.2, 0.7, 0.1]), 0.6, np.array([0.9, 0.3, 0.5]), 0.25
+    rgba = np.zeros((ls.n_vertices, 4), np.float32)
+    rgba[:25] = np.append(c2, a2)     # back line: vertices 0..24
+    rgba[25:] = np.append(c1, a1)     # front line: vertices 25..49
+    fr = orc.build_frame(ls, cam.eye, 0)
+    pix = [(cam.height // 2) * cam.width + cam.width // 2]
+    tr = orc.trace(fr, ls, cam, pix, 1, alpha=0.9, seg_rgba=rgba)
+    f32 = lambda v: np.float32(v).astype(np.float64)  # noqa: E731 - the colours are stored in binary32
+    A1, A2 = f32(a1), f32(a2)
+    exp_c = A1 * f32(c1) + (1 - A1) * A2 * f32(c2)
+    assert tr.n_comp[0] == 2
+    assert np.allclose(tr.rgba[0][:3], exp_c, rtol=0, atol=1e-12)
+    assert abs(tr.rgba[0][3] - (1 - (1 - A1) * (1 - A2))) < 1e-12
+    tro = orc.trace(fr, ls, cam, pix, 0, seg_rgba=rgba)
+    assert np.allclose(tro.rgba[0], np.append(f32(c1), 1.0), rtol=0, atol=1e-12)
+
+
+def test_trace_rgba_equal_to_the_default_reproduces_it(orc):
+    """RGBA rows holding |unit tangent| and the default opacity give the default image (the two colour sources
+    agree), on a random-walk set, opaque and transparent."""
+    ls = synth.random_walk_set(seed=13, n_poly=30, n_seg=20, G=32)
+    cam = synth.grid_camera(ls, 48, 36)
+    fr = orc.build_frame(ls, cam.eye, 0)
+    q = fr.ing.q.astype(np.float64)
+    d = np.zeros_like(q)
+    d[:-1] = q[1:] - q[:-1]
+    n = np.linalg.norm(d, axis=1, keepdims=True)
+    col = np.where(n > 0, np.abs(d) / np.where(n > 0, n, 1), 0.0)
+    pix = np.arange(cam.width * cam.height)
+    for mode, alpha in ((0, 1.0), (1, 0.5)):  # 0.5 and the colours' binary32 rounding: compare loosely
+        rgba = np.concatenate([col, np.full((len(q), 1), alpha)], axis=1).astype(np.float32)
+        a = orc.trace(fr, ls, cam, pix, mode, alpha=alpha)
+        b = orc.trace(fr, ls, cam, pix, mode, alpha=alpha, seg_rgba=rgba)
+        assert np.array_equal(a.id, b.id)
+        assert np.abs(a.rgba - b.rgba).max() < 1e-6
+        assert (a.id >= 0).sum() > 100
