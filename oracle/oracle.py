@@ -72,6 +72,9 @@ def lib():
         L.orc_ray_dirs.argtypes = [P, P, P, i32, i32, P, i64, P]
         L.orc_trace.argtypes = [i32, i32, i32, P, P, P, P, i64, i64, P, P, P, P, P, P, i64, C.c_int,
                                 f64, f64, P, C.c_int, P, P, P, P, P, P]
+        L.orc_shade_dirs.argtypes = [i32, P]
+        L.orc_shade_light.argtypes = [P, P]
+        L.orc_shade.argtypes = [P, P, i32, P, i32, P, P, f64, P, P, P]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -369,3 +372,36 @@ def trace(fr: Frame, ls, cam, pix, mode, alpha=1.0, tau=1.0 / 256.0, brute=False
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+# ---------------------------------------------------------------------------
+# voxel-space shading (Section 3.4)
+
+
+def shade_dirs(K):
+    U = np.zeros((K, 3), np.int32)
+    lib().orc_shade_dirs(int(K), _p(U))
+    return U
+
+
+def shade_light(light):
+    L = np.zeros(3, np.int32)
+    lib().orc_shade_light(_p(np.ascontiguousarray(light, np.float32)), _p(L))
+    return L
+
+
+def shade(occ, vis, n_cones=16, n_samples=4, light=(0.3, 0.5, 0.8), ambient=0.3):
+    """Ambient occlusion, shadow and lit value of every visible voxel (float64 arrays shaped like vis).
+    occ: the occupancy pyramid (level 0 first); vis: level-0 visibility."""
+    G = _i32(vis.shape[::-1])
+    lv = [np.ascontiguousarray(o, np.uint16) for o in occ[:n_samples + 1]]
+    if len(lv) < n_samples + 1:
+        raise ValueError("the pyramid has fewer levels than samples")
+    ptrs = (C.c_void_p * len(lv))(*[o.ctypes.data for o in lv])
+    U = shade_dirs(n_cones)
+    L = shade_light(light)
+    ao, sh, lit = (np.zeros(vis.shape, np.float64) for _ in range(3))
+    lib().orc_shade(_p(G), ptrs, int(n_samples), _p(np.ascontiguousarray(vis, np.uint8)), int(n_cones), _p(U),
+                    _p(L), float(ambient), _p(ao), _p(sh), _p(lit))
+    return ao, sh, lit
+

@@ -665,6 +665,112 @@ void orc_fill_lists(const int32_t *q, const uint8_t *seg_valid, int64_t nv, int6
 }
 
 /* ------------------------------------------------------------------ */
+/* Voxel-space shading (Section 3.4): ambient occlusion from cones traced  */
+/* through the occupancy pyramid and a directional shadow ray, evaluated   */
+/* for the visible voxels only; the tracer takes one value per hit.         */
+
+/* Cone directions: the K points of a Fibonacci sphere (z evenly spaced,
+ * longitude advancing by the golden angle), in 1/256 units, rounded to the
+ * nearest integer in binary64. */
+void orc_shade_dirs(int32_t K, int32_t *U)
+{
+    const double golden = M_PI * (3.0 - sqrt(5.0));
+    for (int32_t k = 0; k < K; k++) {
+        double z = 1.0 - (2.0 * k + 1.0) / (double)K;
+        double r = sqrt(1.0 - z * z), phi = golden * (double)k;
+        U[3 * k] = (int32_t)rint(256.0 * r * cos(phi));
+        U[3 * k + 1] = (int32_t)rint(256.0 * r * sin(phi));
+        U[3 * k + 2] = (int32_t)rint(256.0 * z);
+    }
+}
+
+/* Light direction in 1/256 units (normalized, then rounded in binary64). */
+void orc_shade_light(const float *l, int32_t *L)
+{
+    double n = sqrt((double)l[0] * l[0] + (double)l[1] * l[1] + (double)l[2] * l[2]);
+    for (int c = 0; c < 3; c++) L[c] = (int32_t)rint(256.0 * (double)l[c] / n);
+}
+
+/* Occupancy (fraction) of cell c at pyramid level lv (dims d); 0 outside. */
+static double occ_cell(const uint16_t *lv, const int64_t *d, const int64_t *c)
+{
+    for (int a = 0; a < 3; a++)
+        if (c[a] < 0 || c[a] >= d[a]) return 0.0;
+    return lv[(c[2] * d[1] + c[1]) * d[0] + c[0]] / 256.0;
+}
+
+/* For every voxel v with vis[v] != 0 (dense x-fastest arrays, grid G):
+ *   ambient occlusion: for each cone k, samples j = 1..J at 2^j voxels from
+ *     the voxel centre along U_k, each read from the level-j cell holding it
+ *     (floor division in 1/256 units); the cone's opacity accumulates front
+ *     to back, a += (1 - a) o_j, and AO(v) is the mean of 1 - a over the K
+ *     cones;
+ *   shadow: the ray from the voxel centre along L through the level-0 grid
+ *     (integer walk, tied axes step together, v itself excluded) until it
+ *     leaves the grid; S(v) is the product of 1 - o0(u) over the voxels u
+ *     it enters;
+ *   lit(v) = AO(v) (ambient + (1 - ambient) S(v)).
+ * levels[j] points at occupancy level j (dims ceil(G / 2^j)), j = 0..J.
+ * Invisible voxels get ao = sh = lit = 0. */
+void orc_shade(const int32_t *G, const uint16_t *const *levels, int32_t J, const uint8_t *vis, int32_t K,
+               const int32_t *U, const int32_t *L, double ambient, double *ao, double *sh, double *lit)
+{
+    int64_t nvox = (int64_t)G[0] * G[1] * G[2];
+    int64_t dims[8][3];
+    for (int32_t j = 0; j <= J; j++)
+        for (int a = 0; a < 3; a++) {
+            int64_t d = G[a];
+            for (int32_t t = 0; t < j; t++) d = (d + 1) / 2;
+            dims[j][a] = d;
+        }
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t v = 0; v < nvox; v++) {
+        ao[v] = sh[v] = lit[v] = 0.0;
+        if (!vis[v]) continue;
+        int64_t p[3] = {v % G[0], (v / G[0]) % G[1], v / ((int64_t)G[0] * G[1])};
+        int64_t C[3];
+        for (int a = 0; a < 3; a++) C[a] = p[a] * QS + QS / 2;
+        double sum = 0.0;
+        for (int32_t k = 0; k < K; k++) {
+            double acc = 0.0;
+            for (int32_t j = 1; j <= J; j++) {
+                int64_t cell[3];
+                for (int a = 0; a < 3; a++)
+                    cell[a] = floordiv(C[a] + ((int64_t)U[3 * k + a] << j), (int64_t)QS << j);
+                acc += (1.0 - acc) * occ_cell(levels[j], dims[j], cell);
+            }
+            sum += 1.0 - acc;
+        }
+        ao[v] = sum / (double)K;
+        /* shadow walk: next crossing on axis a at parameter (X_a - C_a) / L_a */
+        double T = 1.0;
+        int64_t u[3] = {p[0], p[1], p[2]};
+        int any = L[0] != 0 || L[1] != 0 || L[2] != 0;
+        while (any) {
+            int64_t num[3], den[3];
+            int best = -1;
+            for (int a = 0; a < 3; a++) {
+                den[a] = llabs((int64_t)L[a]);
+                if (den[a] == 0) continue;
+                int64_t X = (u[a] + (L[a] > 0)) * QS;
+                num[a] = llabs(X - C[a]);
+                if (best < 0 || num[a] * den[best] < num[best] * den[a]) best = a;
+            }
+            int out = 0;
+            for (int a = 0; a < 3; a++) {
+                if (den[a] == 0 || num[a] * den[best] != num[best] * den[a]) continue;
+                u[a] += L[a] > 0 ? 1 : -1;
+                if (u[a] < 0 || u[a] >= G[a]) out = 1;
+            }
+            if (out) break;
+            T *= 1.0 - occ_cell(levels[0], dims[0], u);
+        }
+        sh[v] = T;
+        lit[v] = ao[v] * (ambient + (1.0 - ambient) * T);
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Primary rays (Section 3.5: one ray per pixel through its centre).     */
 
 /* Camera basis in binary64, then rounded to binary32:

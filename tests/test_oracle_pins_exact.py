@@ -473,3 +473,66 @@ def test_trace_rgba_equal_to_the_default_reproduces_it(orc):
         assert np.array_equal(a.id, b.id)
         assert np.abs(a.rgba - b.rgba).max() < 1e-6
         assert (a.id >= 0).sum() > 100
+
+
+# ---------------------------------------------------------------------------
+# Voxel-space shading (Sec. 3.4): cone-traced ambient occlusion over the
+# occupancy pyramid, a directional shadow ray, visible voxels only.  Pinned
+# with synthetic pyramids whose answers are closed forms.
+
+
+def _pyramid(G, fill):
+    """Dense occupancy levels (uint16, 1/256 units) of a G^3 grid, every level filled by fill(level, dims)."""
+    lv, d = [], (G, G, G)
+    while True:
+        lv.append(fill(len(lv), d))
+        if d == (1, 1, 1):
+            return lv
+        d = tuple((x + 1) // 2 for x in d)
+
+
+def test_shade_cone_directions_fibonacci(orc):
+    K = 16
+    U = orc.shade_dirs(K).astype(np.float64)
+    golden = math.pi * (3 - math.sqrt(5))
+    for k in range(K):
+        z = 1 - (2 * k + 1) / K
+        assert U[k, 2] == round(256 * z)  # evenly spaced heights (none is a half-step here)
+        assert abs(np.linalg.norm(U[k]) / 256 - 1) < 2e-3
+        phi = math.atan2(U[k, 1], U[k, 0])
+        assert abs(math.remainder(phi - golden * k, 2 * math.pi)) < 0.02 or abs(z) > 0.99
+
+
+def test_shade_constant_field_closed_form(orc):
+    """Every level holds occupancy 1/4: a voxel whose samples all stay inside the grid has AO = (3/4)^J; the
+    shadow ray along +z crosses G - 1 - z voxels, S = (3/4)^(G-1-z); lit = AO (a + (1 - a) S)."""
+    G, J, amb = 64, 4, 0.3
+    occ = _pyramid(G, lambda L, d: np.full(d[::-1], 64, np.uint16))
+    vis = np.zeros((G, G, G), np.uint8)
+    pts = [(32, 32, 32), (30, 35, 40), (20, 25, 44)]
+    for x, y, z in pts:
+        vis[z, y, x] = 1
+    ao, sh, lit = orc.shade(occ, vis, n_cones=16, n_samples=J, light=(0, 0, 1), ambient=amb)
+    for x, y, z in pts:
+        assert ao[z, y, x] == 0.75 ** J
+        assert sh[z, y, x] == 0.75 ** (G - 1 - z)
+        assert abs(lit[z, y, x] - 0.75 ** J * (amb + (1 - amb) * 0.75 ** (G - 1 - z))) < 1e-15
+    assert (lit[vis == 0] == 0).all()
+
+
+def test_shade_empty_surroundings_and_walk_ties(orc):
+    """With nothing around, AO = S = lit = 1.  A diagonal light in the xy plane from a voxel centre passes the
+    corner line shared with its x and y neighbours: a full voxel there casts no shadow (tied axes step
+    together), a full voxel on the diagonal casts a full one, a half-full one halves the light."""
+    G = 32
+    zero = _pyramid(G, lambda L, d: np.zeros(d[::-1], np.uint16))
+    vis = np.zeros((G, G, G), np.uint8)
+    vis[10, 10, 10] = 1
+    ao, sh, lit = orc.shade(zero, vis, light=(1, 1, 0))
+    assert ao[10, 10, 10] == 1 and sh[10, 10, 10] == 1 and lit[10, 10, 10] == 1
+    for cells, expect in (([(11, 10, 10), (10, 11, 10)], 1.0), ([(12, 12, 10)], 0.0), ([(13, 13, 10)], 0.5)):
+        lv = [z.copy() for z in zero]
+        for (x, y, z) in cells:
+            lv[0][z, y, x] = 128 if expect == 0.5 else 256
+        _, sh, _ = orc.shade(lv, vis, light=(1, 1, 0))
+        assert sh[10, 10, 10] == expect, (cells, sh[10, 10, 10])
