@@ -71,7 +71,7 @@ def lib():
         L.orc_camera_consts.argtypes = [P, P, P, f32, i32, i32, P, P, P]
         L.orc_ray_dirs.argtypes = [P, P, P, i32, i32, P, i64, P]
         L.orc_trace.argtypes = [i32, i32, i32, P, P, P, P, i64, i64, P, P, P, P, P, P, i64, C.c_int,
-                                f64, f64, P, C.c_int, P, P, P, P, P, P]
+                                f64, f64, P, P, C.c_int, P, P, P, P, P, P]
         L.orc_shade_dirs.argtypes = [i32, P]
         L.orc_shade_light.argtypes = [P, P]
         L.orc_shade.argtypes = [P, P, i32, P, i32, P, P, f64, P, P, P]
@@ -342,9 +342,10 @@ class TraceResult:
 
 
 def trace(fr: Frame, ls, cam, pix, mode, alpha=1.0, tau=1.0 / 256.0, brute=False, dirs=None,
-          invoxel=False, seg_rgba=None) -> TraceResult:
+          invoxel=False, seg_rgba=None, lit=None) -> TraceResult:
     """brute: test every segment; invoxel: the paper's per-voxel acceptance rule.  seg_rgba: None (colour =
-    |unit tangent|, opacity alpha) or float32 [n_vertices, 4], the colour and opacity of segment i in row i."""
+    |unit tangent|, opacity alpha) or float32 [n_vertices, 4], the colour and opacity of segment i in row i.
+    lit: None or the voxel-space shading (float64, shaped like the grid) that scales each hit's colour."""
     pix = np.ascontiguousarray(pix, np.int64)
     if dirs is None:
         dirs = ray_dirs(cam, pix)
@@ -361,12 +362,16 @@ def trace(fr: Frame, ls, cam, pix, mode, alpha=1.0, tau=1.0 / 256.0, brute=False
     ids = fr.ids if fr.ids.size else np.zeros(1, np.uint32)
     if seg_rgba is not None:
         seg_rgba = np.ascontiguousarray(seg_rgba, np.float32).reshape(-1, 4)
+    lit_arr = None if lit is None else np.ascontiguousarray(lit, np.float64)
+    if lit_arr is not None and lit_arr.shape != fr.vis.shape:
+        raise ValueError("lit must be shaped like the grid")
     if seg_rgba is not None and seg_rgba.shape[0] < fr.ing.q.shape[0]:
         raise ValueError("rgba needs one row per vertex")
     lib().orc_trace(gx, gy, gz, _p(fr.ing.q), _p(fr.ing.nrm), _p(fr.ing.interior), _p(fr.ing.seg_valid),
                     fr.ing.q.shape[0], fr.ing.rq, _p(fr.vis), _p(fr.words), _p(fr.offsets), _p(ids), _p(eq),
                     _p(np.ascontiguousarray(dirs, np.float32)), n, int(mode), float(alpha), float(tau),
-                    None if seg_rgba is None else _p(seg_rgba), 2 if invoxel else int(brute), _p(out_id), _p(out_t), _p(rgba), _p(mg), _p(mf), _p(nc))
+                    None if seg_rgba is None else _p(seg_rgba), None if lit is None else _p(lit_arr),
+                    2 if invoxel else int(brute), _p(out_id), _p(out_t), _p(rgba), _p(mg), _p(mf), _p(nc))
     return TraceResult(pix, out_id, out_t, out_t * float(ls.voxel_size), rgba, mg, mf, nc)
 
 

@@ -970,6 +970,8 @@ typedef struct {
     int mode;                /* 0 opaque, 1 transparent */
     double alpha, tau;       /* alpha: opacity of a hit on a segment without its own colour */
     const float *rgba;       /* NULL, or per segment s: colour and opacity at rgba[4 s .. 4 s + 3] */
+    const double *lit;       /* NULL, or the voxel-space shading (dense): a hit's colour is scaled by the
+                                value of the voxel holding its point (Section 3.4, one sample per hit) */
 } trace_in;
 
 typedef struct {
@@ -1156,6 +1158,8 @@ static void eval_candidate(const trace_in *T, const double *D, int64_t s, hitbuf
     segment_colour(T, s, A, Bv, x.col, &x.alpha);
     if (!H.accepted) return; /* a rejected entry never counts; its clip margin is in nr */
     x.counted = counted_at(T, x.vox);
+    if (T->lit && x.counted)
+        for (int c = 0; c < 3; c++) x.col[c] *= T->lit[dense(T, x.vox)];
     x.face_margin = face_margin(T, H.P, x.vox, s, x.counted);
     hb_push(B, &x);
 }
@@ -1359,6 +1363,8 @@ static void trace_invoxel(const trace_in *T, const double *D, int64_t *out_id, d
                     x.id = s; x.t = H.t; x.counted = 1; x.face_margin = INFINITY;
                     x.vox[0] = v[0]; x.vox[1] = v[1]; x.vox[2] = v[2];
                     segment_colour(T, s, A, Bv, x.col, &x.alpha);
+                    if (T->lit)
+                        for (int c = 0; c < 3; c++) x.col[c] *= T->lit[dense(T, v)];
                     hb_push(&B, &x);
                 }
                 if (B.n > before) qsort(B.h + before, (size_t)(B.n - before), sizeof(acc_hit), cmp_hit);
@@ -1397,8 +1403,8 @@ static void trace_invoxel(const trace_in *T, const double *D, int64_t *out_id, d
 void orc_trace(int32_t Gx, int32_t Gy, int32_t Gz, const int32_t *q, const float *nrm, const uint8_t *interior,
                const uint8_t *seg_valid, int64_t nv, int64_t rq, const uint8_t *vis, const uint32_t *words,
                const uint32_t *offsets, const uint32_t *ids, const int64_t *eye_q, const float *dirs,
-               int64_t npix, int mode, double alpha, double tau, const float *seg_rgba, int brute, int64_t *out_id,
-               double *out_t, double *out_rgba, double *m_geom, double *m_face, int64_t *n_comp)
+               int64_t npix, int mode, double alpha, double tau, const float *seg_rgba, const double *lit, int brute,
+               int64_t *out_id, double *out_t, double *out_rgba, double *m_geom, double *m_face, int64_t *n_comp)
 {
     trace_in T;
     T.Gx = Gx; T.Gy = Gy; T.Gz = Gz;
@@ -1406,7 +1412,7 @@ void orc_trace(int32_t Gx, int32_t Gy, int32_t Gz, const int32_t *q, const float
     T.r = (double)rq / QS;
     T.vis = vis; T.words = words; T.offsets = offsets; T.ids = ids;
     for (int c = 0; c < 3; c++) T.O[c] = (double)eye_q[c] / QS;
-    T.mode = mode; T.alpha = alpha; T.tau = tau; T.rgba = seg_rgba;
+    T.mode = mode; T.alpha = alpha; T.tau = tau; T.rgba = seg_rgba; T.lit = lit;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < npix; k++) {
         double D[3] = {dirs[3 * k], dirs[3 * k + 1], dirs[3 * k + 2]};

@@ -536,3 +536,29 @@ def test_shade_empty_surroundings_and_walk_ties(orc):
             lv[0][z, y, x] = 128 if expect == 0.5 else 256
         _, sh, _ = orc.shade(lv, vis, light=(1, 1, 0))
         assert sh[10, 10, 10] == expect, (cells, sh[10, 10, 10])
+
+
+def test_trace_shaded_colour_is_the_hit_voxels_value(orc):
+    """Shading scales each hit's colour by the value of the voxel holding the hit point: with a shading
+    field that is constant per x-slab, the opaque colour of a hit equals |tangent| times the value of the
+    slab its depth lands in, and a constant field s scales a transparent composite by exactly s."""
+    ls = synth.random_walk_set(seed=13, n_poly=30, n_seg=20, G=32)
+    cam = synth.grid_camera(ls, 48, 36)
+    fr = orc.build_frame(ls, cam.eye, 0)
+    pix = np.arange(cam.width * cam.height)
+    base0 = orc.trace(fr, ls, cam, pix, 0)
+    base1 = orc.trace(fr, ls, cam, pix, 1, alpha=0.4)
+    slab = np.broadcast_to(np.linspace(0.2, 1.0, 32)[None, None, :], fr.vis.shape).copy()
+    sh0 = orc.trace(fr, ls, cam, pix, 0, lit=slab)
+    assert np.array_equal(sh0.id, base0.id)
+    hit = base0.id >= 0
+    eye = orc.eye_q(cam.eye, ls) / 256.0
+    dirs = orc.ray_dirs(cam, pix).astype(np.float64)
+    P = eye + dirs[hit] * base0.t[hit][:, None]
+    s = np.linspace(0.2, 1.0, 32)[np.floor(P[:, 0]).astype(int)]
+    ok = (np.abs(P[:, 0] - np.round(P[:, 0])) > 1e-6)  # hit points not on an x face
+    assert np.allclose(sh0.rgba[hit][ok, :3], base0.rgba[hit][ok, :3] * s[ok][:, None], atol=1e-12)
+    const = np.full(fr.vis.shape, 0.625)
+    sh1 = orc.trace(fr, ls, cam, pix, 1, alpha=0.4, lit=const)
+    assert np.allclose(sh1.rgba[:, :3], 0.625 * base1.rgba[:, :3], atol=1e-12)
+    assert np.allclose(sh1.rgba[:, 3], base1.rgba[:, 3], atol=1e-12)
