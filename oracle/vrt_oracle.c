@@ -736,7 +736,7 @@ void orc_shade(const int32_t *G, const uint16_t *const *levels, int32_t J, const
             for (int32_t j = 1; j <= J; j++) {
                 int64_t cell[3];
                 for (int a = 0; a < 3; a++)
-                    cell[a] = floordiv(C[a] + ((int64_t)U[3 * k + a] << j), (int64_t)QS << j);
+                    cell[a] = floordiv(C[a] + (int64_t)U[3 * k + a] * ((int64_t)1 << j), (int64_t)QS << j);
                 acc += (1.0 - acc) * occ_cell(levels[j], dims[j], cell);
             }
             sum += 1.0 - acc;
