@@ -78,9 +78,20 @@ typedef struct {
                               of the 8^3 brick holding its midpoint, binary16 clip normals and int16 brick
                               coordinates (32 B per segment instead of two 32-B vertex records); intersection
                               and compositing stay binary32 and voxel membership stays exact int32.  Offsets
-                              are exact while |offset| < 8 voxels. */
+                              are exact while |offset| < 8 voxels; a segment with a longer offset is
+                              read from its plain vertex records instead. */
     int32_t reserved;
 } vrt_desc;
+
+/* Membership of a segment's voxels.  VRT_VOX_CAPSULE is the paper's
+ * conservative capsule voxelization (Section 3.1, Alg. 1 with the projected
+ * radius that is conservative in 3D); the other two are the comparison
+ * voxelizers of Section 4.1 (Table 2), kept for measurement: their lists are
+ * not conservative for the capsules (thin) or much longer (AABB), and the
+ * image they trace is not the capsule image. */
+#define VRT_VOX_CAPSULE 0
+#define VRT_VOX_THIN 2 /* the voxels whose open interior the segment meets, plus its endpoints' cells (a 3D DDA) */
+#define VRT_VOX_AABB 3 /* every voxel touching the capsule's bounding box */
 
 /* A set of polylines with one radius (Section 3.1: capsules of uniform radius
  * per polyline; polylines neither branch nor loop, Section 3.3). */
@@ -91,6 +102,15 @@ typedef struct {
     int64_t n_vertices;
     int64_t n_polylines;
     float radius;                /* capsule radius, world units, >= 0 */
+    float alpha_default;         /* transparent traces: opacity of every segment when rgba is NULL, in (0, 1];
+                                    0 = the camera's alpha */
+    const float *rgba;           /* device, [4 * n_vertices], 16-byte aligned, or NULL: colour and opacity of
+                                    segment i (the one starting at vertex i) at rgba[4 i .. 4 i + 3]; rows of
+                                    polyline end vertices are unused.  Read by vrt_trace (keep it valid until
+                                    the frame's traces complete); opacity is clamped to [0, 1].  NULL: colour =
+                                    |unit tangent| */
+    int32_t voxelizer;           /* VRT_VOX_*; 0 = VRT_VOX_CAPSULE */
+    int32_t reserved;            /* 0 */
 } vrt_lines;
 
 /* Axis-aligned grid of isotropic voxels; voxel (x,y,z) covers
@@ -115,7 +135,8 @@ typedef struct {
     float fovy_deg;                 /* vertical field of view, (0, 180) */
     int32_t width, height;          /* pixels, >= 1 */
     int32_t mode;                   /* VRT_TRACE_* */
-    float alpha;                    /* transparent: per-hit opacity in (0, 1] */
+    float alpha;                    /* transparent: per-hit opacity in (0, 1] (segments without their own
+                                       colour, when the lines give no alpha_default) */
     float tau;                      /* transparent: stop once transmittance < tau */
 } vrt_camera;
 
@@ -134,6 +155,8 @@ typedef struct {
     int64_t n_listed;         /* fragments written to lists (visible voxels only) */
     int64_t n_bricks;         /* occupied 8^3 bricks */
     int64_t required_fragments; /* capacity the frame needed (== n_listed) */
+    int64_t n_occupied;       /* occupied voxels (fragment count > 0) */
+    int64_t n_visible;        /* voxels the last vrt_cull left visible (those with a list) */
 } vrt_frame_info;
 
 /* Read-only device views of the acceleration structure for inspection.
@@ -156,6 +179,7 @@ typedef struct {
     const uint8_t *vis_hi;       /* culling levels >= 4 */
     const uint32_t *list_end;    /* level 0: end of the voxel's list in ids (start = end - count) */
     const uint32_t *ids;         /* [n_listed] segment ids */
+    const float *lit;            /* level 0: voxel-space shading of the visible voxels (after vrt_shade) */
 } vrt_as_view;
 
 /* Creates a context on desc->device and allocates every arena.
@@ -177,6 +201,47 @@ vrt_status vrt_voxelize(vrt_ctx *ctx, const vrt_lines *lines, const vrt_grid *gr
  * which writes each segment's id into the lists of its visible voxels.
  * Requires a preceding vrt_voxelize on the same context. */
 vrt_status vrt_cull(vrt_ctx *ctx, const vrt_view *view, void *stream);
+
+/* Section 3.3 leaves the order of the segment ids inside a voxel's list
+ * undefined, and the slot atomics of pass 2 vary it from run to run.  This
+ * sorts every visible voxel's list ascending by segment id (the canonical
+ * order), after which the id array is a deterministic function of the frame
+ * -- for a static line set built once and traced many times, or to compare
+ * lists byte for byte.  Lists are rebuilt (unsorted) by the next vrt_cull.
+ * Requires a preceding vrt_cull; does nothing after a capacity overflow.
+ * Errors: VRT_ERR_INVALID_ARG, VRT_ERR_NOT_BUILT, VRT_ERR_HIP. */
+vrt_status vrt_sort_lists(vrt_ctx *ctx, void *stream);
+
+/* Voxel-space shading (Section 3.4): after vrt_cull, computes for every
+ * visible voxel
+ *   AO  = mean over n_cones cones of the transmittance 1 - a, where a
+ *         accumulates front to back (a += (1 - a) o_j) the occupancy o_j of
+ *         the level-j pyramid cell holding the point 2^j voxels from the
+ *         voxel centre along the cone's direction, j = 1..n_samples; the
+ *         directions are the points of a Fibonacci sphere (heights evenly
+ *         spaced, longitudes advancing by the golden angle) rounded to
+ *         1/256 voxel;
+ *   S   = the product of (1 - occupancy) over the voxels a ray from the
+ *         voxel centre toward the light enters before it leaves the grid
+ *         (exact integer walk, tied axes step together);
+ *   lit = AO * (ambient + (1 - ambient) * S),
+ * and the following vrt_trace calls scale each hit's colour by lit of the
+ * voxel holding the hit point (opacity unchanged).  The next vrt_cull (new
+ * visibility) turns shading off until vrt_shade runs again.
+ * enable = 0 turns it off without computing anything.
+ * Errors: VRT_ERR_INVALID_ARG (n_cones outside 1..64, n_samples outside
+ * 1..6 or not below the pyramid's level count, ambient outside [0, 1], a
+ * zero or non-finite light direction), VRT_ERR_NOT_BUILT before vrt_cull. */
+typedef struct {
+    float light_dir[3]; /* direction toward the light, world axes (normalized here) */
+    int32_t n_cones;    /* ambient-occlusion cones, 1..64 (16 by default) */
+    int32_t n_samples;  /* samples per cone, 1..6 (4: out to 16 voxels) */
+    float ambient;      /* weight of the unshadowed term, [0, 1] */
+    int32_t enable;     /* 0: unshaded colours */
+    int32_t reserved;   /* 0 */
+} vrt_shading;
+
+vrt_status vrt_shade(vrt_ctx *ctx, const vrt_shading *shading, void *stream);
 
 /* Section 3.5: traces one ray per pixel and writes the image.  Requires a
  * preceding vrt_cull.  The ray origin is cam->eye quantized like the
@@ -239,7 +304,9 @@ vrt_status vrt_batch_destroy(vrt_batch *b);
  *   lane_keys      transparent hits a lane keeps per pass over a list (k): 4 or 8;
  *   shade_blocks   size of the shade launch in units of 256 threads: 256 .. 65535
  *                  (launched as single-wave workgroups, four per unit).
- * Default {256, 16, 2, 4, 4096}.  The batched forms always use the default. */
+ * Default {256, 16, 2, 4, 4096}.  The persistent and staged batch forms use
+ * each set's shade_group (its context's shape for the set's trace mode, e.g.
+ * after vrt_autotune on vrt_batch_context) and the defaults for the rest. */
 typedef struct {
     int32_t march_threads;
     int32_t shade_group;
@@ -352,6 +419,23 @@ typedef struct {
 
 vrt_status vrt_trace_stats_run(vrt_ctx *ctx, const vrt_camera *cam, const vrt_image *out, vrt_trace_stats *stats,
                                void *stream);
+
+/* Memory-system ceilings the frame's kernels are measured against (one
+ * launch between two HIP events on `stream`; synchronizes; *ms its time):
+ *   VRT_MB_COPY           copies the first half of buf (device, `bytes`) to
+ *                         the second half (`bytes` moved in total; ops unused);
+ *   VRT_MB_ATOMIC_RANDOM  `ops` 32-bit atomic adds of 1 on pseudo-random words
+ *                         of buf (the per-fragment atomics of voxelization
+ *                         pass 1, Section 3.1, at no locality);
+ *   VRT_MB_ATOMIC_BRICK   `ops` such adds where the 64 of one wave step fall in
+ *                         one 2 KiB region (one brick's packed words).
+ * buf's contents are overwritten.  Errors: VRT_ERR_INVALID_ARG (null pointer,
+ * bytes not a positive multiple of 4096, ops < 1 for the atomics, bad kind),
+ * VRT_ERR_HIP. */
+#define VRT_MB_COPY 0
+#define VRT_MB_ATOMIC_RANDOM 1
+#define VRT_MB_ATOMIC_BRICK 2
+vrt_status vrt_microbench(int32_t kind, void *buf, int64_t bytes, int64_t ops, float *ms, void *stream);
 
 /* Synchronous copy of `bytes` from device memory to host memory. */
 vrt_status vrt_copy_to_host(void *host_dst, const void *device_src, int64_t bytes);

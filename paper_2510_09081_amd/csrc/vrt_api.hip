@@ -31,7 +31,7 @@ void free_all(Arenas &a) {
     void *ptrs[] = {a.vrec, a.words, a.occ0, a.occ1, a.occ2, a.occ3, a.occ_hi, a.blk, a.blk_bits, a.brick_bits, a.super_blk,
                     a.occ_list, a.vis0,
                     a.vis1, a.vis2,  a.vis3, a.vis_hi, a.cursor, a.cell, a.lmask, a.lmask2, a.queue, a.srec16, a.ids, a.brick_flag, a.bin_count, a.bin_range, a.cand, a.bins, a.long_ids, a.items, a.chunk_cnt, a.brick_list, a.brick_slot,
-                    a.brick_total, a.brick_base, a.status, a.stat_vox, a.stat_seg, a.stat_acc};
+                    a.brick_total, a.brick_base, a.status, a.lit, a.stat_vox, a.stat_seg, a.stat_acc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     a = Arenas();
@@ -63,6 +63,69 @@ int64_t hi_elems_for(int max_dim) {
     int64_t s = 0;
     for (int L = 4; L < n; ++L) s += (int64_t)lv[L].dims[0] * lv[L].dims[1] * lv[L].dims[2];
     return s;
+}
+
+// Capacities of a context derived from its description.
+void ctx_sizes(vrt_ctx *c, const vrt_desc &d) {
+    c->desc = d;
+    const int64_t nbd = d.max_dim / 8;
+    c->max_bricks = nbd * nbd * nbd;
+    const int64_t nsd = (d.max_dim + 63) / 64;
+    c->max_supers = nsd * nsd * nsd;
+    c->hi_elems = hi_elems_for(d.max_dim);
+}
+
+// Every arena of a context with its element count: f(pointer, count) is called
+// once per array, in one fixed order (allocation by vrt_create, placement in a
+// fixed buffer by the no-allocation frame).
+template <class F>
+void arena_fields(Arenas &a, const vrt_desc &d, int64_t mb, int64_t hi_elems, F &&f) {
+    f(a.vrec, d.max_vertices);
+    f(a.words, mb * kBrickVox);
+    f(a.occ0, mb * kBrickVox);
+    f(a.occ1, mb * 64);
+    f(a.occ2, mb * 8);
+    f(a.occ3, mb);
+    f(a.occ_hi, hi_elems);
+    f(a.blk, mb * kBrickVox);
+    f(a.blk_bits, mb * 16);
+    {
+        const int nbd = d.max_dim / 8;
+        const int nbm[3] = {nbd, nbd, nbd};
+        const CellFlagLayout cl = cell_flag_layout(nbm);
+        f(a.brick_bits, cl.words);
+        f(a.super_blk, cl.bytes);
+    }
+    f(a.occ_list, mb * kBrickVox);
+    f(a.vis0, mb * kBrickVox);
+    f(a.vis1, mb * 64);
+    f(a.vis2, mb * 8);
+    f(a.vis3, mb);
+    f(a.vis_hi, hi_elems);
+    f(a.cursor, mb * kBrickVox);
+    f(a.cell, mb * kBrickVox);
+    f(a.lmask, mb * 8);
+    f(a.lmask2, mb);
+    f(a.queue, d.max_pixels);
+    if (d.form == VRT_FORM_FP16) f(a.srec16, d.max_vertices);
+    f(a.ids, d.max_fragments);
+    f(a.brick_flag, mb);
+    f(a.bin_count, mb * kBinStride);
+    f(a.bin_range, mb);
+    f(a.cand, mb);
+    f(a.bins, (int64_t)kMaxBinBricks * d.max_vertices);
+    f(a.long_ids, d.max_vertices);
+    f(a.items, mb + (int64_t)kMaxBinBricks * d.max_vertices / kBinChunk + 1);
+    f(a.chunk_cnt, mb / (1024 * 16) + 1);
+    f(a.brick_list, mb);
+    f(a.brick_slot, mb);
+    f(a.brick_total, mb);
+    f(a.brick_base, mb);
+    f(a.status, 1);
+    f(a.lit, mb * kBrickVox);
+    f(a.stat_vox, mb * kBrickVox);
+    f(a.stat_seg, d.max_vertices);
+    f(a.stat_acc, 16);
 }
 
 bool finite3(const float *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
@@ -98,62 +161,13 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     VRT_HIP(hipSetDevice(desc->device));
     vrt_ctx *c = new (std::nothrow) vrt_ctx();
     if (!c) return VRT_ERR_INVALID_ARG;
-    c->desc = *desc;
-    const int64_t nbd = desc->max_dim / 8;
-    c->max_bricks = nbd * nbd * nbd;
-    const int64_t nsd = (desc->max_dim + 63) / 64;
-    c->max_supers = nsd * nsd * nsd;
-    c->hi_elems = hi_elems_for(desc->max_dim);
+    ctx_sizes(c, *desc);
     Arenas &a = c->a;
     const int64_t mb = c->max_bricks;
     hipError_t e = hipSuccess;
-#define ALLOC(p, n) \
-    if (e == hipSuccess) e = alloc(p, n)
-    ALLOC(a.vrec, desc->max_vertices);
-    ALLOC(a.words, mb * kBrickVox);
-    ALLOC(a.occ0, mb * kBrickVox);
-    ALLOC(a.occ1, mb * 64);
-    ALLOC(a.occ2, mb * 8);
-    ALLOC(a.occ3, mb);
-    ALLOC(a.occ_hi, c->hi_elems);
-    ALLOC(a.blk, mb * kBrickVox);
-    ALLOC(a.blk_bits, mb * 16);
-    {
-        const int nbm[3] = {(int)nbd, (int)nbd, (int)nbd};
-        const CellFlagLayout cl = cell_flag_layout(nbm);
-        ALLOC(a.brick_bits, cl.words);
-        ALLOC(a.super_blk, cl.bytes);
-    }
-    ALLOC(a.occ_list, mb * kBrickVox);
-    ALLOC(a.vis0, mb * kBrickVox);
-    ALLOC(a.vis1, mb * 64);
-    ALLOC(a.vis2, mb * 8);
-    ALLOC(a.vis3, mb);
-    ALLOC(a.vis_hi, c->hi_elems);
-    ALLOC(a.cursor, mb * kBrickVox);
-    ALLOC(a.cell, mb * kBrickVox);
-    ALLOC(a.lmask, mb * 8);
-    ALLOC(a.lmask2, mb);
-    ALLOC(a.queue, desc->max_pixels);
-    if (desc->form == VRT_FORM_FP16) ALLOC(a.srec16, desc->max_vertices);
-    ALLOC(a.ids, desc->max_fragments);
-    ALLOC(a.brick_flag, mb);
-    ALLOC(a.bin_count, mb * kBinStride);
-    ALLOC(a.bin_range, mb);
-    ALLOC(a.cand, mb);
-    ALLOC(a.bins, (int64_t)kMaxBinBricks * desc->max_vertices);
-    ALLOC(a.long_ids, desc->max_vertices);
-    ALLOC(a.items, mb + (int64_t)kMaxBinBricks * desc->max_vertices / kBinChunk + 1);
-    ALLOC(a.chunk_cnt, mb / (1024 * 16) + 1);
-    ALLOC(a.brick_list, mb);
-    ALLOC(a.brick_slot, mb);
-    ALLOC(a.brick_total, mb);
-    ALLOC(a.brick_base, mb);
-    ALLOC(a.status, 1);
-    ALLOC(a.stat_vox, mb * kBrickVox);
-    ALLOC(a.stat_seg, desc->max_vertices);
-    ALLOC(a.stat_acc, 16);
-#undef ALLOC
+    arena_fields(a, *desc, mb, c->hi_elems, [&](auto *&p, int64_t n) {
+        if (e == hipSuccess) e = alloc(p, n);
+    });
     if (e == hipSuccess) e = hipMemset(a.words, 0, (size_t)mb * kBrickVox * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(a.brick_flag, 0, (size_t)mb);
     if (e == hipSuccess) e = hipMemset(a.bin_count, 0, (size_t)mb * kBinStride * sizeof(uint32_t));
@@ -196,6 +210,10 @@ static vrt_status prepare_voxelize(vrt_ctx *c, const vrt_lines *L, const vrt_gri
         L->n_vertices > c->desc.max_vertices || L->n_polylines > L->n_vertices)
         return VRT_ERR_INVALID_ARG;
     if (!(L->radius >= 0.0f) || !std::isfinite(L->radius)) return VRT_ERR_INVALID_ARG;
+    if (L->voxelizer != VRT_VOX_CAPSULE && L->voxelizer != VRT_VOX_THIN && L->voxelizer != VRT_VOX_AABB)
+        return VRT_ERR_INVALID_ARG;
+    if (!(L->alpha_default >= 0.0f && L->alpha_default <= 1.0f) || L->reserved != 0) return VRT_ERR_INVALID_ARG;
+    if (L->rgba && ((uintptr_t)L->rgba % 16) != 0) return VRT_ERR_INVALID_ARG;
     if (!(g->voxel_size > 0.0f) || !std::isfinite(g->voxel_size) || !finite3(g->origin)) return VRT_ERR_INVALID_ARG;
     for (int k = 0; k < 3; ++k)
         if (g->dims[k] < 8 || g->dims[k] % 8 != 0 || g->dims[k] > c->desc.max_dim) return VRT_ERR_INVALID_ARG;
@@ -208,6 +226,9 @@ static vrt_status prepare_voxelize(vrt_ctx *c, const vrt_lines *L, const vrt_gri
     c->voxel_size = g->voxel_size;
     c->rq = (int64_t)rq;
     c->n_vertices = L->n_vertices;
+    c->voxelizer = L->voxelizer;
+    c->seg_rgba = L->rgba;
+    c->alpha_default = L->alpha_default;
     c->n_levels = level_dims(c->dims, c->levels);
     c->voxelized = false;
     c->culled = false;
@@ -259,8 +280,37 @@ vrt_status vrt_cull(vrt_ctx *c, const vrt_view *v, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     c->last_stream = st;
     c->culled = false;
+    c->shaded = false;
     VRT_HIP(launch_cull(c, E, limit, st));
     c->culled = true;
+    return VRT_OK;
+}
+
+vrt_status vrt_shade(vrt_ctx *c, const vrt_shading *sh, void *stream) {
+    if (!c || !sh || sh->reserved != 0) return VRT_ERR_INVALID_ARG;
+    if (!c->culled) return VRT_ERR_NOT_BUILT;
+    if (!sh->enable) {
+        c->shaded = false;
+        return VRT_OK;
+    }
+    int U[3 * 64], L[3];
+    const vrt_status s = shade_params(c, sh, U, L);
+    if (s != VRT_OK) return s;
+    VRT_HIP(hipSetDevice(c->desc.device));
+    hipStream_t st = (hipStream_t)stream;
+    c->last_stream = st;
+    VRT_HIP(launch_shade(c, sh, U, L, st));
+    c->shaded = true;
+    return VRT_OK;
+}
+
+vrt_status vrt_sort_lists(vrt_ctx *c, void *stream) {
+    if (!c) return VRT_ERR_INVALID_ARG;
+    if (!c->culled) return VRT_ERR_NOT_BUILT;
+    VRT_HIP(hipSetDevice(c->desc.device));
+    hipStream_t st = (hipStream_t)stream;
+    c->last_stream = st;
+    VRT_HIP(launch_sort_lists(c, st));
     return VRT_OK;
 }
 
@@ -304,7 +354,9 @@ static vrt_status camera_params(const vrt_ctx *c, const vrt_camera *cam, TracePa
     p.W = cam->width;
     p.H = cam->height;
     p.mode = cam->mode;
-    p.alpha = cam->mode == VRT_TRACE_TRANSPARENT ? cam->alpha : 1.0f;
+    p.alpha = cam->mode == VRT_TRACE_TRANSPARENT ? (c->alpha_default > 0.0f ? c->alpha_default : cam->alpha) : 1.0f;
+    p.seg_rgba = reinterpret_cast<const float4 *>(c->seg_rgba);
+    p.lit = c->shaded ? c->a.lit : nullptr;
     p.tau = cam->mode == VRT_TRACE_TRANSPARENT ? cam->tau : 0.5f;
     p.radius = (float)c->rq / 256.0f;
     p.voxel_size = c->voxel_size;
@@ -383,6 +435,10 @@ vrt_status vrt_frame_status(vrt_ctx *c, vrt_frame_info *out) {
     out->n_listed = (int64_t)h.n_listed;
     out->n_bricks = (int64_t)h.n_bricks;
     out->required_fragments = (int64_t)h.n_listed;
+    out->n_occupied = (int64_t)h.n_occ;
+    unsigned long long nvis = 0;
+    for (int k = 0; k < kStripes; ++k) nvis += h.stripe[k].vvis;
+    out->n_visible = (int64_t)nvis;
     return VRT_OK;
 }
 
@@ -413,6 +469,7 @@ vrt_status vrt_query_as(vrt_ctx *c, vrt_as_view *o) {
     o->vis_hi = a.vis_hi;
     o->list_end = a.cursor;
     o->ids = a.ids;
+    o->lit = a.lit;
     return VRT_OK;
 }
 
@@ -572,3 +629,4 @@ const char *vrt_status_string(vrt_status s) {
 }
 
 }  // extern "C"
+

@@ -23,8 +23,8 @@ constexpr int kBatchThreads = 512;
 constexpr int kMaxBatch = 1024;
 constexpr int kParts = 3;  // stages sharing one phase
 enum : int {
-    P_CLEAR, P_INGEST, P_COUNT, P_COMPACT, P_OCC, P_ERODE, P_WALK, P_CBRICK, P_SCAN, P_OFFSETS, P_SCATTER, P_MARCH,
-    P_SHADE, kPhases
+    P_CLEAR, P_INGEST, P_BIN_COUNT, P_BIN_ALLOC, P_BIN_FILL, P_ACCUM, P_LONG, P_COMPACT, P_OCC, P_ERODE, P_WALK,
+    P_CBRICK, P_SCAN, P_OFFSETS, P_SCATTER, P_SCATTER_LONG, P_MARCH, P_SHADE, kPhases
 };
 
 struct SetDesc {
@@ -38,6 +38,7 @@ struct SetDesc {
     int64_t n_hi;  // elements of the levels >= 4
     unsigned march_blocks;
     int fp16;
+    int shade_group;  // lanes per ray in the shade phase: the set's tuned value (8, 16 or 32)
 };
 
 __device__ __forceinline__ unsigned cdiv(uint64_t n, unsigned d) { return (unsigned)((n + d - 1) / d); }
@@ -49,7 +50,11 @@ __device__ unsigned part_blocks(int ph, int part, const SetDesc &d) {
     switch (ph) {
     case P_CLEAR: return part == 0 ? st->n_bricks : (part == 1 ? cdiv(reset_items(d.vp.nb, d.vp.nw, d.vp.nf), T) : 0u);
     case P_INGEST: return part == 0 ? cdiv(d.vp.nv, T) : 0u;
-    case P_COUNT: return part == 0 ? (d.fp16 ? cdiv(d.vp.nv, T) : 0u) : (part == 1 ? cdiv(d.vp.nv, T) : 0u);
+    case P_BIN_COUNT: return part == 0 ? (d.fp16 ? cdiv(d.vp.nv, T) : 0u) : (part == 1 ? cdiv(d.vp.nv, T) : 0u);
+    case P_BIN_ALLOC: return part == 0 ? cdiv(st->n_cand, T) : 0u;
+    case P_BIN_FILL: return part == 0 ? cdiv(d.vp.nv, T) : 0u;
+    case P_ACCUM: return part == 0 ? st->n_items : 0u;
+    case P_LONG: return part == 0 ? cdiv(st->n_long, T) : 0u;
     case P_COMPACT: return part == 0 ? 1u : 0u;
     case P_OCC: return part == 0 ? st->n_bricks : 0u;
     case P_ERODE:
@@ -60,9 +65,10 @@ __device__ unsigned part_blocks(int ph, int part, const SetDesc &d) {
     case P_CBRICK: return part == 0 ? st->n_bricks : 0u;
     case P_SCAN: return part == 0 ? 1u : 0u;
     case P_OFFSETS: return part == 0 ? st->n_bricks : 0u;
-    case P_SCATTER: return part == 0 ? cdiv(d.cp.nv, T) : (part == 1 ? 1u : 0u);
+    case P_SCATTER: return part == 0 ? st->n_cand : 0u;
+    case P_SCATTER_LONG: return part == 0 ? cdiv(st->n_long, T) : (part == 1 ? 1u : 0u);
     case P_MARCH: return part == 0 ? d.march_blocks : 0u;
-    case P_SHADE: return part == 0 ? cdiv(st->n_queue, T / DefaultShade::kGroup) : 0u;
+    case P_SHADE: return part == 0 ? cdiv(st->n_queue, T / (unsigned)d.shade_group) : 0u;
     default: return 0u;
     }
 }
@@ -78,10 +84,14 @@ __device__ __forceinline__ void run_part(int ph, int part, const SetDesc &d, uns
         else b_reset(A.occ3, A.bin_count, A.brick_bits, d.vp.nb, d.vp.nw, A.super_blk, d.vp.nf, A.status, vb, nvb);
         break;
     case P_INGEST: b_ingest(d.vp.ia, A.vrec, A.status, vb, nvb); break;
-    case P_COUNT:
+    case P_BIN_COUNT:
         if (part == 0) b_pack16(A.vrec, d.vp.nv, A.srec16, vb, nvb);
-        else b_vox_count(d.vp.ca, A.status, vb, nvb);
+        else b_bin_count(d.vp.ba, A.status, vb, nvb);
         break;
+    case P_BIN_ALLOC: b_bin_alloc(d.vp.ba, A.status, vb, nvb); break;
+    case P_BIN_FILL: b_bin_fill(d.vp.ba, A.status, vb, nvb); break;
+    case P_ACCUM: b_brick_accum(d.vp.aa, A.status, vb, nvb); break;
+    case P_LONG: b_vox_long(d.vp.ca, A.long_ids, A.status, vb, nvb); break;
     case P_COMPACT: b_brick_compact(A.brick_flag, d.vp.nb, A.brick_list, A.brick_slot, A.status, 0u, 1u); break;
     case P_OCC: b_occ_brick(A.words, A.brick_list, A.status, A.occ0, A.occ1, A.occ2, A.occ3, A.occ_list, vb, nvb); break;
     case P_ERODE:
@@ -101,14 +111,22 @@ __device__ __forceinline__ void run_part(int ph, int part, const SetDesc &d, uns
         break;
     case P_SCAN: b_scan_bricks(A.brick_total, A.brick_base, A.status, d.capacity, A.vis_hi, d.levels, d.n_levels, 0u, 1u); break;
     case P_OFFSETS: b_list_offsets(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor, A.cell, A.lmask, A.lmask2, vb, nvb); break;
-    case P_SCATTER:
-        if (part == 0) b_scatter(d.cp.sa, vb, nvb);
+    case P_SCATTER: b_scatter_brick(d.cp.sb, A.status, vb, nvb); break;
+    case P_SCATTER_LONG:
+        if (part == 0) b_scatter_long(d.cp.sb, A.status, vb, nvb);
         else b_trace_begin(A.status, 0u, 1u);
         break;
     case P_MARCH: b_trace_march<false>(d.ta, vb, nvb); break;
-    case P_SHADE:
-        if (d.fp16) b_trace_shade<false, VRT_FORM_FP16>(d.ta, vb, nvb);
-        else b_trace_shade<false, VRT_FORM_PLAIN>(d.ta, vb, nvb);
+    case P_SHADE:  // the set's tuned group size; entries per fetch and keys per lane keep their defaults
+        if (d.fp16) {
+            if (d.shade_group == 8) b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<8, 2, 4>>(d.ta, vb, nvb);
+            else if (d.shade_group == 32) b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<32, 2, 4>>(d.ta, vb, nvb);
+            else b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<16, 2, 4>>(d.ta, vb, nvb);
+        } else {
+            if (d.shade_group == 8) b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<8, 2, 4>>(d.ta, vb, nvb);
+            else if (d.shade_group == 32) b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<32, 2, 4>>(d.ta, vb, nvb);
+            else b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<16, 2, 4>>(d.ta, vb, nvb);
+        }
         break;
     default: break;
     }
@@ -175,7 +193,11 @@ const void *phase_kernel(int ph) {
     switch (ph) {
     case P_CLEAR: return (const void *)k_batch_phase<P_CLEAR>;
     case P_INGEST: return (const void *)k_batch_phase<P_INGEST>;
-    case P_COUNT: return (const void *)k_batch_phase<P_COUNT>;
+    case P_BIN_COUNT: return (const void *)k_batch_phase<P_BIN_COUNT>;
+    case P_BIN_ALLOC: return (const void *)k_batch_phase<P_BIN_ALLOC>;
+    case P_BIN_FILL: return (const void *)k_batch_phase<P_BIN_FILL>;
+    case P_ACCUM: return (const void *)k_batch_phase<P_ACCUM>;
+    case P_LONG: return (const void *)k_batch_phase<P_LONG>;
     case P_COMPACT: return (const void *)k_batch_phase<P_COMPACT>;
     case P_OCC: return (const void *)k_batch_phase<P_OCC>;
     case P_ERODE: return (const void *)k_batch_phase<P_ERODE>;
@@ -184,6 +206,7 @@ const void *phase_kernel(int ph) {
     case P_SCAN: return (const void *)k_batch_phase<P_SCAN>;
     case P_OFFSETS: return (const void *)k_batch_phase<P_OFFSETS>;
     case P_SCATTER: return (const void *)k_batch_phase<P_SCATTER>;
+    case P_SCATTER_LONG: return (const void *)k_batch_phase<P_SCATTER_LONG>;
     case P_MARCH: return (const void *)k_batch_phase<P_MARCH>;
     default: return (const void *)k_batch_phase<P_SHADE>;
     }
@@ -282,6 +305,7 @@ vrt_status vrt_batch_run(vrt_batch *b, const vrt_batch_item *items, int32_t n, i
         s = prepare_cull(c, &items[i].view, &E[3 * i], &lim[i]);
         if (s != VRT_OK) return s;
         c->culled = true;
+        c->shaded = false;  // the batched forms trace unshaded
         if (!items[i].image.rgba) return VRT_ERR_INVALID_ARG;
         s = camera_params(c, &items[i].cam, tp[i]);
         if (s != VRT_OK) return s;
@@ -306,6 +330,7 @@ vrt_status vrt_batch_run(vrt_batch *b, const vrt_batch_item *items, int32_t n, i
         d.march_blocks = (unsigned)(((tp[i].W + 15) / 16) *
                                     ((tp[i].H + march_tile_rows(kBatchThreads) - 1) / march_tile_rows(kBatchThreads)));
         d.fp16 = c->desc.form == VRT_FORM_FP16;
+        d.shade_group = c->tune[tp[i].mode == VRT_TRACE_OPAQUE ? 0 : 1].shade_group;
         c->last_stream = st;
     }
     VRT_HIP(hipMemcpyAsync(b->d_sets, b->h_sets, sizeof(SetDesc) * n, hipMemcpyHostToDevice, st));

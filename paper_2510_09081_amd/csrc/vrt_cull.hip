@@ -18,6 +18,7 @@ __device__ __forceinline__ void b_cull_reset(uint8_t *__restrict__ vis3, int64_t
         int *p = st->stripe[i].vbox;
         p[0] = p[1] = p[2] = INT_MAX;
         p[3] = p[4] = p[5] = INT_MIN;
+        st->stripe[i].vvis = 0;
     }
 }
 
@@ -288,7 +289,7 @@ __device__ __forceinline__ void b_list_offsets(const uint32_t *__restrict__ word
                                                       const uint8_t *__restrict__ vis0,
                                                       const int32_t *__restrict__ list,
                                                       const uint32_t *__restrict__ base,
-                                                      const DevStatus *__restrict__ st,
+                                                      DevStatus *__restrict__ st,
                                                       uint32_t *__restrict__ cursor, uint64_t *__restrict__ cell,
                                                       uint64_t *__restrict__ lmask, uint64_t *__restrict__ lmask2,
                                                       unsigned bid_, unsigned nblk_) {
@@ -296,6 +297,7 @@ __device__ __forceinline__ void b_list_offsets(const uint32_t *__restrict__ word
     __shared__ unsigned sq[8];
     const unsigned nbk = st->n_bricks;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    unsigned nvis = 0;  // visible voxels seen by this wave
     for (unsigned sl = bid_; sl < nbk; sl += nblk_) {
         int64_t b = list[sl];
         unsigned c = vis0[b * kBrickVox + t] ? (words[b * kBrickVox + t] & 0xFFFFu) : 0u;
@@ -313,6 +315,7 @@ __device__ __forceinline__ void b_list_offsets(const uint32_t *__restrict__ word
         cell[b * kBrickVox + t] = (uint64_t)start | ((uint64_t)c << 32);
         const unsigned long long nonempty = __ballot(c != 0u);  // the wave holds local voxels 64w .. 64w + 63
         if (lane == 0) lmask[b * 8 + w] = nonempty;
+        nvis += (unsigned)__popcll(nonempty);
         {  // the slice's 2x2 squares holding such a voxel: bit 4 Y + X for square (X, Y)
             unsigned long long s2 = nonempty | (nonempty >> 1);
             s2 |= s2 >> 8;  // bit 16 Y + 2 X: the square's OR
@@ -326,13 +329,14 @@ __device__ __forceinline__ void b_list_offsets(const uint32_t *__restrict__ word
             lmask2[b] = cells;
         }
     }
+    if (lane == 0 && nvis) atomicAdd(&st->stripe[bid_ % kStripes].vvis, (unsigned long long)nvis);
 }
 
 __global__ void __launch_bounds__(512) k_list_offsets(const uint32_t *__restrict__ words,
                                                       const uint8_t *__restrict__ vis0,
                                                       const int32_t *__restrict__ list,
                                                       const uint32_t *__restrict__ base,
-                                                      const DevStatus *__restrict__ st,
+                                                      DevStatus *__restrict__ st,
                                                       uint32_t *__restrict__ cursor, uint64_t *__restrict__ cell,
                                                       uint64_t *__restrict__ lmask, uint64_t *__restrict__ lmask2) {
     b_list_offsets(words, vis0, list, base, st, cursor, cell, lmask, lmask2, blockIdx.x, gridDim.x);
@@ -341,6 +345,7 @@ __global__ void __launch_bounds__(512) k_list_offsets(const uint32_t *__restrict
 struct ScatterArgs {
     const VRec *vrec;
     int64_t nv;
+    int mode;  // VRT_VOX_*
     long long rq;
     int G[3];
     int nb[3];
@@ -362,7 +367,7 @@ __device__ __forceinline__ void scatter_segment(const ScatterArgs &a, int64_t i)
     VRec B = a.vrec[i + 1];
     long long dx = (long long)B.x - A.x, dy = (long long)B.y - A.y, dz = (long long)B.z - A.z;
     if (dx >= 65536 || dx <= -65536 || dy >= 65536 || dy <= -65536 || dz >= 65536 || dz <= -65536) return;
-    SlabSpan s = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), a.rq, a.G);
+    SlabSpan s = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), a.rq, a.G, a.mode);
     if (s.empty) return;
     // voxel ranges back on (x, y, z)
     const int lx = s.a0 == 0 ? s.vlo0 : (s.a1 == 0 ? s.vlo1 : s.vlo2), hx = s.a0 == 0 ? s.vhi0 : (s.a1 == 0 ? s.vhi1 : s.vhi2);
@@ -425,7 +430,7 @@ __device__ __forceinline__ void b_scatter_brick(ScatterBinArgs a, const DevStatu
         for (uint32_t k = t; k < r.y; k += blockDim.x) {
             const uint32_t id = a.bins[r.x + k];
             const VRec A = s.vrec[id], B = s.vrec[id + 1];
-            const SlabSpan sp = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), s.rq, s.G);
+            const SlabSpan sp = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), s.rq, s.G, s.mode);
             for_each_voxel_in_brick(sp, bx, by, bz, [&](int x, int y, int z) {
                 const int l = local_of(x, y, z);
                 if (vis[l]) {
@@ -453,6 +458,101 @@ __global__ void __launch_bounds__(256) k_scatter_brick(ScatterBinArgs a, const D
 }
 __global__ void __launch_bounds__(256) k_scatter_long(ScatterBinArgs a, const DevStatus *__restrict__ st) {
     b_scatter_long(a, st, blockIdx.x, gridDim.x);
+}
+
+// ------------------------------------------------------------------------
+// Optional in-voxel order (Section 3.3 leaves the order of a voxel's list
+// undefined, and the slot atomics of pass 2 make it vary between runs): every
+// visible voxel's list sorted ascending, which makes the whole id array a
+// deterministic function of the frame.
+
+constexpr int kSortShort = 32;     // lists up to this length: insertion sort by their own thread
+constexpr int kSortLds = 4096;     // longer lists up to this padded length: the workgroup sorts in LDS
+
+// Comparator step of an ascending bitonic network over P = 2^p keys: for the
+// first step of a merge of blocks of size `span` the partner is the mirror
+// index in the block, afterwards the element `half` away; every comparator
+// moves the smaller key to the lower index, so keys past the list's end can
+// stand for +inf without being stored.
+template <class Load, class Store>
+__device__ __forceinline__ void bitonic_steps(uint32_t P, uint32_t n, Load &&ld, Store &&st) {
+    for (uint32_t span = 2; span <= P; span <<= 1) {
+        for (uint32_t half = span >> 1; half > 0; half >>= 1) {
+            for (uint32_t c = threadIdx.x; c < P / 2; c += blockDim.x) {
+                const uint32_t blk = c / half, off = c % half;
+                const uint32_t i = blk * 2 * half + off;
+                const uint32_t j = half == span / 2 ? (i / span) * span + span - 1 - (i % span) : i + half;
+                if (j < n) {  // j >= n holds +inf: nothing moves
+                    const uint32_t a = ld(i), b = ld(j);
+                    if (b < a) {
+                        st(i, b);
+                        st(j, a);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// One workgroup (512 threads) per occupied brick, grid-stride over the bricks.
+__device__ __forceinline__ void b_sort_lists(const uint64_t *__restrict__ cell, const int32_t *__restrict__ list,
+                                             const DevStatus *__restrict__ st, uint32_t *__restrict__ ids,
+                                             int64_t capacity, unsigned bid_, unsigned nblk_) {
+    __shared__ uint32_t keys[kSortLds];
+    __shared__ unsigned long long longm[8];
+    const unsigned nbk = st->n_bricks;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (st->n_listed > (unsigned long long)capacity) return;  // lists undefined after a capacity overflow
+    for (unsigned sl = bid_; sl < nbk; sl += nblk_) {
+        const int64_t b = list[sl];
+        const uint64_t cd = cell[b * kBrickVox + t];
+        const uint32_t s0 = (uint32_t)cd, n = (uint32_t)(cd >> 32);
+        if (n > 1 && n <= (uint32_t)kSortShort) {
+            for (uint32_t i = 1; i < n; ++i) {
+                const uint32_t x = ids[s0 + i];
+                uint32_t j = i;
+                for (; j > 0; --j) {
+                    const uint32_t y = ids[s0 + j - 1];
+                    if (!(y > x)) break;
+                    ids[s0 + j] = y;
+                }
+                ids[s0 + j] = x;
+            }
+        }
+        const unsigned long long m = __ballot(n > (uint32_t)kSortShort);
+        if (lane == 0) longm[w] = m;
+        __syncthreads();
+        for (int ww = 0; ww < 8; ++ww) {
+            unsigned long long mm = longm[ww];
+            while (mm) {
+                const int l = __ffsll((long long)mm) - 1;
+                mm &= mm - 1;
+                const uint64_t c2 = cell[b * kBrickVox + 64 * ww + l];
+                const uint32_t s = (uint32_t)c2, len = (uint32_t)(c2 >> 32);
+                uint32_t P = 1;
+                while (P < len) P <<= 1;
+                if (P <= (uint32_t)kSortLds) {
+                    for (uint32_t i = t; i < len; i += blockDim.x) keys[i] = ids[s + i];
+                    __syncthreads();
+                    bitonic_steps(P, len, [&](uint32_t i) { return keys[i]; },
+                                  [&](uint32_t i, uint32_t v) { keys[i] = v; });
+                    for (uint32_t i = t; i < len; i += blockDim.x) ids[s + i] = keys[i];
+                } else {
+                    bitonic_steps(P, len, [&](uint32_t i) { return ids[s + i]; },
+                                  [&](uint32_t i, uint32_t v) { ids[s + i] = v; });
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();  // longm is rewritten for the next brick
+    }
+}
+
+__global__ void __launch_bounds__(512) k_sort_lists(const uint64_t *__restrict__ cell, const int32_t *__restrict__ list,
+                                                    const DevStatus *__restrict__ st, uint32_t *__restrict__ ids,
+                                                    int64_t capacity) {
+    b_sort_lists(cell, list, st, ids, capacity, blockIdx.x, gridDim.x);
 }
 
 }  // namespace
@@ -505,6 +605,7 @@ static CullPlan make_cull_plan(const vrt_ctx *c, const int64_t E[3], int64_t lim
     p.cells.n32y = cl.n32[1];
     p.sa.vrec = A.vrec;
     p.sa.nv = c->n_vertices;
+    p.sa.mode = c->voxelizer;
     p.sa.rq = c->rq;
     for (int k = 0; k < 3; ++k) {
         p.sa.G[k] = p.g.G[k];
@@ -553,6 +654,13 @@ hipError_t launch_cull(vrt_ctx *c, const int64_t E[3], int64_t limit, hipStream_
                                                     A.cell, A.lmask, A.lmask2));
     VRT_LAUNCH(c, "k_scatter_brick", st, k_scatter_brick<<<kBrickBlocks, 256, 0, st>>>(p.sb, A.status));
     VRT_LAUNCH(c, "k_scatter_long", st, k_scatter_long<<<256, 256, 0, st>>>(p.sb, A.status));
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_lists(vrt_ctx *c, hipStream_t st) {
+    Arenas &A = c->a;
+    VRT_LAUNCH(c, "k_sort_lists", st,
+               k_sort_lists<<<4096, 512, 0, st>>>(A.cell, A.brick_list, A.status, A.ids, c->desc.max_fragments));
     return hipGetLastError();
 }
 

@@ -28,7 +28,9 @@ constexpr int kSegValid = 1, kInterior = 2;
 
 // FP16-form segment record (32 B): endpoints as binary16 offsets (voxel units)
 // from the centre of brick (bx, by, bz), binary16 clip normals, flags bit 0:
-// interior A (clip with n0), bit 1: interior B (clip with n1).
+// interior A (clip with n0), bit 1: interior B (clip with n1), bit 2: an
+// offset is 8 voxels or more, where binary16 no longer holds every multiple
+// of 1/256 voxel -- the tracer then reads the segment's plain vertex records.
 struct __align__(16) SRec16 {
     __half a[3], b[3];
     __half n0[3], n1[3];
@@ -36,6 +38,7 @@ struct __align__(16) SRec16 {
     unsigned short flags;
 };
 static_assert(sizeof(SRec16) == 32, "SRec16 is 32 bytes");
+constexpr unsigned kSRecPlain = 4u;
 
 // Device-wide atomics on one cache line serialize (about 11 ns each on
 // MI355X), so per-block tallies go to the stripe of their block (one 128-byte
@@ -46,6 +49,7 @@ struct alignas(128) StatStripe {
     unsigned long long csum;  // sum of the 16-bit count fields
     int bbox[6];              // blocking-voxel bounds
     int vbox[6];              // visible-brick bounds
+    unsigned long long vvis;  // visible voxels (those with a list)
 };
 
 struct DevStatus {
@@ -123,6 +127,7 @@ struct Arenas {
     uint32_t *brick_base = nullptr; // [max_bricks] exclusive scan of brick_total
     DevStatus *status = nullptr;
     // trace statistics (inspection only)
+    float *lit = nullptr;                   // [max_bricks * 512] voxel-space shading of the visible voxels
     uint8_t *stat_vox = nullptr;            // [max_bricks * 512] voxel list read
     uint8_t *stat_seg = nullptr;            // [max_vertices] segment tested
     unsigned long long *stat_acc = nullptr; // [16]
@@ -193,12 +198,15 @@ struct vrt_ctx {
     int64_t hi_elems;  // capacity of occ_hi / vis_hi
     vrt::Arenas a;
     // frame state
-    bool voxelized = false, culled = false;
+    bool voxelized = false, culled = false, shaded = false;
     int dims[3] = {0, 0, 0};
     int n_levels = 0;
     vrt::Level levels[vrt::kMaxLevels];
     int64_t n_vertices = 0;
     int64_t rq = 0;
+    int voxelizer = VRT_VOX_CAPSULE;    // membership of the current frame
+    const float *seg_rgba = nullptr;     // per-segment colour and opacity of the current frame, or null
+    float alpha_default = 0.0f;          // opacity of segments without their own colour (0: the camera's)
     float origin[3] = {0, 0, 0};
     float voxel_size = 1;
     hipStream_t last_stream = nullptr;
@@ -249,6 +257,9 @@ inline void prof_end(vrt_ctx *c, hipStream_t st) {
 
 hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *lines, float s_q, hipStream_t st);
 hipError_t launch_cull(vrt_ctx *c, const int64_t eye_q[3], int64_t limit, hipStream_t st);
+hipError_t launch_sort_lists(vrt_ctx *c, hipStream_t st);
+vrt_status shade_params(const vrt_ctx *c, const vrt_shading *s, int *U, int *L);
+hipError_t launch_shade(vrt_ctx *c, const vrt_shading *s, const int *U, const int *L, hipStream_t st);
 struct TraceParams {
     float F[3], R[3], U[3];  // camera basis: forward, right*tan*aspect, up*tan
     float O[3];              // eye in voxel units (exact)
@@ -257,6 +268,8 @@ struct TraceParams {
     float alpha, tau;
     float radius;            // voxel units
     float voxel_size;
+    const float4 *seg_rgba;  // per-segment colour and opacity, or null (colour = |unit tangent|, opacity alpha)
+    const float *lit;        // voxel-space shading of the hit's voxel (brick-major), or null (unshaded)
 };
 hipError_t launch_trace(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st);
 hipError_t launch_trace_stats(vrt_ctx *c, const TraceParams &p, const vrt_image *img, hipStream_t st);
@@ -305,6 +318,7 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // is kept in axis-permuted scalars (index 0 = major axis a0, 1 and 2 = the
 // minor axes a1 < a2): runtime-indexed arrays would live in per-lane scratch.
 struct SlabSpan {
+    int mode;  // VRT_VOX_*: the capsule set, or a comparison voxelizer's
     int a0, a1, a2;
     long long A0, A1, A2;  // start point on (a0, a1, a2) after the swap
     long long D, d1, d2;   // direction on (a0, a1, a2), D >= 0
@@ -318,8 +332,9 @@ __device__ __forceinline__ long long sel3(long long x, long long y, long long z,
     return k == 0 ? x : (k == 1 ? y : z);
 }
 
-__device__ __forceinline__ SlabSpan make_span(int3 a, int3 b, long long rq, const int *G) {
+__device__ __forceinline__ SlabSpan make_span(int3 a, int3 b, long long rq, const int *G, int mode) {
     SlabSpan s;
+    s.mode = mode;
     const long long dx = (long long)b.x - a.x, dy = (long long)b.y - a.y, dz = (long long)b.z - a.z;
     const long long ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy, az = dz < 0 ? -dz : dz;
     int a0 = 0;
@@ -391,18 +406,76 @@ __device__ __forceinline__ void slab_range(const SlabSpan &s, int x, long long A
     rh = (int)(h < vhi ? h : vhi);
 }
 
+// Thin-line comparison voxelizer (Section 4.1, the "DDA" of Table 2): the
+// voxels whose open interior the open segment meets, plus the cells of its
+// endpoints, inside the box given on the span's axes.  An exact integer walk
+// from the start cell: the next crossing on each axis is the fraction
+// num/den of the segment (den = |d|), the smallest one is taken next, tied
+// axes step together (voxels touched only along an edge or at a corner are
+// not entered), and the walk ends before a crossing at or past the far end,
+// whose cell is added when it differs.  A segment lying in a voxel face
+// plane meets no open interior: only its endpoint cells.
+template <class F>
+__device__ __forceinline__ int for_each_thin_voxel(const SlabSpan &s, int lo0, int hi0, int lo1, int hi1, int lo2,
+                                                   int hi2, F &&f) {
+    const long long A0 = s.A0, A1 = s.A1, A2 = s.A2;
+    const long long d0 = s.D, d1 = s.d1, d2 = s.d2;
+    long long c0 = A0 >> 8, c1 = A1 >> 8, c2 = A2 >> 8;  // floor division by kQ = 256
+    const long long e0 = (A0 + d0) >> 8, e1 = (A1 + d1) >> 8, e2 = (A2 + d2) >> 8;
+    int n = 0;
+    auto emit = [&](long long x, long long j, long long k) {
+        if (x < lo0 || x > hi0 || j < lo1 || j > hi1 || k < lo2 || k > hi2) return;
+        const int vx = s.a0 == 0 ? (int)x : (s.a1 == 0 ? (int)j : (int)k);
+        const int vy = s.a0 == 1 ? (int)x : (s.a1 == 1 ? (int)j : (int)k);
+        const int vz = s.a0 == 2 ? (int)x : (s.a1 == 2 ? (int)j : (int)k);
+        f(vx, vy, vz);
+        ++n;
+    };
+    emit(c0, c1, c2);
+    const bool flat = (d0 == 0 && (A0 & 255) == 0) || (d1 == 0 && (A1 & 255) == 0) || (d2 == 0 && (A2 & 255) == 0);
+    if (d0 != 0 && !flat) {  // d0 = |major component| > 0: not a point
+        // distance (numerator) to the next plane on each axis; den = |d|, 0 when the axis never steps
+        long long n0 = (c0 + 1) * kQ - A0;  // d0 > 0
+        long long n1 = d1 > 0 ? (c1 + 1) * kQ - A1 : A1 - c1 * kQ;
+        long long n2 = d2 > 0 ? (c2 + 1) * kQ - A2 : A2 - c2 * kQ;
+        const long long g1 = d1 < 0 ? -d1 : d1, g2 = d2 < 0 ? -d2 : d2;
+        const int s1 = d1 > 0 ? 1 : -1, s2 = d2 > 0 ? 1 : -1;
+        for (;;) {
+            // smallest crossing fraction among the stepping axes (axis 0 always steps)
+            long long bn = n0, bd = d0;
+            if (g1 && n1 * bd < bn * g1) bn = n1, bd = g1;
+            if (g2 && n2 * bd < bn * g2) bn = n2, bd = g2;
+            if (!(bn < bd)) break;  // at or past the far end
+            const bool t0 = n0 * bd == bn * d0, t1 = g1 && n1 * bd == bn * g1, t2 = g2 && n2 * bd == bn * g2;
+            if (t0) c0 += 1, n0 += kQ;
+            if (t1) c1 += s1, n1 += kQ;
+            if (t2) c2 += s2, n2 += kQ;
+            emit(c0, c1, c2);
+        }
+    }
+    if (c0 != e0 || c1 != e1 || c2 != e2) emit(e0, e1, e2);
+    return n;
+}
+
 // The voxels of the set inside the box [lo0, hi0] x [lo1, hi1] x [lo2, hi2]
 // given on the span's axes (a0, a1, a2); each exactly once.
 template <class F>
 __device__ __forceinline__ int for_each_voxel_clip(const SlabSpan &s, int lo0, int hi0, int lo1, int hi1, int lo2,
                                                    int hi2, F &&f) {
     if (s.empty) return 0;
+    if (s.mode == VRT_VOX_THIN) {
+        const int b0 = s.vlo0 > lo0 ? s.vlo0 : lo0, b1 = s.vlo1 > lo1 ? s.vlo1 : lo1, b2 = s.vlo2 > lo2 ? s.vlo2 : lo2;
+        const int u0 = s.vhi0 < hi0 ? s.vhi0 : hi0, u1 = s.vhi1 < hi1 ? s.vhi1 : hi1, u2 = s.vhi2 < hi2 ? s.vhi2 : hi2;
+        return for_each_thin_voxel(s, b0, u0, b1, u1, b2, u2, f);
+    }
     int n = 0;
     const int x0 = s.vlo0 > lo0 ? s.vlo0 : lo0, x1 = s.vhi0 < hi0 ? s.vhi0 : hi0;
     for (int x = x0; x <= x1; ++x) {
-        int l1, h1, l2, h2;
-        slab_range(s, x, s.A1, s.d1, s.W1, s.vlo1, s.vhi1, l1, h1);
-        slab_range(s, x, s.A2, s.d2, s.W2, s.vlo2, s.vhi2, l2, h2);
+        int l1 = s.vlo1, h1 = s.vhi1, l2 = s.vlo2, h2 = s.vhi2;  // the capsule AABB voxelizer: the whole box
+        if (s.mode == VRT_VOX_CAPSULE) {
+            slab_range(s, x, s.A1, s.d1, s.W1, s.vlo1, s.vhi1, l1, h1);
+            slab_range(s, x, s.A2, s.d2, s.W2, s.vlo2, s.vhi2, l2, h2);
+        }
         l1 = l1 > lo1 ? l1 : lo1;
         h1 = h1 < hi1 ? h1 : hi1;
         l2 = l2 > lo2 ? l2 : lo2;

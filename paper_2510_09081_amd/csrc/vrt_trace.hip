@@ -455,8 +455,26 @@ __device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w,
 // Segment id in the frame of voxel (cx, cy, cz), read in the context's form.
 template <int kForm>
 __device__ __forceinline__ LocalSeg load_seg(const TraceArgs &a, uint32_t id, int cx, int cy, int cz) {
-    if (kForm == VRT_FORM_FP16) return local_seg(a.srec16[id], cx, cy, cz);
+    if (kForm == VRT_FORM_FP16) {
+        const SRec16 r = a.srec16[id];
+        if (!(r.flags & kSRecPlain)) return local_seg(r, cx, cy, cz);
+    }
     return local_seg(a.vrec[id], a.vrec[id + 1], cx, cy, cz);
+}
+
+// Colour and opacity of a hit on segment id: the caller's per-segment RGBA
+// (opacity clamped to [0, 1]) when given, else |unit tangent| and the
+// default opacity.
+template <int kForm>
+__device__ __forceinline__ float3 hit_colour(const TraceArgs &a, uint32_t id, int cx, int cy, int cz, float &alpha) {
+    if (a.p.seg_rgba) {
+        const float4 q = a.p.seg_rgba[id];
+        alpha = fminf(fmaxf(q.w, 0.0f), 1.0f);
+        return make_float3(q.x, q.y, q.z);
+    }
+    alpha = a.p.alpha;
+    const LocalSeg g = load_seg<kForm>(a, id, cx, cy, cz);
+    return seg_colour(g.pa, g.pb);
 }
 
 // Calls f(id, seg) for the entries of the current voxel's list that belong to
@@ -556,8 +574,12 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
         const uint32_t id = (uint32_t)best;
         sh.first = (int)id;
         sh.first_t = w.tcur + __uint_as_float((uint32_t)(best >> 32));
-        const LocalSeg g = load_seg<kForm>(a, id, cx, cy, cz);
-        sh.col = seg_colour(g.pa, g.pb);
+        float unused_alpha;
+        sh.col = hit_colour<kForm>(a, id, cx, cy, cz, unused_alpha);
+        if (a.p.lit) {  // voxel-space shading of the voxel holding the hit (Section 3.4)
+            const float l = a.p.lit[w.vi];
+            sh.col = make_float3(sh.col.x * l, sh.col.y * l, sh.col.z * l);
+        }
         sh.T = 0.0f;
         return true;
     }
@@ -603,18 +625,22 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
                 for (int j = 0; j + 1 < kLaneKeys; ++j) kk[j] = kk[j + 1];
                 kk[kLaneKeys - 1] = kNoKey;
             }
-            const LocalSeg gc = load_seg<kForm>(a, (uint32_t)m, cx, cy, cz);
-            const float3 c = seg_colour(gc.pa, gc.pb);
+            float alpha;
+            float3 c = hit_colour<kForm>(a, (uint32_t)m, cx, cy, cz, alpha);
+            if (a.p.lit) {
+                const float l = a.p.lit[w.vi];
+                c = make_float3(c.x * l, c.y * l, c.z * l);
+            }
             const uint32_t id = (uint32_t)m;
             if (sh.first < 0) {
                 sh.first = (int)id;
                 sh.first_t = w.tcur + __uint_as_float((uint32_t)(m >> 32));
             }
-            const float wgt = sh.T * a.p.alpha;
+            const float wgt = sh.T * alpha;
             sh.col.x += wgt * c.x;
             sh.col.y += wgt * c.y;
             sh.col.z += wgt * c.z;
-            sh.T *= (1.0f - a.p.alpha);
+            sh.T *= (1.0f - alpha);
             thr = m;
             have_thr = true;
             if (sh.T < a.p.tau) return true;

@@ -3,6 +3,8 @@
 #include "vrt_voxelize.hip"
 #include "vrt_cull.hip"
 #include "vrt_trace.hip"
+#include "vrt_shade.hip"
 #include "vrt_api.hip"
 #include "vrt_tune.hip"
 #include "vrt_batch.hip"
+#include "vrt_microbench.hip"

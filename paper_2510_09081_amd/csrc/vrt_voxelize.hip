@@ -201,7 +201,9 @@ __device__ __forceinline__ int occupancy_quantum(const VRec &A, const VRec &B, f
 // FP16 form: one record per segment with its endpoints relative to the centre
 // of the brick holding its midpoint (binary16, voxel units) and its clip
 // normals in binary16.  Quantized positions are multiples of 1/256 voxel, so
-// offsets below 8 voxels are exact.
+// offsets below 8 voxels are exact; a segment with a longer offset (one that
+// reaches beyond the neighbouring bricks) is marked to be read from its plain
+// vertex records instead.
 __device__ __forceinline__ void b_pack16(const VRec *__restrict__ vrec, int64_t nv, SRec16 *__restrict__ out, unsigned bid_, unsigned nblk_) {
     const int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x;
     if (i + 1 >= nv) return;
@@ -227,7 +229,12 @@ __device__ __forceinline__ void b_pack16(const VRec *__restrict__ vrec, int64_t 
     r.bx = (short)bx;
     r.by = (short)by;
     r.bz = (short)bz;
-    r.flags = (unsigned short)(((A.flags & kInterior) ? 1 : 0) | ((B.flags & kInterior) ? 2 : 0));
+    const long long ox[6] = {A.x - cx, A.y - cy, A.z - cz, B.x - cx, B.y - cy, B.z - cz};
+    bool exact = true;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) exact &= ox[k] > -2048 && ox[k] < 2048;  // |offset| < 8 voxels
+    r.flags = (unsigned short)(((A.flags & kInterior) ? 1 : 0) | ((B.flags & kInterior) ? 2 : 0) |
+                               (exact ? 0u : kSRecPlain));
     out[i] = r;
 }
 
@@ -236,6 +243,7 @@ __global__ void k_pack16(const VRec *__restrict__ vrec, int64_t nv, SRec16 *__re
 struct CountArgs {
     const VRec *vrec;
     int64_t nv;
+    int mode;  // VRT_VOX_*
     long long rq;
     float rc, corr;
     int G[3];
@@ -259,7 +267,7 @@ __device__ __forceinline__ unsigned long long vox_count_segment(const CountArgs 
         set_err(st, kErrRange);
         return 0;
     }
-    SlabSpan s = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), a.rq, a.G);
+    SlabSpan s = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), a.rq, a.G, a.mode);
     int64_t last_b = -1;
     return for_each_voxel(s, [&](int x, int y, int z) {
         int q = occupancy_quantum(A, B, a.rc, a.corr, x, y, z);
@@ -468,7 +476,7 @@ __device__ __forceinline__ void b_brick_accum(AccumArgs a, DevStatus *__restrict
             if (kk >= len) continue;
             const uint32_t id = a.bins[r.x + k0 + kk];
             const VRec A = c.vrec[id], B = c.vrec[id + 1];
-            const SlabSpan s = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), c.rq, c.G);
+            const SlabSpan s = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), c.rq, c.G, c.mode);
             nfrag += for_each_voxel_in_brick(s, bx, by, bz, [&](int x, int y, int z) {
                 const int q = occupancy_quantum(A, B, c.rc, c.corr, x, y, z);
                 atomicAdd(&w[local_of(x, y, z)], 1u + ((uint32_t)q << 16));
@@ -957,6 +965,7 @@ static VoxPlan make_vox_plan(const vrt_ctx *c, const vrt_lines *L, float s_q) {
     p.ia.s = s_q;
     p.ca.vrec = A.vrec;
     p.ca.nv = L->n_vertices;
+    p.ca.mode = c->voxelizer;
     p.ca.rq = c->rq;
     const int64_t rcl = c->rq > kRMinQ ? c->rq : kRMinQ;
     const double ratio = (double)c->rq / (double)rcl;

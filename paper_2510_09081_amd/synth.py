@@ -336,6 +336,29 @@ def batch_sets(seed=4, n_sets=64, lo=1e3, hi=1e6, W=512, H=512):
     return items
 
 
+def decimate(ls: LineSet, n: int) -> LineSet:
+    """Level of detail: every polyline keeps its vertices 0, n, 2n, ... and its last one, so segments become
+    about n times longer (the segment-length sweep of the voxelizer comparison)."""
+    if n <= 1:
+        return ls
+    keep, lengths = [], []
+    for p in range(ls.n_polylines):
+        a, b = int(ls.offsets[p]), int(ls.offsets[p + 1])
+        idx = list(range(a, b, n))
+        if idx[-1] != b - 1:
+            idx.append(b - 1)
+        keep.extend(idx)
+        lengths.append(len(idx))
+    return replace(ls, xyz=np.ascontiguousarray(ls.xyz[np.asarray(keep, np.int64)]),
+                   offsets=_offsets_from_lengths(np.asarray(lengths)))
+
+
+def regrid(ls: LineSet, G: int) -> LineSet:
+    """The same world-space line set on a G^3 grid over the same cube (voxel size and radius in voxels scale)."""
+    ext = float(ls.voxel_size) * max(ls.dims)
+    return replace(ls, voxel_size=float(np.float32(ext / G)), dims=(G, G, G))
+
+
 def workload(name: str) -> Workload:
     """Named workloads with the shapes of the benchmark configurations."""
     if name == "random_walk_10k":

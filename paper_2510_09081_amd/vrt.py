@@ -27,7 +27,9 @@ EXPORTED = ["vrt_create", "vrt_destroy", "vrt_voxelize", "vrt_cull", "vrt_trace"
             "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_last_hip_error", "vrt_status_string",
             "vrt_profile_enable", "vrt_profile_read", "vrt_trace_stats_run", "vrt_graph_create",
             "vrt_graph_launch", "vrt_graph_destroy", "vrt_batch_create", "vrt_batch_run", "vrt_batch_context",
-            "vrt_batch_destroy", "vrt_set_tune", "vrt_get_tune", "vrt_autotune", "vrt_autotune_grid"]
+            "vrt_batch_destroy", "vrt_set_tune", "vrt_get_tune", "vrt_autotune", "vrt_autotune_grid",
+            "vrt_microbench", "vrt_sort_lists", "vrt_shade"]
+MB_COPY, MB_ATOMIC_RANDOM, MB_ATOMIC_BRICK = 0, 1, 2
 
 
 class VrtError(RuntimeError):
@@ -43,7 +45,18 @@ class vrt_desc(C.Structure):
 
 class vrt_lines(C.Structure):
     _fields_ = [("xyz", C.c_void_p), ("poly_offsets", C.c_void_p), ("n_vertices", C.c_int64),
-                ("n_polylines", C.c_int64), ("radius", C.c_float)]
+                ("n_polylines", C.c_int64), ("radius", C.c_float), ("alpha_default", C.c_float),
+                ("rgba", C.c_void_p), ("voxelizer", C.c_int32), ("reserved", C.c_int32)]
+
+
+VOX_CAPSULE, VOX_THIN, VOX_AABB = 0, 2, 3
+
+
+def make_lines(xyz, offsets, radius, voxelizer=VOX_CAPSULE, rgba=None, alpha_default=0.0):
+    """vrt_lines for device tensors xyz [n, 3] float32 and offsets [n_polylines + 1] int32; rgba: None or a
+    device float32 tensor [n, 4] (colour and opacity of the segment starting at each vertex)."""
+    return vrt_lines(_ptr(xyz), _ptr(offsets), int(xyz.shape[0]), int(offsets.shape[0] - 1), float(radius),
+                     float(alpha_default), _ptr(rgba), int(voxelizer), 0)
 
 
 class vrt_grid(C.Structure):
@@ -66,14 +79,20 @@ class vrt_image(C.Structure):
 
 class vrt_frame_info(C.Structure):
     _fields_ = [("device_status", C.c_int32), ("n_fragments", C.c_int64), ("n_listed", C.c_int64),
-                ("n_bricks", C.c_int64), ("required_fragments", C.c_int64)]
+                ("n_bricks", C.c_int64), ("required_fragments", C.c_int64), ("n_occupied", C.c_int64),
+                ("n_visible", C.c_int64)]
 
 
 class vrt_as_view(C.Structure):
     _fields_ = [("dims", C.c_int32 * 3), ("n_levels", C.c_int32), ("n_bricks", C.c_int32),
                 ("brick_list", C.c_void_p), ("words", C.c_void_p), ("occ", C.c_void_p * 4), ("occ_hi", C.c_void_p),
                 ("blocking", C.c_void_p), ("vis", C.c_void_p * 4), ("vis_hi", C.c_void_p), ("list_end", C.c_void_p),
-                ("ids", C.c_void_p)]
+                ("ids", C.c_void_p), ("lit", C.c_void_p)]
+
+
+class vrt_shading(C.Structure):
+    _fields_ = [("light_dir", C.c_float * 3), ("n_cones", C.c_int32), ("n_samples", C.c_int32),
+                ("ambient", C.c_float), ("enable", C.c_int32), ("reserved", C.c_int32)]
 
 
 class vrt_batch_item(C.Structure):
@@ -147,6 +166,9 @@ def load():
         L.vrt_autotune_grid.argtypes = [P, C.POINTER(vrt_lines), C.POINTER(vrt_grid), C.c_int32,
                                         C.POINTER(vrt_view), C.POINTER(vrt_camera), C.POINTER(vrt_image), C.c_int32,
                                         C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float), P]
+        L.vrt_microbench.argtypes = [C.c_int32, P, C.c_int64, C.c_int64, C.POINTER(C.c_float), P]
+        L.vrt_sort_lists.argtypes = [P, P]
+        L.vrt_shade.argtypes = [P, C.POINTER(vrt_shading), P]
         L.vrt_last_hip_error.restype = C.c_int32
         L.vrt_status_string.argtypes = [C.c_int32]
         L.vrt_status_string.restype = C.c_char_p
@@ -154,7 +176,8 @@ def load():
                      "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_profile_enable",
                      "vrt_profile_read", "vrt_trace_stats_run", "vrt_graph_create", "vrt_graph_launch",
                      "vrt_graph_destroy", "vrt_batch_create", "vrt_batch_run", "vrt_batch_context",
-                     "vrt_batch_destroy", "vrt_set_tune", "vrt_get_tune", "vrt_autotune", "vrt_autotune_grid"]:
+                     "vrt_batch_destroy", "vrt_set_tune", "vrt_get_tune", "vrt_autotune", "vrt_autotune_grid",
+                     "vrt_microbench", "vrt_sort_lists", "vrt_shade"]:
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -204,6 +227,19 @@ def make_camera(eye, target, up, fovy_deg, width, height, mode=TRACE_OPAQUE, alp
                       float(alpha), float(tau))
 
 
+def microbench(kind, buf, ops=0, stream=None):
+    """Time (ms) of one memory-system microbenchmark launch over the device tensor buf (see vrt.h)."""
+    ms = C.c_float()
+    _check(load().vrt_microbench(int(kind), _ptr(buf), int(buf.numel() * buf.element_size()), int(ops),
+                                 C.byref(ms), _stream_ptr(stream)), "vrt_microbench")
+    return float(ms.value)
+
+
+def _info_dict(info):
+    return {"device_status": info.device_status, "n_fragments": info.n_fragments, "n_listed": info.n_listed,
+            "n_bricks": info.n_bricks, "n_occupied": info.n_occupied, "n_visible": info.n_visible}
+
+
 class Context:
     """One voxel ray tracing context: arenas sized at creation, reused per frame."""
 
@@ -227,15 +263,26 @@ class Context:
         except Exception:  # noqa: BLE001 - interpreter shutdown
             pass
 
-    def voxelize(self, xyz, offsets, radius, origin, voxel_size, dims, stream=None):
-        """xyz: device float32 [n, 3]; offsets: device int32 [n_polylines + 1]."""
-        lines = vrt_lines(_ptr(xyz), _ptr(offsets), int(xyz.shape[0]), int(offsets.shape[0] - 1), float(radius))
+    def voxelize(self, xyz, offsets, radius, origin, voxel_size, dims, stream=None, voxelizer=VOX_CAPSULE,
+                 rgba=None, alpha_default=0.0):
+        """xyz: device float32 [n, 3]; offsets: device int32 [n_polylines + 1]; see make_lines."""
+        lines = make_lines(xyz, offsets, radius, voxelizer, rgba, alpha_default)
         grid = vrt_grid(_f3(origin), float(voxel_size), (C.c_int32 * 3)(*[int(x) for x in dims]))
         _check(load().vrt_voxelize(self._h, C.byref(lines), C.byref(grid), _stream_ptr(stream)), "vrt_voxelize")
 
     def cull(self, eye, mode, alpha=1.0, tau=1.0 / 256.0, stream=None):
         view = vrt_view(_f3(eye), int(mode), float(alpha), float(tau))
         _check(load().vrt_cull(self._h, C.byref(view), _stream_ptr(stream)), "vrt_cull")
+
+    def shade(self, light_dir=(0.3, 0.5, 0.8), n_cones=16, n_samples=4, ambient=0.3, enable=True, stream=None):
+        """Voxel-space shading of the visible voxels (ambient occlusion + directional shadow); the following
+        traces scale hit colours by it, until the next cull."""
+        sh = vrt_shading(_f3(light_dir), int(n_cones), int(n_samples), float(ambient), int(bool(enable)), 0)
+        _check(load().vrt_shade(self._h, C.byref(sh), _stream_ptr(stream)), "vrt_shade")
+
+    def sort_lists(self, stream=None):
+        """Sorts every visible voxel's list ascending by segment id (canonical order)."""
+        _check(load().vrt_sort_lists(self._h, _stream_ptr(stream)), "vrt_sort_lists")
 
     def trace(self, camera: vrt_camera, rgba, depth=None, first_id=None, stream=None):
         img = vrt_image(_ptr(rgba), _ptr(depth), _ptr(first_id))
@@ -256,8 +303,7 @@ class Context:
     def frame_status(self):
         info = vrt_frame_info()
         _check(load().vrt_frame_status(self._h, C.byref(info)), "vrt_frame_status")
-        return {"device_status": info.device_status, "n_fragments": info.n_fragments, "n_listed": info.n_listed,
-                "n_bricks": info.n_bricks}
+        return _info_dict(info)
 
     def set_tune(self, mode, **shape):
         """Sets the tracer launch shape of trace mode `mode`; unnamed fields keep their current value."""
@@ -291,7 +337,7 @@ class Context:
         """Times whole frames for each candidate grid (origin, voxel_size, dims); passes as in frame_graph.
         Returns (index of the fastest grid, [mean frame ms per grid, inf where it did not fit]).  Synchronizes;
         the context holds the last candidate's structure afterwards."""
-        lines = vrt_lines(_ptr(xyz), _ptr(offsets), int(xyz.shape[0]), int(offsets.shape[0] - 1), float(radius))
+        lines = make_lines(xyz, offsets, radius)
         gs = (vrt_grid * len(grids))()
         for i, (origin, voxel_size, dims) in enumerate(grids):
             gs[i] = vrt_grid(_f3(origin), float(voxel_size), (C.c_int32 * 3)(*[int(x) for x in dims]))
@@ -329,7 +375,7 @@ class Context:
     def frame_graph(self, xyz, offsets, radius, origin, voxel_size, dims, passes):
         """Captures one frame as a HIP graph.  passes: list of (view, camera, rgba, depth, first_id) with
         view = (eye, cull_mode, alpha, tau).  Returns a FrameGraph; keep the tensors alive while it exists."""
-        lines = vrt_lines(_ptr(xyz), _ptr(offsets), int(xyz.shape[0]), int(offsets.shape[0] - 1), float(radius))
+        lines = make_lines(xyz, offsets, radius)
         grid = vrt_grid(_f3(origin), float(voxel_size), (C.c_int32 * 3)(*[int(x) for x in dims]))
         n = len(passes)
         views, cams, imgs = self._passes(passes)
@@ -401,7 +447,8 @@ class Batch:
             x, o = it["xyz"], it["offsets"]
             eye, cm, al, tau = it["view"]
             arr[i] = vrt_batch_item(
-                vrt_lines(_ptr(x), _ptr(o), int(x.shape[0]), int(o.shape[0] - 1), float(it["radius"])),
+                make_lines(x, o, it["radius"], it.get("voxelizer", VOX_CAPSULE), it.get("rgba_seg"),
+                           it.get("alpha_default", 0.0)),
                 vrt_grid(_f3(it["origin"]), float(it["voxel_size"]), (C.c_int32 * 3)(*[int(v) for v in it["dims"]])),
                 vrt_view(_f3(eye), int(cm), float(al), float(tau)), it["camera"],
                 vrt_image(_ptr(it["rgba"]), _ptr(it.get("depth")), _ptr(it.get("first_id"))))

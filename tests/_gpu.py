@@ -104,6 +104,7 @@ def fetch_as(ctx):
         out["vis"].append(vis_hi[off_elems:off_elems + n].reshape(c, b, a))
         off_elems += n
     out["list_end"] = lvl(v.list_end, 0, np.uint32)
+    out["lit"] = lvl(v.lit, 0, np.float32)
     return out
 
 
@@ -119,3 +120,96 @@ def canonical_lists(words, vis, start, ids):
     s = start.ravel()[sel].astype(np.int64)
     c = cnt.ravel()[sel]
     return {int(v): tuple(sorted(ids[a:a + n].tolist())) for v, a, n in zip(sel, s, c)}
+
+
+def lists_equal(words, vis, start, ids, offsets_ref, ids_ref):
+    """Canonical list comparison for large grids (vectorized): the visible
+    voxels' list starts agree, their ranges tile the id array in brick-major
+    order, and every voxel's list holds the same ids in both arrays."""
+    cnt = (np.ascontiguousarray(words).ravel() & 0xFFFF).astype(np.int64)
+    sel = np.flatnonzero((np.ascontiguousarray(vis).ravel() > 0) & (cnt > 0))
+    c = cnt[sel]
+    so = np.ascontiguousarray(offsets_ref).ravel()[sel].astype(np.int64)
+    sg = np.ascontiguousarray(start).ravel()[sel].astype(np.int64)
+    if not np.array_equal(sg, so):
+        return False
+    order = np.argsort(so, kind="stable")
+    so, c = so[order], c[order]
+    if len(c) and not np.array_equal(so, np.concatenate([[0], np.cumsum(c)[:-1]])):
+        return False
+    total = int(c.sum())
+    if len(ids) < total or len(ids_ref) < total:
+        return False
+    label = np.repeat(np.arange(len(c), dtype=np.int64), c) << 32
+    kg = np.sort(label | np.asarray(ids[:total], np.int64))
+    ko = np.sort(label | np.asarray(ids_ref[:total], np.int64))
+    return bool(np.array_equal(kg, ko))
+
+
+# Certification of a traced pixel by the oracle: every decision that can change
+# its result (hit/miss and clip-plane distances, hit-order gaps) has a margin
+# above EPS_GEOM voxel, and the hit point lies farther than EPS_FACE0 +
+# EPS_FACE_T * t voxel from any voxel face across which its listed status
+# changes (binary32 boundary parameters have relative error 2^-24).
+EPS_GEOM = 2e-5
+EPS_FACE0 = 1e-5
+EPS_FACE_T = 2.4e-7
+MAX_UNCERTIFIED = 2e-3
+
+
+def certified(tr):
+    t = np.where(np.isfinite(tr.t), tr.t, 0.0)
+    return (tr.m_geom > EPS_GEOM) & (tr.m_face > EPS_FACE0 + EPS_FACE_T * t)
+
+
+def structure_report(fr, got, ids, st=None):
+    """Bit-exact comparison of a fetched acceleration structure with the oracle frame, as booleans."""
+    r = {"dims": got["dims"] == fr.dims}
+    r["words"] = bool(np.array_equal(got["words"], fr.words))
+    r["occupancy_levels"] = len(got["occ"]) == len(fr.occ) and all(
+        np.array_equal(a, b) for a, b in zip(got["occ"], fr.occ))
+    r["blocking"] = bool(np.array_equal(got["blocking"], fr.blocking))
+    r["culling_levels"] = len(got["vis"]) == len(fr.vis_levels) and all(
+        np.array_equal(a, b) for a, b in zip(got["vis"], fr.vis_levels))
+    cnt = (fr.words & 0xFFFF).astype(np.int64)
+    start = got["list_end"].astype(np.int64) - cnt * (fr.vis > 0)
+    nbx, nby, nbz = fr.dims[0] // 8, fr.dims[1] // 8, fr.dims[2] // 8
+    occ_b = np.zeros(nbx * nby * nbz, bool)
+    occ_b[got["bricks"]] = True
+    occupied = np.repeat(np.repeat(np.repeat(occ_b.reshape(nbz, nby, nbx), 8, 0), 8, 1), 8, 2)
+    r["offsets"] = bool(np.array_equal(start[occupied], fr.offsets.astype(np.int64)[occupied]))
+    r["lists"] = lists_equal(fr.words, fr.vis, start, ids, fr.offsets, fr.ids)
+    if st is not None:
+        r["totals"] = (st["n_fragments"] == fr.n_fragments and st["n_listed"] == fr.total
+                       and st["n_occupied"] == int((cnt > 0).sum()) and st["n_visible"] == int((fr.vis > 0).sum()))
+    return r
+
+
+def trace_report(tr, gid, gdepth, grgba, voxel_size, mode):
+    """Image against the oracle: certified fraction, id equality and errors on certified pixels (with the
+    parity tolerances), and the plain error statistics over every pixel."""
+    cert = certified(tr)
+    hit = cert & (tr.id >= 0)
+    dd = np.abs(gdepth[hit].astype(np.float64) - tr.depth[hit]) / float(voxel_size)
+    derr_ok = bool((dd <= 1e-5 * tr.t[hit] + 1e-4).all())
+    cerr = np.abs(grgba.astype(np.float64) - tr.rgba)
+    cc = cerr[cert]
+    ctol = 1e-6 if mode == 0 else 1e-4
+    same = (gid == tr.id)
+    both = (tr.id >= 0) & same
+    d_all = np.abs(gdepth[both].astype(np.float64) - tr.depth[both]) / float(voxel_size)
+    r = {
+        "certified_frac": float(cert.mean()),
+        "ids_equal_certified": bool(same[cert].all()),
+        "depth_within_tol_certified": derr_ok and bool(np.isinf(gdepth[cert & (tr.id < 0)]).all()),
+        "colour_within_tol_certified": bool(cc.max(initial=0) <= ctol and (mode == 0 or cc.mean() <= 1e-6)),
+        "id_match_all": float(same.mean()),
+        "id_match_certified": float(same[cert].mean()) if cert.any() else 1.0,
+        "colour_err_max": float(cerr.max()), "colour_err_mean": float(cerr.mean()),
+        "depth_err_max_vox": float(d_all.max(initial=0)), "depth_err_mean_vox": float(d_all.mean()) if d_all.size else 0.0,
+        "hit_pixels": int((tr.id >= 0).sum()),
+    }
+    r["pass"] = (r["ids_equal_certified"] and r["depth_within_tol_certified"] and r["colour_within_tol_certified"]
+                 and 1.0 - r["certified_frac"] <= MAX_UNCERTIFIED)
+    return r
+

@@ -90,3 +90,30 @@ def test_persistent_batch_equals_sequential(orc):
         pb.close()
         sb.close()
         tb.close()
+
+
+def test_batch_uses_each_sets_shade_group(orc):
+    """Sets whose contexts carry different tuned shade groups (8, 16, 32 lanes per ray): the persistent and
+    staged launches still give the sequential calls' images exactly."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU: the gpu tests need an MI355X")
+    sets = small_batch(n=6, seed=11)
+    pb, sb, tb = vrt.Batch(caps(sets)), vrt.Batch(caps(sets)), vrt.Batch(caps(sets))
+    try:
+        for bb in (pb, sb, tb):
+            for i, (_, _, _, mode) in enumerate(sets):
+                bb.context(i).set_tune(mode, shade_group=(8, 16, 32)[i % 3])
+        ip, isq, ist = make_items(sets), make_items(sets), make_items(sets)
+        pb.run(ip, vrt.BATCH_PERSISTENT)
+        sb.run(isq, vrt.BATCH_SEQUENTIAL)
+        tb.run(ist, vrt.BATCH_STAGED)
+        torch.cuda.synchronize()
+        for i in range(len(sets)):
+            for key in ("rgba", "depth", "first_id"):
+                assert torch.equal(ip[i][key], isq[i][key]), (i, key)
+                assert torch.equal(ist[i][key], isq[i][key]), (i, key)
+    finally:
+        pb.close()
+        sb.close()
+        tb.close()

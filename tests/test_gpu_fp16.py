@@ -71,3 +71,47 @@ def test_fp16_form_error_against_oracle(orc, ctxs, name, mode, cull, alpha):
     d = np.abs(out["plain"][2] - out["fp16"][2]).max(axis=1)
     assert (d > 1e-4).mean() <= 2e-3
     assert d.mean() <= 1e-4
+
+
+def test_fp16_form_reads_long_segments_from_plain_records(orc, ctxs):
+    """Single-segment polylines of 40-60 voxels: 99% have a brick-relative offset of 8 voxels or more,
+    which binary16 cannot hold on the 1/256 grid, and the FP16 form reads those from the plain vertex
+    records.  Without clip planes (no interior vertices) both kinds of record give the same binary32
+    endpoints, so the FP16 images equal the plain form's bit for bit (and match the oracle)."""
+    plain, half = ctxs
+    ls = synth.random_walk_set(seed=17, n_poly=200, n_seg=1, G=128, step_lo=40.0, step_hi=60.0)
+    cam = synth.grid_camera(ls, 200, 150)
+    for mode, cull, alpha in ((0, vrt.CULL_OPAQUE, 1.0), (1, vrt.CULL_NONE, 0.3)):
+        out = []
+        for ctx in (plain, half):
+            G.run_build(ctx, ls, cam.eye, cull, alpha=alpha)
+            assert ctx.frame_status()["device_status"] == 0
+            out.append(G.run_trace(ctx, cam, mode, alpha=alpha))
+        for a, b in zip(out[0], out[1]):
+            assert np.array_equal(a, b)
+        fr = orc.build_frame(ls, cam.eye, cull, alpha=alpha)
+        tr = orc.trace(fr, ls, cam, np.arange(cam.width * cam.height), mode, alpha=alpha)
+        cert = certified(tr, mode)
+        assert (tr.id >= 0).sum() > 500
+        assert not (cert & (out[1][0] != tr.id)).any()
+
+
+def test_fp16_form_mixed_long_and_short(orc, ctxs):
+    """Short segments (exact binary16 offsets) next to long ones (plain records): first hits agree with the
+    oracle on the certified pixels."""
+    plain, half = ctxs
+    short = synth.random_walk_set(seed=18, n_poly=60, n_seg=40, G=128)
+    long_ = synth.random_walk_set(seed=19, n_poly=30, n_seg=4, G=128, step_lo=20.0, step_hi=60.0)
+    ls = synth.LineSet(xyz=np.concatenate([short.xyz, long_.xyz]),
+                       offsets=np.concatenate([short.offsets, short.offsets[-1] + long_.offsets[1:]]).astype(np.int32),
+                       radius=short.radius, origin=short.origin, voxel_size=short.voxel_size, dims=short.dims)
+    cam = synth.grid_camera(ls, 240, 180)
+    fr = orc.build_frame(ls, cam.eye, vrt.CULL_NONE)
+    tr = orc.trace(fr, ls, cam, np.arange(cam.width * cam.height), 0)
+    G.run_build(half, ls, cam.eye, vrt.CULL_NONE)
+    gid, gdepth, grgba = G.run_trace(half, cam, 0)
+    cert = certified(tr, 0)
+    assert (tr.id >= 0).sum() > 1000
+    assert ((gid == tr.id)[cert]).mean() >= 0.999
+    e = error_report(tr, gid, gdepth, grgba, ls)
+    assert e["colour_err_mean"] <= 1e-4

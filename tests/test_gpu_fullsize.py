@@ -1,0 +1,200 @@
+"""Oracle parity at the benchmark configurations' full sizes.
+
+- The 5.5M-segment tractography-shaped set on 512^3 at 1920x1080: packed
+  words, every occupancy and culling level (levels >= 8 come from the
+  top-level averaging launch), blocking flags, list offsets and canonical
+  lists bit-exact for the opaque-culled and the alpha-culled view; first-hit
+  ids, depth and colour on every certified pixel of both passes.
+- Dynamic pathlines (2M segments per frame, 256^3, 1280x720): frames 0, 59
+  and 119 taken from the replayed frame graph against the oracle.
+- The 64-set batch: the persistent launch's largest-grid set (256^3) and its
+  largest set against the oracle.
+- Duplicated polylines: hits of identical capsules tie exactly and the lower
+  segment id wins (Section 3.5, correct hit ordering; ties by id).
+"""
+import numpy as np
+import pytest
+
+from paper_2510_09081_amd import synth, vrt
+
+from . import _gpu as G
+from .test_gpu_parity import certified, compare_trace
+
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU: the gpu tests need an MI355X")
+
+
+def compare_structure_large(fr, got, ids):
+    """compare_structure for large grids: the same bit-exact checks, vectorized."""
+    assert got["dims"] == fr.dims
+    assert np.array_equal(got["words"], fr.words), "packed words differ"
+    assert len(got["occ"]) == len(fr.occ) == got["n_levels"]
+    for L, (a, b) in enumerate(zip(got["occ"], fr.occ)):
+        assert np.array_equal(a, b), f"occupancy level {L} differs"
+    assert np.array_equal(got["blocking"], fr.blocking), "blocking flags differ"
+    assert len(got["vis"]) == len(fr.vis_levels)
+    for L, (a, b) in enumerate(zip(got["vis"], fr.vis_levels)):
+        assert np.array_equal(a, b), f"culling level {L} differs"
+    cnt = (fr.words & 0xFFFF).astype(np.int64)
+    start = got["list_end"].astype(np.int64) - cnt * (fr.vis > 0)
+    nbx, nby, nbz = fr.dims[0] // 8, fr.dims[1] // 8, fr.dims[2] // 8
+    occ_b = np.zeros(nbx * nby * nbz, bool)
+    occ_b[got["bricks"]] = True
+    occupied = np.repeat(np.repeat(np.repeat(occ_b.reshape(nbz, nby, nbx), 8, 0), 8, 1), 8, 2)
+    assert np.array_equal(start[occupied], fr.offsets.astype(np.int64)[occupied]), "list offsets differ"
+    assert G.lists_equal(fr.words, fr.vis, start, ids, fr.offsets, fr.ids), "canonical lists differ"
+
+
+def _structure_and_trace(orc, ctx, ls, cam, fr, cull, mode, alpha, label, dev=None):
+    G.run_build(ctx, ls, cam.eye, cull, alpha=alpha, dev=dev)
+    st = ctx.frame_status()
+    assert st["device_status"] == 0, label
+    assert st["n_fragments"] == fr.n_fragments, label
+    assert st["n_listed"] == fr.total, label
+    assert st["n_occupied"] == int(((fr.words & 0xFFFF) > 0).sum()), label
+    assert st["n_visible"] == int((fr.vis > 0).sum()), label
+    compare_structure_large(fr, G.fetch_as(ctx), G.fetch_ids(ctx, fr.total))
+    gid, gdepth, grgba = G.run_trace(ctx, cam, mode, alpha=alpha)
+    tr = orc.trace(fr, ls, cam, np.arange(cam.width * cam.height), mode, alpha=alpha)
+    assert (tr.id >= 0).sum() > 1000, label
+    return compare_trace(tr, gid, gdepth, grgba, ls, mode, label)
+
+
+@pytest.fixture(scope="module")
+def bundles_5m():
+    return synth.workload("bundles_5m")
+
+
+def test_bundles_5m_full_frame(orc, bundles_5m):
+    _need_gpu()
+    w = bundles_5m
+    ls, cam = w.lines, w.camera
+    print(f"bundles_5m: {ls.n_segments} segments, {ls.dims}, {cam.width}x{cam.height}", flush=True)
+    fo = orc.build_frame(ls, cam.eye, orc.CULL_OPAQUE)
+    assert fo.status == 0 and len(fo.occ) == 10
+    ctx = vrt.Context(max_vertices=ls.n_vertices, max_fragments=8 * ls.n_segments, max_dim=max(ls.dims))
+    try:
+        dev = G.to_device(ls)
+        unc = _structure_and_trace(orc, ctx, ls, cam, fo, vrt.CULL_OPAQUE, 0, 1.0, "bundles_5m opaque", dev)
+        print(f"opaque pass: {fo.total} listed, {unc:.2e} of pixels uncertified", flush=True)
+        fa = orc.recull_frame(fo, ls, cam.eye, orc.CULL_ALPHA, 0.2)
+        del fo
+        unc = _structure_and_trace(orc, ctx, ls, cam, fa, vrt.CULL_ALPHA, 1, 0.2, "bundles_5m alpha", dev)
+        print(f"alpha pass: {fa.total} listed, {unc:.2e} of pixels uncertified", flush=True)
+    finally:
+        ctx.close()
+
+
+def test_pathline_frames_from_graph_replay(orc):
+    _need_gpu()
+    import torch
+    frames = synth.pathline_frames()
+    ls0 = synth.pathline_frame(frames, 0)
+    cam = synth.grid_camera(ls0, 1280, 720)
+    P = cam.width * cam.height
+    print(f"pathlines: {ls0.n_segments} segments per frame, {ls0.dims}, {cam.width}x{cam.height}", flush=True)
+    ctx = vrt.Context(max_vertices=ls0.n_vertices, max_fragments=16 * ls0.n_segments, max_dim=max(ls0.dims),
+                      max_pixels=P)
+    xyz = torch.from_numpy(ls0.xyz).cuda()
+    off = torch.from_numpy(ls0.offsets).cuda()
+    rgba, depth = torch.empty(4 * P, device="cuda"), torch.empty(P, device="cuda")
+    fid = torch.empty(P, dtype=torch.int32, device="cuda")
+    eye = np.asarray(cam.eye, np.float32)
+    cam_a = G.camera_struct(cam, vrt.TRACE_TRANSPARENT, 0.3)
+    graph = ctx.frame_graph(xyz, off, ls0.radius, ls0.origin, ls0.voxel_size, ls0.dims,
+                            [((eye, vrt.CULL_ALPHA, 0.3, 1.0 / 256.0), cam_a, rgba, depth, fid)])
+    try:
+        for f in range(120):
+            ls = synth.pathline_frame(frames, f)
+            xyz.copy_(torch.from_numpy(ls.xyz))  # in place: the graph reads this address
+            graph.launch()
+            if f not in (0, 59, 119):
+                continue
+            torch.cuda.synchronize()
+            st = ctx.frame_status()
+            assert st["device_status"] == 0
+            fr = orc.build_frame(ls, cam.eye, orc.CULL_ALPHA, alpha=0.3)
+            assert st["n_fragments"] == fr.n_fragments and st["n_listed"] == fr.total, f
+            compare_structure_large(fr, G.fetch_as(ctx), G.fetch_ids(ctx, fr.total))
+            tr = orc.trace(fr, ls, cam, np.arange(P), 1, alpha=0.3)
+            assert (tr.id >= 0).sum() > 1000
+            unc = compare_trace(tr, fid.cpu().numpy().astype(np.int64), depth.cpu().numpy(),
+                                rgba.cpu().numpy().reshape(P, 4), ls, 1, f"pathline frame {f}")
+            print(f"frame {f}: {fr.total} listed, {unc:.2e} of pixels uncertified", flush=True)
+    finally:
+        graph.close()
+        ctx.close()
+
+
+def test_batch64_large_sets(orc):
+    _need_gpu()
+    import torch
+    ws = synth.batch_sets()
+    items, caps = [], []
+    for w in ws:
+        ls, cam = w.lines, w.camera
+        n = cam.width * cam.height
+        x, o = G.to_device(ls)
+        items.append(dict(xyz=x, offsets=o, radius=ls.radius, origin=ls.origin, voxel_size=ls.voxel_size,
+                          dims=ls.dims, view=(np.asarray(cam.eye, np.float32), vrt.CULL_OPAQUE, 1.0, 1.0 / 256.0),
+                          camera=G.camera_struct(cam, vrt.TRACE_OPAQUE), rgba=torch.zeros(4 * n, device="cuda"),
+                          depth=torch.zeros(n, device="cuda"), first_id=torch.zeros(n, dtype=torch.int32,
+                                                                                     device="cuda")))
+        caps.append((ls.n_vertices, 16 * ls.n_segments, max(ls.dims), n))
+    b = vrt.Batch(caps)
+    try:
+        b.run(items, vrt.BATCH_PERSISTENT)
+        torch.cuda.synchronize()
+        big_grid = max(range(len(ws)), key=lambda i: (max(ws[i].lines.dims), ws[i].lines.n_segments))
+        big_set = max(range(len(ws)), key=lambda i: ws[i].lines.n_segments)
+        assert max(ws[big_grid].lines.dims) >= 256
+        for k in sorted({big_grid, big_set}):
+            ls, cam = ws[k].lines, ws[k].camera
+            print(f"batch set {k}: {ls.n_segments} segments, {ls.dims}", flush=True)
+            c = b.context(k)
+            st = c.frame_status()
+            assert st["device_status"] == 0
+            fr = orc.build_frame(ls, cam.eye, orc.CULL_OPAQUE)
+            assert st["n_fragments"] == fr.n_fragments and st["n_listed"] == fr.total
+            compare_structure_large(fr, G.fetch_as(c), G.fetch_ids(c, fr.total))
+            P = cam.width * cam.height
+            tr = orc.trace(fr, ls, cam, np.arange(P), 0)
+            compare_trace(tr, items[k]["first_id"].cpu().numpy().astype(np.int64), items[k]["depth"].cpu().numpy(),
+                          items[k]["rgba"].cpu().numpy().reshape(P, 4), ls, 0, f"batch set {k}")
+    finally:
+        b.close()
+
+
+def test_duplicate_segments_tie_to_lower_id(orc):
+    """Every polyline appears three times: identical capsules are hit at bit-identical parameters on the
+    GPU, and the oracle orders their hits by id (not by an unresolvable gap), so the pixels they cover are
+    certified and the first hit must be the lowest id of the copies."""
+    _need_gpu()
+    base = synth.random_walk_set(seed=21, n_poly=60, n_seg=40, G=64)
+    nvp = 41
+    polys = base.xyz.reshape(60, nvp, 3)
+    xyz = np.repeat(polys[:, None], 3, axis=1).reshape(-1, 3)  # polyline p three times in a row
+    off = np.arange(0, 180 * nvp + 1, nvp, dtype=np.int32)
+    ls = synth.LineSet(xyz=np.ascontiguousarray(xyz, np.float32), offsets=off, radius=base.radius,
+                       origin=base.origin, voxel_size=base.voxel_size, dims=base.dims)
+    cam = synth.grid_camera(ls, 160, 120)
+    ctx = vrt.Context(max_vertices=ls.n_vertices, max_fragments=4_000_000, max_dim=64)
+    try:
+        for mode, cull, alpha in ((0, vrt.CULL_OPAQUE, 1.0), (1, vrt.CULL_NONE, 0.3)):
+            fr = orc.build_frame(ls, cam.eye, cull, alpha=alpha)
+            G.run_build(ctx, ls, cam.eye, cull, alpha=alpha)
+            gid, gdepth, grgba = G.run_trace(ctx, cam, mode, alpha=alpha)
+            tr = orc.trace(fr, ls, cam, np.arange(cam.width * cam.height), mode, alpha=alpha)
+            cert = certified(tr, mode)
+            hit = cert & (tr.id >= 0)
+            # the oracle's first hit is always the first copy of its polyline (ids of copy 0 are < 41 mod 123)
+            assert hit.sum() > 500
+            assert ((tr.id[hit] % (3 * nvp)) < nvp).all()
+            compare_trace(tr, gid, gdepth, grgba, ls, mode, f"duplicates mode {mode}")
+    finally:
+        ctx.close()

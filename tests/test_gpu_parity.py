@@ -17,10 +17,10 @@ from . import _gpu as G
 
 pytestmark = pytest.mark.gpu
 
-EPS_GEOM = 2e-5       # voxel units: hit/miss, clip plane and hit-order margins
-EPS_FACE0 = 1e-5      # voxel units, plus EPS_FACE_T * t: voxel-face margins
-EPS_FACE_T = 2.4e-7   # 4x the binary32 rounding of a boundary parameter t
-MAX_UNCERTIFIED = 2e-3
+EPS_GEOM = G.EPS_GEOM        # voxel units: hit/miss, clip plane and hit-order margins
+EPS_FACE0 = G.EPS_FACE0      # voxel units, plus EPS_FACE_T * t: voxel-face margins
+EPS_FACE_T = G.EPS_FACE_T    # 4x the binary32 rounding of a boundary parameter t
+MAX_UNCERTIFIED = G.MAX_UNCERTIFIED
 
 
 @pytest.fixture(scope="module")
@@ -73,8 +73,7 @@ def compare_structure(orc, fr, got, check_lists=True, ids=None):
 
 
 def certified(tr, mode):
-    t = np.where(np.isfinite(tr.t), tr.t, 0.0)
-    return (tr.m_geom > EPS_GEOM) & (tr.m_face > EPS_FACE0 + EPS_FACE_T * t)
+    return G.certified(tr)
 
 
 def compare_trace(tr, gid, gdepth, grgba, ls, mode, label):
@@ -119,6 +118,8 @@ def test_structure_parity(orc, ctx, wl_cache, name, cull):
     assert st["device_status"] == 0
     assert st["n_fragments"] == fr.n_fragments
     assert st["n_listed"] == fr.total
+    assert st["n_occupied"] == int(((fr.words & 0xFFFF) > 0).sum())
+    assert st["n_visible"] == int((fr.vis > 0).sum())
     got = G.fetch_as(ctx)
     ids = G.fetch_ids(ctx, fr.total)
     compare_structure(orc, fr, got, ids=ids)
@@ -296,3 +297,161 @@ def test_not_built_order():
         assert e.value.status == vrt.VRT_ERR_NOT_BUILT
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+@pytest.mark.parametrize("cull", [vrt.CULL_NONE, vrt.CULL_OPAQUE, vrt.CULL_ALPHA])
+def test_sorted_lists_equal_the_oracle_bytes(orc, ctx, wl_cache, name, cull):
+    """After vrt_sort_lists every list is in ascending id order, so the whole id array equals the oracle's
+    (whose lists are built in id order) byte for byte; the images do not change."""
+    w = get_wl(name, wl_cache)
+    fr = orc.build_frame(w.lines, w.camera.eye, cull, alpha=0.2)
+    G.run_build(ctx, w.lines, w.camera.eye, cull, alpha=0.2)
+    before = G.run_trace(ctx, w.camera, 1, alpha=0.2)
+    ctx.sort_lists()
+    ids = G.fetch_ids(ctx, fr.total)
+    assert np.array_equal(ids, fr.ids.astype(np.uint32)), "sorted id array differs from the oracle's"
+    after = G.run_trace(ctx, w.camera, 1, alpha=0.2)
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+
+
+def test_sorted_lists_long_lists(orc, ctx):
+    """Lists longer than the LDS sort (5000 segments crossing one voxel) and of medium length (the crowded
+    brick) sort to the oracle's bytes too."""
+    rng = np.random.default_rng(5)
+    c = np.array([4.5, 4.5, 4.5])
+    d = rng.normal(size=(5000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    polys = [[c - 0.4 * u, c + 0.4 * u] for u in d]
+    for ls in (_make(polys, 16, 0.05), EDGE_SETS["crowded_brick"]()):
+        eye = np.array([2.0, 1.3, 1.5])
+        fr = orc.build_frame(ls, eye, vrt.CULL_NONE)
+        G.run_build(ctx, ls, eye, vrt.CULL_NONE)
+        assert ctx.frame_status()["device_status"] == 0
+        ctx.sort_lists()
+        ids = G.fetch_ids(ctx, fr.total)
+        assert np.array_equal(ids, fr.ids.astype(np.uint32))
+        assert int((fr.words & 0xFFFF).max()) > 1000
+
+
+@pytest.mark.parametrize("alpha", [0.05, 0.1, 0.5, 0.9, 1.0])
+def test_alpha_sweep_parity(orc, ctx, wl_cache, alpha):
+    """The opacity sweep: alpha culling (the blocking limit follows alpha) and the transparent trace at
+    each opacity match the oracle, and so does the unculled transparent trace at the same opacity."""
+    w = get_wl("bundles_small", wl_cache)
+    ls, cam = w.lines, w.camera
+    pix = np.arange(cam.width * cam.height)
+    for cull in (vrt.CULL_ALPHA, vrt.CULL_NONE):
+        fr = orc.build_frame(ls, cam.eye, cull, alpha=alpha)
+        G.run_build(ctx, ls, cam.eye, cull, alpha=alpha)
+        st = ctx.frame_status()
+        assert st["device_status"] == 0 and st["n_listed"] == fr.total
+        compare_structure(orc, fr, G.fetch_as(ctx), ids=G.fetch_ids(ctx, fr.total))
+        gid, gdepth, grgba = G.run_trace(ctx, cam, 1, alpha=alpha)
+        tr = orc.trace(fr, ls, cam, pix, 1, alpha=alpha)
+        compare_trace(tr, gid, gdepth, grgba, ls, 1, f"alpha={alpha} cull={cull}")
+
+
+def _build_mode(ctx, ls, eye, cull, voxelizer, alpha=1.0, rgba=None, alpha_default=0.0):
+    import torch
+    xyz, off = G.to_device(ls)
+    ctx.voxelize(xyz, off, ls.radius, ls.origin, ls.voxel_size, ls.dims, voxelizer=voxelizer, rgba=rgba,
+                 alpha_default=alpha_default)
+    ctx.cull(np.asarray(eye, np.float32), cull, alpha)
+    torch.cuda.synchronize()
+    return xyz, off
+
+
+@pytest.mark.parametrize("voxelizer", [vrt.VOX_THIN, vrt.VOX_AABB])
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_comparison_voxelizers_parity(orc, ctx, wl_cache, name, voxelizer):
+    """The thin-line and capsule-AABB voxelizers (Sec. 4.1, Table 2): words, pyramids and lists bit-exact
+    against the oracle's definitions; the AABB lists contain the capsule lists, so its trace is the capsule
+    image (certified pixels)."""
+    w = get_wl(name, wl_cache)
+    ls, cam = w.lines, w.camera
+    for cull in (vrt.CULL_NONE, vrt.CULL_OPAQUE):
+        fr = orc.build_frame(ls, cam.eye, cull, mode=voxelizer)
+        _build_mode(ctx, ls, cam.eye, cull, voxelizer)
+        st = ctx.frame_status()
+        assert st["device_status"] == 0 and st["n_fragments"] == fr.n_fragments and st["n_listed"] == fr.total
+        compare_structure(orc, fr, G.fetch_as(ctx), ids=G.fetch_ids(ctx, fr.total))
+    if voxelizer == vrt.VOX_AABB:
+        gid, gdepth, grgba = G.run_trace(ctx, cam, 0)
+        tr = orc.trace(fr, ls, cam, np.arange(cam.width * cam.height), 0)
+        compare_trace(tr, gid, gdepth, grgba, ls, 0, f"{name} AABB lists")
+
+
+@pytest.mark.parametrize("name", sorted(EDGE_SETS))
+def test_comparison_voxelizers_edge_cases(orc, ctx, name):
+    ls = EDGE_SETS[name]()
+    eye = ls.origin + np.array(ls.dims, float) * ls.voxel_size * np.array([1.8, -0.6, 1.4])
+    for voxelizer in (vrt.VOX_THIN, vrt.VOX_AABB):
+        fr = orc.build_frame(ls, eye, vrt.CULL_NONE, mode=voxelizer)
+        _build_mode(ctx, ls, eye, vrt.CULL_NONE, voxelizer)
+        st = ctx.frame_status()
+        assert st["device_status"] == fr.status == 0
+        assert st["n_fragments"] == fr.n_fragments, (name, voxelizer)
+        compare_structure(orc, fr, G.fetch_as(ctx), ids=G.fetch_ids(ctx, fr.total))
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_per_segment_colour_and_opacity(orc, ctx, wl_cache, name):
+    """Per-segment RGBA (random colours, opacities in [0.05, 0.95]): opaque colour of the first hit and
+    front-to-back compositing with each hit's own opacity match the oracle; without RGBA the lines' default
+    opacity replaces the camera's."""
+    import torch
+    w = get_wl(name, wl_cache)
+    ls, cam = w.lines, w.camera
+    rng = np.random.default_rng(8)
+    rgba = np.concatenate([rng.uniform(0, 1, (ls.n_vertices, 3)), rng.uniform(0.05, 0.95, (ls.n_vertices, 1))],
+                          axis=1).astype(np.float32)
+    rgba_d = torch.from_numpy(rgba).cuda()
+    pix = np.arange(cam.width * cam.height)
+    for mode, cull in ((0, vrt.CULL_OPAQUE), (1, vrt.CULL_NONE)):
+        fr = orc.build_frame(ls, cam.eye, cull)
+        _build_mode(ctx, ls, cam.eye, cull, vrt.VOX_CAPSULE, rgba=rgba_d)
+        gid, gdepth, grgba = G.run_trace(ctx, cam, mode, alpha=0.3)
+        tr = orc.trace(fr, ls, cam, pix, mode, alpha=0.3, seg_rgba=rgba)
+        compare_trace(tr, gid, gdepth, grgba, ls, mode, f"{name} rgba mode {mode}")
+    fr = orc.build_frame(ls, cam.eye, vrt.CULL_NONE)
+    _build_mode(ctx, ls, cam.eye, vrt.CULL_NONE, vrt.VOX_CAPSULE, alpha_default=0.45)
+    gid, gdepth, grgba = G.run_trace(ctx, cam, 1, alpha=0.3)
+    tr = orc.trace(fr, ls, cam, pix, 1, alpha=0.45)
+    compare_trace(tr, gid, gdepth, grgba, ls, 1, f"{name} alpha_default")
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+@pytest.mark.parametrize("light,cones,samples,ambient", [((0.3, 0.5, 0.8), 16, 4, 0.3),
+                                                          ((-1.0, 0.2, -0.1), 32, 3, 0.0),
+                                                          ((0.0, 0.0, 1.0), 6, 5, 0.6)])
+def test_voxel_shading_parity(orc, ctx, wl_cache, name, light, cones, samples, ambient):
+    """Voxel-space shading (Sec. 3.4): the shading of every visible voxel against the oracle's binary64
+    evaluation (the sample cells and the shadow walk are integer-exact; the binary32 accumulations differ
+    by rounding only), and the shaded images on the certified pixels."""
+    w = get_wl(name, wl_cache)
+    ls, cam = w.lines, w.camera
+    pix = np.arange(cam.width * cam.height)
+    for mode, cull, alpha in ((0, vrt.CULL_OPAQUE, 1.0), (1, vrt.CULL_ALPHA, 0.3)):
+        fr = orc.build_frame(ls, cam.eye, cull, alpha=alpha)
+        ao, sh, lit = orc.shade(fr.occ, fr.vis, n_cones=cones, n_samples=samples, light=light, ambient=ambient)
+        G.run_build(ctx, ls, cam.eye, cull, alpha=alpha)
+        ctx.shade(light, cones, samples, ambient)
+        got = G.fetch_as(ctx)["lit"]
+        v = fr.vis > 0
+        err = np.abs(got[v].astype(np.float64) - lit[v])
+        assert err.max() <= 1e-4, f"shading differs by {err.max():.2e}"
+        assert lit[v].min() < 0.9 and lit[v].max() > ambient * 0.5  # the field is not trivial
+        gid, gdepth, grgba = G.run_trace(ctx, cam, mode, alpha=alpha)
+        tr = orc.trace(fr, ls, cam, pix, mode, alpha=alpha, lit=lit)
+        cert = certified(tr, mode)
+        assert not (cert & (gid != tr.id)).any()
+        cerr = np.abs(grgba[cert].astype(np.float64) - tr.rgba[cert])
+        assert cerr.max(initial=0) <= 2e-4, f"shaded colour differs by {cerr.max():.2e}"
+    # the next cull turns shading off: the plain image again
+    gid, gdepth, grgba = G.run_trace(ctx, cam, 1, alpha=0.3)
+    ctx.cull(np.asarray(cam.eye, np.float32), vrt.CULL_ALPHA, 0.3)
+    plain = G.run_trace(ctx, cam, 1, alpha=0.3)
+    tr = orc.trace(fr, ls, cam, pix, 1, alpha=0.3)
+    compare_trace(tr, *plain, ls, 1, "unshaded after a new cull")
