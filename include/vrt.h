@@ -264,6 +264,36 @@ vrt_status vrt_graph_create(vrt_ctx *ctx, const vrt_lines *lines, const vrt_grid
 vrt_status vrt_graph_launch(vrt_graph *g, void *stream);
 vrt_status vrt_graph_destroy(vrt_graph *g);
 
+/* One frame without allocation, for callers that cannot allocate device memory
+ * (work under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels as vrt_voxelize(lines, grid), vrt_cull(view)
+ * and vrt_trace(cam, img) in sequence, with no context.  The acceleration
+ * structure lives in one fixed device array of VRT_NOALLOC_SCRATCH_BYTES per
+ * device, which the library holds from the first call on that device until
+ * the process ends; the call itself allocates nothing (no hipMalloc, no
+ * allocating library routine).  The caller passes the inputs and the output
+ * image, as for the per-stage calls (device pointers, borrowed until the
+ * stream work completes).
+ * Limits: n_vertices <= VRT_NOALLOC_MAX_VERTICES, every grid dimension <=
+ * VRT_NOALLOC_MAX_DIM and width * height <= VRT_NOALLOC_MAX_PIXELS, else
+ * VRT_ERR_CAPACITY before anything is enqueued; more than
+ * VRT_NOALLOC_MAX_FRAGMENTS listed fragments latch VRT_ERR_CAPACITY on the
+ * device.  Other argument errors as for the per-stage calls, also before
+ * anything is enqueued.
+ * info: NULL (nothing synchronizes; device errors of this frame are then not
+ * reported) or filled as by vrt_frame_status (synchronizes the stream).
+ * Every call on one device shares that device's array and the host state of
+ * its frame, which keep the last call's contents (each call clears what it
+ * needs at zero): calls that overlap on one device -- two streams, or two
+ * threads -- race and must be serialized by the caller. */
+#define VRT_NOALLOC_MAX_VERTICES 65536
+#define VRT_NOALLOC_MAX_FRAGMENTS (1 << 20)
+#define VRT_NOALLOC_MAX_DIM 64
+#define VRT_NOALLOC_MAX_PIXELS (512 * 512)
+#define VRT_NOALLOC_SCRATCH_BYTES (24 << 20)
+vrt_status vrt_frame_noalloc(const vrt_lines *lines, const vrt_grid *grid, const vrt_view *view,
+                             const vrt_camera *cam, const vrt_image *img, vrt_frame_info *info, void *stream);
+
 /* Batched form: many independent line sets, each with its own grid, view,
  * camera and image, built and traced together.  VRT_BATCH_PERSISTENT runs
  * every stage of every set in ONE cooperative launch: the frame's stages are

@@ -630,3 +630,115 @@ const char *vrt_status_string(vrt_status s) {
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// One frame without allocation, for callers that cannot allocate device
+// memory.  The acceleration structure lives in `scratch`, one fixed array per
+// device; host code reaches it only through the address hipGetSymbolAddress
+// returns for that device (the array's name is a host-side stand-in).
+
+#include <mutex>
+#include <type_traits>
+
+static __device__ __align__(256) unsigned char scratch[VRT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+
+struct NoAllocSlot {
+    bool ready = false;
+    unsigned char *ptr = nullptr;  // this device's copy of scratch
+    vrt_ctx ctx;                   // host state of the frame; its arenas are placed in ptr
+};
+NoAllocSlot g_noalloc[kNoAllocDevices];
+std::mutex g_noalloc_mu;
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void fill_u32(void *p, int64_t n, uint32_t v, hipStream_t st) {
+    if (n <= 0) return;
+    const int64_t blocks = (n + 255) / 256;
+    k_fill_u32<<<(unsigned)(blocks < 1024 ? blocks : 1024), 256, 0, st>>>((uint32_t *)p, n, v);
+}
+
+// The current device's slot; on its first use looks up the device address of
+// scratch and places every arena in it.
+vrt_status noalloc_slot(NoAllocSlot **out) {
+    int dev = 0;
+    VRT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocDevices) return VRT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    NoAllocSlot &s = g_noalloc[dev];
+    if (!s.ready) {
+        void *p = nullptr;
+        VRT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        vrt_desc d = {VRT_NOALLOC_MAX_VERTICES, VRT_NOALLOC_MAX_FRAGMENTS, VRT_NOALLOC_MAX_DIM, dev,
+                      VRT_NOALLOC_MAX_PIXELS, VRT_FORM_PLAIN, 0};
+        vrt_ctx &c = s.ctx;
+        ctx_sizes(&c, d);
+        unsigned char *base = static_cast<unsigned char *>(p);
+        size_t off = 0;
+        arena_fields(c.a, d, c.max_bricks, c.hi_elems, [&](auto *&q, int64_t n) {
+            using T = std::remove_reference_t<decltype(*q)>;
+            off = (off + 255) & ~(size_t)255;
+            q = reinterpret_cast<T *>(base + off);
+            off += (size_t)(n > 0 ? n : 1) * sizeof(T);
+        });
+        if (off > (size_t)VRT_NOALLOC_SCRATCH_BYTES) {  // the limits above do not fit the array
+            c = vrt_ctx();
+            return VRT_ERR_CAPACITY;
+        }
+        s.ptr = base;
+        s.ready = true;
+    }
+    *out = &s;
+    return VRT_OK;
+}
+
+}  // namespace
+
+extern "C" vrt_status vrt_frame_noalloc(const vrt_lines *lines, const vrt_grid *grid, const vrt_view *view,
+                                        const vrt_camera *cam, const vrt_image *img, vrt_frame_info *info,
+                                        void *stream) {
+    if (!lines || !grid || !view || !cam || !img || !img->rgba) return VRT_ERR_INVALID_ARG;
+    if (lines->n_vertices > VRT_NOALLOC_MAX_VERTICES || grid->dims[0] > VRT_NOALLOC_MAX_DIM ||
+        grid->dims[1] > VRT_NOALLOC_MAX_DIM || grid->dims[2] > VRT_NOALLOC_MAX_DIM ||
+        (int64_t)cam->width * (int64_t)cam->height > VRT_NOALLOC_MAX_PIXELS)
+        return VRT_ERR_CAPACITY;
+    NoAllocSlot *s = nullptr;
+    vrt_status r = noalloc_slot(&s);
+    if (r != VRT_OK) return r;
+    vrt_ctx *c = &s->ctx;
+    // every argument is validated before anything is enqueued
+    float s_q;
+    r = prepare_voxelize(c, lines, grid, &s_q);
+    if (r != VRT_OK) return r;
+    c->voxelized = true;
+    int64_t E[3], limit;
+    r = prepare_cull(c, view, E, &limit);
+    if (r != VRT_OK) return r;
+    TraceParams p;
+    r = camera_params(c, cam, p);
+    if (r != VRT_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    c->last_stream = st;
+    // the previous call's contents: clear what the frame expects at zero
+    // (words, brick flags, bin counters, status) and the brick-slot map
+    const Arenas &A = c->a;
+    const int64_t nb = (int64_t)(c->dims[0] / 8) * (c->dims[1] / 8) * (c->dims[2] / 8);
+    fill_u32(A.words, nb * kBrickVox, 0u, st);
+    fill_u32(A.brick_flag, (nb + 3) / 4, 0u, st);
+    fill_u32(A.bin_count, nb * kBinStride, 0u, st);
+    fill_u32(A.brick_slot, nb, 0xFFFFFFFFu, st);
+    fill_u32(A.status, (int64_t)(sizeof(DevStatus) / 4), 0u, st);
+    VRT_HIP(hipGetLastError());
+    VRT_HIP(launch_voxelize(c, lines, s_q, st));
+    VRT_HIP(launch_cull(c, E, limit, st));
+    c->culled = true;
+    VRT_HIP(launch_trace(c, p, img, st));
+    if (info) return vrt_frame_status(c, info);
+    return VRT_OK;
+}

@@ -28,8 +28,9 @@ EXPORTED = ["vrt_create", "vrt_destroy", "vrt_voxelize", "vrt_cull", "vrt_trace"
             "vrt_profile_enable", "vrt_profile_read", "vrt_trace_stats_run", "vrt_graph_create",
             "vrt_graph_launch", "vrt_graph_destroy", "vrt_batch_create", "vrt_batch_run", "vrt_batch_context",
             "vrt_batch_destroy", "vrt_set_tune", "vrt_get_tune", "vrt_autotune", "vrt_autotune_grid",
-            "vrt_microbench", "vrt_sort_lists", "vrt_shade"]
+            "vrt_frame_noalloc", "vrt_microbench", "vrt_sort_lists", "vrt_shade"]
 MB_COPY, MB_ATOMIC_RANDOM, MB_ATOMIC_BRICK = 0, 1, 2
+NOALLOC_MAX_VERTICES, NOALLOC_MAX_FRAGMENTS, NOALLOC_MAX_DIM, NOALLOC_MAX_PIXELS = 65536, 1 << 20, 64, 512 * 512
 
 
 class VrtError(RuntimeError):
@@ -166,6 +167,8 @@ def load():
         L.vrt_autotune_grid.argtypes = [P, C.POINTER(vrt_lines), C.POINTER(vrt_grid), C.c_int32,
                                         C.POINTER(vrt_view), C.POINTER(vrt_camera), C.POINTER(vrt_image), C.c_int32,
                                         C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float), P]
+        L.vrt_frame_noalloc.argtypes = [C.POINTER(vrt_lines), C.POINTER(vrt_grid), C.POINTER(vrt_view),
+                                        C.POINTER(vrt_camera), C.POINTER(vrt_image), C.POINTER(vrt_frame_info), P]
         L.vrt_microbench.argtypes = [C.c_int32, P, C.c_int64, C.c_int64, C.POINTER(C.c_float), P]
         L.vrt_sort_lists.argtypes = [P, P]
         L.vrt_shade.argtypes = [P, C.POINTER(vrt_shading), P]
@@ -177,7 +180,7 @@ def load():
                      "vrt_profile_read", "vrt_trace_stats_run", "vrt_graph_create", "vrt_graph_launch",
                      "vrt_graph_destroy", "vrt_batch_create", "vrt_batch_run", "vrt_batch_context",
                      "vrt_batch_destroy", "vrt_set_tune", "vrt_get_tune", "vrt_autotune", "vrt_autotune_grid",
-                     "vrt_microbench", "vrt_sort_lists", "vrt_shade"]:
+                     "vrt_frame_noalloc", "vrt_microbench", "vrt_sort_lists", "vrt_shade"]:
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -238,6 +241,24 @@ def microbench(kind, buf, ops=0, stream=None):
 def _info_dict(info):
     return {"device_status": info.device_status, "n_fragments": info.n_fragments, "n_listed": info.n_listed,
             "n_bricks": info.n_bricks, "n_occupied": info.n_occupied, "n_visible": info.n_visible}
+
+
+def frame_noalloc(xyz, offsets, radius, origin, voxel_size, dims, view, camera: vrt_camera, rgba, depth=None,
+                  first_id=None, status=True, stream=None):
+    """One frame (voxelize, cull, trace) in the library's fixed per-device arena, with no context and no
+    allocation.  view = (eye, cull_mode, alpha, tau).  status: synchronize and return the frame totals
+    (as Context.frame_status), else return None without synchronizing."""
+    lines = make_lines(xyz, offsets, radius)
+    grid = vrt_grid(_f3(origin), float(voxel_size), (C.c_int32 * 3)(*[int(x) for x in dims]))
+    eye, mode, alpha, tau = view
+    v = vrt_view(_f3(eye), int(mode), float(alpha), float(tau))
+    img = vrt_image(_ptr(rgba), _ptr(depth), _ptr(first_id))
+    info = vrt_frame_info()
+    _check(load().vrt_frame_noalloc(C.byref(lines), C.byref(grid), C.byref(v), C.byref(camera), C.byref(img),
+                                    C.byref(info) if status else None, _stream_ptr(stream)), "vrt_frame_noalloc")
+    if not status:
+        return None
+    return _info_dict(info)
 
 
 class Context:
