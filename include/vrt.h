@@ -75,7 +75,7 @@ typedef struct {
     int64_t max_pixels;    /* largest width * height accepted by vrt_trace */
     int32_t form;          /* VRT_FORM_PLAIN or VRT_FORM_FP16: the segment records the tracer reads.  FP16:
                               each segment stores its endpoints as binary16 offsets (voxel units) from the centre
-                              of the 8^3 brick holding its midpoint, binary16 clip normals and int16 brick
+                              of the 8^3 brick holding its midpoint, 16-bit fixed-point clip normals and int16 brick
                               coordinates (32 B per segment instead of two 32-B vertex records); intersection
                               and compositing stay binary32 and voxel membership stays exact int32.  Offsets
                               are exact while |offset| < 8 voxels; a segment with a longer offset is

@@ -22,10 +22,18 @@ namespace {
 constexpr int kBatchThreads = 512;
 constexpr int kMaxBatch = 1024;
 constexpr int kParts = 3;  // stages sharing one phase
+// Work per virtual block of the per-brick phases (their bodies loop over
+// slots with the virtual block's stride): fewer tickets and barriers.
+constexpr unsigned kBricksPerVB = 8;  // occupied bricks
+constexpr unsigned kItemsPerVB = 4;   // binned (brick, chunk) items or candidate bricks
 enum : int {
     P_CLEAR, P_INGEST, P_BIN_COUNT, P_BIN_ALLOC, P_BIN_FILL, P_ACCUM, P_LONG, P_COMPACT, P_OCC, P_ERODE, P_WALK,
-    P_CBRICK, P_SCAN, P_OFFSETS, P_SCATTER, P_SCATTER_LONG, P_MARCH, P_SHADE, kPhases
+    P_CBRICK, P_SCAN, P_OFFSETS, P_SCATTER, P_SCATTER_LONG, P_MARCH, P_SHADE8, P_SHADE16, P_SHADE32, kPhases
 };
+// The shade phase is split by the sets' group size, so that each staged
+// kernel holds the tracer body of one group size only (and keeps its
+// register budget).
+__host__ __device__ constexpr int shade_phase_group(int ph) { return ph == P_SHADE8 ? 8 : (ph == P_SHADE16 ? 16 : 32); }
 
 struct SetDesc {
     Arenas a;
@@ -48,27 +56,33 @@ __device__ unsigned part_blocks(int ph, int part, const SetDesc &d) {
     const DevStatus *st = d.a.status;
     const unsigned T = kBatchThreads;
     switch (ph) {
-    case P_CLEAR: return part == 0 ? st->n_bricks : (part == 1 ? cdiv(reset_items(d.vp.nb, d.vp.nw, d.vp.nf), T) : 0u);
+    case P_CLEAR:
+        return part == 0 ? cdiv(st->n_bricks, kBricksPerVB)
+                         : (part == 1 ? cdiv(reset_items(d.vp.nb, d.vp.nw, d.vp.nf), T) : 0u);
     case P_INGEST: return part == 0 ? cdiv(d.vp.nv, T) : 0u;
     case P_BIN_COUNT: return part == 0 ? (d.fp16 ? cdiv(d.vp.nv, T) : 0u) : (part == 1 ? cdiv(d.vp.nv, T) : 0u);
     case P_BIN_ALLOC: return part == 0 ? cdiv(st->n_cand, T) : 0u;
     case P_BIN_FILL: return part == 0 ? cdiv(d.vp.nv, T) : 0u;
-    case P_ACCUM: return part == 0 ? st->n_items : 0u;
+    case P_ACCUM: return part == 0 ? cdiv(st->n_items, kItemsPerVB) : 0u;
     case P_LONG: return part == 0 ? cdiv(st->n_long, T) : 0u;
     case P_COMPACT: return part == 0 ? 1u : 0u;
-    case P_OCC: return part == 0 ? st->n_bricks : 0u;
+    case P_OCC: return part == 0 ? cdiv(st->n_bricks, kBricksPerVB) : 0u;
     case P_ERODE:
-        if (part == 0) return st->n_bricks;
+        if (part == 0) return cdiv(st->n_bricks, kBricksPerVB);
         if (part == 1) return d.n_levels > 4 ? mip_tree_regions(d.levels) : 0u;
         return cdiv(d.cp.nb > d.n_hi ? d.cp.nb : d.n_hi, T);
     case P_WALK: return part == 0 ? (d.cp.limit >= 0 ? cdiv(st->n_occ, T) : 0u) : (part == 1 && d.n_levels > 8 ? 1u : 0u);
-    case P_CBRICK: return part == 0 ? st->n_bricks : 0u;
+    case P_CBRICK: return part == 0 ? cdiv(st->n_bricks, kBricksPerVB) : 0u;
     case P_SCAN: return part == 0 ? 1u : 0u;
-    case P_OFFSETS: return part == 0 ? st->n_bricks : 0u;
-    case P_SCATTER: return part == 0 ? st->n_cand : 0u;
+    case P_OFFSETS: return part == 0 ? cdiv(st->n_bricks, kBricksPerVB) : 0u;
+    case P_SCATTER: return part == 0 ? cdiv(st->n_cand, kItemsPerVB) : 0u;
     case P_SCATTER_LONG: return part == 0 ? cdiv(st->n_long, T) : (part == 1 ? 1u : 0u);
     case P_MARCH: return part == 0 ? d.march_blocks : 0u;
-    case P_SHADE: return part == 0 ? cdiv(st->n_queue, T / (unsigned)d.shade_group) : 0u;
+    case P_SHADE8:
+    case P_SHADE16:
+    case P_SHADE32:  // one-wave units, in the phase of the set's group size
+        return part == 0 && d.shade_group == shade_phase_group(ph) ? cdiv(st->n_queue, 64u / (unsigned)d.shade_group)
+                                                                    : 0u;
     default: return 0u;
     }
 }
@@ -90,7 +104,7 @@ __device__ __forceinline__ void run_part(int ph, int part, const SetDesc &d, uns
         break;
     case P_BIN_ALLOC: b_bin_alloc(d.vp.ba, A.status, vb, nvb); break;
     case P_BIN_FILL: b_bin_fill(d.vp.ba, A.status, vb, nvb); break;
-    case P_ACCUM: b_brick_accum(d.vp.aa, A.status, vb, nvb); break;
+    case P_ACCUM: b_brick_accum<-1>(d.vp.aa, A.status, vb, nvb); break;
     case P_LONG: b_vox_long(d.vp.ca, A.long_ids, A.status, vb, nvb); break;
     case P_COMPACT: b_brick_compact(A.brick_flag, d.vp.nb, A.brick_list, A.brick_slot, A.status, 0u, 1u); break;
     case P_OCC: b_occ_brick(A.words, A.brick_list, A.status, A.occ0, A.occ1, A.occ2, A.occ3, A.occ_list, vb, nvb); break;
@@ -111,25 +125,45 @@ __device__ __forceinline__ void run_part(int ph, int part, const SetDesc &d, uns
         break;
     case P_SCAN: b_scan_bricks(A.brick_total, A.brick_base, A.status, d.capacity, A.vis_hi, d.levels, d.n_levels, 0u, 1u); break;
     case P_OFFSETS: b_list_offsets(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor, A.cell, A.lmask, A.lmask2, vb, nvb); break;
-    case P_SCATTER: b_scatter_brick(d.cp.sb, A.status, vb, nvb); break;
+    case P_SCATTER: b_scatter_brick<-1>(d.cp.sb, A.status, vb, nvb); break;
     case P_SCATTER_LONG:
         if (part == 0) b_scatter_long(d.cp.sb, A.status, vb, nvb);
         else b_trace_begin(A.status, 0u, 1u);
         break;
     case P_MARCH: b_trace_march<false>(d.ta, vb, nvb); break;
-    case P_SHADE:  // the set's tuned group size; entries per fetch and keys per lane keep their defaults
-        if (d.fp16) {
-            if (d.shade_group == 8) b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<8, 2, 4>>(d.ta, vb, nvb);
-            else if (d.shade_group == 32) b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<32, 2, 4>>(d.ta, vb, nvb);
-            else b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<16, 2, 4>>(d.ta, vb, nvb);
-        } else {
-            if (d.shade_group == 8) b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<8, 2, 4>>(d.ta, vb, nvb);
-            else if (d.shade_group == 32) b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<32, 2, 4>>(d.ta, vb, nvb);
-            else b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<16, 2, 4>>(d.ta, vb, nvb);
-        }
+    case P_SHADE8:  // one wave per unit; the set's tuned group size, default batch and keys
+        if (d.fp16) b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<8, 2, 4>>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
+        else b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<8, 2, 4>>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
+        break;
+    case P_SHADE16:
+        if (d.fp16) b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<16, 2, 4>>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
+        else b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<16, 2, 4>>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
+        break;
+    case P_SHADE32:
+        if (d.fp16) b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<32, 2, 4>>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
+        else b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<32, 2, 4>>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
         break;
     default: break;
     }
+}
+
+// Runs ticket t of a phase: the (set, stage) whose range of pre[] holds it.
+// The ticket is uniform over the wave, and so are the set index and the
+// virtual block derived from it (made explicit with readfirstlane), so the
+// set's arguments are read with scalar loads into scalar registers, as a
+// kernel's own arguments are.
+__device__ __forceinline__ void run_ticket(int ph, const SetDesc *__restrict__ sets, int nk, const unsigned *pre,
+                                           unsigned t) {
+    int lo = 0, hi = nk - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const unsigned b0 = (unsigned)__builtin_amdgcn_readfirstlane((int)pre[lo]);
+    const unsigned b1 = (unsigned)__builtin_amdgcn_readfirstlane((int)pre[lo + 1]);
+    run_part(ph, lo % kParts, sets[lo / kParts], t - b0, b1 - b0);
 }
 
 // One phase of the batch: the resident blocks take the phase's virtual blocks
@@ -148,24 +182,33 @@ __device__ __forceinline__ void batch_phase(int ph, const SetDesc *__restrict__ 
     }
     __syncthreads();
     const unsigned total = pre[nk];
+    if (ph >= P_SHADE8) {  // the waves take one-wave units on their own: a long ray holds only its wave
+        const unsigned lane = threadIdx.x & 63u;
+        for (;;) {
+            unsigned t = 0;
+            if (lane == 0) t = atomicAdd(&tickets[ph], 1u);
+            t = (unsigned)__builtin_amdgcn_readfirstlane((int)t);  // wave-uniform: scalar from here on
+            if (t >= total) break;
+            run_ticket(ph, sets, nk, pre, t);
+        }
+        __syncthreads();  // pre[] is rewritten by the next phase
+        return;
+    }
     for (;;) {
         if (threadIdx.x == 0) ticket = atomicAdd(&tickets[ph], 1u);
         __syncthreads();
-        const unsigned t = ticket;
+        const unsigned t = (unsigned)__builtin_amdgcn_readfirstlane((int)ticket);
         __syncthreads();
         if (t >= total) break;
-        int lo = 0, hi = nk - 1;  // the (set, stage) whose range holds ticket t
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (pre[mid] <= t) lo = mid;
-            else hi = mid - 1;
-        }
-        run_part(ph, lo % kParts, sets[lo / kParts], t - pre[lo], pre[lo + 1] - pre[lo]);
+        run_ticket(ph, sets, nk, pre, t);
         __syncthreads();
     }
 }
 
-// The persistent batch kernel: every phase, separated by grid barriers.
+// The persistent batch kernel: every phase, separated by grid barriers.  Its
+// register budget is the largest phase's (the tracer's, three group sizes
+// and two record forms in one function): about 240 registers, two waves per
+// SIMD; capping it at three or four waves spills hundreds of bytes per lane.
 __global__ void __launch_bounds__(kBatchThreads) k_batch(const SetDesc *__restrict__ sets, int nsets,
                                                          unsigned *__restrict__ tickets) {
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
@@ -183,6 +226,15 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(const SetDesc *__restri
 template <int kPh>
 __global__ void __launch_bounds__(kBatchThreads) k_batch_phase(const SetDesc *__restrict__ sets, int nsets,
                                                                unsigned *__restrict__ tickets) {
+    __shared__ unsigned pre[kMaxBatch * kParts + 1];
+    __shared__ unsigned ticket;
+    batch_phase(kPh, sets, nsets, tickets, pre, ticket);
+}
+
+// The staged shade phases, at the tracer kernel's four waves per SIMD.
+template <int kPh>
+__global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_batch_shade_phase(const SetDesc *__restrict__ sets, int nsets, unsigned *__restrict__ tickets) {
     __shared__ unsigned pre[kMaxBatch * kParts + 1];
     __shared__ unsigned ticket;
     batch_phase(kPh, sets, nsets, tickets, pre, ticket);
@@ -208,7 +260,9 @@ const void *phase_kernel(int ph) {
     case P_SCATTER: return (const void *)k_batch_phase<P_SCATTER>;
     case P_SCATTER_LONG: return (const void *)k_batch_phase<P_SCATTER_LONG>;
     case P_MARCH: return (const void *)k_batch_phase<P_MARCH>;
-    default: return (const void *)k_batch_phase<P_SHADE>;
+    case P_SHADE8: return (const void *)k_batch_shade_phase<P_SHADE8>;
+    case P_SHADE16: return (const void *)k_batch_shade_phase<P_SHADE16>;
+    default: return (const void *)k_batch_shade_phase<P_SHADE32>;
     }
 }
 

@@ -410,6 +410,7 @@ struct ScatterBinArgs {
 // LDS copies of the brick's cursors, so a brick's ids land in its own
 // contiguous range of the list array; the cursors are stored back for the
 // long segments that follow.
+template <int kMode>
 __device__ __forceinline__ void b_scatter_brick(ScatterBinArgs a, const DevStatus *__restrict__ st, unsigned bid_,
                                                 unsigned nblk_) {
     __shared__ uint32_t cur[kBrickVox];
@@ -431,7 +432,7 @@ __device__ __forceinline__ void b_scatter_brick(ScatterBinArgs a, const DevStatu
             const uint32_t id = a.bins[r.x + k];
             const VRec A = s.vrec[id], B = s.vrec[id + 1];
             const SlabSpan sp = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), s.rq, s.G, s.mode);
-            for_each_voxel_in_brick(sp, bx, by, bz, [&](int x, int y, int z) {
+            for_each_voxel_in_brick<kMode>(sp, bx, by, bz, [&](int x, int y, int z) {
                 const int l = local_of(x, y, z);
                 if (vis[l]) {
                     const uint32_t slot = atomicAdd(&cur[l], 1u);
@@ -453,8 +454,9 @@ __device__ __forceinline__ void b_scatter_long(ScatterBinArgs a, const DevStatus
 }
 
 __global__ void __launch_bounds__(256) k_scatter(ScatterArgs a) { b_scatter(a, blockIdx.x, gridDim.x); }
+template <int kMode>
 __global__ void __launch_bounds__(256) k_scatter_brick(ScatterBinArgs a, const DevStatus *__restrict__ st) {
-    b_scatter_brick(a, st, blockIdx.x, gridDim.x);
+    b_scatter_brick<kMode>(a, st, blockIdx.x, gridDim.x);
 }
 __global__ void __launch_bounds__(256) k_scatter_long(ScatterBinArgs a, const DevStatus *__restrict__ st) {
     b_scatter_long(a, st, blockIdx.x, gridDim.x);
@@ -466,7 +468,7 @@ __global__ void __launch_bounds__(256) k_scatter_long(ScatterBinArgs a, const De
 // visible voxel's list sorted ascending, which makes the whole id array a
 // deterministic function of the frame.
 
-constexpr int kSortShort = 32;     // lists up to this length: insertion sort by their own thread
+constexpr int kSortShort = 64;     // lists up to this length: one wave, one id per lane
 constexpr int kSortLds = 4096;     // longer lists up to this padded length: the workgroup sorts in LDS
 
 // Comparator step of an ascending bitonic network over P = 2^p keys: for the
@@ -507,18 +509,23 @@ __device__ __forceinline__ void b_sort_lists(const uint64_t *__restrict__ cell, 
     for (unsigned sl = bid_; sl < nbk; sl += nblk_) {
         const int64_t b = list[sl];
         const uint64_t cd = cell[b * kBrickVox + t];
-        const uint32_t s0 = (uint32_t)cd, n = (uint32_t)(cd >> 32);
-        if (n > 1 && n <= (uint32_t)kSortShort) {
-            for (uint32_t i = 1; i < n; ++i) {
-                const uint32_t x = ids[s0 + i];
-                uint32_t j = i;
-                for (; j > 0; --j) {
-                    const uint32_t y = ids[s0 + j - 1];
-                    if (!(y > x)) break;
-                    ids[s0 + j] = y;
+        const uint32_t n = (uint32_t)(cd >> 32);
+        // the wave's 64 voxels one after another: a list of 2..64 ids is loaded one id per lane (the rest
+        // padded with the largest key) and sorted by a bitonic network across the lanes
+        unsigned long long todo = __ballot(n > 1 && n <= (uint32_t)kSortShort);
+        while (todo) {
+            const int l = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            const uint64_t c = __shfl(cd, l, 64);
+            const uint32_t s = (uint32_t)c, len = (uint32_t)(c >> 32);
+            uint32_t key = (uint32_t)lane < len ? ids[s + lane] : 0xFFFFFFFFu;
+            for (int k = 2; k <= 64; k <<= 1)
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    const uint32_t other = __shfl_xor(key, j, 64);
+                    const bool up = (lane & k) == 0, low = (lane & j) == 0;
+                    key = (low == up) ? (key < other ? key : other) : (key < other ? other : key);
                 }
-                ids[s0 + j] = x;
-            }
+            if ((uint32_t)lane < len) ids[s + lane] = key;
         }
         const unsigned long long m = __ballot(n > (uint32_t)kSortShort);
         if (lane == 0) longm[w] = m;
@@ -652,7 +659,13 @@ hipError_t launch_cull(vrt_ctx *c, const int64_t E[3], int64_t limit, hipStream_
     VRT_LAUNCH(c, "k_list_offsets", st,
                k_list_offsets<<<4096, 512, 0, st>>>(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor,
                                                     A.cell, A.lmask, A.lmask2));
-    VRT_LAUNCH(c, "k_scatter_brick", st, k_scatter_brick<<<kBrickBlocks, 256, 0, st>>>(p.sb, A.status));
+    if (c->voxelizer == VRT_VOX_THIN)
+        VRT_LAUNCH(c, "k_scatter_brick", st, k_scatter_brick<VRT_VOX_THIN><<<kBrickBlocks, 256, 0, st>>>(p.sb, A.status));
+    else if (c->voxelizer == VRT_VOX_AABB)
+        VRT_LAUNCH(c, "k_scatter_brick", st, k_scatter_brick<VRT_VOX_AABB><<<kBrickBlocks, 256, 0, st>>>(p.sb, A.status));
+    else
+        VRT_LAUNCH(c, "k_scatter_brick", st,
+                   k_scatter_brick<VRT_VOX_CAPSULE><<<kBrickBlocks, 256, 0, st>>>(p.sb, A.status));
     VRT_LAUNCH(c, "k_scatter_long", st, k_scatter_long<<<256, 256, 0, st>>>(p.sb, A.status));
     return hipGetLastError();
 }

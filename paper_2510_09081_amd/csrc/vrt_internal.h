@@ -27,13 +27,15 @@ struct __align__(16) VRec {
 constexpr int kSegValid = 1, kInterior = 2;
 
 // FP16-form segment record (32 B): endpoints as binary16 offsets (voxel units)
-// from the centre of brick (bx, by, bz), binary16 clip normals, flags bit 0:
+// from the centre of brick (bx, by, bz), clip normals as 16-bit signed
+// fixed point (n * 32767: a unit vector's components keep an absolute error
+// below 2^-16, where binary16 would leave up to 2^-12), flags bit 0:
 // interior A (clip with n0), bit 1: interior B (clip with n1), bit 2: an
 // offset is 8 voxels or more, where binary16 no longer holds every multiple
 // of 1/256 voxel -- the tracer then reads the segment's plain vertex records.
 struct __align__(16) SRec16 {
     __half a[3], b[3];
-    __half n0[3], n1[3];
+    short n0[3], n1[3];
     short bx, by, bz;
     unsigned short flags;
 };
@@ -458,12 +460,15 @@ __device__ __forceinline__ int for_each_thin_voxel(const SlabSpan &s, int lo0, i
 }
 
 // The voxels of the set inside the box [lo0, hi0] x [lo1, hi1] x [lo2, hi2]
-// given on the span's axes (a0, a1, a2); each exactly once.
-template <class F>
+// given on the span's axes (a0, a1, a2); each exactly once.  kMode: the
+// membership mode when known at compile time (the per-brick kernels are
+// instantiated per mode), -1 to read it from the span.
+template <int kMode = -1, class F>
 __device__ __forceinline__ int for_each_voxel_clip(const SlabSpan &s, int lo0, int hi0, int lo1, int hi1, int lo2,
                                                    int hi2, F &&f) {
+    const int mode = kMode >= 0 ? kMode : s.mode;
     if (s.empty) return 0;
-    if (s.mode == VRT_VOX_THIN) {
+    if (mode == VRT_VOX_THIN) {
         const int b0 = s.vlo0 > lo0 ? s.vlo0 : lo0, b1 = s.vlo1 > lo1 ? s.vlo1 : lo1, b2 = s.vlo2 > lo2 ? s.vlo2 : lo2;
         const int u0 = s.vhi0 < hi0 ? s.vhi0 : hi0, u1 = s.vhi1 < hi1 ? s.vhi1 : hi1, u2 = s.vhi2 < hi2 ? s.vhi2 : hi2;
         return for_each_thin_voxel(s, b0, u0, b1, u1, b2, u2, f);
@@ -472,7 +477,7 @@ __device__ __forceinline__ int for_each_voxel_clip(const SlabSpan &s, int lo0, i
     const int x0 = s.vlo0 > lo0 ? s.vlo0 : lo0, x1 = s.vhi0 < hi0 ? s.vhi0 : hi0;
     for (int x = x0; x <= x1; ++x) {
         int l1 = s.vlo1, h1 = s.vhi1, l2 = s.vlo2, h2 = s.vhi2;  // the capsule AABB voxelizer: the whole box
-        if (s.mode == VRT_VOX_CAPSULE) {
+        if (mode == VRT_VOX_CAPSULE) {
             slab_range(s, x, s.A1, s.d1, s.W1, s.vlo1, s.vhi1, l1, h1);
             slab_range(s, x, s.A2, s.d2, s.W2, s.vlo2, s.vhi2, l2, h2);
         }
@@ -493,17 +498,17 @@ __device__ __forceinline__ int for_each_voxel_clip(const SlabSpan &s, int lo0, i
     return n;
 }
 
-template <class F>
+template <int kMode = -1, class F>
 __device__ __forceinline__ int for_each_voxel(const SlabSpan &s, F &&f) {
-    return for_each_voxel_clip(s, s.vlo0, s.vhi0, s.vlo1, s.vhi1, s.vlo2, s.vhi2, f);
+    return for_each_voxel_clip<kMode>(s, s.vlo0, s.vhi0, s.vlo1, s.vhi1, s.vlo2, s.vhi2, f);
 }
 
 // The voxels of the set inside brick (bx, by, bz).
-template <class F>
+template <int kMode = -1, class F>
 __device__ __forceinline__ int for_each_voxel_in_brick(const SlabSpan &s, int bx, int by, int bz, F &&f) {
     const int l0 = 8 * (int)sel3(bx, by, bz, s.a0), l1 = 8 * (int)sel3(bx, by, bz, s.a1);
     const int l2 = 8 * (int)sel3(bx, by, bz, s.a2);
-    return for_each_voxel_clip(s, l0, l0 + 7, l1, l1 + 7, l2, l2 + 7, f);
+    return for_each_voxel_clip<kMode>(s, l0, l0 + 7, l1, l1 + 7, l2, l2 + 7, f);
 }
 
 // Voxel box of the set on the original axes.

@@ -48,6 +48,81 @@ __device__ __forceinline__ float occ_cell(const ShadeArgs &a, int L, int x, int 
     return (float)o * (1.0f / 256.0f);
 }
 
+// Transmittance toward the light from the centre of voxel p: the product of
+// 1 - occupancy over the voxels the ray enters until it leaves the grid.  The
+// walk is exact in 32-bit integers: the next crossing on axis k is the
+// fraction n_k / d_k of the ray's unit step (d_k = |L_k|, n_k grows by one
+// voxel per plane; every value stays below 2^27 on grids up to 1024^3), the
+// smallest is taken, tied axes step together.  An unoccupied brick holds no
+// occupancy, so the walk jumps to its exit: the axis whose far face comes
+// first, and on every axis the planes crossed at or before that parameter.
+// The walk stops once the transmittance is below kShadowEps, which moves the
+// result by less than kShadowEps.
+constexpr float kShadowEps = 1.0f / 65536.0f;
+
+__device__ __forceinline__ float shadow_walk(const ShadeArgs &a, int p0, int p1, int p2) {
+    int u[3] = {p0, p1, p2};
+    int n[3] = {kQ / 2, kQ / 2, kQ / 2};
+    int d[3], s[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        d[k] = a.L[k] < 0 ? -a.L[k] : a.L[k];
+        s[k] = a.L[k] > 0 ? 1 : -1;
+    }
+    float T = 1.0f;
+    for (int guard = 0; guard < 4 * (a.g.G[0] + a.g.G[1] + a.g.G[2]); ++guard) {
+        // one crossing: the smallest n/d over the stepping axes, ties together
+        int bn = 0, bd = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (d[k] && (!bd || n[k] * bd < bn * d[k])) bn = n[k], bd = d[k];
+        if (!bd) break;
+        bool out = false;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (d[k] && n[k] * bd == bn * d[k]) {
+                u[k] += s[k];
+                n[k] += kQ;
+                out |= u[k] < 0 || u[k] >= a.g.G[k];
+            }
+        if (out) break;
+        const int64_t b = ((int64_t)(u[2] >> 3) * a.g.nb[1] + (u[1] >> 3)) * a.g.nb[0] + (u[0] >> 3);
+        if (a.slot[b] >= 0) {
+            const int local = ((u[2] & 7) << 6) | ((u[1] & 7) << 3) | (u[0] & 7);
+            T = T * (1.0f - (float)a.occ0[b * kBrickVox + local] * (1.0f / 256.0f));
+            if (T < kShadowEps) break;
+            continue;
+        }
+        // an unoccupied brick: its exit parameter N/D is the first far-face crossing
+        int N = 0, D = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (!d[k]) continue;
+            const int lo = u[k] & ~7;
+            const int cross = s[k] > 0 ? lo + 8 - u[k] : u[k] - lo + 1;  // planes to the far face, that one included
+            const int e = n[k] + (cross - 1) * kQ;
+            if (!D || e * D < N * d[k]) N = e, D = d[k];
+        }
+        // every plane crossed at or before N/D is passed: the walk resumes in the voxel after the exit
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (!d[k] || n[k] * D > N * d[k]) continue;
+            const int c = (N * d[k] - n[k] * D) / (kQ * D) + 1;
+            u[k] += s[k] * c;
+            n[k] += c * kQ;
+            out |= u[k] < 0 || u[k] >= a.g.G[k];
+        }
+        if (out) break;
+        const int64_t b2 = ((int64_t)(u[2] >> 3) * a.g.nb[1] + (u[1] >> 3)) * a.g.nb[0] + (u[0] >> 3);
+        if (a.slot[b2] >= 0) {
+            const int local = ((u[2] & 7) << 6) | ((u[1] & 7) << 3) | (u[0] & 7);
+            T = T * (1.0f - (float)a.occ0[b2 * kBrickVox + local] * (1.0f / 256.0f));
+            if (T < kShadowEps) break;
+        }
+    }
+    return T;
+}
+
 // One workgroup (512 threads, one voxel each) per occupied brick.
 __global__ void __launch_bounds__(512) k_shade(ShadeArgs a) {
     const unsigned nbk = a.st->n_bricks;
@@ -59,55 +134,24 @@ __global__ void __launch_bounds__(512) k_shade(ShadeArgs a) {
         const int bx = (int)(b % a.g.nb[0]), by = (int)((b / a.g.nb[0]) % a.g.nb[1]);
         const int bz = (int)(b / ((int64_t)a.g.nb[0] * a.g.nb[1]));
         const int p0 = 8 * bx + (t & 7), p1 = 8 * by + ((t >> 3) & 7), p2 = 8 * bz + (t >> 6);
-        const long long C0 = (long long)p0 * kQ + kQ / 2, C1 = (long long)p1 * kQ + kQ / 2,
-                        C2 = (long long)p2 * kQ + kQ / 2;
+        // voxel centre in 1/256 units (below 2^18 on grids up to 1024^3: 32-bit arithmetic is exact)
+        const int C0 = p0 * kQ + kQ / 2, C1 = p1 * kQ + kQ / 2, C2 = p2 * kQ + kQ / 2;
         // ambient occlusion: sample j of cone k at 2^j voxels, in the level-j cell holding it
         float sum = 0.0f;
         for (int k = 0; k < a.K; ++k) {
             float acc = 0.0f;
             for (int j = 1; j <= a.J; ++j) {
-                const long long step = 1ll << j;  // 2^j voxels; the arithmetic shift below is a floor division
-                const int x = (int)((C0 + (long long)a.U[3 * k] * step) >> (8 + j));
-                const int y = (int)((C1 + (long long)a.U[3 * k + 1] * step) >> (8 + j));
-                const int z = (int)((C2 + (long long)a.U[3 * k + 2] * step) >> (8 + j));
+                const int step = 1 << j;  // 2^j voxels; the arithmetic shift below is a floor division
+                const int x = (C0 + a.U[3 * k] * step) >> (8 + j);
+                const int y = (C1 + a.U[3 * k + 1] * step) >> (8 + j);
+                const int z = (C2 + a.U[3 * k + 2] * step) >> (8 + j);
                 acc = acc + (1.0f - acc) * occ_cell(a, j, x, y, z);
             }
             sum = sum + (1.0f - acc);
         }
         const float ao = sum / (float)a.K;
         // shadow: integer walk from the voxel centre along L to the grid edge (tied axes step together)
-        float T = 1.0f;
-        int u0 = p0, u1 = p1, u2 = p2;
-        const long long d0 = a.L[0] < 0 ? -a.L[0] : a.L[0], d1 = a.L[1] < 0 ? -a.L[1] : a.L[1],
-                        d2 = a.L[2] < 0 ? -a.L[2] : a.L[2];
-        const int s0 = a.L[0] > 0 ? 1 : -1, s1 = a.L[1] > 0 ? 1 : -1, s2 = a.L[2] > 0 ? 1 : -1;
-        long long n0 = kQ / 2, n1 = kQ / 2, n2 = kQ / 2;  // distance to the next plane on each axis
-        for (;;) {
-            // smallest crossing n/d over the stepping axes
-            long long bn = 0, bd = 0;
-            if (d0) bn = n0, bd = d0;
-            if (d1 && (!bd || n1 * bd < bn * d1)) bn = n1, bd = d1;
-            if (d2 && (!bd || n2 * bd < bn * d2)) bn = n2, bd = d2;
-            if (!bd) break;
-            bool out = false;
-            if (d0 && n0 * bd == bn * d0) {
-                u0 += s0;
-                n0 += kQ;
-                out |= u0 < 0 || u0 >= a.g.G[0];
-            }
-            if (d1 && n1 * bd == bn * d1) {
-                u1 += s1;
-                n1 += kQ;
-                out |= u1 < 0 || u1 >= a.g.G[1];
-            }
-            if (d2 && n2 * bd == bn * d2) {
-                u2 += s2;
-                n2 += kQ;
-                out |= u2 < 0 || u2 >= a.g.G[2];
-            }
-            if (out) break;
-            T = T * (1.0f - occ_cell(a, 0, u0, u1, u2));
-        }
+        const float T = shadow_walk(a, p0, p1, p2);
         a.lit[vi] = ao * (a.ambient + (1.0f - a.ambient) * T);
     }
 }

@@ -158,8 +158,9 @@ __device__ __forceinline__ LocalSeg local_seg(const SRec16 &r, int cx, int cy, i
                 oz = (float)(8 * (int)r.bz + 4 - cz);
     s.pa = make_float3(ox + __half2float(r.a[0]), oy + __half2float(r.a[1]), oz + __half2float(r.a[2]));
     s.pb = make_float3(ox + __half2float(r.b[0]), oy + __half2float(r.b[1]), oz + __half2float(r.b[2]));
-    s.n0 = make_float3(__half2float(r.n0[0]), __half2float(r.n0[1]), __half2float(r.n0[2]));
-    s.n1 = make_float3(__half2float(r.n1[0]), __half2float(r.n1[1]), __half2float(r.n1[2]));
+    constexpr float kSn = 1.0f / 32767.0f;
+    s.n0 = make_float3((float)r.n0[0] * kSn, (float)r.n0[1] * kSn, (float)r.n0[2] * kSn);
+    s.n1 = make_float3((float)r.n1[0] * kSn, (float)r.n1[1] * kSn, (float)r.n1[2] * kSn);
     s.ia = (r.flags & 1u) != 0;
     s.ib = (r.flags & 2u) != 0;
     return s;
@@ -756,13 +757,17 @@ __global__ void __launch_bounds__(512) k_trace_march(TraceArgs a) { b_trace_marc
 // Phase 2, one kGroup-lane group per queued ray: lists, capsule tests and
 // compositing, continuing the walk until the ray is finished.  All lanes of a
 // group follow the same walk; list entries are split across them.
+// Work unit bid_ of nblk_, each of unit_threads threads (this thread is
+// unit_tid of its unit): the whole workgroup, or one wave of it when the
+// waves of a workgroup take work on their own.
 template <bool kStats, int kForm, class Cfg = DefaultShade>
-__device__ __forceinline__ void b_trace_shade(TraceArgs a, unsigned bid_, unsigned nblk_) {
+__device__ __forceinline__ void b_trace_shade(TraceArgs a, unsigned bid_, unsigned nblk_, unsigned unit_threads,
+                                              unsigned unit_tid) {
     constexpr int kGroup = Cfg::kGroup;
     const int lane = threadIdx.x & 63;
     const unsigned n = a.st->n_queue;
-    const unsigned ngroups = nblk_ * (blockDim.x / kGroup);
-    const unsigned grp = bid_ * (blockDim.x / kGroup) + threadIdx.x / kGroup;
+    const unsigned ngroups = nblk_ * (unit_threads / kGroup);
+    const unsigned grp = bid_ * (unit_threads / kGroup) + unit_tid / kGroup;
     __shared__ uint64_t s_mask[8 * kMaxShadeGroups];  // the list mask of each group's brick
     MaskLds mk{s_mask + threadIdx.x / kGroup, (int)(blockDim.x / kGroup)};
     // every group runs the same number of rounds so counters can be reduced per wave
@@ -817,7 +822,7 @@ __device__ __forceinline__ void b_debug_rays(TraceParams p, const int64_t *__res
 // memory latency, and the fourth wave hides more of it than the few spilled
 // registers cost.
 template <bool kStats, int kForm, class Cfg>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm, Cfg>(a, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm, Cfg>(a, blockIdx.x, gridDim.x, blockDim.x, threadIdx.x); }
 
 __global__ void k_debug_rays(TraceParams p, const int64_t *__restrict__ pix, int64_t n, float *__restrict__ dirs) { b_debug_rays(p, pix, n, dirs, blockIdx.x, gridDim.x); }
 

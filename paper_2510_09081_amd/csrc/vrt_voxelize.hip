@@ -200,7 +200,7 @@ __device__ __forceinline__ int occupancy_quantum(const VRec &A, const VRec &B, f
 
 // FP16 form: one record per segment with its endpoints relative to the centre
 // of the brick holding its midpoint (binary16, voxel units) and its clip
-// normals in binary16.  Quantized positions are multiples of 1/256 voxel, so
+// normals in 16-bit signed fixed point.  Quantized positions are multiples of 1/256 voxel, so
 // offsets below 8 voxels are exact; a segment with a longer offset (one that
 // reaches beyond the neighbouring bricks) is marked to be read from its plain
 // vertex records instead.
@@ -220,12 +220,12 @@ __device__ __forceinline__ void b_pack16(const VRec *__restrict__ vrec, int64_t 
     r.b[0] = __float2half((float)(B.x - cx) * (1.0f / kQ));
     r.b[1] = __float2half((float)(B.y - cy) * (1.0f / kQ));
     r.b[2] = __float2half((float)(B.z - cz) * (1.0f / kQ));
-    r.n0[0] = __float2half(A.nx);
-    r.n0[1] = __float2half(A.ny);
-    r.n0[2] = __float2half(A.nz);
-    r.n1[0] = __float2half(B.nx);
-    r.n1[1] = __float2half(B.ny);
-    r.n1[2] = __float2half(B.nz);
+    r.n0[0] = (short)rintf(A.nx * 32767.0f);
+    r.n0[1] = (short)rintf(A.ny * 32767.0f);
+    r.n0[2] = (short)rintf(A.nz * 32767.0f);
+    r.n1[0] = (short)rintf(B.nx * 32767.0f);
+    r.n1[1] = (short)rintf(B.ny * 32767.0f);
+    r.n1[2] = (short)rintf(B.nz * 32767.0f);
     r.bx = (short)bx;
     r.by = (short)by;
     r.bz = (short)bz;
@@ -457,6 +457,7 @@ struct AccumArgs {
 // chunk) or adds them to the words (every word is zero at the start of a
 // frame: the previous frame's occupied bricks are cleared), and flags the
 // brick when it holds a fragment.
+template <int kMode>
 __device__ __forceinline__ void b_brick_accum(AccumArgs a, DevStatus *__restrict__ st, unsigned bid_, unsigned nblk_) {
     __shared__ uint32_t w[kBrickVox];
     const CountArgs &c = a.ca;
@@ -477,7 +478,7 @@ __device__ __forceinline__ void b_brick_accum(AccumArgs a, DevStatus *__restrict
             const uint32_t id = a.bins[r.x + k0 + kk];
             const VRec A = c.vrec[id], B = c.vrec[id + 1];
             const SlabSpan s = make_span(make_int3(A.x, A.y, A.z), make_int3(B.x, B.y, B.z), c.rq, c.G, c.mode);
-            nfrag += for_each_voxel_in_brick(s, bx, by, bz, [&](int x, int y, int z) {
+            nfrag += for_each_voxel_in_brick<kMode>(s, bx, by, bz, [&](int x, int y, int z) {
                 const int q = occupancy_quantum(A, B, c.rc, c.corr, x, y, z);
                 atomicAdd(&w[local_of(x, y, z)], 1u + ((uint32_t)q << 16));
             });
@@ -513,7 +514,8 @@ __global__ void __launch_bounds__(256) k_bin_count(BinArgs a, DevStatus *__restr
 __global__ void __launch_bounds__(256) k_bin_alloc(BinArgs a, DevStatus *__restrict__ st) { b_bin_alloc(a, st, blockIdx.x, gridDim.x); }
 __global__ void __launch_bounds__(256) k_bin_fill(BinArgs a, DevStatus *__restrict__ st) { b_bin_fill(a, st, blockIdx.x, gridDim.x); }
 // six waves per SIMD (at most 80 registers, a few spilled): more bins in flight
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_brick_accum(AccumArgs a, DevStatus *__restrict__ st) { b_brick_accum(a, st, blockIdx.x, gridDim.x); }
+template <int kMode>
+__global__ void __launch_bounds__(256) k_brick_accum(AccumArgs a, DevStatus *__restrict__ st) { b_brick_accum<kMode>(a, st, blockIdx.x, gridDim.x); }
 __global__ void __launch_bounds__(256) k_vox_long(CountArgs a, const uint32_t *__restrict__ long_ids, DevStatus *__restrict__ st) { b_vox_long(a, long_ids, st, blockIdx.x, gridDim.x); }
 
 // One workgroup compacts the touched-brick flags of bricks [first, last) into
@@ -1013,7 +1015,12 @@ hipError_t launch_voxelize(vrt_ctx *c, const vrt_lines *L, float s_q, hipStream_
     VRT_LAUNCH(c, "k_bin_count", st, k_bin_count<<<eb, 256, 0, st>>>(p.ba, A.status));
     VRT_LAUNCH(c, "k_bin_alloc", st, k_bin_alloc<<<64, 256, 0, st>>>(p.ba, A.status));
     VRT_LAUNCH(c, "k_bin_fill", st, k_bin_fill<<<eb, 256, 0, st>>>(p.ba, A.status));
-    VRT_LAUNCH(c, "k_brick_accum", st, k_brick_accum<<<kBrickBlocks, 256, 0, st>>>(p.aa, A.status));
+    if (c->voxelizer == VRT_VOX_THIN)
+        VRT_LAUNCH(c, "k_brick_accum", st, k_brick_accum<VRT_VOX_THIN><<<kBrickBlocks, 256, 0, st>>>(p.aa, A.status));
+    else if (c->voxelizer == VRT_VOX_AABB)
+        VRT_LAUNCH(c, "k_brick_accum", st, k_brick_accum<VRT_VOX_AABB><<<kBrickBlocks, 256, 0, st>>>(p.aa, A.status));
+    else
+        VRT_LAUNCH(c, "k_brick_accum", st, k_brick_accum<VRT_VOX_CAPSULE><<<kBrickBlocks, 256, 0, st>>>(p.aa, A.status));
     VRT_LAUNCH(c, "k_vox_long", st, k_vox_long<<<256, 256, 0, st>>>(p.ca, A.long_ids, A.status));
     const unsigned nchunks = (unsigned)((p.nb + kCompactChunk - 1) / kCompactChunk);
     VRT_LAUNCH(c, "k_compact_count", st,

@@ -2,8 +2,9 @@
 
 Voxel membership, lists and culling are unchanged (int32); the tracer reads
 binary16 endpoints (exact here: offsets below 8 voxels on the 1/256 grid) and
-binary16 clip normals (relative error 2^-11), so results differ from the plain
-form only where a hit point lies within ~1e-3 voxel of a clip plane.  The
+16-bit fixed-point clip normals (absolute error below 2^-16), so results differ
+from the plain form only where a hit point lies within ~1e-5 voxel of a clip
+plane.  The
 error against the binary64 oracle is reported and bounded.
 """
 import numpy as np
