@@ -126,11 +126,13 @@ def frame_bytes(n, form="plain"):
 def memory_ceilings(torch, vrt):
     """Measured streaming-copy bandwidth and device-atomic rates (random words, and 64 atomics per wave step
     inside one 2 KiB brick region) over a 512 MiB array."""
-    buf = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
     out = {}
-    vrt.microbench(vrt.MB_COPY, buf)  # warm-up
-    ms = min(vrt.microbench(vrt.MB_COPY, buf) for _ in range(3))
-    out["copy"] = {"bytes": buf.numel(), "ms": round(ms, 4), "GB_s": round(buf.numel() / (ms * 1e-3) / 1e9, 1)}
+    big = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")  # 1 GiB read + 1 GiB written per copy
+    vrt.microbench(vrt.MB_COPY, big)  # warm-up
+    ms = min(vrt.microbench(vrt.MB_COPY, big) for _ in range(5))
+    out["copy"] = {"bytes": big.numel(), "ms": round(ms, 4), "GB_s": round(big.numel() / (ms * 1e-3) / 1e9, 1)}
+    del big
+    buf = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
     ops = 1 << 28
     for label, kind in (("atomic_random", vrt.MB_ATOMIC_RANDOM), ("atomic_brick_local", vrt.MB_ATOMIC_BRICK)):
         vrt.microbench(kind, buf, 1 << 24)
