@@ -11,6 +11,8 @@
   largest set against the oracle.
 - Duplicated polylines: hits of identical capsules tie exactly and the lower
   segment id wins (Section 3.5, correct hit ordering; ties by id).
+- The same frame's voxel-space shading (Section 3.4) and the two comparison
+  voxelizers' structures (Section 4.1) against the oracle.
 """
 import numpy as np
 import pytest
@@ -82,6 +84,15 @@ def test_bundles_5m_full_frame(orc, bundles_5m):
         dev = G.to_device(ls)
         unc = _structure_and_trace(orc, ctx, ls, cam, fo, vrt.CULL_OPAQUE, 0, 1.0, "bundles_5m opaque", dev)
         print(f"opaque pass: {fo.total} listed, {unc:.2e} of pixels uncertified", flush=True)
+        # voxel-space shading of the opaque view's visible voxels (Sec. 3.4) against the oracle's binary64
+        ao, sh, lit = orc.shade(fo.occ, fo.vis)
+        ctx.shade()
+        got = G.fetch_as(ctx)["lit"]
+        v = fo.vis > 0
+        err = np.abs(got[v].astype(np.float64) - lit[v])
+        print(f"shading: {int(v.sum())} visible voxels, max error {err.max():.2e}", flush=True)
+        assert err.max() <= 1e-4
+        del ao, sh, lit, got
         fa = orc.recull_frame(fo, ls, cam.eye, orc.CULL_ALPHA, 0.2)
         del fo
         unc = _structure_and_trace(orc, ctx, ls, cam, fa, vrt.CULL_ALPHA, 1, 0.2, "bundles_5m alpha", dev)
@@ -196,5 +207,27 @@ def test_duplicate_segments_tie_to_lower_id(orc):
             assert hit.sum() > 500
             assert ((tr.id[hit] % (3 * nvp)) < nvp).all()
             compare_trace(tr, gid, gdepth, grgba, ls, mode, f"duplicates mode {mode}")
+    finally:
+        ctx.close()
+
+
+def test_bundles_5m_comparison_voxelizers(orc, bundles_5m):
+    """The thin-line and capsule-AABB voxelizers on the 5.5M-segment set at 512^3: packed words, every level
+    and the lists of the opaque-culled view bit-exact against the oracle's definitions."""
+    _need_gpu()
+    w = bundles_5m
+    ls, cam = w.lines, w.camera
+    ctx = vrt.Context(max_vertices=ls.n_vertices, max_fragments=8 * ls.n_segments, max_dim=max(ls.dims))
+    try:
+        xyz, off = G.to_device(ls)
+        for mode in (vrt.VOX_THIN, vrt.VOX_AABB):
+            fr = orc.build_frame(ls, cam.eye, orc.CULL_OPAQUE, mode=mode)
+            ctx.voxelize(xyz, off, ls.radius, ls.origin, ls.voxel_size, ls.dims, voxelizer=mode)
+            ctx.cull(np.asarray(cam.eye, np.float32), vrt.CULL_OPAQUE)
+            st = ctx.frame_status()
+            assert st["device_status"] == 0
+            assert st["n_fragments"] == fr.n_fragments and st["n_listed"] == fr.total, mode
+            compare_structure_large(fr, G.fetch_as(ctx), G.fetch_ids(ctx, fr.total))
+            print(f"voxelizer {mode}: {fr.n_fragments} fragments, {fr.total} listed", flush=True)
     finally:
         ctx.close()
