@@ -290,7 +290,7 @@ vrt_status vrt_graph_destroy(vrt_graph *g);
 #define VRT_NOALLOC_MAX_FRAGMENTS (1 << 20)
 #define VRT_NOALLOC_MAX_DIM 64
 #define VRT_NOALLOC_MAX_PIXELS (512 * 512)
-#define VRT_NOALLOC_SCRATCH_BYTES (24 << 20)
+#define VRT_NOALLOC_SCRATCH_BYTES (32 << 20)
 vrt_status vrt_frame_noalloc(const vrt_lines *lines, const vrt_grid *grid, const vrt_view *view,
                              const vrt_camera *cam, const vrt_image *img, vrt_frame_info *info, void *stream);
 

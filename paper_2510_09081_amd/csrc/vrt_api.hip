@@ -30,7 +30,7 @@ hipError_t alloc(T *&p, int64_t n) {
 void free_all(Arenas &a) {
     void *ptrs[] = {a.vrec, a.words, a.occ0, a.occ1, a.occ2, a.occ3, a.occ_hi, a.blk, a.blk_bits, a.brick_bits, a.super_blk,
                     a.occ_list, a.vis0,
-                    a.vis1, a.vis2,  a.vis3, a.vis_hi, a.cursor, a.cell, a.lmask, a.lmask2, a.queue, a.srec16, a.ids, a.brick_flag, a.bin_count, a.bin_range, a.cand, a.bins, a.long_ids, a.items, a.chunk_cnt, a.brick_list, a.brick_slot,
+                    a.vis1, a.vis2,  a.vis3, a.bskip, a.vis_hi, a.cursor, a.cell, a.lmask, a.lmask2, a.queue, a.walk, a.srec16, a.ids, a.brick_flag, a.bin_count, a.bin_range, a.cand, a.bins, a.long_ids, a.items, a.chunk_cnt, a.brick_list, a.brick_slot,
                     a.brick_total, a.brick_base, a.status, a.lit, a.stat_vox, a.stat_seg, a.stat_acc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -73,13 +73,14 @@ void ctx_sizes(vrt_ctx *c, const vrt_desc &d) {
     const int64_t nsd = (d.max_dim + 63) / 64;
     c->max_supers = nsd * nsd * nsd;
     c->hi_elems = hi_elems_for(d.max_dim);
+    c->walk_entries = d.max_pixels * kWalkPerPixel;
 }
 
 // Every arena of a context with its element count: f(pointer, count) is called
 // once per array, in one fixed order (allocation by vrt_create, placement in a
 // fixed buffer by the no-allocation frame).
 template <class F>
-void arena_fields(Arenas &a, const vrt_desc &d, int64_t mb, int64_t hi_elems, F &&f) {
+void arena_fields(Arenas &a, const vrt_desc &d, int64_t mb, int64_t hi_elems, int64_t walk_entries, F &&f) {
     f(a.vrec, d.max_vertices);
     f(a.words, mb * kBrickVox);
     f(a.occ0, mb * kBrickVox);
@@ -101,12 +102,14 @@ void arena_fields(Arenas &a, const vrt_desc &d, int64_t mb, int64_t hi_elems, F 
     f(a.vis1, mb * 64);
     f(a.vis2, mb * 8);
     f(a.vis3, mb);
+    f(a.bskip, mb);
     f(a.vis_hi, hi_elems);
     f(a.cursor, mb * kBrickVox);
     f(a.cell, mb * kBrickVox);
     f(a.lmask, mb * 8);
     f(a.lmask2, mb);
     f(a.queue, d.max_pixels);
+    f(a.walk, walk_entries);
     if (d.form == VRT_FORM_FP16) f(a.srec16, d.max_vertices);
     f(a.ids, d.max_fragments);
     f(a.brick_flag, mb);
@@ -165,7 +168,7 @@ vrt_status vrt_create(const vrt_desc *desc, vrt_ctx **out) {
     Arenas &a = c->a;
     const int64_t mb = c->max_bricks;
     hipError_t e = hipSuccess;
-    arena_fields(a, *desc, mb, c->hi_elems, [&](auto *&p, int64_t n) {
+    arena_fields(a, *desc, mb, c->hi_elems, c->walk_entries, [&](auto *&p, int64_t n) {
         if (e == hipSuccess) e = alloc(p, n);
     });
     if (e == hipSuccess) e = hipMemset(a.words, 0, (size_t)mb * kBrickVox * sizeof(uint32_t));
@@ -679,9 +682,10 @@ vrt_status noalloc_slot(NoAllocSlot **out) {
                       VRT_NOALLOC_MAX_PIXELS, VRT_FORM_PLAIN, 0};
         vrt_ctx &c = s.ctx;
         ctx_sizes(&c, d);
+        c.walk_entries = (int64_t)VRT_NOALLOC_MAX_PIXELS * 4;  // half the usual walk budget: rays past it march on
         unsigned char *base = static_cast<unsigned char *>(p);
         size_t off = 0;
-        arena_fields(c.a, d, c.max_bricks, c.hi_elems, [&](auto *&q, int64_t n) {
+        arena_fields(c.a, d, c.max_bricks, c.hi_elems, c.walk_entries, [&](auto *&q, int64_t n) {
             using T = std::remove_reference_t<decltype(*q)>;
             off = (off + 255) & ~(size_t)255;
             q = reinterpret_cast<T *>(base + off);

@@ -72,6 +72,11 @@ struct DevStatus {
 // A segment is binned into every brick of its voxel box when that box has at
 // most this many bricks; longer segments take the per-segment path.
 constexpr int kMaxBinBricks = 8;
+// Walk entries per pixel of max_pixels: the trace's walk phase gives every
+// queued ray walk_entries / n_queue entries (at most kWalkMax), so rays are
+// walked in full unless most pixels reach a list.
+constexpr int kWalkPerPixel = 8;
+constexpr int kWalkMax = 4096;
 // Bins are processed in chunks of at most this many segments (one workgroup
 // each), so that crowded bricks are spread over several workgroups.
 constexpr int kBinChunk = 1024;
@@ -107,12 +112,14 @@ struct Arenas {
     uint8_t *vis1 = nullptr;        // [max_bricks * 64]
     uint8_t *vis2 = nullptr;        // [max_bricks * 8]
     uint8_t *vis3 = nullptr;        // [max_bricks]
+    uint8_t *bskip = nullptr;       // [max_bricks] 0: visible brick, else the shift of the largest invisible cell holding it
     uint8_t *vis_hi = nullptr;      // levels >= 4
     uint32_t *cursor = nullptr;     // [max_bricks * 512] list start, then end after pass 2
     uint64_t *cell = nullptr;       // [max_bricks * 512] list start (low 32) | visible count (high 32)
     uint64_t *lmask = nullptr;      // [max_bricks * 8] voxels with a non-empty list, one bit each (64 per word)
     uint64_t *lmask2 = nullptr;     // [max_bricks] 2^3 cells holding such a voxel, bit 16 Z + 4 Y + X
     uint4 *queue = nullptr;         // [max_pixels] rays that reached a list
+    uint2 *walk = nullptr;          // [walk_entries] list voxels of the queued rays, in walk order (voxel, entry t)
     SRec16 *srec16 = nullptr;       // [max_vertices] FP16-form segment records (FP16 form only)
     uint32_t *ids = nullptr;        // [max_fragments]
     uint8_t *brick_flag = nullptr;  // [max_bricks]
@@ -198,6 +205,7 @@ struct vrt_ctx {
     int64_t max_bricks;
     int64_t max_supers;
     int64_t hi_elems;  // capacity of occ_hi / vis_hi
+    int64_t walk_entries;  // capacity of walk, shared by the queued rays of a trace
     vrt::Arenas a;
     // frame state
     bool voxelized = false, culled = false, shaded = false;

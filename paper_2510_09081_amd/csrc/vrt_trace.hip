@@ -104,6 +104,7 @@ struct TraceArgs {
     int n4[3], n5[3], n6[3];  // 16^3, 32^3 and 64^3 cells per axis (culling levels 4, 5, 6)
     const uint8_t *vis4, *vis5, *vis6;  // culling levels 4..6, each null when the grid has no such level
     const uint8_t *vis3;      // culling level 3 (bricks)
+    uint8_t *bskip;           // per brick: 0 if visible, else log2 of the largest invisible cell holding it
     const uint64_t *cell;     // per voxel: list start | visible count << 32
     const uint64_t *lmask;    // per brick: voxels with a non-empty list (8 words, z-slice w in word w)
     const uint64_t *lmask2;   // per brick: 2^3 cells holding such a voxel
@@ -113,7 +114,10 @@ struct TraceArgs {
     const SRec16 *srec16;     // FP16 form only
     int64_t nv;               // vertices of the frame (ids must be < nv - 1)
     int64_t capacity;         // entries of ids
-    uint4 *queue;             // rays that reached a list: pixel, packed voxel, t
+    uint4 *queue;             // rays that reached a list: pixel, packed voxel (after the walk phase: walked
+                              // entries | more << 31), entry t, exit t of the visible box
+    uint2 *walk;              // walk_capacity(walk_entries, n_queue) entries per queued ray: packed voxel, entry t
+    int64_t walk_entries;
     float *rgba;
     float *depth;
     int *first_id;
@@ -354,6 +358,10 @@ struct MaskRegs {
         return (z & 4) ? b1 : b0;
     }
 };
+// Registers, read beside the culling flags (one round trip per brick entered).
+struct MaskRegsEarly : MaskRegs {
+    static constexpr bool kEarly = true;
+};
 struct MaskLds {
     static constexpr bool kEarly = true;  // read beside the culling flags, before they are known
     static constexpr bool kCells = true;  // crosses list-free 2^3 and 4^3 cells in one jump
@@ -373,82 +381,124 @@ struct MaskLds {
     __device__ uint64_t slice(int z) const { return p[(z & 7) * stride]; }
 };
 
-// Advances from the current voxel (included) to the first visible voxel with
-// a non-empty list, skipping invisible cells of 8^3 to 64^3 voxels; false if
-// none.  In a visible brick, list-free 4^3 and 2^3 cells are crossed in one
-// jump and single voxels without a list are passed on the brick's list mask,
-// both loaded once when the walk enters the brick.
-template <bool kStats, class Mask>
-__device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w, Counters &cn, Mask &mk) {
-    const int max_iter = 3 * (a.G[0] + a.G[1] + a.G[2]) + 16;
-    for (int it = 0; it < max_iter; ++it) {
-        if (!(w.tcur < w.tout)) return false;
-        const int64_t b = ((int64_t)(w.v[2] >> 3) * a.nb[1] + (w.v[1] >> 3)) * a.nb[0] + (w.v[0] >> 3);
-        if (b != w.bvis) {  // a new brick: its own culling flag, and its 64^3 cell's
-            // both read at once; a 64^3 cell is visible iff one of its bricks is
-            uint64_t m[8];  // the brick's list mask, read early by walkers that keep it
-            uint64_t c2 = 0;
-            if (Mask::kEarly) {
+// Exit axis and exit parameter of the current voxel from its boundary
+// parameters (the lowest axis wins a tie).
+__device__ __forceinline__ void voxel_exit(Walk &w) {
+    float tm = w.tnext[0];
+    w.m = 0;
+    if (w.tnext[1] < tm) {
+        w.m = 1;
+        tm = w.tnext[1];
+    }
+    if (w.tnext[2] < tm) {
+        w.m = 2;
+        tm = w.tnext[2];
+    }
+    w.texit = fmaxf(tm, w.tcur);
+}
+
+// Boundary parameters of voxel v's exit planes; every walk computes them with
+// this one expression, so a voxel entered by a step, after a jump or from a
+// stored walk entry has the same exit parameter.
+__device__ __forceinline__ void voxel_bounds(const Ray &r, Walk &w) {
+    for (int k = 0; k < 3; ++k)
+        w.tnext[k] = r.step[k] == 0 ? INFINITY : tcross(w.v[k] + (r.step[k] > 0), r.O[k], r.inv[k]);
+}
+
+__device__ __forceinline__ uint32_t pack_voxel(const int *v) {
+    return (uint32_t)v[0] | ((uint32_t)v[1] << 10) | ((uint32_t)v[2] << 20);
+}
+__device__ __forceinline__ void unpack_voxel(uint32_t p, int *v) {
+    v[0] = (int)(p & 1023u);
+    v[1] = (int)((p >> 10) & 1023u);
+    v[2] = (int)((p >> 20) & 1023u);
+}
+// Brick-major index of voxel v.
+__device__ __forceinline__ int64_t voxel_index(const TraceArgs &a, const int *v) {
+    const int64_t b = ((int64_t)(v[2] >> 3) * a.nb[1] + (v[1] >> 3)) * a.nb[0] + (v[0] >> 3);
+    return b * kBrickVox + local_of(v[0], v[1], v[2]);
+}
+
+// One step of the march from the current voxel (included) towards the first
+// visible voxel with a non-empty list: an invisible cell of 8^3 to 64^3
+// voxels is crossed in one jump; in a visible brick, a list-free 4^3 or 2^3
+// cell is crossed in one jump and a single voxel without a list is stepped
+// past on the brick's list mask (both loaded once when the walk enters the
+// brick).  Returns 1 when the current voxel is such a voxel, -1 when the ray
+// has left the box or the grid, 0 after a jump or step.  Every step advances
+// the walk by at least one voxel.
+template <bool kStats, class Mask, bool kLoadCd>
+__device__ __forceinline__ int march_step(const TraceArgs &a, const Ray &r, Walk &w, Counters &cn, Mask &mk) {
+    if (!(w.tcur < w.tout)) return -1;
+    const int64_t b = ((int64_t)(w.v[2] >> 3) * a.nb[1] + (w.v[1] >> 3)) * a.nb[0] + (w.v[0] >> 3);
+    if (b != w.bvis) {  // a new brick: its own culling flag, and its 64^3 cell's
+        // both read at once; a 64^3 cell is visible iff one of its bricks is
+        uint64_t m[8];  // the brick's list mask, read early by walkers that keep it
+        uint64_t c2 = 0;
+        if (Mask::kEarly) {
 #pragma unroll
-                for (int k = 0; k < 8; ++k) m[k] = a.lmask[b * 8 + k];
-                c2 = a.lmask2[b];
+            for (int k = 0; k < 8; ++k) m[k] = a.lmask[b * 8 + k];
+            c2 = a.lmask2[b];
+        }
+        const uint8_t v3 = a.vis3[b];
+        const uint8_t v4 = a.vis4 ? a.vis4[coarse_index(w.v, 4, a.n4)] : 1;
+        const uint8_t v5 = a.vis5 ? a.vis5[coarse_index(w.v, 5, a.n5)] : 1;
+        const uint8_t v6 = a.vis6 ? a.vis6[coarse_index(w.v, 6, a.n6)] : 1;
+        if (!v3) {  // the largest invisible cell holding the brick is crossed in one jump
+            const int sh = !v6 ? 6 : (!v5 ? 5 : (!v4 ? 4 : 3));
+            if (kStats) {
+                if (sh == 6) ++cn.skip64;
+                else ++cn.skip8;
             }
-            const uint8_t v3 = a.vis3[b];
-            const uint8_t v4 = a.vis4 ? a.vis4[coarse_index(w.v, 4, a.n4)] : 1;
-            const uint8_t v5 = a.vis5 ? a.vis5[coarse_index(w.v, 5, a.n5)] : 1;
-            const uint8_t v6 = a.vis6 ? a.vis6[coarse_index(w.v, 6, a.n6)] : 1;
-            if (!v3) {  // the largest invisible cell holding the brick is crossed in one jump
-                const int sh = !v6 ? 6 : (!v5 ? 5 : (!v4 ? 4 : 3));
-                if (kStats) {
-                    if (sh == 6) ++cn.skip64;
-                    else ++cn.skip8;
-                }
-                if (!skip_cell(r, a.G, sh, w.v, w.tcur)) return false;
-                w.fresh = true;
-                continue;
-            }
-            if (Mask::kEarly) {
-                mk.put(m);
-                mk.c2 = c2;
-            } else {
-                mk.set(a.lmask + b * 8, a.lmask2 + b);
-            }
-            w.bvis = b;
+            if (!skip_cell(r, a.G, sh, w.v, w.tcur)) return -1;
+            w.fresh = true;
+            return 0;
         }
-        if (Mask::kCells) {  // a 2^3 or 4^3 cell of the brick without list voxels is crossed in one jump
-            const int xl = w.v[0] & 7, yl = w.v[1] & 7, zl = w.v[2] & 7;
-            if (!((mk.c2 >> (((zl >> 1) << 4) | ((yl >> 1) << 2) | (xl >> 1))) & 1ull)) {
-                const bool e4 = !(mk.c2 & (0x00330033ull << (((zl >> 2) << 5) | ((yl >> 2) << 3) | ((xl >> 2) << 1))));
-                if (kStats) ++cn.skip8;
-                if (!skip_cell(r, a.G, e4 ? 2 : 1, w.v, w.tcur)) return false;
-                w.fresh = true;
-                continue;
-            }
+        if (Mask::kEarly) {
+            mk.put(m);
+            mk.c2 = c2;
+        } else {
+            mk.set(a.lmask + b * 8, a.lmask2 + b);
         }
-        if (w.fresh) {
-            for (int k = 0; k < 3; ++k)
-                w.tnext[k] = r.step[k] == 0 ? INFINITY : tcross(w.v[k] + (r.step[k] > 0), r.O[k], r.inv[k]);
-            w.fresh = false;
+        w.bvis = b;
+    }
+    if (Mask::kCells) {  // a 2^3 or 4^3 cell of the brick without list voxels is crossed in one jump
+        const int xl = w.v[0] & 7, yl = w.v[1] & 7, zl = w.v[2] & 7;
+        if (!((mk.c2 >> (((zl >> 1) << 4) | ((yl >> 1) << 2) | (xl >> 1))) & 1ull)) {
+            const bool e4 = !(mk.c2 & (0x00330033ull << (((zl >> 2) << 5) | ((yl >> 2) << 3) | ((xl >> 2) << 1))));
+            if (kStats) ++cn.skip8;
+            if (!skip_cell(r, a.G, e4 ? 2 : 1, w.v, w.tcur)) return -1;
+            w.fresh = true;
+            return 0;
         }
-        float tm = w.tnext[0];
-        w.m = 0;
-        if (w.tnext[1] < tm) {
-            w.m = 1;
-            tm = w.tnext[1];
-        }
-        if (w.tnext[2] < tm) {
-            w.m = 2;
-            tm = w.tnext[2];
-        }
-        w.texit = fmaxf(tm, w.tcur);
-        if (kStats) ++cn.vox;
-        const int l = local_of(w.v[0], w.v[1], w.v[2]);
-        if ((mk.slice(w.v[2]) >> (l & 63)) & 1ull) {
-            w.vi = b * kBrickVox + l;
-            w.cd = a.cell[w.vi];
-            return true;
-        }
-        if (!step_voxel(a, r, w)) return false;
+    }
+    if (w.fresh) {
+        voxel_bounds(r, w);
+        w.fresh = false;
+    }
+    voxel_exit(w);
+    if (kStats) ++cn.vox;
+    const int l = local_of(w.v[0], w.v[1], w.v[2]);
+    if ((mk.slice(w.v[2]) >> (l & 63)) & 1ull) {
+        w.vi = b * kBrickVox + l;
+        if (kLoadCd) w.cd = a.cell[w.vi];
+        return 1;
+    }
+    return step_voxel(a, r, w) ? 0 : -1;
+}
+
+// Steps a walk bounded by every grid dimension three times over (each step
+// advances it by a voxel at least).
+__device__ __forceinline__ int march_limit(const TraceArgs &a) { return 3 * (a.G[0] + a.G[1] + a.G[2]) + 16; }
+
+// Advances from the current voxel (included) to the first visible voxel with
+// a non-empty list; false if none.  kLoadCd: also read its list descriptor.
+template <bool kStats, class Mask, bool kLoadCd = true>
+__device__ __forceinline__ bool march(const TraceArgs &a, const Ray &r, Walk &w, Counters &cn, Mask &mk) {
+    const int max_iter = march_limit(a);
+    for (int it = 0; it < max_iter; ++it) {
+        const int st = march_step<kStats, Mask, kLoadCd>(a, r, w, cn, mk);
+        if (st != 0) return st > 0;
     }
     return false;
 }
@@ -744,8 +794,7 @@ __device__ __forceinline__ void b_trace_march(TraceArgs a, unsigned bid_, unsign
         unsigned pos = s_base + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
         for (int k = 0; k < wv; ++k) pos += s_wcnt[k];
         const uint32_t pix = (uint32_t)(py * a.p.W + px);
-        const uint32_t vp = (uint32_t)w.v[0] | ((uint32_t)w.v[1] << 10) | ((uint32_t)w.v[2] << 20);
-        a.queue[pos] = make_uint4(pix, vp, __float_as_uint(w.tcur), __float_as_uint(w.tout));
+        a.queue[pos] = make_uint4(pix, pack_voxel(w.v), __float_as_uint(w.tcur), __float_as_uint(w.tout));
     }
     flush_counters<kStats>(a, cn, false, lane, 1);
     if (live && !found) write_pixel(a, (int64_t)py * a.p.W + px, Shade());
@@ -754,13 +803,169 @@ __device__ __forceinline__ void b_trace_march(TraceArgs a, unsigned bid_, unsign
 template <bool kStats>
 __global__ void __launch_bounds__(512) k_trace_march(TraceArgs a) { b_trace_march<kStats>(a, blockIdx.x, gridDim.x); }
 
+// Walk entries per queued ray (0: no walk phase; the shade phase walks).
+__device__ __forceinline__ int64_t walk_capacity(int64_t entries, unsigned n) {
+    if (n == 0) return 0;
+    const int64_t k = entries / (int64_t)n;
+    return k < kWalkMax ? k : kWalkMax;
+}
+
+// Per brick of the grid: 0 when the brick is visible, else the shift (3..6)
+// of the largest invisible cell of 8^3 .. 64^3 voxels holding it (a 64^3
+// cell is visible iff one of its bricks is), so the walk phase reads one byte
+// per brick it enters.
+__device__ __forceinline__ void b_brick_skip(TraceArgs a, unsigned bid_, unsigned nblk_) {
+    const uint32_t nb = (uint32_t)a.nb[0] * a.nb[1] * a.nb[2];
+    for (uint32_t b = bid_ * blockDim.x + threadIdx.x; b < nb; b += nblk_ * blockDim.x) {
+        uint8_t sh = 0;
+        if (!a.vis3[b]) {
+            const int v[3] = {(int)(b % (uint32_t)a.nb[0]) * 8, (int)((b / (uint32_t)a.nb[0]) % (uint32_t)a.nb[1]) * 8,
+                              (int)(b / ((uint32_t)a.nb[0] * a.nb[1])) * 8};
+            const uint8_t v4 = a.vis4 ? a.vis4[coarse_index(v, 4, a.n4)] : 1;
+            const uint8_t v5 = a.vis5 ? a.vis5[coarse_index(v, 5, a.n5)] : 1;
+            const uint8_t v6 = a.vis6 ? a.vis6[coarse_index(v, 6, a.n6)] : 1;
+            sh = !v6 ? 6 : (!v5 ? 5 : (!v4 ? 4 : 3));
+        }
+        a.bskip[b] = sh;
+    }
+}
+__global__ void __launch_bounds__(256) k_brick_skip(TraceArgs a) { b_brick_skip(a, blockIdx.x, gridDim.x); }
+
+// One step of the walk phase (the march's step with one jump site, so that
+// the lanes of a wave in different states run fewer distinct paths): -1 when
+// the ray has left the box or the grid, 0 after a jump over an invisible cell
+// or a list-free 2^3 / 4^3 cell, 1 on a voxel without a list, 2 on a visible
+// voxel with a list (the caller steps past both).
+__device__ __forceinline__ int walk_step(const TraceArgs &a, const Ray &r, Walk &w, MaskRegs &mk) {
+    if (!(w.tcur < w.tout)) return -1;
+    const uint32_t b = ((uint32_t)(w.v[2] >> 3) * (uint32_t)a.nb[1] + (uint32_t)(w.v[1] >> 3)) * (uint32_t)a.nb[0] +
+                       (uint32_t)(w.v[0] >> 3);
+    int sh = 0;
+    if ((int64_t)b != w.bvis) {
+        sh = a.bskip[b];
+        if (sh == 0) {
+            mk.set(a.lmask + (size_t)b * 8, a.lmask2 + b);
+            w.bvis = b;
+        }
+    }
+    const int xl = w.v[0] & 7, yl = w.v[1] & 7, zl = w.v[2] & 7;
+    if (sh == 0 && !((mk.c2 >> (((zl >> 1) << 4) | ((yl >> 1) << 2) | (xl >> 1))) & 1ull))
+        sh = (mk.c2 & (0x00330033ull << (((zl >> 2) << 5) | ((yl >> 2) << 3) | ((xl >> 2) << 1)))) ? 1 : 2;
+    if (sh) {
+        if (!skip_cell(r, a.G, sh, w.v, w.tcur)) return -1;
+        w.fresh = true;
+        return 0;
+    }
+    if (w.fresh) {
+        voxel_bounds(r, w);
+        w.fresh = false;
+    }
+    voxel_exit(w);
+    return ((mk.slice(w.v[2]) >> (local_of(xl, yl, zl) & 63)) & 1ull) ? 2 : 1;
+}
+
+// Walk phase, one thread per queued ray: continues the march from the ray's
+// first list voxel and records every visible voxel with a list it passes, in
+// order, with its entry parameter (at most walk_capacity entries).  The ray's
+// queue entry then holds the count and whether the walk stopped at the limit
+// with list voxels left.  The walk needs no list data, so the shade phase's
+// lanes find the voxels of a ray without walking them one after another.
+__device__ __forceinline__ void b_trace_walk(TraceArgs a, unsigned bid_, unsigned nblk_) {
+    const unsigned n = a.st->n_queue;
+    const int64_t K = walk_capacity(a.walk_entries, n);
+    for (unsigned i = bid_ * blockDim.x + threadIdx.x; i < n; i += nblk_ * blockDim.x) {
+        const uint4 q = a.queue[i];
+        const float3 D = primary_dir(a.p, (int)(q.x % (uint32_t)a.p.W), (int)(q.x / (uint32_t)a.p.W));
+        const Ray r = make_ray(a.p, D);
+        Walk w;
+        unpack_voxel(q.y, w.v);
+        w.tcur = __uint_as_float(q.z);
+        w.tout = __uint_as_float(q.w);
+        w.fresh = true;
+        MaskRegs mk;
+        uint2 *out = a.walk + (int64_t)i * K;
+        uint32_t cnt = 0;
+        bool more = false;
+        // one loop of single steps: a lane that finds a list voxel records it
+        // and steps on while the other lanes of the wave are still marching
+        const int max_iter = march_limit(a);
+        for (int it = 0; it < max_iter; ++it) {
+            const int st = walk_step(a, r, w, mk);
+            if (st < 0) break;
+            if (st == 2) {
+                if (cnt == (uint64_t)K) {
+                    more = true;
+                    break;
+                }
+                out[cnt++] = make_uint2(pack_voxel(w.v), __float_as_uint(w.tcur));
+            }
+            if (st > 0 && !step_voxel(a, r, w)) break;
+        }
+        a.queue[i].y = cnt | (more ? 0x80000000u : 0u);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_trace_walk(TraceArgs a) { b_trace_walk(a, blockIdx.x, gridDim.x); }
+
 // Phase 2, one kGroup-lane group per queued ray: lists, capsule tests and
 // compositing, continuing the walk until the ray is finished.  All lanes of a
 // group follow the same walk; list entries are split across them.
 // Work unit bid_ of nblk_, each of unit_threads threads (this thread is
 // unit_tid of its unit): the whole workgroup, or one wave of it when the
 // waves of a workgroup take work on their own.
-template <bool kStats, int kForm, class Cfg = DefaultShade>
+// The walked voxels of queued ray i (K entries per ray), then, when its walk
+// stopped at the limit, the rest of its walk.  The lanes of the group read
+// kGroup entries and their list descriptors at once and take the voxels in
+// order from them.
+template <int kForm, class Cfg>
+__device__ __forceinline__ void shade_walked(const TraceArgs &a, const Ray &r, const uint4 &q, unsigned i, int64_t K,
+                                             Shade &sh, Counters &cn, int lane, MaskLds &mk) {
+    constexpr int kGroup = Cfg::kGroup;
+    const int gl = lane & (kGroup - 1), gbase = lane & ~(kGroup - 1);
+    const uint32_t cnt = q.y & 0x7FFFFFFFu;
+    const uint2 *ent = a.walk + (int64_t)i * K;
+    Walk w;
+    w.tout = __uint_as_float(q.w);
+    uint2 cur = make_uint2(0u, 0u);
+    for (uint32_t base = 0; base < cnt; base += kGroup) {
+        uint2 e = make_uint2(0u, 0u);
+        uint64_t cd = 0;
+        if (base + gl < cnt) {
+            e = ent[base + gl];
+            int v[3];
+            unpack_voxel(e.x, v);
+            cd = a.cell[voxel_index(a, v)];
+        }
+        const uint32_t m = cnt - base < (uint32_t)kGroup ? cnt - base : (uint32_t)kGroup;
+        for (uint32_t j = 0; j < m; ++j) {
+            const int src = gbase + (int)j;
+            cur.x = (uint32_t)__shfl((int)e.x, src, 64);
+            cur.y = (uint32_t)__shfl((int)e.y, src, 64);
+            w.cd = __shfl(cd, src, 64);
+            unpack_voxel(cur.x, w.v);
+            w.tcur = __uint_as_float(cur.y);
+            voxel_bounds(r, w);
+            voxel_exit(w);
+            w.vi = voxel_index(a, w.v);
+            if (shade_voxel<false, kForm, Cfg>(a, r, w, sh, cn, lane)) return;
+        }
+    }
+    if (!(q.y >> 31)) return;
+    // the walk stopped at the limit: re-enter the last walked voxel and go on from there
+    unpack_voxel(cur.x, w.v);
+    w.tcur = __uint_as_float(cur.y);
+    w.fresh = true;
+    bool have = march<false>(a, r, w, cn, mk) && step_voxel(a, r, w) && march<false>(a, r, w, cn, mk);
+    while (have) {
+        if (shade_voxel<false, kForm, Cfg>(a, r, w, sh, cn, lane)) return;
+        if (!step_voxel(a, r, w)) return;
+        have = march<false>(a, r, w, cn, mk);
+    }
+}
+
+// kWalked: the walk phase has run (plain launches); the statistics variant
+// and the batched form walk in this phase.
+template <bool kStats, int kForm, class Cfg = DefaultShade, bool kWalked = false>
 __device__ __forceinline__ void b_trace_shade(TraceArgs a, unsigned bid_, unsigned nblk_, unsigned unit_threads,
                                               unsigned unit_tid) {
     constexpr int kGroup = Cfg::kGroup;
@@ -772,19 +977,24 @@ __device__ __forceinline__ void b_trace_shade(TraceArgs a, unsigned bid_, unsign
     MaskLds mk{s_mask + threadIdx.x / kGroup, (int)(blockDim.x / kGroup)};
     // every group runs the same number of rounds so counters can be reduced per wave
     const unsigned rounds = (n + ngroups - 1) / ngroups;
+    const int64_t K = kWalked ? walk_capacity(a.walk_entries, n) : 0;
     for (unsigned rd = 0; rd < rounds; ++rd) {
         const unsigned i = rd * ngroups + grp;
         Counters cn;
         Shade sh;
-        if (i < n) {
+        if (kWalked && i < n) {  // K >= 1: walk_entries >= max_pixels >= n
+            const uint4 q = a.queue[i];
+            const float3 D = primary_dir(a.p, (int)(q.x % (uint32_t)a.p.W), (int)(q.x / (uint32_t)a.p.W));
+            const Ray r = make_ray(a.p, D);
+            shade_walked<kForm, Cfg>(a, r, q, i, K, sh, cn, lane, mk);
+            if ((lane & (kGroup - 1)) == 0) write_pixel(a, (int64_t)q.x, sh);
+        } else if (!kWalked && i < n) {
             const uint4 q = a.queue[i];
             const int px = (int)(q.x % (uint32_t)a.p.W), py = (int)(q.x / (uint32_t)a.p.W);
             const float3 D = primary_dir(a.p, px, py);
             const Ray r = make_ray(a.p, D);
             Walk w;
-            w.v[0] = (int)(q.y & 1023u);
-            w.v[1] = (int)((q.y >> 10) & 1023u);
-            w.v[2] = (int)((q.y >> 20) & 1023u);
+            unpack_voxel(q.y, w.v);
             w.tcur = __uint_as_float(q.z);
             w.tout = __uint_as_float(q.w);
             w.fresh = true;
@@ -821,8 +1031,8 @@ __device__ __forceinline__ void b_debug_rays(TraceParams p, const int64_t *__res
 // Four waves per SIMD (at most 128 registers): the shade phase is bound by
 // memory latency, and the fourth wave hides more of it than the few spilled
 // registers cost.
-template <bool kStats, int kForm, class Cfg>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm, Cfg>(a, blockIdx.x, gridDim.x, blockDim.x, threadIdx.x); }
+template <bool kStats, int kForm, class Cfg, bool kWalked>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm, Cfg, kWalked>(a, blockIdx.x, gridDim.x, blockDim.x, threadIdx.x); }
 
 __global__ void k_debug_rays(TraceParams p, const int64_t *__restrict__ pix, int64_t n, float *__restrict__ dirs) { b_debug_rays(p, pix, n, dirs, blockIdx.x, gridDim.x); }
 
@@ -880,6 +1090,7 @@ static TraceArgs trace_args(vrt_ctx *c, const TraceParams &p, const vrt_image *i
         a.nb[k] = c->dims[k] / 8;
     }
     a.vis3 = c->a.vis3;
+    a.bskip = c->a.bskip;
     const uint8_t **hv[3] = {&a.vis4, &a.vis5, &a.vis6};
     int *hn[3] = {a.n4, a.n5, a.n6};
     for (int L = 4; L <= 6; ++L) {
@@ -901,6 +1112,8 @@ static TraceArgs trace_args(vrt_ctx *c, const TraceParams &p, const vrt_image *i
     a.nv = c->n_vertices;
     a.capacity = c->desc.max_fragments;
     a.queue = c->a.queue;
+    a.walk = c->a.walk;
+    a.walk_entries = c->walk_entries;
     a.rgba = img->rgba;
     a.depth = img->depth;
     a.first_id = img->first_id;
@@ -924,6 +1137,17 @@ static unsigned march_grid(const TraceParams &p, int threads) {
     return (unsigned)(((p.W + 15) / 16) * ((p.H + rows - 1) / rows));
 }
 
+// Walk phase grid: one thread per pixel that could be queued, at most 2048 blocks (grid-stride beyond).
+static unsigned walk_grid(const TraceParams &p) {
+    const int64_t b = ((int64_t)p.W * p.H + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+}
+
+static unsigned skip_grid(const vrt_ctx *c) {
+    const int64_t b = ((int64_t)(c->dims[0] / 8) * (c->dims[1] / 8) * (c->dims[2] / 8) + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
 // Launches the shade kernel instance of shape (group, batch, keys).
 template <bool kStats, int kForm>
 static void launch_shade(const vrt_tune &t, const TraceArgs &a, hipStream_t st) {
@@ -932,7 +1156,7 @@ static void launch_shade(const vrt_tune &t, const TraceArgs &a, hipStream_t st) 
     const unsigned blocks = (unsigned)t.shade_blocks * 4u;
 #define VRT_SHADE_CASE(G, B, K)                                                                  \
     case G * 100 + B * 10 + K:                                                                   \
-        k_trace_shade<kStats, kForm, ShadeCfg<G, B, K>><<<blocks, 64, 0, st>>>(a);               \
+        k_trace_shade<kStats, kForm, ShadeCfg<G, B, K>, !kStats><<<blocks, 64, 0, st>>>(a);     \
         break;
     switch (t.shade_group * 100 + t.shade_batch * 10 + t.lane_keys) {
         VRT_SHADE_CASE(8, 2, 4) VRT_SHADE_CASE(8, 2, 8) VRT_SHADE_CASE(8, 4, 4) VRT_SHADE_CASE(8, 4, 8)
@@ -948,6 +1172,8 @@ hipError_t launch_trace(vrt_ctx *c, const TraceParams &p, const vrt_image *img, 
     const vrt_tune &t = c->tune[p.mode == VRT_TRACE_OPAQUE ? 0 : 1];
     VRT_LAUNCH(c, "k_trace_begin", st, k_trace_begin<<<1, 64, 0, st>>>(a.st));
     VRT_LAUNCH(c, "k_trace_march", st, k_trace_march<false><<<march_grid(p, t.march_threads), t.march_threads, 0, st>>>(a));
+    VRT_LAUNCH(c, "k_brick_skip", st, k_brick_skip<<<skip_grid(c), 256, 0, st>>>(a));
+    VRT_LAUNCH(c, "k_trace_walk", st, k_trace_walk<<<walk_grid(p), 256, 0, st>>>(a));
     if (c->desc.form == VRT_FORM_FP16)
         VRT_LAUNCH(c, "k_trace_shade", st, (launch_shade<false, VRT_FORM_FP16>(t, a, st)));
     else
@@ -962,8 +1188,8 @@ hipError_t launch_trace_stats(vrt_ctx *c, const TraceParams &p, const vrt_image 
     k_stat_clear<<<1024, 256, 0, st>>>(c->a.brick_list, c->a.status, c->n_vertices, a.stat_vox, a.stat_seg, a.stat_acc);
     k_trace_begin<<<1, 64, 0, st>>>(a.st);
     k_trace_march<true><<<march_grid(p, 256), 256, 0, st>>>(a);
-    if (c->desc.form == VRT_FORM_FP16) k_trace_shade<true, VRT_FORM_FP16, DefaultShade><<<16384, 64, 0, st>>>(a);
-    else k_trace_shade<true, VRT_FORM_PLAIN, DefaultShade><<<16384, 64, 0, st>>>(a);
+    if (c->desc.form == VRT_FORM_FP16) k_trace_shade<true, VRT_FORM_FP16, DefaultShade, false><<<16384, 64, 0, st>>>(a);
+    else k_trace_shade<true, VRT_FORM_PLAIN, DefaultShade, false><<<16384, 64, 0, st>>>(a);
     k_stat_reduce<<<1024, 256, 0, st>>>(c->a.brick_list, c->a.status, c->n_vertices, a.stat_vox, a.cell, a.stat_seg,
                                         a.stat_acc);
     return hipGetLastError();
