@@ -30,7 +30,7 @@ hipError_t alloc(T *&p, int64_t n) {
 void free_all(Arenas &a) {
     void *ptrs[] = {a.vrec, a.words, a.occ0, a.occ1, a.occ2, a.occ3, a.occ_hi, a.blk, a.blk_bits, a.brick_bits, a.super_blk,
                     a.occ_list, a.vis0,
-                    a.vis1, a.vis2,  a.vis3, a.bskip, a.vis_hi, a.cursor, a.cell, a.lmask, a.lmask2, a.queue, a.walk, a.srec16, a.ids, a.brick_flag, a.bin_count, a.bin_range, a.cand, a.bins, a.long_ids, a.items, a.chunk_cnt, a.brick_list, a.brick_slot,
+                    a.vis1, a.vis2,  a.vis3, a.bskip, a.vis_hi, a.cursor, a.cell, a.lmask, a.lmask2, a.queue, a.walk, a.cont, a.srec16, a.ids, a.brick_flag, a.bin_count, a.bin_range, a.cand, a.bins, a.long_ids, a.items, a.chunk_cnt, a.brick_list, a.brick_slot,
                     a.brick_total, a.brick_base, a.status, a.lit, a.stat_vox, a.stat_seg, a.stat_acc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -110,6 +110,7 @@ void arena_fields(Arenas &a, const vrt_desc &d, int64_t mb, int64_t hi_elems, in
     f(a.lmask2, mb);
     f(a.queue, d.max_pixels);
     f(a.walk, walk_entries);
+    f(a.cont, d.max_pixels);
     if (d.form == VRT_FORM_FP16) f(a.srec16, d.max_vertices);
     f(a.ids, d.max_fragments);
     f(a.brick_flag, mb);

@@ -28,7 +28,8 @@ constexpr unsigned kBricksPerVB = 8;  // occupied bricks
 constexpr unsigned kItemsPerVB = 4;   // binned (brick, chunk) items or candidate bricks
 enum : int {
     P_CLEAR, P_INGEST, P_BIN_COUNT, P_BIN_ALLOC, P_BIN_FILL, P_ACCUM, P_LONG, P_COMPACT, P_OCC, P_ERODE, P_WALK,
-    P_CBRICK, P_SCAN, P_OFFSETS, P_SCATTER, P_SCATTER_LONG, P_MARCH, P_SHADE8, P_SHADE16, P_SHADE32, kPhases
+    P_CBRICK, P_SCAN, P_OFFSETS, P_SCATTER, P_SCATTER_LONG, P_MARCH, P_RAYWALK, P_SHADE8, P_SHADE16, P_SHADE32,
+    P_RESUME, kPhases
 };
 // The shade phase is split by the sets' group size, so that each staged
 // kernel holds the tracer body of one group size only (and keeps its
@@ -75,14 +76,16 @@ __device__ unsigned part_blocks(int ph, int part, const SetDesc &d) {
     case P_CBRICK: return part == 0 ? cdiv(st->n_bricks, kBricksPerVB) : 0u;
     case P_SCAN: return part == 0 ? 1u : 0u;
     case P_OFFSETS: return part == 0 ? cdiv(st->n_bricks, kBricksPerVB) : 0u;
-    case P_SCATTER: return part == 0 ? cdiv(st->n_cand, kItemsPerVB) : 0u;
+    case P_SCATTER: return part == 0 ? cdiv(st->n_cand, kItemsPerVB) : (part == 1 ? cdiv(d.cp.nb, T) : 0u);
     case P_SCATTER_LONG: return part == 0 ? cdiv(st->n_long, T) : (part == 1 ? 1u : 0u);
     case P_MARCH: return part == 0 ? d.march_blocks : 0u;
+    case P_RAYWALK: return part == 0 ? cdiv(st->n_queue, T) : 0u;
     case P_SHADE8:
     case P_SHADE16:
     case P_SHADE32:  // one-wave units, in the phase of the set's group size
         return part == 0 && d.shade_group == shade_phase_group(ph) ? cdiv(st->n_queue, 64u / (unsigned)d.shade_group)
                                                                     : 0u;
+    case P_RESUME: return part == 0 ? cdiv(st->n_cont, 64u / 16u) : 0u;
     default: return 0u;
     }
 }
@@ -125,23 +128,31 @@ __device__ __forceinline__ void run_part(int ph, int part, const SetDesc &d, uns
         break;
     case P_SCAN: b_scan_bricks(A.brick_total, A.brick_base, A.status, d.capacity, A.vis_hi, d.levels, d.n_levels, 0u, 1u); break;
     case P_OFFSETS: b_list_offsets(A.words, A.vis0, A.brick_list, A.brick_base, A.status, A.cursor, A.cell, A.lmask, A.lmask2, vb, nvb); break;
-    case P_SCATTER: b_scatter_brick<-1>(d.cp.sb, A.status, vb, nvb); break;
+    case P_SCATTER:  // the lists, and the trace's per-brick skip bytes (the culling levels are final)
+        if (part == 0) b_scatter_brick<-1>(d.cp.sb, A.status, vb, nvb);
+        else b_brick_skip(d.ta, vb, nvb);
+        break;
     case P_SCATTER_LONG:
         if (part == 0) b_scatter_long(d.cp.sb, A.status, vb, nvb);
         else b_trace_begin(A.status, 0u, 1u);
         break;
     case P_MARCH: b_trace_march<false>(d.ta, vb, nvb); break;
+    case P_RAYWALK: b_trace_walk(d.ta, vb, nvb); break;
     case P_SHADE8:  // one wave per unit; the set's tuned group size, default batch and keys
-        if (d.fp16) b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<8, 2, 4>>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
-        else b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<8, 2, 4>>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
+        if (d.fp16) b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<8, 2, 4>, true>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
+        else b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<8, 2, 4>, true>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
         break;
     case P_SHADE16:
-        if (d.fp16) b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<16, 2, 4>>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
-        else b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<16, 2, 4>>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
+        if (d.fp16) b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<16, 2, 4>, true>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
+        else b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<16, 2, 4>, true>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
         break;
     case P_SHADE32:
-        if (d.fp16) b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<32, 2, 4>>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
-        else b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<32, 2, 4>>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
+        if (d.fp16) b_trace_shade<false, VRT_FORM_FP16, ShadeCfg<32, 2, 4>, true>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
+        else b_trace_shade<false, VRT_FORM_PLAIN, ShadeCfg<32, 2, 4>, true>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
+        break;
+    case P_RESUME:  // rays past the walk limit, default group size
+        if (d.fp16) b_trace_resume<VRT_FORM_FP16>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
+        else b_trace_resume<VRT_FORM_PLAIN>(d.ta, vb, nvb, 64u, threadIdx.x & 63u);
         break;
     default: break;
     }
@@ -260,9 +271,11 @@ const void *phase_kernel(int ph) {
     case P_SCATTER: return (const void *)k_batch_phase<P_SCATTER>;
     case P_SCATTER_LONG: return (const void *)k_batch_phase<P_SCATTER_LONG>;
     case P_MARCH: return (const void *)k_batch_phase<P_MARCH>;
+    case P_RAYWALK: return (const void *)k_batch_phase<P_RAYWALK>;
     case P_SHADE8: return (const void *)k_batch_shade_phase<P_SHADE8>;
     case P_SHADE16: return (const void *)k_batch_shade_phase<P_SHADE16>;
-    default: return (const void *)k_batch_shade_phase<P_SHADE32>;
+    case P_SHADE32: return (const void *)k_batch_shade_phase<P_SHADE32>;
+    default: return (const void *)k_batch_shade_phase<P_RESUME>;
     }
 }
 

@@ -62,6 +62,7 @@ struct DevStatus {
     unsigned int n_occ;  // occupied voxels (entries of occ_list)
     int vbox[6];         // visible-brick bounds: min bx,by,bz then max (bricks), combined at trace start
     unsigned int n_queue;  // rays queued by the trace's march phase
+    unsigned int n_cont;   // queued rays whose walk stopped at the limit, resumed after the shade phase
     unsigned int n_cand;           // bricks with a non-empty segment bin (entries of cand)
     unsigned int n_long;           // segments too long for the bins (entries of long_ids)
     unsigned long long bin_total;  // bin entries allocated
@@ -75,7 +76,7 @@ constexpr int kMaxBinBricks = 8;
 // Walk entries per pixel of max_pixels: the trace's walk phase gives every
 // queued ray walk_entries / n_queue entries (at most kWalkMax), so rays are
 // walked in full unless most pixels reach a list.
-constexpr int kWalkPerPixel = 8;
+constexpr int kWalkPerPixel = 8;  // at least 4: a ray's slot also holds its resume state (32 B)
 constexpr int kWalkMax = 4096;
 // Bins are processed in chunks of at most this many segments (one workgroup
 // each), so that crowded bricks are spread over several workgroups.
@@ -120,6 +121,7 @@ struct Arenas {
     uint64_t *lmask2 = nullptr;     // [max_bricks] 2^3 cells holding such a voxel, bit 16 Z + 4 Y + X
     uint4 *queue = nullptr;         // [max_pixels] rays that reached a list
     uint2 *walk = nullptr;          // [walk_entries] list voxels of the queued rays, in walk order (voxel, entry t)
+    uint32_t *cont = nullptr;       // [max_pixels] queued rays resumed after the walk limit
     SRec16 *srec16 = nullptr;       // [max_vertices] FP16-form segment records (FP16 form only)
     uint32_t *ids = nullptr;        // [max_fragments]
     uint8_t *brick_flag = nullptr;  // [max_bricks]

@@ -118,6 +118,7 @@ struct TraceArgs {
                               // entries | more << 31), entry t, exit t of the visible box
     uint2 *walk;              // walk_capacity(walk_entries, n_queue) entries per queued ray: packed voxel, entry t
     int64_t walk_entries;
+    uint32_t *cont;           // queued rays whose walk stopped at the limit unfinished, resumed by a later launch
     float *rgba;
     float *depth;
     int *first_id;
@@ -731,10 +732,87 @@ __device__ __forceinline__ void flush_counters(const TraceArgs &a, const Counter
     if (lane == 0 && mx) atomicMax(&a.stat_acc[7], mx);
 }
 
+// Per brick of the grid: 0 when the brick is visible, else the shift (3..6)
+// of the largest invisible cell of 8^3 .. 64^3 voxels holding it (a 64^3
+// cell is visible iff one of its bricks is), so the walk phase reads one byte
+// per brick it enters.
+__device__ __forceinline__ void b_brick_skip(TraceArgs a, unsigned bid_, unsigned nblk_) {
+    const uint32_t nb = (uint32_t)a.nb[0] * a.nb[1] * a.nb[2];
+    for (uint32_t b = bid_ * blockDim.x + threadIdx.x; b < nb; b += nblk_ * blockDim.x) {
+        uint8_t sh = 0;
+        if (!a.vis3[b]) {
+            const int v[3] = {(int)(b % (uint32_t)a.nb[0]) * 8, (int)((b / (uint32_t)a.nb[0]) % (uint32_t)a.nb[1]) * 8,
+                              (int)(b / ((uint32_t)a.nb[0] * a.nb[1])) * 8};
+            const uint8_t v4 = a.vis4 ? a.vis4[coarse_index(v, 4, a.n4)] : 1;
+            const uint8_t v5 = a.vis5 ? a.vis5[coarse_index(v, 5, a.n5)] : 1;
+            const uint8_t v6 = a.vis6 ? a.vis6[coarse_index(v, 6, a.n6)] : 1;
+            sh = !v6 ? 6 : (!v5 ? 5 : (!v4 ? 4 : 3));
+        }
+        a.bskip[b] = sh;
+    }
+}
+__global__ void __launch_bounds__(256) k_brick_skip(TraceArgs a) { b_brick_skip(a, blockIdx.x, gridDim.x); }
+
+// One step of the walk phase (the march's step with one jump site, so that
+// the lanes of a wave in different states run fewer distinct paths): -1 when
+// the ray has left the box or the grid, 0 after a jump over an invisible cell
+// or a list-free 2^3 / 4^3 cell, 1 on a voxel without a list, 2 on a visible
+// voxel with a list (the caller steps past both).
+template <bool kStats>
+__device__ __forceinline__ int walk_step(const TraceArgs &a, const Ray &r, Walk &w, MaskRegs &mk, Counters &cn) {
+    if (!(w.tcur < w.tout)) return -1;
+    const uint32_t b = ((uint32_t)(w.v[2] >> 3) * (uint32_t)a.nb[1] + (uint32_t)(w.v[1] >> 3)) * (uint32_t)a.nb[0] +
+                       (uint32_t)(w.v[0] >> 3);
+    int sh = 0;
+    if ((int64_t)b != w.bvis) {
+        sh = a.bskip[b];
+        if (sh == 0) {
+            mk.set(a.lmask + (size_t)b * 8, a.lmask2 + b);
+            w.bvis = b;
+        }
+    }
+    const int xl = w.v[0] & 7, yl = w.v[1] & 7, zl = w.v[2] & 7;
+    if (sh == 0 && !((mk.c2 >> (((zl >> 1) << 4) | ((yl >> 1) << 2) | (xl >> 1))) & 1ull))
+        sh = (mk.c2 & (0x00330033ull << (((zl >> 2) << 5) | ((yl >> 2) << 3) | ((xl >> 2) << 1)))) ? 1 : 2;
+    if (sh) {
+        if (kStats) {
+            if (sh == 6) ++cn.skip64;
+            else ++cn.skip8;
+        }
+        if (!skip_cell(r, a.G, sh, w.v, w.tcur)) return -1;
+        w.fresh = true;
+        return 0;
+    }
+    if (w.fresh) {
+        voxel_bounds(r, w);
+        w.fresh = false;
+    }
+    voxel_exit(w);
+    if (kStats) ++cn.vox;
+    return ((mk.slice(w.v[2]) >> (local_of(xl, yl, zl) & 63)) & 1ull) ? 2 : 1;
+}
+
+// Advances from the current voxel (included) to the first visible voxel with
+// a list in walk-phase steps; false if none.  Leaves its list descriptor unread.
+template <bool kStats>
+__device__ __forceinline__ bool first_list_voxel(const TraceArgs &a, const Ray &r, Walk &w, Counters &cn, MaskRegs &mk) {
+    const int max_iter = march_limit(a);
+    for (int it = 0; it < max_iter; ++it) {
+        const int st = walk_step<kStats>(a, r, w, mk, cn);
+        if (st < 0) return false;
+        if (st == 2) return true;
+        if (st == 1 && !step_voxel(a, r, w)) return false;
+    }
+    return false;
+}
+
 // Clears the ray queue and combines the stripes of the visible-brick box.
 __device__ __forceinline__ void b_trace_begin(DevStatus *st, unsigned bid_, unsigned nblk_) {
     const int k = threadIdx.x;
-    if (k == 0) st->n_queue = 0;
+    if (k == 0) {
+        st->n_queue = 0;
+        st->n_cont = 0;
+    }
     if (k < 6) {
         int v = k < 3 ? INT_MAX : INT_MIN;
         for (int s = 0; s < kStripes; ++s) {
@@ -776,7 +854,7 @@ __device__ __forceinline__ void b_trace_march(TraceArgs a, unsigned bid_, unsign
         }
         w.fresh = true;
         MaskRegs mk;
-        found = march<kStats>(a, r, w, cn, mk);
+        found = first_list_voxel<kStats>(a, r, w, cn, mk);
     }
     // one queue append per block (same-address atomics serialize)
     __shared__ unsigned s_wcnt[16];
@@ -810,60 +888,6 @@ __device__ __forceinline__ int64_t walk_capacity(int64_t entries, unsigned n) {
     return k < kWalkMax ? k : kWalkMax;
 }
 
-// Per brick of the grid: 0 when the brick is visible, else the shift (3..6)
-// of the largest invisible cell of 8^3 .. 64^3 voxels holding it (a 64^3
-// cell is visible iff one of its bricks is), so the walk phase reads one byte
-// per brick it enters.
-__device__ __forceinline__ void b_brick_skip(TraceArgs a, unsigned bid_, unsigned nblk_) {
-    const uint32_t nb = (uint32_t)a.nb[0] * a.nb[1] * a.nb[2];
-    for (uint32_t b = bid_ * blockDim.x + threadIdx.x; b < nb; b += nblk_ * blockDim.x) {
-        uint8_t sh = 0;
-        if (!a.vis3[b]) {
-            const int v[3] = {(int)(b % (uint32_t)a.nb[0]) * 8, (int)((b / (uint32_t)a.nb[0]) % (uint32_t)a.nb[1]) * 8,
-                              (int)(b / ((uint32_t)a.nb[0] * a.nb[1])) * 8};
-            const uint8_t v4 = a.vis4 ? a.vis4[coarse_index(v, 4, a.n4)] : 1;
-            const uint8_t v5 = a.vis5 ? a.vis5[coarse_index(v, 5, a.n5)] : 1;
-            const uint8_t v6 = a.vis6 ? a.vis6[coarse_index(v, 6, a.n6)] : 1;
-            sh = !v6 ? 6 : (!v5 ? 5 : (!v4 ? 4 : 3));
-        }
-        a.bskip[b] = sh;
-    }
-}
-__global__ void __launch_bounds__(256) k_brick_skip(TraceArgs a) { b_brick_skip(a, blockIdx.x, gridDim.x); }
-
-// One step of the walk phase (the march's step with one jump site, so that
-// the lanes of a wave in different states run fewer distinct paths): -1 when
-// the ray has left the box or the grid, 0 after a jump over an invisible cell
-// or a list-free 2^3 / 4^3 cell, 1 on a voxel without a list, 2 on a visible
-// voxel with a list (the caller steps past both).
-__device__ __forceinline__ int walk_step(const TraceArgs &a, const Ray &r, Walk &w, MaskRegs &mk) {
-    if (!(w.tcur < w.tout)) return -1;
-    const uint32_t b = ((uint32_t)(w.v[2] >> 3) * (uint32_t)a.nb[1] + (uint32_t)(w.v[1] >> 3)) * (uint32_t)a.nb[0] +
-                       (uint32_t)(w.v[0] >> 3);
-    int sh = 0;
-    if ((int64_t)b != w.bvis) {
-        sh = a.bskip[b];
-        if (sh == 0) {
-            mk.set(a.lmask + (size_t)b * 8, a.lmask2 + b);
-            w.bvis = b;
-        }
-    }
-    const int xl = w.v[0] & 7, yl = w.v[1] & 7, zl = w.v[2] & 7;
-    if (sh == 0 && !((mk.c2 >> (((zl >> 1) << 4) | ((yl >> 1) << 2) | (xl >> 1))) & 1ull))
-        sh = (mk.c2 & (0x00330033ull << (((zl >> 2) << 5) | ((yl >> 2) << 3) | ((xl >> 2) << 1)))) ? 1 : 2;
-    if (sh) {
-        if (!skip_cell(r, a.G, sh, w.v, w.tcur)) return -1;
-        w.fresh = true;
-        return 0;
-    }
-    if (w.fresh) {
-        voxel_bounds(r, w);
-        w.fresh = false;
-    }
-    voxel_exit(w);
-    return ((mk.slice(w.v[2]) >> (local_of(xl, yl, zl) & 63)) & 1ull) ? 2 : 1;
-}
-
 // Walk phase, one thread per queued ray: continues the march from the ray's
 // first list voxel and records every visible voxel with a list it passes, in
 // order, with its entry parameter (at most walk_capacity entries).  The ray's
@@ -883,6 +907,7 @@ __device__ __forceinline__ void b_trace_walk(TraceArgs a, unsigned bid_, unsigne
         w.tout = __uint_as_float(q.w);
         w.fresh = true;
         MaskRegs mk;
+        Counters cn;
         uint2 *out = a.walk + (int64_t)i * K;
         uint32_t cnt = 0;
         bool more = false;
@@ -890,7 +915,7 @@ __device__ __forceinline__ void b_trace_walk(TraceArgs a, unsigned bid_, unsigne
         // and steps on while the other lanes of the wave are still marching
         const int max_iter = march_limit(a);
         for (int it = 0; it < max_iter; ++it) {
-            const int st = walk_step(a, r, w, mk);
+            const int st = walk_step<false>(a, r, w, mk, cn);
             if (st < 0) break;
             if (st == 2) {
                 if (cnt == (uint64_t)K) {
@@ -913,13 +938,14 @@ __global__ void __launch_bounds__(256) k_trace_walk(TraceArgs a) { b_trace_walk(
 // Work unit bid_ of nblk_, each of unit_threads threads (this thread is
 // unit_tid of its unit): the whole workgroup, or one wave of it when the
 // waves of a workgroup take work on their own.
-// The walked voxels of queued ray i (K entries per ray), then, when its walk
-// stopped at the limit, the rest of its walk.  The lanes of the group read
-// kGroup entries and their list descriptors at once and take the voxels in
-// order from them.
+// The walked voxels of queued ray i (K entries per ray).  The lanes of the
+// group read kGroup entries and their list descriptors at once and take the
+// voxels in order from them.  A ray whose walk stopped at the limit and that
+// is not finished after its entries is left to the resume launch.
+// Returns false when the ray went to the resume list (its pixel is written there).
 template <int kForm, class Cfg>
-__device__ __forceinline__ void shade_walked(const TraceArgs &a, const Ray &r, const uint4 &q, unsigned i, int64_t K,
-                                             Shade &sh, Counters &cn, int lane, MaskLds &mk) {
+__device__ __forceinline__ bool shade_walked(const TraceArgs &a, const Ray &r, const uint4 &q, unsigned i, int64_t K,
+                                             Shade &sh, Counters &cn, int lane) {
     constexpr int kGroup = Cfg::kGroup;
     const int gl = lane & (kGroup - 1), gbase = lane & ~(kGroup - 1);
     const uint32_t cnt = q.y & 0x7FFFFFFFu;
@@ -947,20 +973,22 @@ __device__ __forceinline__ void shade_walked(const TraceArgs &a, const Ray &r, c
             voxel_bounds(r, w);
             voxel_exit(w);
             w.vi = voxel_index(a, w.v);
-            if (shade_voxel<false, kForm, Cfg>(a, r, w, sh, cn, lane)) return;
+            if (shade_voxel<false, kForm, Cfg>(a, r, w, sh, cn, lane)) return true;
         }
     }
-    if (!(q.y >> 31)) return;
-    // the walk stopped at the limit: re-enter the last walked voxel and go on from there
-    unpack_voxel(cur.x, w.v);
-    w.tcur = __uint_as_float(cur.y);
-    w.fresh = true;
-    bool have = march<false>(a, r, w, cn, mk) && step_voxel(a, r, w) && march<false>(a, r, w, cn, mk);
-    while (have) {
-        if (shade_voxel<false, kForm, Cfg>(a, r, w, sh, cn, lane)) return;
-        if (!step_voxel(a, r, w)) return;
-        have = march<false>(a, r, w, cn, mk);
+    if (!(q.y >> 31)) return true;
+    // the walk stopped at the limit: the ray's state goes to its walk slot (whose
+    // entries are all read) and the ray to the resume list
+    if (gl == 0) {
+        uint32_t *slot = reinterpret_cast<uint32_t *>(a.walk + (int64_t)i * K);
+        const uint32_t vals[8] = {cur.x, cur.y, __float_as_uint(sh.col.x), __float_as_uint(sh.col.y),
+                                  __float_as_uint(sh.col.z), __float_as_uint(sh.T), (uint32_t)sh.first,
+                                  __float_as_uint(sh.first_t)};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) slot[k] = vals[k];
+        a.cont[atomicAdd(&a.st->n_cont, 1u)] = i;
     }
+    return false;
 }
 
 // kWalked: the walk phase has run (plain launches); the statistics variant
@@ -986,8 +1014,8 @@ __device__ __forceinline__ void b_trace_shade(TraceArgs a, unsigned bid_, unsign
             const uint4 q = a.queue[i];
             const float3 D = primary_dir(a.p, (int)(q.x % (uint32_t)a.p.W), (int)(q.x / (uint32_t)a.p.W));
             const Ray r = make_ray(a.p, D);
-            shade_walked<kForm, Cfg>(a, r, q, i, K, sh, cn, lane, mk);
-            if ((lane & (kGroup - 1)) == 0) write_pixel(a, (int64_t)q.x, sh);
+            if (shade_walked<kForm, Cfg>(a, r, q, i, K, sh, cn, lane) && (lane & (kGroup - 1)) == 0)
+                write_pixel(a, (int64_t)q.x, sh);
         } else if (!kWalked && i < n) {
             const uint4 q = a.queue[i];
             const int px = (int)(q.x % (uint32_t)a.p.W), py = (int)(q.x / (uint32_t)a.p.W);
@@ -1015,6 +1043,52 @@ __device__ __forceinline__ void b_trace_shade(TraceArgs a, unsigned bid_, unsign
         }
         flush_counters<kStats>(a, cn, sh.first >= 0 && (lane & (kGroup - 1)) == 0, lane, kGroup);
     }
+}
+
+// Resume launch, one kGroup-lane group per ray of the resume list: the
+// saved state, then the walk from the last walked voxel on, as the shade
+// phase does without a walk phase.
+template <int kForm, class Cfg = DefaultShade>
+__device__ __forceinline__ void b_trace_resume(TraceArgs a, unsigned bid_, unsigned nblk_, unsigned unit_threads,
+                                               unsigned unit_tid) {
+    constexpr int kGroup = Cfg::kGroup;
+    const int lane = threadIdx.x & 63;
+    const unsigned n = a.st->n_cont;
+    const int64_t K = walk_capacity(a.walk_entries, a.st->n_queue);
+    const unsigned ngroups = nblk_ * (unit_threads / kGroup);
+    __shared__ uint64_t s_mask[8 * kMaxShadeGroups];
+    MaskLds mk{s_mask + threadIdx.x / kGroup, (int)(blockDim.x / kGroup)};
+    for (unsigned k = bid_ * (unit_threads / kGroup) + unit_tid / kGroup; k < n; k += ngroups) {
+        const unsigned i = a.cont[k];
+        const uint4 q = a.queue[i];
+        const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.walk + (int64_t)i * K);
+        Shade sh;
+        sh.col = make_float3(__uint_as_float(slot[2]), __uint_as_float(slot[3]), __uint_as_float(slot[4]));
+        sh.T = __uint_as_float(slot[5]);
+        sh.first = (int)slot[6];
+        sh.first_t = __uint_as_float(slot[7]);
+        const float3 D = primary_dir(a.p, (int)(q.x % (uint32_t)a.p.W), (int)(q.x / (uint32_t)a.p.W));
+        const Ray r = make_ray(a.p, D);
+        Walk w;
+        unpack_voxel(slot[0], w.v);
+        w.tcur = __uint_as_float(slot[1]);
+        w.tout = __uint_as_float(q.w);
+        w.fresh = true;
+        Counters cn;
+        // re-enter the last walked voxel, step past it and go on
+        bool have = march<false>(a, r, w, cn, mk) && step_voxel(a, r, w) && march<false>(a, r, w, cn, mk);
+        while (have) {
+            if (shade_voxel<false, kForm, Cfg>(a, r, w, sh, cn, lane)) break;
+            if (!step_voxel(a, r, w)) break;
+            have = march<false>(a, r, w, cn, mk);
+        }
+        if ((lane & (kGroup - 1)) == 0) write_pixel(a, (int64_t)q.x, sh);
+    }
+}
+
+template <int kForm>
+__global__ void __launch_bounds__(64) k_trace_resume(TraceArgs a) {
+    b_trace_resume<kForm>(a, blockIdx.x, gridDim.x, blockDim.x, threadIdx.x);
 }
 
 __device__ __forceinline__ void b_debug_rays(TraceParams p, const int64_t *__restrict__ pix, int64_t n, float *__restrict__ dirs, unsigned bid_, unsigned nblk_) {
@@ -1113,6 +1187,7 @@ static TraceArgs trace_args(vrt_ctx *c, const TraceParams &p, const vrt_image *i
     a.capacity = c->desc.max_fragments;
     a.queue = c->a.queue;
     a.walk = c->a.walk;
+    a.cont = c->a.cont;
     a.walk_entries = c->walk_entries;
     a.rgba = img->rgba;
     a.depth = img->depth;
@@ -1143,6 +1218,10 @@ static unsigned walk_grid(const TraceParams &p) {
     return (unsigned)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
 }
 
+// Resume launch: rays past the walk limit are rare (they need more than
+// kWalkPerPixel * max_pixels / n_queue list voxels).
+constexpr unsigned kResumeBlocks = 256;
+
 static unsigned skip_grid(const vrt_ctx *c) {
     const int64_t b = ((int64_t)(c->dims[0] / 8) * (c->dims[1] / 8) * (c->dims[2] / 8) + 255) / 256;
     return (unsigned)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
@@ -1171,13 +1250,16 @@ hipError_t launch_trace(vrt_ctx *c, const TraceParams &p, const vrt_image *img, 
     TraceArgs a = trace_args(c, p, img);
     const vrt_tune &t = c->tune[p.mode == VRT_TRACE_OPAQUE ? 0 : 1];
     VRT_LAUNCH(c, "k_trace_begin", st, k_trace_begin<<<1, 64, 0, st>>>(a.st));
-    VRT_LAUNCH(c, "k_trace_march", st, k_trace_march<false><<<march_grid(p, t.march_threads), t.march_threads, 0, st>>>(a));
     VRT_LAUNCH(c, "k_brick_skip", st, k_brick_skip<<<skip_grid(c), 256, 0, st>>>(a));
+    VRT_LAUNCH(c, "k_trace_march", st, k_trace_march<false><<<march_grid(p, t.march_threads), t.march_threads, 0, st>>>(a));
     VRT_LAUNCH(c, "k_trace_walk", st, k_trace_walk<<<walk_grid(p), 256, 0, st>>>(a));
-    if (c->desc.form == VRT_FORM_FP16)
+    if (c->desc.form == VRT_FORM_FP16) {
         VRT_LAUNCH(c, "k_trace_shade", st, (launch_shade<false, VRT_FORM_FP16>(t, a, st)));
-    else
+        VRT_LAUNCH(c, "k_trace_resume", st, k_trace_resume<VRT_FORM_FP16><<<kResumeBlocks, 64, 0, st>>>(a));
+    } else {
         VRT_LAUNCH(c, "k_trace_shade", st, (launch_shade<false, VRT_FORM_PLAIN>(t, a, st)));
+        VRT_LAUNCH(c, "k_trace_resume", st, k_trace_resume<VRT_FORM_PLAIN><<<kResumeBlocks, 64, 0, st>>>(a));
+    }
     return hipGetLastError();
 }
 
@@ -1187,6 +1269,7 @@ hipError_t launch_trace_stats(vrt_ctx *c, const TraceParams &p, const vrt_image 
     TraceArgs a = trace_args(c, p, img);
     k_stat_clear<<<1024, 256, 0, st>>>(c->a.brick_list, c->a.status, c->n_vertices, a.stat_vox, a.stat_seg, a.stat_acc);
     k_trace_begin<<<1, 64, 0, st>>>(a.st);
+    k_brick_skip<<<skip_grid(c), 256, 0, st>>>(a);
     k_trace_march<true><<<march_grid(p, 256), 256, 0, st>>>(a);
     if (c->desc.form == VRT_FORM_FP16) k_trace_shade<true, VRT_FORM_FP16, DefaultShade, false><<<16384, 64, 0, st>>>(a);
     else k_trace_shade<true, VRT_FORM_PLAIN, DefaultShade, false><<<16384, 64, 0, st>>>(a);
