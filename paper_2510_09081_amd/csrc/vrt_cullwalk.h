@@ -159,8 +159,34 @@ __host__ __device__ inline void walk_begin(CullWalk &w, const int *G, int x, int
     if (!none) walk_enter(w, cells);
 }
 
-// One step of the walk: a voxel, or an empty cell crossed in one jump; then
-// the blocking test of the voxel entered.  Sets done when the walk ends.
+// q = floor(num / den) for 0 <= num < 2^sh den, 0 <= sh <= 6 (den > 0,
+// 64 den < 2^63), from a binary32 estimate corrected by one multiply and
+// compare each way: the estimate's relative error is below 2^-21, so with
+// q < 64 it is off by at most one.  Also returns q * den in `qd`.
+__host__ __device__ inline int walk_small_quot_est(long long num, long long den, long long &qd) {
+    const float fn = (float)(unsigned)(num >> 32) * 4294967296.0f + (float)(unsigned)num;
+    const float fd = (float)(unsigned)(den >> 32) * 4294967296.0f + (float)(unsigned)den;
+    int q = (int)(fn / fd);
+    q = q < 0 ? 0 : (q > 64 ? 64 : q);
+    long long p = den * q;
+    if (p > num) {
+        --q;
+        p -= den;
+    } else if (p + den <= num) {
+        ++q;
+        p += den;
+    }
+    qd = p;
+    return q;
+}
+
+// One step of the walk: the cell of S^3 voxels holding the current voxel is
+// crossed (S = 1 for a voxel, larger for a cell without a blocker), then the
+// blocking test of the voxel entered.  A voxel is the cell with S = 1: every
+// axis whose next crossing ties the smallest steps once, the others not at
+// all, as in the voxel walk; one code path serves both, so the lanes of a
+// wave that step voxels and those that jump cells run it together.  Sets done
+// when the walk ends.
 template <class Cells>
 __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &cells) {
     constexpr long long kNever = 0x7FFFFFFFFFFFFFFFll;
@@ -170,65 +196,43 @@ __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &c
     } else if (!((w.m2 >> walk_cell2(w.cur[0], w.cur[1], w.cur[2])) & 1ull)) {
         sh = (w.m2 & walk_cell4_mask(w.cur[0], w.cur[1], w.cur[2])) ? 1 : 2;
     }
-    if (sh == 0) {
-        long long tm = w.T[0] < w.T[1] ? w.T[0] : w.T[1];
-        tm = w.T[2] < tm ? w.T[2] : tm;
-        if (!(tm < w.P)) {  // eye reached
-            w.done = true;
-            return;
-        }
-        bool out = false;
+    long long Tc[3];
+    const int s1 = (1 << sh) - 1;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (w.T[a] == tm) {
-                w.cur[a] += w.step[a];
-                w.T[a] += w.dT[a];
-                if (w.step[a] > 0 ? w.cur[a] > w.lim[a] : w.cur[a] < w.lim[a]) out = true;
-            }
-        }
-        if (out) {
-            w.done = true;
-            return;
-        }
-    } else {
-        long long Tc[3];
-        const int s1 = (1 << sh) - 1;
+    for (int a = 0; a < 3; ++a) {
+        Tc[a] = kNever;
+        if (w.step[a] == 0) continue;
+        const int cs = w.cur[a] & ~s1;  // cur >= 0
+        const unsigned k = (unsigned)(w.step[a] > 0 ? cs + s1 - w.cur[a] : w.cur[a] - cs);
+        Tc[a] = w.T[a] + (long long)((unsigned long long)w.dT[a] * k);
+    }
+    long long te = Tc[0] < Tc[1] ? Tc[0] : Tc[1];
+    te = Tc[2] < te ? Tc[2] : te;
+    if (!(te < w.P)) {  // the eye lies inside this cell (or is reached at its exit)
+        w.done = true;
+        return;
+    }
+    bool out = false;
+    int na[3];
+    long long nd[3];  // na * dT
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            Tc[a] = kNever;
-            if (w.step[a] == 0) continue;
-            const int cs = w.cur[a] & ~s1;  // cur >= 0
-            const unsigned k = (unsigned)(w.step[a] > 0 ? cs + s1 - w.cur[a] : w.cur[a] - cs);
-            Tc[a] = w.T[a] + (long long)((unsigned long long)w.dT[a] * k);
-        }
-        long long te = Tc[0] < Tc[1] ? Tc[0] : Tc[1];
-        te = Tc[2] < te ? Tc[2] : te;
-        if (!(te < w.P)) {  // the eye lies inside this empty cell
-            w.done = true;
-            return;
-        }
-        bool out = false;
-        int na[3];
-        long long nd[3];  // na * dT
+    for (int a = 0; a < 3; ++a) {
+        na[a] = 0;
+        nd[a] = 0;
+        if (w.step[a] == 0 || te < w.T[a]) continue;
+        na[a] = walk_small_quot_est(te - w.T[a], w.dT[a], nd[a]) + 1;
+        nd[a] += w.dT[a];
+        const int nx = w.cur[a] + w.step[a] * na[a];
+        if (w.step[a] > 0 ? nx > w.lim[a] : nx < w.lim[a]) out = true;
+    }
+    if (out) {
+        w.done = true;
+        return;
+    }
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            na[a] = 0;
-            nd[a] = 0;
-            if (w.step[a] == 0 || te < w.T[a]) continue;
-            na[a] = walk_small_quot(te - w.T[a], w.dT[a], sh, nd[a]) + 1;
-            nd[a] += w.dT[a];
-            const int nx = w.cur[a] + w.step[a] * na[a];
-            if (w.step[a] > 0 ? nx > w.lim[a] : nx < w.lim[a]) out = true;
-        }
-        if (out) {
-            w.done = true;
-            return;
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            w.cur[a] += w.step[a] * na[a];
-            w.T[a] += nd[a];
-        }
+    for (int a = 0; a < 3; ++a) {
+        w.cur[a] += w.step[a] * na[a];
+        w.T[a] += nd[a];
     }
     if (walk_enter(w, cells) && cells.blocking(w.cur[0], w.cur[1], w.cur[2]) && ++w.n >= limit) w.done = true;
 }
