@@ -6,31 +6,6 @@
 
 namespace vrt {
 
-// One bit of a long division: q gets bit s if (q + 2^s) den <= num.
-__host__ __device__ inline void walk_quot_bit(int s, long long num, long long den, long long &acc, int &q) {
-    const long long t = acc + (den << s);
-    if (t <= num) {
-        acc = t;
-        q |= 1 << s;
-    }
-}
-
-// q = floor(num / den) for 0 <= num < 2^sh den, 1 <= sh <= 6 (den > 0,
-// 64 den < 2^63), bit by bit from the top: additions and comparisons only,
-// sh bits.  Also returns q * den in `qd`.
-__host__ __device__ inline int walk_small_quot(long long num, long long den, int sh, long long &qd) {
-    int q = 0;
-    long long acc = 0;
-    if (sh > 5) walk_quot_bit(5, num, den, acc, q);
-    if (sh > 4) walk_quot_bit(4, num, den, acc, q);
-    if (sh > 3) walk_quot_bit(3, num, den, acc, q);
-    if (sh > 2) walk_quot_bit(2, num, den, acc, q);
-    if (sh > 1) walk_quot_bit(1, num, den, acc, q);
-    walk_quot_bit(0, num, den, acc, q);
-    qd = acc;
-    return q;
-}
-
 // Within a brick: index of the 2^3 cell holding voxel (x, y, z), and the mask
 // of the eight 2^3 cells of its 4^3 cell, in a brick's 64-bit mask of
 // 2^3 cells (bit 16 Z + 4 Y + X for cell (X, Y, Z), 0 <= X, Y, Z < 4).
@@ -82,6 +57,7 @@ __host__ __device__ inline uint64_t walk_cell4_mask(int x, int y, int z) {
 struct CullWalk {
     int cur[3], step[3], lim[3];
     long long T[3], dT[3], P;
+    float rdT[3];  // 1 / dT in binary32 (0 on a still axis): the estimate of a jump's crossing counts
     uint64_t m2;  // sub_mask of the brick with key k2
     int k2;       // packed brick coordinates of m2, or -1
     int n;        // blocking voxels met so far
@@ -139,6 +115,7 @@ __host__ __device__ inline void walk_begin(CullWalk &w, const int *G, int x, int
             if (b != a && w.step[b] != 0) L *= adel[b];
         w.T[a] = w.step[a] != 0 ? (Q / 2) * L : kNever;
         w.dT[a] = w.step[a] != 0 ? Q * L : kNever;
+        w.rdT[a] = w.step[a] != 0 ? 1.0f / (float)(Q * L) : 0.0f;
         if (w.step[a] != 0 && (double)adel[a] * (double)L < 9.0e18) w.P = adel[a] * L;
     }
     // The walk is monotone on every axis, so it can stop as soon as it leaves
@@ -159,23 +136,22 @@ __host__ __device__ inline void walk_begin(CullWalk &w, const int *G, int x, int
     if (!none) walk_enter(w, cells);
 }
 
-// q = floor(num / den) for 0 <= num < 2^sh den, 0 <= sh <= 6 (den > 0,
-// 64 den < 2^63), from a binary32 estimate corrected by one multiply and
-// compare each way: the estimate's relative error is below 2^-21, so with
-// q < 64 it is off by at most one.  Also returns q * den in `qd`.
-__host__ __device__ inline int walk_small_quot_est(long long num, long long den, long long &qd) {
-    const float fn = (float)(unsigned)(num >> 32) * 4294967296.0f + (float)(unsigned)num;
-    const float fd = (float)(unsigned)(den >> 32) * 4294967296.0f + (float)(unsigned)den;
-    int q = (int)(fn / fd);
-    q = q < 0 ? 0 : (q > 64 ? 64 : q);
+// q = floor(num / den) for 0 <= num < 64 den (den > 0, 65 den < 2^63), from
+// the binary32 estimate num * rden (rden = 1 / den rounded) corrected by one
+// multiply and compare each way: the estimate's relative error is below
+// 2^-20, so with q < 64 it is off by at most one.  Also returns q * den in `qd`.
+__host__ __device__ inline int walk_small_quot_est(long long num, long long den, float rden, long long &qd) {
+    // num in binary32 from its two 32-bit halves (relative error below 2^-22)
+    const float fn = fmaf((float)(uint32_t)((unsigned long long)num >> 32), 4294967296.0f, (float)(uint32_t)num);
+    int q = (int)(fn * rden);
+    q = q < 0 ? 0 : (q > 63 ? 63 : q);
     long long p = den * q;
-    if (p > num) {
-        --q;
-        p -= den;
-    } else if (p + den <= num) {
-        ++q;
-        p += den;
-    }
+    const bool over = p > num;
+    q -= over ? 1 : 0;
+    p -= over ? den : 0;
+    const bool under = p + den <= num;
+    q += under ? 1 : 0;
+    p += under ? den : 0;
     qd = p;
     return q;
 }
@@ -217,13 +193,15 @@ __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &c
     long long nd[3];  // na * dT
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        na[a] = 0;
-        nd[a] = 0;
-        if (w.step[a] == 0 || te < w.T[a]) continue;
-        na[a] = walk_small_quot_est(te - w.T[a], w.dT[a], nd[a]) + 1;
-        nd[a] += w.dT[a];
-        const int nx = w.cur[a] + w.step[a] * na[a];
-        if (w.step[a] > 0 ? nx > w.lim[a] : nx < w.lim[a]) out = true;
+        // an axis crosses when te reaches its next crossing (a still axis never: its T is kNever > te)
+        const long long num = te - w.T[a];
+        const bool moves = num >= 0;
+        long long qd;
+        const int q = walk_small_quot_est(moves ? num : 0, moves ? w.dT[a] : 1, w.rdT[a], qd);
+        na[a] = moves ? q + 1 : 0;
+        nd[a] = moves ? qd + w.dT[a] : 0;
+        // past the limit on this axis: step (cur + step na) > step lim
+        out |= w.step[a] * (w.cur[a] + w.step[a] * na[a]) > w.step[a] * w.lim[a];
     }
     if (out) {
         w.done = true;
