@@ -529,6 +529,14 @@ __device__ __forceinline__ float3 hit_colour(const TraceArgs &a, uint32_t id, in
     return seg_colour(g.pa, g.pb);
 }
 
+// hit_colour with the opacity in w.
+template <int kForm>
+__device__ __forceinline__ float4 hit_rgba(const TraceArgs &a, uint32_t id, int cx, int cy, int cz) {
+    float alpha;
+    const float3 c = hit_colour<kForm>(a, id, cx, cy, cz, alpha);
+    return make_float4(c.x, c.y, c.z, alpha);
+}
+
 // Calls f(id, seg) for the entries of the current voxel's list that belong to
 // lane `gl` of a kGroup-lane group (entries gl, gl + kGroup, ...).  The
 // records of kBatch entries are fetched before any of them is tested, so each
@@ -641,6 +649,7 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
     // otherwise it rescans above the last composited key.
     unsigned long long thr = 0ull;
     bool have_thr = false;
+    const float lit = a.p.lit ? a.p.lit[w.vi] : 1.0f;  // voxel-space shading of this voxel (Section 3.4)
     for (;;) {
         unsigned long long kk[kLaneKeys];
 #pragma unroll
@@ -663,6 +672,11 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
         });
         const bool dropped = nacc > kLaneKeys;
         bool rescan = false;
+        // each lane holds the colour and opacity of its smallest key, read as
+        // soon as that key is at the head, so a pop takes them from the owner
+        // lane instead of reading them after the group has found the minimum
+        float4 hc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (kk[0] != kNoKey) hc = hit_rgba<kForm>(a, (uint32_t)kk[0], cx, cy, cz);
         for (;;) {
             if (group_any<kGroup>(dropped && kk[0] == kNoKey, lane)) {
                 rescan = true;
@@ -672,17 +686,16 @@ __device__ __forceinline__ bool shade_voxel(const TraceArgs &a, const Ray &r, co
             const unsigned long long m = group_min<kGroup>(kk[0]);
             // keys are unique (one per segment), so exactly one lane holds m: it pops, and its colour is used
             const bool own = kk[0] == m;
+            const int src = (lane & ~(kGroup - 1)) + __ffsll((long long)group_ballot<kGroup>(own, lane)) - 1;
+            float3 c = make_float3(__shfl(hc.x, src, 64), __shfl(hc.y, src, 64), __shfl(hc.z, src, 64));
+            const float alpha = __shfl(hc.w, src, 64);
             if (own) {
 #pragma unroll
                 for (int j = 0; j + 1 < kLaneKeys; ++j) kk[j] = kk[j + 1];
                 kk[kLaneKeys - 1] = kNoKey;
+                if (kk[0] != kNoKey) hc = hit_rgba<kForm>(a, (uint32_t)kk[0], cx, cy, cz);
             }
-            float alpha;
-            float3 c = hit_colour<kForm>(a, (uint32_t)m, cx, cy, cz, alpha);
-            if (a.p.lit) {
-                const float l = a.p.lit[w.vi];
-                c = make_float3(c.x * l, c.y * l, c.z * l);
-            }
+            c = make_float3(c.x * lit, c.y * lit, c.z * lit);
             const uint32_t id = (uint32_t)m;
             if (sh.first < 0) {
                 sh.first = (int)id;
