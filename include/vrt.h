@@ -248,7 +248,7 @@ vrt_status vrt_shade(vrt_ctx *ctx, const vrt_shading *shading, void *stream);
  * vertices; directions are a fixed binary32 function of the camera. */
 vrt_status vrt_trace(vrt_ctx *ctx, const vrt_camera *cam, const vrt_image *out, void *stream);
 
-/* Per-frame graph (spec batching pattern for dynamic line sets): captures
+/* Per-frame graph (the replay pattern for dynamic line sets): captures
  * one frame -- vrt_voxelize, then for each pass i vrt_cull(views[i]) and
  * vrt_trace(cams[i], imgs[i]) -- into a HIP graph on a private capture stream.
  * Each vrt_graph_launch replays the whole frame on `stream` with no host work;
