@@ -116,7 +116,8 @@ __host__ __device__ inline void walk_begin(CullWalk &w, const int *G, int x, int
         w.T[a] = w.step[a] != 0 ? (Q / 2) * L : kNever;
         w.dT[a] = w.step[a] != 0 ? Q * L : kNever;
         w.rdT[a] = w.step[a] != 0 ? 1.0f / (float)(Q * L) : 0.0f;
-        if (w.step[a] != 0 && (double)adel[a] * (double)L < 9.0e18) w.P = adel[a] * L;
+        // the product fits in int64 when its binary32 estimate (relative error below 2^-22) is below 9e18
+        if (w.step[a] != 0 && (float)adel[a] * (float)L < 9.0e18f) w.P = adel[a] * L;
     }
     // The walk is monotone on every axis, so it can stop as soon as it leaves
     // the grid or the box of blocking voxels: lim[a] is the last coordinate

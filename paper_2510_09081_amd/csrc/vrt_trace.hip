@@ -805,18 +805,27 @@ __device__ __forceinline__ int walk_step(const TraceArgs &a, const Ray &r, Walk 
     return ((mk.slice(w.v[2]) >> (local_of(xl, yl, zl) & 63)) & 1ull) ? 2 : 1;
 }
 
+// Steps of the march phase: a ray that has not reached a list voxel after
+// them is queued where it stands and the walk phase goes on from there, so a
+// few long marches do not hold the march launch (the walk phase records list
+// voxels wherever it starts; a ray that meets none is written as a miss).
+constexpr int kMarchSteps = 64;
+
 // Advances from the current voxel (included) to the first visible voxel with
-// a list in walk-phase steps; false if none.  Leaves its list descriptor unread.
+// a list in walk-phase steps: true when it is there or after kMarchSteps
+// steps (the ray is queued either way), false when the ray meets none.
+// Leaves the list descriptor unread.
 template <bool kStats>
 __device__ __forceinline__ bool first_list_voxel(const TraceArgs &a, const Ray &r, Walk &w, Counters &cn, MaskRegs &mk) {
-    const int max_iter = march_limit(a);
+    const int limit = march_limit(a);
+    const int max_iter = limit < kMarchSteps ? limit : kMarchSteps;
     for (int it = 0; it < max_iter; ++it) {
         const int st = walk_step<kStats>(a, r, w, mk, cn);
         if (st < 0) return false;
         if (st == 2) return true;
         if (st == 1 && !step_voxel(a, r, w)) return false;
     }
-    return false;
+    return max_iter < limit;
 }
 
 // Clears the ray queue and combines the stripes of the visible-brick box.
@@ -1004,16 +1013,32 @@ __device__ __forceinline__ bool shade_walked(const TraceArgs &a, const Ray &r, c
     return false;
 }
 
+// Order of the shade phase's single-wave workgroups over the rays.  The
+// workgroups of a launch go to the eight XCDs in turn (workgroup b to XCD
+// b mod 8) and each XCD has an L2 of its own, so consecutive workgroups would
+// spread neighbouring rays, which test the same segments, over all eight L2s.
+// Instead the workgroups of one XCD take kXcdChunk consecutive waves' worth of
+// rays at a time, the XCDs' chunks interleaved (chunk c of XCD x is the
+// (8c + x)-th), so each L2 sees neighbouring rays and the XCDs still share
+// every part of the image.  Identity when the count does not split evenly.
+constexpr unsigned kXcdChunk = 64;
+__device__ __forceinline__ unsigned xcd_wave_order(unsigned b, unsigned nb) {
+    if (nb % (8u * kXcdChunk) != 0u) return b;
+    const unsigned x = b % 8u, j = b / 8u;
+    return ((j / kXcdChunk) * 8u + x) * kXcdChunk + j % kXcdChunk;
+}
+
 // kWalked: the walk phase has run (plain launches); the statistics variant
-// and the batched form walk in this phase.
-template <bool kStats, int kForm, class Cfg = DefaultShade, bool kWalked = false>
+// and the batched form walk in this phase.  kXcd: bid_ is the hardware
+// workgroup of a single-wave launch (rays taken in xcd_wave_order).
+template <bool kStats, int kForm, class Cfg = DefaultShade, bool kWalked = false, bool kXcd = false>
 __device__ __forceinline__ void b_trace_shade(TraceArgs a, unsigned bid_, unsigned nblk_, unsigned unit_threads,
                                               unsigned unit_tid) {
     constexpr int kGroup = Cfg::kGroup;
     const int lane = threadIdx.x & 63;
     const unsigned n = a.st->n_queue;
     const unsigned ngroups = nblk_ * (unit_threads / kGroup);
-    const unsigned grp = bid_ * (unit_threads / kGroup) + unit_tid / kGroup;
+    const unsigned grp = (kXcd ? xcd_wave_order(bid_, nblk_) : bid_) * (unit_threads / kGroup) + unit_tid / kGroup;
     __shared__ uint64_t s_mask[8 * kMaxShadeGroups];  // the list mask of each group's brick
     MaskLds mk{s_mask + threadIdx.x / kGroup, (int)(blockDim.x / kGroup)};
     // every group runs the same number of rounds so counters can be reduced per wave
@@ -1119,7 +1144,7 @@ __device__ __forceinline__ void b_debug_rays(TraceParams p, const int64_t *__res
 // memory latency, and the fourth wave hides more of it than the few spilled
 // registers cost.
 template <bool kStats, int kForm, class Cfg, bool kWalked>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm, Cfg, kWalked>(a, blockIdx.x, gridDim.x, blockDim.x, threadIdx.x); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm, Cfg, kWalked, true>(a, blockIdx.x, gridDim.x, blockDim.x, threadIdx.x); }
 
 __global__ void k_debug_rays(TraceParams p, const int64_t *__restrict__ pix, int64_t n, float *__restrict__ dirs) { b_debug_rays(p, pix, n, dirs, blockIdx.x, gridDim.x); }
 
