@@ -86,6 +86,22 @@ constexpr int kBinChunk = 1024;
 // counters do not queue behind each other.
 constexpr int kBinStride = 32;
 
+// Workgroup order for launches whose neighbouring work items read the same
+// data.  The workgroups of a launch go to the eight XCDs in turn (workgroup b
+// to XCD b mod 8) and each XCD has an L2 of its own, so consecutive items
+// would be spread over all eight L2s.  A kernel that takes item
+// xcd_order(b, nb) (+ multiples of nb) in workgroup b gives each XCD runs of
+// kXcdChunk consecutive items, the XCDs' runs interleaved (run c of XCD x is
+// the (8c + x)-th), so each L2 sees neighbouring items and every XCD still
+// takes a share of every part of the item list.  Identity when nb does not
+// split evenly.
+constexpr unsigned kXcdChunk = 64;
+__device__ __forceinline__ unsigned xcd_order(unsigned b, unsigned nb) {
+    if (nb % (8u * kXcdChunk) != 0u) return b;
+    const unsigned x = b % 8u, j = b / 8u;
+    return ((j / kXcdChunk) * 8u + x) * kXcdChunk + j % kXcdChunk;
+}
+
 // Index of the k-th item of a chunk in the order its workgroup reads it:
 // within every group of 64, lane L takes entry 8 (L % 8) + L / 8, so that the
 // lanes of a wave take segments eight apart in the bin (consecutive segments

@@ -1013,32 +1013,16 @@ __device__ __forceinline__ bool shade_walked(const TraceArgs &a, const Ray &r, c
     return false;
 }
 
-// Order of the shade phase's single-wave workgroups over the rays.  The
-// workgroups of a launch go to the eight XCDs in turn (workgroup b to XCD
-// b mod 8) and each XCD has an L2 of its own, so consecutive workgroups would
-// spread neighbouring rays, which test the same segments, over all eight L2s.
-// Instead the workgroups of one XCD take kXcdChunk consecutive waves' worth of
-// rays at a time, the XCDs' chunks interleaved (chunk c of XCD x is the
-// (8c + x)-th), so each L2 sees neighbouring rays and the XCDs still share
-// every part of the image.  Identity when the count does not split evenly.
-constexpr unsigned kXcdChunk = 64;
-__device__ __forceinline__ unsigned xcd_wave_order(unsigned b, unsigned nb) {
-    if (nb % (8u * kXcdChunk) != 0u) return b;
-    const unsigned x = b % 8u, j = b / 8u;
-    return ((j / kXcdChunk) * 8u + x) * kXcdChunk + j % kXcdChunk;
-}
-
 // kWalked: the walk phase has run (plain launches); the statistics variant
-// and the batched form walk in this phase.  kXcd: bid_ is the hardware
-// workgroup of a single-wave launch (rays taken in xcd_wave_order).
-template <bool kStats, int kForm, class Cfg = DefaultShade, bool kWalked = false, bool kXcd = false>
+// and the batched form walk in this phase.
+template <bool kStats, int kForm, class Cfg = DefaultShade, bool kWalked = false>
 __device__ __forceinline__ void b_trace_shade(TraceArgs a, unsigned bid_, unsigned nblk_, unsigned unit_threads,
                                               unsigned unit_tid) {
     constexpr int kGroup = Cfg::kGroup;
     const int lane = threadIdx.x & 63;
     const unsigned n = a.st->n_queue;
     const unsigned ngroups = nblk_ * (unit_threads / kGroup);
-    const unsigned grp = (kXcd ? xcd_wave_order(bid_, nblk_) : bid_) * (unit_threads / kGroup) + unit_tid / kGroup;
+    const unsigned grp = bid_ * (unit_threads / kGroup) + unit_tid / kGroup;
     __shared__ uint64_t s_mask[8 * kMaxShadeGroups];  // the list mask of each group's brick
     MaskLds mk{s_mask + threadIdx.x / kGroup, (int)(blockDim.x / kGroup)};
     // every group runs the same number of rounds so counters can be reduced per wave
@@ -1140,11 +1124,11 @@ __device__ __forceinline__ void b_debug_rays(TraceParams p, const int64_t *__res
     dirs[3 * i + 2] = d.z;
 }
 
-// Four waves per SIMD (at most 128 registers): the shade phase is bound by
-// memory latency, and the fourth wave hides more of it than the few spilled
-// registers cost.
+// Four waves per SIMD (at most 128 registers): the fourth wave hides more
+// latency than the few spilled registers cost.  Rays are taken in xcd_order
+// (neighbouring rays test the same segments).
 template <bool kStats, int kForm, class Cfg, bool kWalked>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm, Cfg, kWalked, true>(a, blockIdx.x, gridDim.x, blockDim.x, threadIdx.x); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_trace_shade(TraceArgs a) { b_trace_shade<kStats, kForm, Cfg, kWalked>(a, xcd_order(blockIdx.x, gridDim.x), gridDim.x, blockDim.x, threadIdx.x); }
 
 __global__ void k_debug_rays(TraceParams p, const int64_t *__restrict__ pix, int64_t n, float *__restrict__ dirs) { b_debug_rays(p, pix, n, dirs, blockIdx.x, gridDim.x); }
 

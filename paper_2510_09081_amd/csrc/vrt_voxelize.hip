@@ -513,7 +513,6 @@ __global__ void __launch_bounds__(256) k_vox_count(CountArgs a, DevStatus *__res
 __global__ void __launch_bounds__(256) k_bin_count(BinArgs a, DevStatus *__restrict__ st) { b_bin_count(a, st, blockIdx.x, gridDim.x); }
 __global__ void __launch_bounds__(256) k_bin_alloc(BinArgs a, DevStatus *__restrict__ st) { b_bin_alloc(a, st, blockIdx.x, gridDim.x); }
 __global__ void __launch_bounds__(256) k_bin_fill(BinArgs a, DevStatus *__restrict__ st) { b_bin_fill(a, st, blockIdx.x, gridDim.x); }
-// six waves per SIMD (at most 80 registers, a few spilled): more bins in flight
 template <int kMode>
 __global__ void __launch_bounds__(256) k_brick_accum(AccumArgs a, DevStatus *__restrict__ st) { b_brick_accum<kMode>(a, st, blockIdx.x, gridDim.x); }
 __global__ void __launch_bounds__(256) k_vox_long(CountArgs a, const uint32_t *__restrict__ long_ids, DevStatus *__restrict__ st) { b_vox_long(a, long_ids, st, blockIdx.x, gridDim.x); }
