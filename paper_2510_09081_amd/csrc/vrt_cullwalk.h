@@ -91,6 +91,7 @@ __host__ __device__ inline void walk_begin(CullWalk &w, const int *G, int x, int
                                            const int *bbox, const Cells &cells) {
     constexpr long long Q = 256;
     constexpr long long kNever = 0x7FFFFFFFFFFFFFFFll;
+    constexpr long long kStill = kNever - 64;
     long long adel[3];
     w.cur[0] = x;
     w.cur[1] = y;
@@ -113,8 +114,10 @@ __host__ __device__ inline void walk_begin(CullWalk &w, const int *G, int x, int
 #pragma unroll
         for (int b = 0; b < 3; ++b)
             if (b != a && w.step[b] != 0) L *= adel[b];
-        w.T[a] = w.step[a] != 0 ? (Q / 2) * L : kNever;
-        w.dT[a] = w.step[a] != 0 ? Q * L : kNever;
+        // a still axis never crosses: its crossing time stays above every reachable one
+        // (kStill + dT * 63 < kNever) and its crossing count at zero
+        w.T[a] = w.step[a] != 0 ? (Q / 2) * L : kStill;
+        w.dT[a] = w.step[a] != 0 ? Q * L : 1;
         w.rdT[a] = w.step[a] != 0 ? 1.0f / (float)(Q * L) : 0.0f;
         // the product fits in int64 when its binary32 estimate (relative error below 2^-22) is below 9e18
         if (w.step[a] != 0 && (float)adel[a] * (float)L < 9.0e18f) w.P = adel[a] * L;
@@ -166,7 +169,6 @@ __host__ __device__ inline int walk_small_quot_est(long long num, long long den,
 // when the walk ends.
 template <class Cells>
 __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &cells) {
-    constexpr long long kNever = 0x7FFFFFFFFFFFFFFFll;
     int sh = 0;  // the cell crossed has S = 2^sh voxels a side
     if (w.be) {
         sh = cells.empty_shift(w.cur[0], w.cur[1], w.cur[2]);
@@ -176,11 +178,9 @@ __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &c
     long long Tc[3];
     const int s1 = (1 << sh) - 1;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        Tc[a] = kNever;
-        if (w.step[a] == 0) continue;
-        const int cs = w.cur[a] & ~s1;  // cur >= 0
-        const unsigned k = (unsigned)(w.step[a] > 0 ? cs + s1 - w.cur[a] : w.cur[a] - cs);
+    for (int a = 0; a < 3; ++a) {  // crossings to the cell's far face on axis a (cur >= 0)
+        const int low = w.cur[a] & s1;
+        const unsigned k = (unsigned)(w.step[a] > 0 ? s1 - low : low);
         Tc[a] = w.T[a] + (long long)((unsigned long long)w.dT[a] * k);
     }
     long long te = Tc[0] < Tc[1] ? Tc[0] : Tc[1];
@@ -194,11 +194,11 @@ __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &c
     long long nd[3];  // na * dT
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        // an axis crosses when te reaches its next crossing (a still axis never: its T is kNever > te)
+        // an axis crosses when te reaches its next crossing (a still axis never: its T is above every reachable te)
         const long long num = te - w.T[a];
         const bool moves = num >= 0;
         long long qd;
-        const int q = walk_small_quot_est(moves ? num : 0, moves ? w.dT[a] : 1, w.rdT[a], qd);
+        const int q = walk_small_quot_est(moves ? num : 0, w.dT[a], w.rdT[a], qd);
         na[a] = moves ? q + 1 : 0;
         nd[a] = moves ? qd + w.dT[a] : 0;
         // past the limit on this axis: step (cur + step na) > step lim
