@@ -59,10 +59,7 @@ struct CullCells {
         return !((brick_bits[b >> 5] >> (b & 31u)) & 1u);
     }
     __device__ uint64_t sub_mask(int x, int y, int z) const { return blk_bits[brick_of(x, y, z) * 16u + 8u]; }
-    __device__ bool blocking(int x, int y, int z) const {
-        const unsigned l = (unsigned)(((z & 7) << 6) | ((y & 7) << 3) | (x & 7));
-        return (blk_bits[brick_of(x, y, z) * 16u + (l >> 6)] >> (l & 63u)) & 1ull;
-    }
+    __device__ uint64_t slice_bits(int x, int y, int z) const { return blk_bits[brick_of(x, y, z) * 16u + (unsigned)(z & 7)]; }
 };
 
 // Bytes of the brick and cell flags when staged in LDS.

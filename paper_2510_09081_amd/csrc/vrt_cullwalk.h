@@ -51,7 +51,9 @@ __host__ __device__ inline uint64_t walk_cell4_mask(int x, int y, int z) {
 //                                 (only asked in empty bricks)
 //   uint64_t sub_mask(x, y, z) -- the 2^3 cells of that brick holding a blocker
 //                                 (only asked in non-empty bricks)
-//   bool blocking(x, y, z)     -- the voxel blocks (only asked in non-empty 2^3 cells)
+//   uint64_t slice_bits(x, y, z) -- the blocking voxels of the brick's z-slice holding
+//                                 voxel (x, y, z), bit 8 (y mod 8) + (x mod 8)
+//                                 (only asked in non-empty bricks)
 //
 // State of one culling walk between steps (everything in registers).
 struct CullWalk {
@@ -71,17 +73,22 @@ __host__ __device__ inline int walk_brick_key(int x, int y, int z) {
 }
 
 // The brick flag of the current voxel, the 2^3-cell mask of its brick when
-// that holds a blocker, and whether the current voxel's 2^3 cell does.
+// that holds a blocker, and whether the current voxel blocks.  In a brick
+// with a blocker the voxel's blocking bits (its z-slice of the brick) are
+// read together with the brick's mask when that is new, so the two reads
+// overlap instead of waiting one after the other.
 template <class Cells>
 __host__ __device__ inline bool walk_enter(CullWalk &w, const Cells &cells) {
     w.be = cells.brick_empty(w.cur[0], w.cur[1], w.cur[2]);
     if (w.be) return false;
+    const uint64_t slice = cells.slice_bits(w.cur[0], w.cur[1], w.cur[2]);
     const int key = walk_brick_key(w.cur[0], w.cur[1], w.cur[2]);
     if (key != w.k2) {
         w.m2 = cells.sub_mask(w.cur[0], w.cur[1], w.cur[2]);
         w.k2 = key;
     }
-    return (w.m2 >> walk_cell2(w.cur[0], w.cur[1], w.cur[2])) & 1ull;
+    const bool cell = (w.m2 >> walk_cell2(w.cur[0], w.cur[1], w.cur[2])) & 1ull;
+    return cell && ((slice >> (((w.cur[1] & 7) << 3) | (w.cur[0] & 7))) & 1ull);
 }
 
 // Sets up the walk from voxel (x, y, z); done at once when the eye is at the
@@ -213,7 +220,7 @@ __host__ __device__ inline void walk_step(CullWalk &w, int limit, const Cells &c
         w.cur[a] += w.step[a] * na[a];
         w.T[a] += nd[a];
     }
-    if (walk_enter(w, cells) && cells.blocking(w.cur[0], w.cur[1], w.cur[2]) && ++w.n >= limit) w.done = true;
+    if (walk_enter(w, cells) && ++w.n >= limit) w.done = true;
 }
 
 // The whole walk: the number of blocking voxels met, at most `limit`.

@@ -46,6 +46,15 @@ struct HostCells {
         if (!flag[4][idx(4, x, y, z)]) return 4;
         return 3;
     }
+    uint64_t slice_bits(int x, int y, int z) const {  // blocking voxels of the brick's z-slice, bit 8 y + x
+        uint64_t m = 0;
+        for (int Y = 0; Y < 8; ++Y)
+            for (int X = 0; X < 8; ++X) {
+                const int cx = (x & ~7) + X, cy = (y & ~7) + Y;
+                if (cx < G[0] && cy < G[1] && blocking(cx, cy, z)) m |= 1ull << (8 * Y + X);
+            }
+        return m;
+    }
     uint64_t sub_mask(int x, int y, int z) const {  // 2^3 cells of the brick, bit 16 Z + 4 Y + X
         uint64_t m = 0;
         for (int Z = 0; Z < 4; ++Z)
