@@ -562,9 +562,9 @@ __global__ void __launch_bounds__(512) k_sort_lists(const uint64_t *__restrict__
 }  // namespace
 
 // Blocks of the LDS-staged walk: each copies the flags once, then takes
-// occupied voxels grid-stride.  Twice as many blocks as fit at once, so a
-// compute unit whose blocks drew short walks starts another block while
-// others are still walking (1024 blocks: 12% slower on the benchmark frame).
+// occupied voxels grid-stride.  More blocks than fit at once, so a compute
+// unit whose blocks drew short walks starts another block while others are
+// still walking (1024 blocks: 12% slower on the benchmark frame, 4096: 2%).
 static constexpr unsigned kCullWalkBlocks = 2048;
 
 // Arguments of every culling and list kernel for one view of context c.
