@@ -313,21 +313,22 @@ __device__ __forceinline__ int64_t brick_index_of(int x, int y, int z, int nbx, 
 __device__ __forceinline__ int local_of(int x, int y, int z) { return ((z & 7) << 6) | ((y & 7) << 3) | (x & 7); }
 
 // floor(n / m) for 0 < m, |n| + m < 2^52 and |n / m| < 2^20 (voxel indices),
-// exact: n, m and every product q * m below are exact binary64 values, so an
-// estimate from the hardware reciprocal (off by less than one at these
-// quotients) is corrected with exact comparisons.
+// exact, with no binary64 arithmetic: the binary32 estimate from n, m and the
+// hardware reciprocal has a relative error below 2^-21, hence an absolute
+// error below one half at these quotients, and is corrected by one exact
+// 64-bit integer comparison each way (|q m| stays below |n| + 2m < 2^53).
 __device__ __forceinline__ long long floor_div(long long n, long long m) {
-    const double dn = (double)n, dm = (double)m;
-    double q = floor(dn * __builtin_amdgcn_rcp(dm));
-    if (q * dm > dn) q -= 1.0;
-    else if ((q + 1.0) * dm <= dn) q += 1.0;
-    return (long long)q;
+    long long q = (long long)floorf((float)n * __builtin_amdgcn_rcpf((float)m));
+    if (q * m > n) q -= 1;
+    else if ((q + 1) * m <= n) q += 1;
+    return q;
 }
 
-// smallest w >= 0 with w*w >= n
+// smallest w >= 0 with w*w >= n (n < 2^62), exact: a binary32 square root
+// estimate corrected by exact 64-bit integer comparisons
 __device__ __forceinline__ long long ceil_isqrt(long long n) {
     if (n <= 0) return 0;
-    long long w = (long long)sqrt((double)n);
+    long long w = (long long)__builtin_amdgcn_sqrtf((float)n);
     while (w * w < n) ++w;
     while (w > 0 && (w - 1) * (w - 1) >= n) --w;
     return w;

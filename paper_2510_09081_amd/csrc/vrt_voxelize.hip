@@ -97,7 +97,7 @@ __device__ __forceinline__ void b_ingest(IngestArgs a, VRec *__restrict__ out, D
     // same search in every lane: from the proportional guess, doubling steps
     // until the polyline is bracketed, then halving; each lane then scans
     // forward to its own
-    int64_t g = (int64_t)((double)i0 * (double)a.np / (double)a.nv);
+    int64_t g = (int64_t)((float)i0 * ((float)a.np / (float)a.nv));  // a guess only: the search corrects it
     g = g < 0 ? 0 : (g > a.np - 1 ? a.np - 1 : g);
     int64_t lo, hi;  // off[lo] <= i0 (or lo = 0), and hi = np or off[hi] > i0
     if ((int64_t)a.off[g] <= i0) {
