@@ -849,8 +849,9 @@ __global__ void k_trace_begin(DevStatus *st) { b_trace_begin(st, blockIdx.x, gri
 
 // Phase 1, one thread per pixel (a 64-lane wavefront covers an 8x8 tile):
 // primary ray, clip to the box of visible bricks, march through empty cells to
-// the first visible voxel with a list.  Rays that reach one are appended to the
-// queue (wave-aggregated); the others are written as misses.
+// the first visible voxel with a list (at most kMarchSteps steps).  Rays that
+// reach one, or are still marching after those steps, are appended to the
+// queue (wave-aggregated) where they stand; the others are written as misses.
 // Block tile of the march phase: 16 pixels wide, 8 rows per pair of wavefronts.
 __device__ __host__ inline int march_tile_rows(int threads) { return (threads / 128) * 8; }
 
@@ -910,11 +911,12 @@ __device__ __forceinline__ int64_t walk_capacity(int64_t entries, unsigned n) {
     return k < kWalkMax ? k : kWalkMax;
 }
 
-// Walk phase, one thread per queued ray: continues the march from the ray's
-// first list voxel and records every visible voxel with a list it passes, in
-// order, with its entry parameter (at most walk_capacity entries).  The ray's
-// queue entry then holds the count and whether the walk stopped at the limit
-// with list voxels left.  The walk needs no list data, so the shade phase's
+// Walk phase, one thread per queued ray: continues the march from where the
+// march phase left the ray (its first list voxel, or where its march steps
+// ran out) and records every visible voxel with a list it passes, in order,
+// with its entry parameter (at most walk_capacity entries).  The ray's queue
+// entry then holds the count and whether the walk stopped at the limit with
+// list voxels left.  The walk needs no list data, so the shade phase's
 // lanes find the voxels of a ray without walking them one after another.
 __device__ __forceinline__ void b_trace_walk(TraceArgs a, unsigned bid_, unsigned nblk_) {
     const unsigned n = a.st->n_queue;
