@@ -22,6 +22,10 @@ if ROOT not in sys.path:
 METRIC = "per-frame AS build ms + Mrays/s at 1080p, 5M segs; batched/FP16 vs plain"
 TUNE_CACHE = os.path.join(ROOT, "paper_2510_09081_amd", "tune_cache.json")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_bundles_5m_plain.md")
+SQ_SUMMARY = os.path.join(ROOT, "profiles", "sq_bundles_5m_plain.md")
+# Vector-ALU issue peak of MI355X: 256 compute units x 4 SIMDs, each issuing one wave64 instruction per
+# 4 cycles (64 lanes on 16-lane units) at 2.4 GHz = 614.4 G wave64 VALU instructions/s (39.3 T lane-ops/s).
+VALU_ISSUE_PEAK_G = 256 * 4 * 2.4 / 4
 
 
 def source_digest():
@@ -56,6 +60,25 @@ def measured_traffic(kernel, shapes):
         return None
     return {"bytes_per_launch": int(k["fetch_bytes"] + k["write_bytes"]), "fetch_bytes": int(k["fetch_bytes"]),
             "write_bytes": int(k["write_bytes"])}
+
+
+def measured_valu(kernel, shapes):
+    """Wave64 VALU instructions per launch of `kernel` from the committed SQ counter summary (SQ_INSTS_VALU,
+    averaged over the kernel's dispatches), or None when the summary is missing or was taken for other sources
+    or launch shapes."""
+    import re
+    try:
+        with open(SQ_SUMMARY) as f:
+            m = re.search(r"<!-- sq (\{.*\}) -->", f.read())
+    except OSError:
+        return None
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    k = d.get("kernels", {}).get(kernel)
+    if k is None or d.get("source_sha256") != source_digest() or d.get("shapes") != shapes:
+        return None
+    return float(k["valu_per_launch"])
 
 
 def calibrate_copy():
@@ -121,6 +144,16 @@ def frame_bytes(n, form="plain"):
         "trace_segment_records": sum(rs * n[tp]["distinct_segments"] for _, tp in passes),
     }
     return {k: int(v) for k, v in t.items()}
+
+
+def valu_issue(valu_per_launch, avg_ms):
+    """The kernel against the vector-ALU issue peak: counted VALU instructions per launch over the live average
+    launch time (the shade kernel issues instructions more than it waits on memory)."""
+    if valu_per_launch is None:
+        return None
+    ach = valu_per_launch / (avg_ms * 1e-3) / 1e9
+    return {"valu_per_launch": int(valu_per_launch), "achieved": round(ach, 2), "peak": VALU_ISSUE_PEAK_G,
+            "unit": "G wave64 VALU instructions/s", "frac": round(ach / VALU_ISSUE_PEAK_G, 4)}
 
 
 def memory_ceilings(torch, vrt):
@@ -674,6 +707,7 @@ def main():
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None if tr is None else tr["bytes_per_launch"],
                     "traffic_detail": tr, "bytes_per_launch": int(b),
+                    "valu_issue": valu_issue(measured_valu(dom, shapes), per_kernel[dom]["avg_ms"]),
                     "kernel_avg_ms": round(per_kernel[dom]["avg_ms"], 5),
                     "frame_bytes": b_alg, "frame_bytes_terms": fb,
                     "frame_achieved": round(b_alg / (frame_ms * 1e-3) / 1e9, 2),
