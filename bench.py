@@ -238,7 +238,8 @@ def bench_dynamic(torch, vrt, synth, warmup):
 
 def bench_batched(torch, vrt, synth, steps, warmup):
     """64 uneven line sets (1k-1M segments, 64^3-256^3 grids, 512x512 each, opaque, culled):
-    one persistent launch and one launch per phase against the plain calls set by set."""
+    one persistent launch, one launch per phase, and the split form (one cooperative launch up to the ray walk,
+    then one launch per shade phase) against the plain calls set by set."""
     ws = synth.batch_sets()
     items, capsl = [], []
     for w in ws:
@@ -257,7 +258,7 @@ def bench_batched(torch, vrt, synth, steps, warmup):
 
     def timed(suffix):
         for label, mode in (("persistent", vrt.BATCH_PERSISTENT), ("staged", vrt.BATCH_STAGED),
-                            ("sequential", vrt.BATCH_SEQUENTIAL)):
+                            ("split", vrt.BATCH_SPLIT), ("sequential", vrt.BATCH_SEQUENTIAL)):
             for _ in range(warmup):
                 b.run(items, mode)
             torch.cuda.synchronize()
@@ -277,9 +278,11 @@ def bench_batched(torch, vrt, synth, steps, warmup):
                                   sweeps=1)
         groups[r["best"]["shade_group"]] = groups.get(r["best"]["shade_group"], 0) + 1
     timed("_tuned")
-    same = all(torch.equal(a, c) and torch.equal(s, c) and torch.equal(a2, c) and torch.equal(s2, c)
-               for a, s, c, a2, s2 in zip(res["persistent_ids"], res["staged_ids"], res["sequential_ids"],
-                                          res["persistent_tuned_ids"], res["staged_tuned_ids"]))
+    same = all(torch.equal(a, c) and torch.equal(s, c) and torch.equal(x, c) and torch.equal(a2, c)
+               and torch.equal(s2, c) and torch.equal(x2, c)
+               for a, s, x, c, a2, s2, x2 in zip(res["persistent_ids"], res["staged_ids"], res["split_ids"],
+                                                 res["sequential_ids"], res["persistent_tuned_ids"],
+                                                 res["staged_tuned_ids"], res["split_tuned_ids"]))
     bad = [i for i in range(len(ws)) if b.context(i).frame_status()["device_status"] != 0]
     b.close()
     if bad:
@@ -289,15 +292,17 @@ def bench_batched(torch, vrt, synth, steps, warmup):
                         "64^3-256^3 grids, 512x512 each, opaque with opaque culling",
             "sets": len(ws), "segments": int(sum(w.lines.n_segments for w in ws)), "rays": rays,
             "persistent_ms": round(res["persistent"], 4), "staged_ms": round(res["staged"], 4),
-            "sequential_ms": round(res["sequential"], 4),
+            "split_ms": round(res["split"], 4), "sequential_ms": round(res["sequential"], 4),
             "persistent_speedup": round(res["sequential"] / res["persistent"], 4),
             "staged_speedup": round(res["sequential"] / res["staged"], 4),
+            "split_speedup": round(res["sequential"] / res["split"], 4),
             "tuned": {"persistent_ms": round(res["persistent_tuned"], 4), "staged_ms": round(res["staged_tuned"], 4),
-                      "sequential_ms": round(res["sequential_tuned"], 4),
+                      "split_ms": round(res["split_tuned"], 4), "sequential_ms": round(res["sequential_tuned"], 4),
                       "persistent_speedup_vs_untuned_sequential": round(res["sequential"] / res["persistent_tuned"], 4),
                       "shade_groups_chosen": {str(k): v for k, v in sorted(groups.items())}},
             "mrays_s_persistent": round(rays / (res["persistent"] * 1e-3) / 1e6, 2),
             "mrays_s_staged": round(rays / (res["staged"] * 1e-3) / 1e6, 2),
+            "mrays_s_split": round(rays / (res["split"] * 1e-3) / 1e6, 2),
             "first_ids_identical": bool(same)}
 
 

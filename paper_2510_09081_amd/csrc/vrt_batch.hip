@@ -216,16 +216,20 @@ __device__ __forceinline__ void batch_phase(int ph, const SetDesc *__restrict__ 
     }
 }
 
-// The persistent batch kernel: every phase, separated by grid barriers.  Its
-// register budget is the largest phase's (the tracer's, three group sizes
-// and two record forms in one function): about 240 registers, two waves per
-// SIMD; capping it at three or four waves spills hundreds of bytes per lane.
-__global__ void __launch_bounds__(kBatchThreads) k_batch(const SetDesc *__restrict__ sets, int nsets,
-                                                         unsigned *__restrict__ tickets) {
+// The persistent batch kernel: phases [0, kEnd), separated by grid barriers
+// (kEnd = kPhases: every phase).  As one function holding every phase it
+// would take about 240 registers (one 512-thread block per compute unit,
+// two waves per SIMD); it is capped at four waves per SIMD, which costs
+// about 430 bytes of spills per lane and is still 1.27x faster on the
+// 64-set batch.  kEnd = P_SHADE8 holds the phases up to the ray walk only
+// (the build-and-walk launch of the split form, about 260 bytes of spills).
+template <int kEnd>
+__global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_batch(const SetDesc *__restrict__ sets, int nsets, unsigned *__restrict__ tickets) {
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
     __shared__ unsigned pre[kMaxBatch * kParts + 1];
     __shared__ unsigned ticket;
-    for (int ph = 0; ph < kPhases; ++ph) {
+    for (int ph = 0; ph < kEnd; ++ph) {
         batch_phase(ph, sets, nsets, tickets, pre, ticket);
         grid.sync();
     }
@@ -292,6 +296,7 @@ struct vrt_batch {
     hipEvent_t copied = nullptr;
     bool copy_pending = false;
     unsigned grid = 0;                     // resident blocks of the persistent kernel
+    unsigned grid_split = 0;               // resident blocks of the split form's build-and-walk kernel
     unsigned phase_grid[vrt::kPhases] = {}; // resident blocks of each staged phase kernel
 };
 
@@ -323,9 +328,11 @@ vrt_status vrt_batch_create(const vrt_desc *descs, int32_t n, vrt_batch **out) {
     if (st == VRT_OK && e == hipSuccess) e = hipMalloc((void **)&b->d_tickets, sizeof(unsigned) * kPhases);
     if (st == VRT_OK && e == hipSuccess) e = hipMemset(b->d_tickets, 0, sizeof(unsigned) * kPhases);
     if (st == VRT_OK && e == hipSuccess) e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming);
-    int per_cu = 0, ncu = 0;
+    int per_cu = 0, per_cu_split = 0, ncu = 0;
     if (st == VRT_OK && e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kBatchThreads, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<kPhases>, kBatchThreads, 0);
+    if (st == VRT_OK && e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_split, k_batch<P_SHADE8>, kBatchThreads, 0);
     if (st == VRT_OK && e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device);
     for (int ph = 0; ph < kPhases && st == VRT_OK && e == hipSuccess; ++ph) {
         int pc = 0;
@@ -334,8 +341,9 @@ vrt_status vrt_batch_create(const vrt_desc *descs, int32_t n, vrt_batch **out) {
     }
     if (st == VRT_OK && e == hipSuccess) e = hipDeviceSynchronize();
     if (st == VRT_OK && e != hipSuccess) st = hip_fail(e);
-    if (st == VRT_OK && per_cu < 1) st = VRT_ERR_INVALID_ARG;
+    if (st == VRT_OK && (per_cu < 1 || per_cu_split < 1)) st = VRT_ERR_INVALID_ARG;
     b->grid = (unsigned)(per_cu * ncu);
+    b->grid_split = (unsigned)(per_cu_split * ncu);
     if (st != VRT_OK) {
         vrt_batch_destroy(b);
         return st;
@@ -347,7 +355,8 @@ vrt_status vrt_batch_create(const vrt_desc *descs, int32_t n, vrt_batch **out) {
 vrt_status vrt_batch_run(vrt_batch *b, const vrt_batch_item *items, int32_t n, int32_t mode, void *stream) {
     using namespace vrt;
     if (!b || !items || n != b->n) return VRT_ERR_INVALID_ARG;
-    if (mode != VRT_BATCH_PERSISTENT && mode != VRT_BATCH_SEQUENTIAL && mode != VRT_BATCH_STAGED)
+    if (mode != VRT_BATCH_PERSISTENT && mode != VRT_BATCH_SEQUENTIAL && mode != VRT_BATCH_STAGED &&
+        mode != VRT_BATCH_SPLIT)
         return VRT_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     VRT_HIP(hipSetDevice(b->device));
@@ -412,7 +421,15 @@ vrt_status vrt_batch_run(vrt_batch *b, const vrt_batch_item *items, int32_t n, i
             VRT_HIP(hipLaunchKernel(phase_kernel(ph), dim3(b->phase_grid[ph]), dim3(kBatchThreads), args, 0, st));
         return VRT_OK;
     }
-    VRT_HIP(hipLaunchCooperativeKernel((const void *)k_batch, dim3(b->grid), dim3(kBatchThreads), args, 0, st));
+    if (mode == VRT_BATCH_SPLIT) {  // build-and-walk phases in one cooperative launch, then the shade phases
+        VRT_HIP(hipLaunchCooperativeKernel((const void *)k_batch<P_SHADE8>, dim3(b->grid_split), dim3(kBatchThreads),
+                                           args, 0, st));
+        for (int ph = P_SHADE8; ph < kPhases; ++ph)
+            VRT_HIP(hipLaunchKernel(phase_kernel(ph), dim3(b->phase_grid[ph]), dim3(kBatchThreads), args, 0, st));
+        return VRT_OK;
+    }
+    VRT_HIP(hipLaunchCooperativeKernel((const void *)k_batch<kPhases>, dim3(b->grid), dim3(kBatchThreads), args, 0,
+                                       st));
     return VRT_OK;
 }
 

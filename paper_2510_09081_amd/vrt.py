@@ -21,7 +21,7 @@ VRT_ERR_CAPACITY, VRT_ERR_COUNT_OVERFLOW, VRT_ERR_HIP = 4, 5, 6
 CULL_NONE, CULL_OPAQUE, CULL_ALPHA = 0, 1, 2
 TRACE_OPAQUE, TRACE_TRANSPARENT = 0, 1
 FORM_PLAIN, FORM_FP16 = 0, 1
-BATCH_PERSISTENT, BATCH_SEQUENTIAL, BATCH_STAGED = 0, 1, 2
+BATCH_PERSISTENT, BATCH_SEQUENTIAL, BATCH_STAGED, BATCH_SPLIT = 0, 1, 2, 3
 
 EXPORTED = ["vrt_create", "vrt_destroy", "vrt_voxelize", "vrt_cull", "vrt_trace", "vrt_frame_status",
             "vrt_query_as", "vrt_debug_rays", "vrt_copy_to_host", "vrt_last_hip_error", "vrt_status_string",

@@ -58,23 +58,27 @@ def test_persistent_batch_equals_sequential(orc):
     if not torch.cuda.is_available():
         pytest.fail("no GPU: the gpu tests need an MI355X")
     sets = small_batch()
-    pb, sb, tb = vrt.Batch(caps(sets)), vrt.Batch(caps(sets)), vrt.Batch(caps(sets))
+    pb, sb, tb, xb = vrt.Batch(caps(sets)), vrt.Batch(caps(sets)), vrt.Batch(caps(sets)), vrt.Batch(caps(sets))
     try:
-        ip, isq, ist = make_items(sets), make_items(sets), make_items(sets)
+        ip, isq, ist, isp = make_items(sets), make_items(sets), make_items(sets), make_items(sets)
         for rep in range(3):  # repeated launches reuse the arenas and the ticket counters
             pb.run(ip, vrt.BATCH_PERSISTENT)
             sb.run(isq, vrt.BATCH_SEQUENTIAL)
             tb.run(ist, vrt.BATCH_STAGED)
+            xb.run(isp, vrt.BATCH_SPLIT)
             torch.cuda.synchronize()
             for i in range(len(sets)):
                 sp, ss, s3 = pb.context(i).frame_status(), sb.context(i).frame_status(), tb.context(i).frame_status()
-                assert sp["device_status"] == ss["device_status"] == s3["device_status"] == 0
+                s4 = xb.context(i).frame_status()
+                assert sp["device_status"] == ss["device_status"] == s3["device_status"] == s4["device_status"] == 0
                 assert (sp["n_fragments"], sp["n_listed"], sp["n_bricks"]) == \
                        (ss["n_fragments"], ss["n_listed"], ss["n_bricks"]) == \
-                       (s3["n_fragments"], s3["n_listed"], s3["n_bricks"]), (rep, i)
+                       (s3["n_fragments"], s3["n_listed"], s3["n_bricks"]) == \
+                       (s4["n_fragments"], s4["n_listed"], s4["n_bricks"]), (rep, i)
                 for key in ("rgba", "depth", "first_id"):
                     assert torch.equal(ip[i][key], isq[i][key]), (rep, i, key)
                     assert torch.equal(ist[i][key], isq[i][key]), (rep, i, key)
+                    assert torch.equal(isp[i][key], isq[i][key]), (rep, i, key)
         # one set of the persistent batch against the oracle
         k = 4
         ls, cam, cull, mode = sets[k]
@@ -90,30 +94,34 @@ def test_persistent_batch_equals_sequential(orc):
         pb.close()
         sb.close()
         tb.close()
+        xb.close()
 
 
 def test_batch_uses_each_sets_shade_group(orc):
     """Sets whose contexts carry different tuned shade groups (8, 16, 32 lanes per ray): the persistent and
-    staged launches still give the sequential calls' images exactly."""
+    staged and split launches still give the sequential calls' images exactly."""
     import torch
     if not torch.cuda.is_available():
         pytest.fail("no GPU: the gpu tests need an MI355X")
     sets = small_batch(n=6, seed=11)
-    pb, sb, tb = vrt.Batch(caps(sets)), vrt.Batch(caps(sets)), vrt.Batch(caps(sets))
+    pb, sb, tb, xb = vrt.Batch(caps(sets)), vrt.Batch(caps(sets)), vrt.Batch(caps(sets)), vrt.Batch(caps(sets))
     try:
-        for bb in (pb, sb, tb):
+        for bb in (pb, sb, tb, xb):
             for i, (_, _, _, mode) in enumerate(sets):
                 bb.context(i).set_tune(mode, shade_group=(8, 16, 32)[i % 3])
-        ip, isq, ist = make_items(sets), make_items(sets), make_items(sets)
+        ip, isq, ist, isp = make_items(sets), make_items(sets), make_items(sets), make_items(sets)
         pb.run(ip, vrt.BATCH_PERSISTENT)
         sb.run(isq, vrt.BATCH_SEQUENTIAL)
         tb.run(ist, vrt.BATCH_STAGED)
+        xb.run(isp, vrt.BATCH_SPLIT)
         torch.cuda.synchronize()
         for i in range(len(sets)):
             for key in ("rgba", "depth", "first_id"):
                 assert torch.equal(ip[i][key], isq[i][key]), (i, key)
                 assert torch.equal(ist[i][key], isq[i][key]), (i, key)
+                assert torch.equal(isp[i][key], isq[i][key]), (i, key)
     finally:
         pb.close()
         sb.close()
         tb.close()
+        xb.close()
