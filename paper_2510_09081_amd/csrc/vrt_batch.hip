@@ -220,9 +220,9 @@ __device__ __forceinline__ void batch_phase(int ph, const SetDesc *__restrict__ 
 // (kEnd = kPhases: every phase).  As one function holding every phase it
 // would take about 240 registers (one 512-thread block per compute unit,
 // two waves per SIMD); it is capped at four waves per SIMD, which costs
-// about 430 bytes of spills per lane and is still 1.27x faster on the
+// 416 bytes of spills per lane and is still 1.27x faster on the
 // 64-set batch.  kEnd = P_SHADE8 holds the phases up to the ray walk only
-// (the build-and-walk launch of the split form, about 260 bytes of spills).
+// (the build-and-walk launch of the split form, 240 bytes of spills).
 template <int kEnd>
 __global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_batch(const SetDesc *__restrict__ sets, int nsets, unsigned *__restrict__ tickets) {
