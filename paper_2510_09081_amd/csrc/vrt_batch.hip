@@ -7,7 +7,9 @@
 // launch of that stage would use, counted from the device-side sizes the
 // previous phases produced -- and the resident blocks take them from a ticket
 // counter, the sets in decreasing size order so the largest start first.
-// Each virtual block runs the same kernel body as the plain launch.
+// Each virtual block runs the same kernel body as the plain launch.  The
+// same phases also run as one launch each (staged form), or up to the ray
+// walk in one cooperative launch and the shade phases after it (split form).
 #include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
