@@ -110,10 +110,9 @@ __device__ __forceinline__ void b_cull_walk(CullArgs a, CullCells cells, const u
     const unsigned n = st->n_occ;
     for (unsigned i = bid_ * blockDim.x + threadIdx.x; i < n; i += nblk_ * blockDim.x) {
         const uint32_t v = occ_list[i];
-        const int64_t b = v >> 9;
         const int l = (int)(v & 511u);
-        const int bx = (int)(b % a.g.nb[0]), by = (int)((b / a.g.nb[0]) % a.g.nb[1]);
-        const int bz = (int)(b / ((int64_t)a.g.nb[0] * a.g.nb[1]));
+        int bx, by, bz;
+        brick_xyz(v >> 9, a.g.nb, bx, by, bz);
         const int x = bx * 8 + (l & 7), y = by * 8 + ((l >> 3) & 7), z = bz * 8 + (l >> 6);
         const int nblk = culling_walk(a.g.G, x, y, z, a.E, a.limit, bbox, cells);
         vis0[v] = nblk < a.limit ? 1 : 0;
@@ -181,8 +180,8 @@ __device__ __forceinline__ void b_cull_brick(int limit, GridArgs g, const uint32
             for (int k = 0; k < 8; ++k) tot += wsum[k];
             brick_total[sl] = tot;
             if (o) {
-                const int bx = (int)(b % g.nb[0]), by = (int)((b / g.nb[0]) % g.nb[1]);
-                const int bz = (int)(b / ((int64_t)g.nb[0] * g.nb[1]));
+                int bx, by, bz;
+                brick_xyz((uint32_t)b, g.nb, bx, by, bz);
                 int *p = st->stripe[bid_ % kStripes].vbox;
                 atomicMin(&p[0], bx); atomicMin(&p[1], by); atomicMin(&p[2], bz);
                 atomicMax(&p[3], bx); atomicMax(&p[4], by); atomicMax(&p[5], bz);

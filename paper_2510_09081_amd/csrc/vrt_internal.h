@@ -167,6 +167,17 @@ struct GridArgs {
     int ns[3];  // 64^3 cells per axis
 };
 
+// Brick coordinates of brick index b, x fastest.  Grids are at most 1024
+// voxels a side, so b < 2^21 and 32-bit division is exact (64-bit division
+// is a long emulated sequence).
+__device__ __forceinline__ void brick_xyz(uint32_t b, const int *nb, int &bx, int &by, int &bz) {
+    const uint32_t n0 = (uint32_t)nb[0], n1 = (uint32_t)nb[1];
+    const uint32_t q = b / n0;
+    bx = (int)(b - q * n0);
+    bz = (int)(q / n1);
+    by = (int)(q - (uint32_t)bz * n1);
+}
+
 // Blocker flags above the voxel level, each array x fastest.  Bits, in one
 // word array: one per brick, then one per 16^3 cell (2^3 bricks) from word
 // w16.  Bytes, in one byte array: one per 64^3 cell, then one per 32^3 cell

@@ -131,8 +131,8 @@ __global__ void __launch_bounds__(512) k_shade(ShadeArgs a) {
         const int64_t b = a.list[sl];
         const int64_t vi = b * kBrickVox + t;
         if (!a.vis0[vi]) continue;
-        const int bx = (int)(b % a.g.nb[0]), by = (int)((b / a.g.nb[0]) % a.g.nb[1]);
-        const int bz = (int)(b / ((int64_t)a.g.nb[0] * a.g.nb[1]));
+        int bx, by, bz;
+        brick_xyz((uint32_t)b, a.g.nb, bx, by, bz);
         const int p0 = 8 * bx + (t & 7), p1 = 8 * by + ((t >> 3) & 7), p2 = 8 * bz + (t >> 6);
         // voxel centre in 1/256 units (below 2^18 on grids up to 1024^3: 32-bit arithmetic is exact)
         const int C0 = p0 * kQ + kQ / 2, C1 = p1 * kQ + kQ / 2, C2 = p2 * kQ + kQ / 2;

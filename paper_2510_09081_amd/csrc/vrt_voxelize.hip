@@ -757,7 +757,8 @@ __device__ __forceinline__ void b_erode(GridArgs g, const uint16_t *__restrict__
     __syncthreads();
     for (unsigned sl = bid_; sl < nbk; sl += nblk_) {
         int64_t b = list[sl];
-        int bx = (int)(b % g.nb[0]), by = (int)((b / g.nb[0]) % g.nb[1]), bz = (int)(b / ((int64_t)g.nb[0] * g.nb[1]));
+        int bx, by, bz;
+        brick_xyz((uint32_t)b, g.nb, bx, by, bz);
         int x = bx * 8 + (t & 7), y = by * 8 + ((t >> 3) & 7), z = bz * 8 + (t >> 6);
         unsigned e = occ0[b * kBrickVox + t];
         if (e >= 256u) {
