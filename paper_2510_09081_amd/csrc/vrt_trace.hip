@@ -77,24 +77,31 @@ __device__ __forceinline__ float capsule_entry(float3 ro, float3 D, float3 pa, f
     const float3 ba = sub3(pb, pa), oa = sub3(ro, pa);
     const float baba = dot3(ba, ba);
     const float r2 = r * r;
-    if (baba == 0.0f) return sphere_entry(oa, D, r2);
-    const float3 w = cross3(D, ba), u = cross3(oa, ba);
-    const float ww = dot3(w, w);
-    const float bard = dot3(ba, D), baoa = dot3(ba, oa);
-    const float c = dot3(u, u) - r2 * baba;
-    if (ww == 0.0f) {  // parallel to the axis: inside the cylinder or a miss
-        if (c > 0.0f) return -INFINITY;
-        return sphere_entry(bard > 0.0f ? oa : sub3(ro, pb), D, r2);
+    // The three ways to an end sphere (a point segment, a ray parallel to the
+    // axis, an entry beyond an end) share one sphere test, so that lanes of a
+    // wave taking different ways run it together.
+    float3 oc = oa;
+    if (baba != 0.0f) {
+        const float3 w = cross3(D, ba), u = cross3(oa, ba);
+        const float ww = dot3(w, w);
+        const float bard = dot3(ba, D), baoa = dot3(ba, oa);
+        const float c = dot3(u, u) - r2 * baba;
+        if (ww == 0.0f) {  // parallel to the axis: inside the cylinder or a miss
+            if (c > 0.0f) return -INFINITY;
+            if (!(bard > 0.0f)) oc = sub3(ro, pb);
+        } else {
+            const float ow = dot3(oa, w);
+            const float g = r2 * ww - ow * ow;
+            if (g < 0.0f) return -INFINITY;  // misses the infinite cylinder, hence the capsule
+            const float b = dot3(w, u);
+            const float sq = fsqrt(baba * g);
+            const float t = fdiv(b >= 0.0f ? -(b + sq) : c, b >= 0.0f ? ww : sq - b);  // the stable root
+            const float y = baoa + t * bard;
+            if (y > 0.0f && y < baba) return t;
+            if (!(y <= 0.0f)) oc = sub3(ro, pb);
+        }
     }
-    const float ow = dot3(oa, w);
-    const float g = r2 * ww - ow * ow;
-    if (g < 0.0f) return -INFINITY;  // misses the infinite cylinder, hence the capsule
-    const float b = dot3(w, u);
-    const float sq = fsqrt(baba * g);
-    const float t = b >= 0.0f ? fdiv(-(b + sq), ww) : fdiv(c, sq - b);
-    const float y = baoa + t * bard;
-    if (y > 0.0f && y < baba) return t;
-    return sphere_entry(y <= 0.0f ? oa : sub3(ro, pb), D, r2);
+    return sphere_entry(oc, D, r2);
 }
 
 struct TraceArgs {
