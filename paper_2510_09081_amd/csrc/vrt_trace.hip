@@ -961,7 +961,7 @@ __device__ __forceinline__ void b_trace_walk(TraceArgs a, unsigned bid_, unsigne
     }
 }
 
-__global__ void __launch_bounds__(256) k_trace_walk(TraceArgs a) { b_trace_walk(a, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(64) k_trace_walk(TraceArgs a) { b_trace_walk(a, blockIdx.x, gridDim.x); }
 
 // Phase 2, one kGroup-lane group per queued ray: lists, capsule tests and
 // compositing, continuing the walk until the ray is finished.  All lanes of a
@@ -1243,10 +1243,13 @@ static unsigned march_grid(const TraceParams &p, int threads) {
     return (unsigned)(((p.W + 15) / 16) * ((p.H + rows - 1) / rows));
 }
 
-// Walk phase grid: one thread per pixel that could be queued, at most 2048 blocks (grid-stride beyond).
+// Walk phase grid: one thread per pixel that could be queued, one wave per
+// block (the queued rays' waves then spread evenly over the compute units:
+// 2.5% faster than four-wave blocks), at most 8192 blocks (grid-stride beyond).
+constexpr int kWalkThreads = 64;
 static unsigned walk_grid(const TraceParams &p) {
-    const int64_t b = ((int64_t)p.W * p.H + 255) / 256;
-    return (unsigned)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+    const int64_t b = ((int64_t)p.W * p.H + kWalkThreads - 1) / kWalkThreads;
+    return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
 }
 
 // Resume launch: rays past the walk limit are rare (they need more than
@@ -1283,7 +1286,7 @@ hipError_t launch_trace(vrt_ctx *c, const TraceParams &p, const vrt_image *img, 
     VRT_LAUNCH(c, "k_trace_begin", st, k_trace_begin<<<1, 64, 0, st>>>(a.st));
     VRT_LAUNCH(c, "k_brick_skip", st, k_brick_skip<<<skip_grid(c), 256, 0, st>>>(a));
     VRT_LAUNCH(c, "k_trace_march", st, k_trace_march<false><<<march_grid(p, t.march_threads), t.march_threads, 0, st>>>(a));
-    VRT_LAUNCH(c, "k_trace_walk", st, k_trace_walk<<<walk_grid(p), 256, 0, st>>>(a));
+    VRT_LAUNCH(c, "k_trace_walk", st, k_trace_walk<<<walk_grid(p), kWalkThreads, 0, st>>>(a));
     if (c->desc.form == VRT_FORM_FP16) {
         VRT_LAUNCH(c, "k_trace_shade", st, (launch_shade<false, VRT_FORM_FP16>(t, a, st)));
         VRT_LAUNCH(c, "k_trace_resume", st, k_trace_resume<VRT_FORM_FP16><<<kResumeBlocks, 64, 0, st>>>(a));
