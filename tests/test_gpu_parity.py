@@ -223,6 +223,29 @@ def test_edge_cases(orc, ctx, name):
             assert err.max(initial=0) <= (1e-6 if mode == 0 else 1e-4)
 
 
+def test_ray_along_segment_axis(orc, ctx):
+    """A ray exactly parallel to a segment's axis (its cross product with the axis is zero, so the capsule
+    test takes the end-sphere way for rays inside the infinite cylinder): with an odd image the centre
+    pixel's direction is exactly +x, along the segment from (4, 4, 4) to (12, 4, 4); it enters the near end
+    sphere at x = 4 - r, at distance 0.71875 from the eye."""
+    ls = _make([[[4, 4, 4], [12, 4, 4]], [[2, 10, 10], [6, 14, 14]]], 16, 0.5)
+    cam = synth.Camera(eye=np.array([-0.5, 0.25, 0.25]), target=np.array([0.5, 0.25, 0.25]),
+                       up=np.array([0.0, 0.0, 1.0]), fovy_deg=40.0, width=33, height=33)
+    c = 16 * 33 + 16
+    for cull in (vrt.CULL_NONE, vrt.CULL_OPAQUE):
+        fr = orc.build_frame(ls, cam.eye, cull)
+        G.run_build(ctx, ls, cam.eye, cull)
+        for mode in (0, 1):
+            gid, gdepth, grgba = G.run_trace(ctx, cam, mode, alpha=0.3)
+            tr = orc.trace(fr, ls, cam, np.arange(cam.width * cam.height), mode, alpha=0.3)
+            cert = certified(tr, mode)
+            assert cert[c] and tr.id[c] == 0 and gid[c] == 0, (cull, mode, tr.id[c], gid[c])
+            assert abs(float(gdepth[c]) - 0.71875) < 1e-5
+            assert not (cert & (gid != tr.id)).any()
+            err = np.abs(grgba[cert].astype(np.float64) - tr.rgba[cert])
+            assert err.max(initial=0) <= (1e-6 if mode == 0 else 1e-4)
+
+
 def test_capacity_error_and_recovery(orc, ctx):
     import torch
     ls = synth.random_walk_set(seed=3, n_poly=50, n_seg=30, G=32)
