@@ -238,8 +238,8 @@ def bench_dynamic(torch, vrt, synth, warmup):
 
 def bench_batched(torch, vrt, synth, steps, warmup):
     """64 uneven line sets (1k-1M segments, 64^3-256^3 grids, 512x512 each, opaque, culled):
-    one persistent launch, one launch per phase, and the split form (one cooperative launch up to the ray walk,
-    then one launch per shade phase) against the plain calls set by set."""
+    one persistent launch, one launch per phase, and the split form (one cooperative launch for the build, then one
+    launch per view-dependent phase) against the plain calls set by set."""
     ws = synth.batch_sets()
     items, capsl = [], []
     for w in ws:

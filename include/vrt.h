@@ -301,10 +301,10 @@ vrt_status vrt_frame_noalloc(const vrt_lines *lines, const vrt_grid *grid, const
  * take (set, stage, block) work items from a counter, largest sets first.
  * VRT_BATCH_STAGED runs the same phases as one launch each (kernel boundaries
  * instead of grid barriers; each phase kernel is compiled for its own stages,
- * so it keeps their register budget).  VRT_BATCH_SPLIT runs the phases up to
- * the ray walk in one cooperative launch and the tracer's shade phases (whose
- * register budget the cooperative kernel would otherwise have to hold) as
- * one launch each after it.  VRT_BATCH_SEQUENTIAL issues the plain
+ * so it keeps their register budget).  VRT_BATCH_SPLIT runs the view-
+ * independent build (ingest, bins, pass 1, pyramid, erosion) in one
+ * cooperative launch and every view-dependent phase (culling, lists, trace)
+ * as a launch of its own after it.  VRT_BATCH_SEQUENTIAL issues the plain
  * vrt_voxelize / vrt_cull / vrt_trace calls set after set (the reference the
  * batched forms are compared with).  All give identical results.  Set i uses the arenas of a context created
  * from descs[i] (reachable with vrt_batch_context for vrt_frame_status and

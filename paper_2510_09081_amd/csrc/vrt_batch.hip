@@ -8,8 +8,9 @@
 // previous phases produced -- and the resident blocks take them from a ticket
 // counter, the sets in decreasing size order so the largest start first.
 // Each virtual block runs the same kernel body as the plain launch.  The
-// same phases also run as one launch each (staged form), or up to the ray
-// walk in one cooperative launch and the shade phases after it (split form).
+// same phases also run as one launch each (staged form), or the view-
+// independent build (up to the erosion) in one cooperative launch and every
+// later phase as a launch of its own (split form).
 #include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
@@ -223,8 +224,12 @@ __device__ __forceinline__ void batch_phase(int ph, const SetDesc *__restrict__ 
 // would take about 240 registers (one 512-thread block per compute unit,
 // two waves per SIMD); it is capped at four waves per SIMD, which costs
 // 416 bytes of spills per lane and is still 1.27x faster on the
-// 64-set batch.  kEnd = P_SHADE8 holds the phases up to the ray walk only
-// (the build-and-walk launch of the split form, 240 bytes of spills).
+// 64-set batch.  kEnd = P_WALK holds the build phases only (the cooperative
+// launch of the split form, 240 bytes of spills).  Its occupancy is set by
+// its heaviest phase, so every phase runs with fewer resident waves than its
+// own phase kernel: on the 64-set batch each phase moved from the
+// cooperative launch to a launch of its own saves 0.15-0.3 ms, the culling
+// phases most.
 template <int kEnd>
 __global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_batch(const SetDesc *__restrict__ sets, int nsets, unsigned *__restrict__ tickets) {
@@ -298,7 +303,7 @@ struct vrt_batch {
     hipEvent_t copied = nullptr;
     bool copy_pending = false;
     unsigned grid = 0;                     // resident blocks of the persistent kernel
-    unsigned grid_split = 0;               // resident blocks of the split form's build-and-walk kernel
+    unsigned grid_split = 0;               // resident blocks of the split form's build kernel
     unsigned phase_grid[vrt::kPhases] = {}; // resident blocks of each staged phase kernel
 };
 
@@ -334,7 +339,7 @@ vrt_status vrt_batch_create(const vrt_desc *descs, int32_t n, vrt_batch **out) {
     if (st == VRT_OK && e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<kPhases>, kBatchThreads, 0);
     if (st == VRT_OK && e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_split, k_batch<P_SHADE8>, kBatchThreads, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_split, k_batch<P_WALK>, kBatchThreads, 0);
     if (st == VRT_OK && e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device);
     for (int ph = 0; ph < kPhases && st == VRT_OK && e == hipSuccess; ++ph) {
         int pc = 0;
@@ -423,10 +428,10 @@ vrt_status vrt_batch_run(vrt_batch *b, const vrt_batch_item *items, int32_t n, i
             VRT_HIP(hipLaunchKernel(phase_kernel(ph), dim3(b->phase_grid[ph]), dim3(kBatchThreads), args, 0, st));
         return VRT_OK;
     }
-    if (mode == VRT_BATCH_SPLIT) {  // build-and-walk phases in one cooperative launch, then the shade phases
-        VRT_HIP(hipLaunchCooperativeKernel((const void *)k_batch<P_SHADE8>, dim3(b->grid_split), dim3(kBatchThreads),
+    if (mode == VRT_BATCH_SPLIT) {  // the build phases in one cooperative launch, then one launch per phase
+        VRT_HIP(hipLaunchCooperativeKernel((const void *)k_batch<P_WALK>, dim3(b->grid_split), dim3(kBatchThreads),
                                            args, 0, st));
-        for (int ph = P_SHADE8; ph < kPhases; ++ph)
+        for (int ph = P_WALK; ph < kPhases; ++ph)
             VRT_HIP(hipLaunchKernel(phase_kernel(ph), dim3(b->phase_grid[ph]), dim3(kBatchThreads), args, 0, st));
         return VRT_OK;
     }
